@@ -1,0 +1,102 @@
+/*
+ * pfr_oracle.h -- TEST INFRASTRUCTURE ONLY.
+ *
+ * A plain, slow, single-threaded CPU reference for the particle-filter
+ * resampling step of Murray, Lee & Jacob, "Parallel resampling in the
+ * particle filter" (arXiv:1301.4019).  It exists so that tests, the smoke
+ * check and the CPU-baseline leg of the benchmark can check the HIP library
+ * against the paper.  Nothing in the product path may link, load or call it.
+ * It shares no code with the HIP library (own Philox, own sums, own
+ * comparisons).
+ *
+ * Conventions (0-based, see the paper's section 1.1 for the 1-based form):
+ *   weights    w[0..n)  doubles (FP32 inputs are widened exactly)
+ *   ancestors  a[0..n)  int32, a[i] = index of the parent of particle i
+ *   offspring  o[0..n)  int32
+ * Random numbers come from Philox4x32-10 with the counter layout
+ *   ctr = (index, (domain << 28) | step, filter, offset), key = seed.
+ *
+ * Every function that has a flags argument ORs the ORC_FLAG_* bits into it
+ * (it may be NULL).  Return value is 0, or -1 for invalid arguments.
+ */
+#ifndef PFR_ORACLE_H
+#define PFR_ORACLE_H
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ORC_FLAG_ZERO_TOTAL   1u  /* total weight is zero                          */
+#define ORC_FLAG_TRIAL_CAP    2u  /* a rejection lane used all its trials          */
+#define ORC_FLAG_BAD_COUNTS   4u  /* offspring negative or not summing to n        */
+#define ORC_FLAG_BAD_WEIGHTS  8u  /* a weight is negative, NaN or infinite         */
+#define ORC_FLAG_BAD_ANCESTOR 16u /* an ancestor index lies outside [0, n)         */
+
+#define ORC_DOM_STRATA 0u /* stratified / systematic offsets  */
+#define ORC_DOM_EXP    1u /* exponential spacings (multinomial) */
+#define ORC_DOM_TRIAL  2u /* Metropolis steps, rejection trials */
+#define ORC_DOM_NOISE  3u /* state-space model propagation     */
+#define ORC_DOM_INIT   4u /* state-space model initial state   */
+
+/* Philox4x32 with 10 rounds (Salmon et al., SC'11). */
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+
+/* Canonical draws shared by definition with the HIP library.                  */
+/* u in (0,1]: ((x + 1) * 2^-32); index in [0,n): floor(((x1<<32)|x0) * n / 2^64) */
+double orc_u_accept(uint32_t x);
+int64_t orc_index(uint32_t x0, uint32_t x1, int64_t n);
+/* Exact decision u * w_k <= w_j (Metropolis, Code 2; rejection, Code 3). */
+int orc_accept(double u, double w_k, double w_j);
+
+/* Code 2 (Metropolis-Ancestors), B steps per lane. */
+int orc_resample_metropolis(const double* w, int64_t n, int32_t B, uint64_t seed,
+                            uint32_t filter, uint32_t offset, int32_t* a);
+
+/* Code 3 (Rejection-Ancestors) with first proposal j = i.  trials[i] (may be
+ * NULL) receives the number of trials lane i used. */
+int orc_resample_rejection(const double* w, int64_t n, double w_max, uint32_t max_trials,
+                           uint64_t seed, uint32_t filter, uint32_t offset, int32_t* a,
+                           uint32_t* trials, uint32_t* flags);
+
+/* Code 7 (stratified) with explicit stratum offsets u[0..n) in [0,1).
+ * r_out (may be NULL) receives the scaled prefix r_i = n W_i / W_n (rounded
+ * to double from the oracle's binary128 value). */
+int orc_stratified_u(const double* w, int64_t n, const double* u, int32_t* a,
+                     double* r_out, uint32_t* flags);
+/* Code 7 with Philox offsets (stratum m uses word m&3 of call m>>2, domain 0). */
+int orc_resample_stratified(const double* w, int64_t n, uint64_t seed, uint32_t filter,
+                            uint32_t offset, int32_t* a, double* r_out, uint32_t* flags);
+/* Code 8 (systematic): one offset, word 0 of call 0, domain 0. */
+int orc_resample_systematic(const double* w, int64_t n, uint64_t seed, uint32_t filter,
+                            uint32_t offset, int32_t* a, double* r_out, uint32_t* flags);
+/* The systematic offset the canonical draw produces (for tests). */
+double orc_systematic_offset(uint64_t seed, uint32_t filter, uint32_t offset);
+/* The stratum offsets the canonical draw produces (for tests). */
+void orc_stratum_offsets(int64_t n, uint64_t seed, uint32_t filter, uint32_t offset, double* u);
+
+/* Code 5 (multinomial) driven by sorted uniforms from exponential spacings:
+ * E_k (k = 0..n) from word k&3 of call k>>2, domain 1; p_k = n S_k / S_n for
+ * k < n; a[k] = #{ i < n-1 : r_i <= p_k }.  p_out (may be NULL) gets p. */
+int orc_resample_multinomial(const double* w, int64_t n, uint64_t seed, uint32_t filter,
+                             uint32_t offset, int32_t* a, double* r_out, double* p_out,
+                             uint32_t* flags);
+/* The same search with caller-given sorted points p[0..n) in [0,n]. */
+int orc_multinomial_points(const double* w, int64_t n, const double* p, int32_t* a,
+                           uint32_t* flags);
+
+/* Code 11 (Cumulative-Offspring-to-Ancestors) on offspring counts. */
+int orc_offspring_to_ancestors(const int32_t* o, int64_t n, int32_t* a, uint32_t* flags);
+/* Code 12 (Ancestors-to-Offspring). */
+int orc_ancestors_to_offspring(const int32_t* a, int64_t n, int32_t* o, uint32_t* flags);
+
+/* Code 10 (Prepermute + Permute); c receives the permuted ancestry, d (may be
+ * NULL) the final claim vector (n = unclaimed). */
+int orc_permute(const int32_t* a, int64_t n, int32_t* c, int32_t* d, uint32_t* flags);
+/* Code 9 (serial in-place Permute), used only as an invariant cross-check. */
+int orc_permute_serial(int32_t* a, int64_t n);
+
+#ifdef __cplusplus
+}
+#endif
+#endif
