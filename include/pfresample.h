@@ -1,0 +1,213 @@
+/*
+ * pfresample.h -- C ABI of libpfresample, the particle-filter resampling step
+ * of Murray, Lee & Jacob, "Parallel resampling in the particle filter"
+ * (arXiv:1301.4019), for AMD Instinct MI355X (gfx950).
+ *
+ * The resampling step maps a weight vector w in [0, inf)^n to an ancestry
+ * vector a in {0..n-1}^n, a_i being the index of the parent of particle i
+ * (section 1.1 of the paper, 0-based here).  The library provides the five
+ * resamplers the paper studies, the conversion of offspring counts to
+ * ancestors and the ancestor permutation that makes in-place propagation safe.
+ *
+ * Conventions for every entry point
+ *   - All arrays are DEVICE pointers owned by the caller.  The library never
+ *     allocates, frees or synchronises: a call only enqueues kernels on
+ *     `stream` (a hipStream_t; NULL = the default stream) and returns.
+ *   - Return value: a pfr_status, reporting only argument and launch errors,
+ *     detected synchronously on the host.  Problems in the data (zero total
+ *     weight, non-finite weights, bad counts, ...) are reported
+ *     asynchronously by OR-ing PFR_FLAG_* bits into *dev_flags (a device
+ *     uint32, may be NULL); each has a defined output (see the flags below).
+ *   - n is the particle count of one vector, below 2^31.  Ragged batches of
+ *     independent vectors are described by pfr_segments (see below); every
+ *     index in a batched output is local to its segment.
+ *   - Weights are float32 or float64 (pfr_dtype), contiguous.  The collective
+ *     resamplers read them with 16-byte vector loads when the segment start
+ *     is 16-byte aligned and fall back to scalar loads otherwise.
+ *   - Workspaces are caller-provided device buffers of at least
+ *     pfr_workspace_bytes() bytes, 256-byte aligned, and must be set to zero
+ *     once (pfr_workspace_init) before their first use; the library keeps
+ *     them in a reusable state after every call.  Calls that share a
+ *     workspace must be ordered (same stream, or synchronised).
+ *   - Outputs must not alias inputs.
+ *   - Random numbers come from Philox4x32-10 (Salmon et al., SC'11) with
+ *     counter (index, domain << 28 | step, filter, offset) and key = seed, so
+ *     results are bit-reproducible and independent of the launch shape.
+ */
+#ifndef PFRESAMPLE_H
+#define PFRESAMPLE_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#if defined(__GNUC__)
+#define PFR_API __attribute__((visibility("default")))
+#else
+#define PFR_API
+#endif
+
+typedef enum {
+    PFR_OK = 0,
+    PFR_EINVAL = 1,     /* invalid argument (null pointer, size, alias, ...) */
+    PFR_EWORKSPACE = 2, /* workspace missing, too small or misaligned */
+    PFR_ELAUNCH = 3,    /* a kernel launch failed */
+    PFR_ENOTSUP = 4     /* combination not supported */
+} pfr_status;
+
+typedef enum { PFR_F32 = 0, PFR_F64 = 1 } pfr_dtype;
+
+/* Arithmetic of the prefix sum of the collective resamplers.
+ *   PFR_SCAN_EXACT      exact fixed-point sums (default; see below)
+ *   PFR_SCAN_F64        binary64 sums and scaling
+ *   PFR_SCAN_COMP_F32   compensated (two-sum) binary32 sums, binary64 scaling
+ *   PFR_SCAN_NAIVE_F32  binary32 sums and the literal binary32 floor(r + u) of
+ *                       Codes 7 and 8 (reproduces the bias the paper reports)
+ * In the floating-point modes a zero weight may be selected when rounding
+ * puts a point exactly on its empty interval. */
+typedef enum {
+    PFR_SCAN_EXACT = 0,
+    PFR_SCAN_F64 = 1,
+    PFR_SCAN_COMP_F32 = 2,
+    PFR_SCAN_NAIVE_F32 = 3
+} pfr_precision;
+
+/* Asynchronous data flags (OR-ed into *dev_flags). */
+#define PFR_FLAG_ZERO_TOTAL 1u   /* all weights zero: output is the identity a_i = i */
+#define PFR_FLAG_TRIAL_CAP 2u    /* rejection: a particle rejected max_trials proposals; it keeps a_i = i */
+#define PFR_FLAG_BAD_COUNTS 4u   /* offspring negative or not summing to n (see offspring_to_ancestors);
+                                    also raised by a batched collective call whose segment exceeds
+                                    PFR_MAX_BATCH_SEGMENT (that segment gets the identity) */
+#define PFR_FLAG_BAD_WEIGHTS 8u  /* a weight is negative, NaN or infinite: output is the identity */
+#define PFR_FLAG_BAD_ANCESTOR 16u /* permute: an ancestor outside [0, n) is replaced by its own index */
+
+/* Longest segment a batched collective call (n_filters > 1) accepts. */
+#define PFR_MAX_BATCH_SEGMENT (256 * 1024 - 1)
+
+/* A ragged batch of independent vectors stored back to back: segment f holds
+ * global positions [offsets[f], offsets[f+1]).  offsets is a DEVICE int64
+ * array of n_filters + 1 non-decreasing values with offsets[0] = 0 and
+ * offsets[n_filters] = n_total; it may be NULL when n_filters == 1.
+ * max_len is a host-side upper bound on the segment lengths (0 = unknown). */
+typedef struct {
+    int64_t n_total;
+    int32_t n_filters;
+    const int64_t* offsets;
+    int64_t max_len;
+} pfr_segments;
+
+/* Philox key and counter words: seed is the 64-bit key, offset the last
+ * counter word (e.g. the time step of a filter), filter_base the filter id of
+ * segment 0 (segment f uses filter_base + f). */
+typedef struct {
+    uint64_t seed;
+    uint32_t offset;
+    uint32_t filter_base;
+} pfr_rng;
+
+typedef enum {
+    PFR_OP_MULTINOMIAL = 0,
+    PFR_OP_STRATIFIED = 1,
+    PFR_OP_SYSTEMATIC = 2,
+    PFR_OP_METROPOLIS = 3,
+    PFR_OP_REJECTION = 4,
+    PFR_OP_OFFSPRING_TO_ANCESTORS = 5,
+    PFR_OP_PERMUTE = 6
+} pfr_op;
+
+/* Bytes of workspace the operation needs for these segments (0 if none). */
+PFR_API size_t pfr_workspace_bytes(pfr_op op, const pfr_segments* seg, pfr_dtype dtype);
+
+/* Zero a workspace (enqueued on stream; no hipMemset, so it may be captured
+ * in a graph).  Needed once per workspace, before its first use. */
+PFR_API int pfr_workspace_init(void* ws, size_t ws_bytes, void* stream);
+
+/* ---------------------------------------------------------------- resamplers
+ * Collective resamplers (appendix B of the paper).  They need the total
+ * weight, which the library forms as an exact fixed-point prefix sum: each
+ * block of 1024 weights is quantised to integers below 2^53 relative to the
+ * block maximum and summed exactly, so the result is deterministic and the
+ * only rounding is the final scaling r_i = n W_i / W_n to binary64.  Zero
+ * weights are never selected.  Output ancestry is sorted (non-decreasing).
+ */
+
+/* Multinomial resampling (Code 5): draws the order statistics of n uniforms
+ * from exponential spacings E_k = -log((x + 1/2) 2^-32), k = 0..n, taken from
+ * word k&3 of Philox call k>>2 (domain 1), p_k = n S_k / S_n, and sets
+ * a_k = #{i < n-1 : r_i <= p_k}. */
+PFR_API int resample_multinomial(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                         pfr_precision precision, pfr_rng rng,
+                         int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                         void* stream);
+
+/* Stratified resampling (Code 7 then Code 11): stratum s takes the point
+ * s + 1 - u_s with u_s = word s&3 of Philox call s>>2 (domain 0) times 2^-32,
+ * and a_s = min{i : r_i >= s + 1 - u_s}. */
+PFR_API int resample_stratified(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                        pfr_precision precision, pfr_rng rng,
+                        int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                        void* stream);
+
+/* Systematic resampling (Code 8): as stratified with the single offset
+ * u = word 0 of Philox call 0 (domain 0) times 2^-32 for every stratum. */
+PFR_API int resample_systematic(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                        pfr_precision precision, pfr_rng rng,
+                        int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                        void* stream);
+
+/* Metropolis resampling (Code 2): lane i starts at k = i and runs B steps;
+ * step s draws Philox call (i, 2<<28 | s), j = floor(((x1<<32)|x0) n / 2^64),
+ * u = (x2 + 1) 2^-32, and moves to j when u w_k <= w_j (decided exactly).
+ * B_dev (device int32[n_filters], may be NULL) overrides B per segment.
+ * No workspace; no collective operation. */
+PFR_API int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segments* seg, int32_t B,
+                        const int32_t* B_dev, pfr_rng rng, int32_t* ancestors, void* stream);
+
+/* Rejection resampling (Code 3): particle i first proposes j = i, then draws
+ * j as above from Philox call (i, 2<<28 | t) for trial t >= 1 (every trial
+ * takes u from its own call), and keeps the first j with u w_max <= w_j
+ * (decided exactly).  w_max must bound the weights (else the output is
+ * biased); w_max_dev (device double[n_filters], may be NULL) overrides it per
+ * segment.  After max_trials trials (>= 1) a particle keeps a_i = i and
+ * PFR_FLAG_TRIAL_CAP is raised.  The workspace holds a work queue. */
+PFR_API int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, double w_max,
+                       const double* w_max_dev, uint32_t max_trials, pfr_rng rng,
+                       int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                       void* stream);
+
+/* ---------------------------------------------------------------- auxiliaries */
+
+/* Offspring counts to ancestors (appendix D, Code 11 after an inclusive prefix
+ * sum): a[O_{i-1} .. O_i) = i.  A negative count is used as 0; positions at
+ * or beyond n are dropped; if the counts sum to less than n the remaining
+ * positions s get a_s = s.  Each of these raises PFR_FLAG_BAD_COUNTS. */
+PFR_API int offspring_to_ancestors(const int32_t* offspring, const pfr_segments* seg, int32_t* ancestors,
+                           void* ws, size_t ws_bytes, uint32_t* dev_flags, void* stream);
+
+/* Ancestor permutation (section 2.3 and appendix C, Code 10): returns in
+ * `permuted` a permutation c of `ancestors` with c_j = j for every j that
+ * appears in the ancestry (a particle with offspring is its own first
+ * descendant), so that the copy x_i <- x_{c_i} for c_i != i followed by
+ * in-place propagation never reads a slot that is written.  Slot j is claimed by the lowest i with
+ * a_i = j; unsuccessful claimers follow x <- d_x to a free slot.  With
+ * sorted_hint != 0 the input must be non-decreasing (as produced by the
+ * collective resamplers) and the claim needs no atomics; otherwise any
+ * ancestry is accepted.  An ancestor outside [0, n) is treated as its own
+ * index and raises PFR_FLAG_BAD_ANCESTOR.  The workspace holds the claim
+ * vector. */
+PFR_API int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t sorted_hint,
+                      int32_t* permuted, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                      void* stream);
+
+/* ---------------------------------------------------------------- misc */
+PFR_API const char* pfr_status_string(int status);
+/* Library version, e.g. "0.1.0". */
+PFR_API const char* pfr_version(void);
+
+#ifdef __cplusplus
+}
+#endif
+#endif /* PFRESAMPLE_H */

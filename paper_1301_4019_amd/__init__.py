@@ -1,0 +1,221 @@
+"""Particle-filter resampling on AMD Instinct MI355X (gfx950).
+
+Python face of libpfresample (include/pfresample.h): the resamplers of Murray,
+Lee & Jacob, "Parallel resampling in the particle filter" (arXiv:1301.4019),
+the conversion of offspring counts to ancestors and the ancestor permutation
+for in-place propagation.  Functions take torch tensors that live on the GPU
+and enqueue the library's HIP kernels on the current torch stream; torch only
+provides memory and streams.  Nothing here computes on the CPU.
+
+    import paper_1301_4019_amd as pfr
+    a = pfr.resample_systematic(w, seed=1)              # w: float32/float64 on cuda
+    c = pfr.permute_ancestors(a, sorted_hint=True)
+"""
+from __future__ import annotations
+
+import ctypes
+
+from . import _lib
+from ._lib import (FLAG_BAD_ANCESTOR, FLAG_BAD_COUNTS, FLAG_BAD_WEIGHTS, FLAG_TRIAL_CAP,
+                   FLAG_ZERO_TOTAL, MAX_BATCH_SEGMENT, SCAN_COMP_F32, SCAN_EXACT, SCAN_F64,
+                   SCAN_NAIVE_F32, PfrError)
+
+__all__ = [
+    "resample_multinomial", "resample_stratified", "resample_systematic",
+    "resample_metropolis", "resample_rejection", "offspring_to_ancestors",
+    "permute_ancestors", "workspace_bytes", "new_workspace", "version", "PfrError",
+    "SCAN_EXACT", "SCAN_F64", "SCAN_COMP_F32", "SCAN_NAIVE_F32",
+    "FLAG_ZERO_TOTAL", "FLAG_TRIAL_CAP", "FLAG_BAD_COUNTS", "FLAG_BAD_WEIGHTS",
+    "FLAG_BAD_ANCESTOR", "MAX_BATCH_SEGMENT",
+]
+
+
+def _torch():
+    import torch
+    return torch
+
+
+def version() -> str:
+    return _lib.load().pfr_version().decode()
+
+
+def _stream():
+    return ctypes.c_void_p(_torch().cuda.current_stream().cuda_stream)
+
+
+def _ptr(t):
+    return None if t is None else ctypes.c_void_p(t.data_ptr())
+
+
+def _dtype_code(w):
+    torch = _torch()
+    if w.dtype == torch.float32:
+        return _lib.PFR_F32
+    if w.dtype == torch.float64:
+        return _lib.PFR_F64
+    raise TypeError("weights must be float32 or float64")
+
+
+def _require_cuda(*ts):
+    for t in ts:
+        if t is not None and (not t.is_cuda or not t.is_contiguous()):
+            raise ValueError("tensors must be contiguous GPU tensors")
+
+
+def _segments(n_total, offsets=None, max_len=None):
+    if offsets is None:
+        return _lib.Segments(int(n_total), 1, None, int(n_total))
+    _require_cuda(offsets)
+    torch = _torch()
+    if offsets.dtype != torch.int64:
+        raise TypeError("offsets must be int64")
+    nf = offsets.numel() - 1
+    return _lib.Segments(int(n_total), int(nf), offsets.data_ptr(),
+                         int(max_len) if max_len is not None else 0)
+
+
+def _rng(seed, offset, filter_base):
+    return _lib.Rng(int(seed) & (2**64 - 1), int(offset) & 0xFFFFFFFF,
+                    int(filter_base) & 0xFFFFFFFF)
+
+
+# workspaces are zeroed once and reused; calls sharing one must be ordered on
+# one stream (the default here: torch's current stream)
+_WS_CACHE: dict = {}
+
+
+def workspace_bytes(op: int, n_total: int, offsets=None, max_len=None, dtype_code=0) -> int:
+    seg = _segments(n_total, offsets, max_len)
+    return int(_lib.load().pfr_workspace_bytes(op, ctypes.byref(seg), dtype_code))
+
+
+def new_workspace(nbytes: int, device=None):
+    """A zero-initialised workspace of at least nbytes (256-byte aligned)."""
+    torch = _torch()
+    nbytes = max(256, (int(nbytes) + 255) // 256 * 256)
+    ws = torch.empty(nbytes, dtype=torch.uint8, device=device or "cuda")
+    _lib.check(_lib.load().pfr_workspace_init(_ptr(ws), nbytes, _stream()), "workspace_init")
+    return ws
+
+
+def _workspace(op, seg, dtype_code, device, ws):
+    need = int(_lib.load().pfr_workspace_bytes(op, ctypes.byref(seg), dtype_code))
+    if ws is not None:
+        return ws, need
+    if need == 0:
+        return None, 0
+    key = (str(device), op, need)
+    cached = _WS_CACHE.get(key)
+    if cached is None:
+        cached = new_workspace(need, device)
+        _WS_CACHE[key] = cached
+    return cached, need
+
+
+def _out_like(n, device, out):
+    torch = _torch()
+    if out is None:
+        return torch.empty(n, dtype=torch.int32, device=device)
+    if out.dtype != torch.int32 or out.numel() != n:
+        raise ValueError("out must be an int32 tensor with one entry per particle")
+    _require_cuda(out)
+    return out
+
+
+def _collective(fn_name, op, w, seed, offset, filter_base, precision, offsets, max_len, out,
+                flags, workspace):
+    _require_cuda(w, flags)
+    dt = _dtype_code(w)
+    seg = _segments(w.numel(), offsets, max_len)
+    a = _out_like(w.numel(), w.device, out)
+    ws, _ = _workspace(op, seg, dt, w.device, workspace)
+    fn = getattr(_lib.load(), fn_name)
+    rc = fn(_ptr(w), dt, ctypes.byref(seg), int(precision), _rng(seed, offset, filter_base),
+            _ptr(a), _ptr(ws), 0 if ws is None else ws.numel(), _ptr(flags), _stream())
+    _lib.check(rc, fn_name)
+    return a
+
+
+def resample_multinomial(w, seed=0, offset=0, filter_base=0, precision=SCAN_EXACT, offsets=None,
+                         max_len=None, out=None, flags=None, workspace=None):
+    """Multinomial ancestry (Code 5, sorted uniforms); see resample_multinomial in the C header."""
+    return _collective("resample_multinomial", _lib.OP_MULTINOMIAL, w, seed, offset, filter_base,
+                       precision, offsets, max_len, out, flags, workspace)
+
+
+def resample_stratified(w, seed=0, offset=0, filter_base=0, precision=SCAN_EXACT, offsets=None,
+                        max_len=None, out=None, flags=None, workspace=None):
+    """Stratified ancestry (Code 7 + Code 11)."""
+    return _collective("resample_stratified", _lib.OP_STRATIFIED, w, seed, offset, filter_base,
+                       precision, offsets, max_len, out, flags, workspace)
+
+
+def resample_systematic(w, seed=0, offset=0, filter_base=0, precision=SCAN_EXACT, offsets=None,
+                        max_len=None, out=None, flags=None, workspace=None):
+    """Systematic ancestry (Code 8 + Code 11)."""
+    return _collective("resample_systematic", _lib.OP_SYSTEMATIC, w, seed, offset, filter_base,
+                       precision, offsets, max_len, out, flags, workspace)
+
+
+def resample_metropolis(w, B, seed=0, offset=0, filter_base=0, B_per_filter=None, offsets=None,
+                        max_len=None, out=None):
+    """Metropolis ancestry (Code 2), B steps per lane (or B_per_filter[f])."""
+    _require_cuda(w, B_per_filter)
+    dt = _dtype_code(w)
+    seg = _segments(w.numel(), offsets, max_len)
+    a = _out_like(w.numel(), w.device, out)
+    rc = _lib.load().resample_metropolis(_ptr(w), dt, ctypes.byref(seg), int(B),
+                                         _ptr(B_per_filter), _rng(seed, offset, filter_base),
+                                         _ptr(a), _stream())
+    _lib.check(rc, "resample_metropolis")
+    return a
+
+
+def resample_rejection(w, w_max, seed=0, offset=0, filter_base=0, max_trials=1 << 20,
+                       w_max_per_filter=None, offsets=None, max_len=None, out=None, flags=None,
+                       workspace=None):
+    """Rejection ancestry (Code 3) with first proposal j = i and bound w_max."""
+    _require_cuda(w, w_max_per_filter, flags)
+    dt = _dtype_code(w)
+    seg = _segments(w.numel(), offsets, max_len)
+    a = _out_like(w.numel(), w.device, out)
+    ws, _ = _workspace(_lib.OP_REJECTION, seg, dt, w.device, workspace)
+    rc = _lib.load().resample_rejection(_ptr(w), dt, ctypes.byref(seg), float(w_max),
+                                        _ptr(w_max_per_filter), int(max_trials),
+                                        _rng(seed, offset, filter_base), _ptr(a), _ptr(ws),
+                                        ws.numel(), _ptr(flags), _stream())
+    _lib.check(rc, "resample_rejection")
+    return a
+
+
+def offspring_to_ancestors(o, offsets=None, max_len=None, out=None, flags=None, workspace=None):
+    """Ancestors from int32 offspring counts (Code 11 after a prefix sum)."""
+    torch = _torch()
+    _require_cuda(o, flags)
+    if o.dtype != torch.int32:
+        raise TypeError("offspring must be int32")
+    seg = _segments(o.numel(), offsets, max_len)
+    a = _out_like(o.numel(), o.device, out)
+    ws, _ = _workspace(_lib.OP_OFFSPRING_TO_ANCESTORS, seg, 0, o.device, workspace)
+    rc = _lib.load().offspring_to_ancestors(_ptr(o), ctypes.byref(seg), _ptr(a), _ptr(ws),
+                                            0 if ws is None else ws.numel(), _ptr(flags),
+                                            _stream())
+    _lib.check(rc, "offspring_to_ancestors")
+    return a
+
+
+def permute_ancestors(a, sorted_hint=False, offsets=None, max_len=None, out=None, flags=None,
+                      workspace=None):
+    """Permutation of an ancestry for in-place propagation (Code 10)."""
+    torch = _torch()
+    _require_cuda(a, flags)
+    if a.dtype != torch.int32:
+        raise TypeError("ancestors must be int32")
+    seg = _segments(a.numel(), offsets, max_len)
+    c = _out_like(a.numel(), a.device, out)
+    ws, _ = _workspace(_lib.OP_PERMUTE, seg, 0, a.device, workspace)
+    rc = _lib.load().permute_ancestors(_ptr(a), ctypes.byref(seg), 1 if sorted_hint else 0,
+                                       _ptr(c), _ptr(ws), 0 if ws is None else ws.numel(),
+                                       _ptr(flags), _stream())
+    _lib.check(rc, "permute_ancestors")
+    return c

@@ -1,0 +1,88 @@
+"""ctypes binding of libpfresample.so (argument marshalling only).
+
+Every entry point mirrors a C function of include/pfresample.h; tensors are
+torch device tensors, passed as raw device pointers together with the current
+HIP stream.  All arithmetic runs in the library's HIP kernels: if the shared
+library is missing the import fails loudly.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libpfresample.so")
+
+PFR_OK, PFR_EINVAL, PFR_EWORKSPACE, PFR_ELAUNCH, PFR_ENOTSUP = range(5)
+PFR_F32, PFR_F64 = 0, 1
+SCAN_EXACT, SCAN_F64, SCAN_COMP_F32, SCAN_NAIVE_F32 = 0, 1, 2, 3
+(OP_MULTINOMIAL, OP_STRATIFIED, OP_SYSTEMATIC, OP_METROPOLIS, OP_REJECTION,
+ OP_OFFSPRING_TO_ANCESTORS, OP_PERMUTE) = range(7)
+
+FLAG_ZERO_TOTAL = 1
+FLAG_TRIAL_CAP = 2
+FLAG_BAD_COUNTS = 4
+FLAG_BAD_WEIGHTS = 8
+FLAG_BAD_ANCESTOR = 16
+MAX_BATCH_SEGMENT = 256 * 1024 - 1
+
+EXPORTS = (
+    "pfr_workspace_bytes", "pfr_workspace_init", "resample_multinomial", "resample_stratified",
+    "resample_systematic", "resample_metropolis", "resample_rejection", "offspring_to_ancestors",
+    "permute_ancestors", "pfr_status_string", "pfr_version",
+)
+
+
+class Segments(ctypes.Structure):
+    _fields_ = [("n_total", ctypes.c_int64), ("n_filters", ctypes.c_int32),
+                ("offsets", ctypes.c_void_p), ("max_len", ctypes.c_int64)]
+
+
+class Rng(ctypes.Structure):
+    _fields_ = [("seed", ctypes.c_uint64), ("offset", ctypes.c_uint32),
+                ("filter_base", ctypes.c_uint32)]
+
+
+class PfrError(RuntimeError):
+    pass
+
+
+_lib = None
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """Load the shared library and declare every signature."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise ImportError(f"{path} is not built; run `python -m paper_1301_4019_amd.build`")
+    lib = ctypes.CDLL(path)
+    P, I, U32, I32, D, SZ = (ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_int32,
+                             ctypes.c_double, ctypes.c_size_t)
+    SEG = ctypes.POINTER(Segments)
+    sigs = {
+        "pfr_workspace_bytes": (SZ, [I, SEG, I]),
+        "pfr_workspace_init": (I, [P, SZ, P]),
+        "resample_multinomial": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),
+        "resample_stratified": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),
+        "resample_systematic": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),
+        "resample_metropolis": (I, [P, I, SEG, I32, P, Rng, P, P]),
+        "resample_rejection": (I, [P, I, SEG, D, P, U32, Rng, P, P, SZ, P, P]),
+        "offspring_to_ancestors": (I, [P, SEG, P, P, SZ, P, P]),
+        "permute_ancestors": (I, [P, SEG, I32, P, P, SZ, P, P]),
+        "pfr_status_string": (ctypes.c_char_p, [I]),
+        "pfr_version": (ctypes.c_char_p, []),
+    }
+    for name, (res, args) in sigs.items():
+        fn = getattr(lib, name)
+        fn.restype = res
+        fn.argtypes = args
+    _lib = lib
+    return lib
+
+
+def check(rc: int, what: str) -> None:
+    if rc != PFR_OK:
+        msg = load().pfr_status_string(rc).decode()
+        raise PfrError(f"{what}: {msg} (status {rc})")

@@ -1,0 +1,237 @@
+// pfr_api.hip -- the C ABI of libpfresample (declared in include/pfresample.h):
+// argument checks, workspace sizing and kernel launches.  Nothing here
+// allocates, frees or synchronises.
+#include "pfresample.h"
+#include "pfr_kernels.h"
+
+namespace {
+
+using namespace pfr;
+
+constexpr int64_t kMaxN = (int64_t)1 << 31;
+constexpr int64_t kSingleWGMax = 16384;  // single vectors up to this run in one workgroup
+
+struct SegInfo {
+  int64_t n_total;
+  uint32_t n_filters;
+  const int64_t* offsets;  // NULL for one segment
+  int64_t max_len;
+};
+
+// Validates the segment description; returns PFR_OK and fills info.
+int check_segments(const pfr_segments* seg, SegInfo* info) {
+  if (!seg) return PFR_EINVAL;
+  if (seg->n_total < 0 || seg->n_total >= kMaxN) return PFR_EINVAL;
+  if (seg->n_filters < 1) return PFR_EINVAL;
+  if (seg->n_filters > 1 && !seg->offsets) return PFR_EINVAL;
+  info->n_total = seg->n_total;
+  info->n_filters = (uint32_t)seg->n_filters;
+  info->offsets = seg->n_filters > 1 ? seg->offsets : seg->offsets;
+  info->max_len = seg->max_len;
+  if (seg->n_filters == 1) {
+    info->offsets = nullptr;  // one segment covers [0, n_total)
+    info->max_len = seg->n_total;
+  }
+  return PFR_OK;
+}
+
+Key make_key(uint64_t seed) {
+  Key k;
+  k.k0 = (uint32_t)seed;
+  k.k1 = (uint32_t)(seed >> 32);
+  return k;
+}
+
+bool aligned256(const void* p) { return (reinterpret_cast<uintptr_t>(p) & 255u) == 0; }
+
+bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
+  const uintptr_t a0 = (uintptr_t)a, b0 = (uintptr_t)b;
+  return a0 < b0 + bbytes && b0 < a0 + abytes;
+}
+
+int launch_result(hipError_t e) { return e == hipSuccess ? PFR_OK : PFR_ELAUNCH; }
+
+size_t dtype_size(pfr_dtype dt) { return dt == PFR_F64 ? 8 : 4; }
+
+bool uses_scan_workspace(const SegInfo& s) {
+  return s.n_filters == 1 && s.n_total > kSingleWGMax;
+}
+
+int collective(int scheme, const void* w, pfr_dtype dtype, const pfr_segments* seg,
+               pfr_precision precision, pfr_rng rng, int32_t* a, void* ws, size_t ws_bytes,
+               uint32_t* dev_flags, void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (dtype != PFR_F32 && dtype != PFR_F64) return PFR_EINVAL;
+  if (precision != PFR_SCAN_EXACT) return PFR_ENOTSUP;
+  if (s.n_total == 0) return PFR_OK;
+  if (!w || !a) return PFR_EINVAL;
+  if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), a, (size_t)s.n_total * 4))
+    return PFR_EINVAL;
+  const hipStream_t st = (hipStream_t)stream;
+  const Key key = make_key(rng.seed);
+  if (!uses_scan_workspace(s)) {
+    if (s.n_filters > 1 && s.max_len > PFR_MAX_BATCH_SEGMENT) return PFR_ENOTSUP;
+    return launch_result(launch_scan_batched(scheme, dtype == PFR_F64, w, s.n_total, s.offsets,
+                                             s.n_filters, key, rng.offset, rng.filter_base, a,
+                                             dev_flags, st));
+  }
+  const ScanLayout L = scan_layout(s.n_total, scheme == SCHEME_MULTINOMIAL);
+  if (!ws || ws_bytes < L.total) return PFR_EWORKSPACE;
+  if (!aligned256(ws)) return PFR_EWORKSPACE;
+  return launch_result(launch_scan(scheme, dtype == PFR_F64, w, s.n_total, key, rng.offset,
+                                   rng.filter_base, a, ws, dev_flags, st));
+}
+
+constexpr size_t kRejectionWs = 256;
+
+int rejection_grid(int64_t n_total) {
+  // enough resident waves to fill the chip, never more than the work needs
+  int64_t blocks = (n_total + 1023) / 1024;  // 4 waves x 256 particles per block to start
+  if (blocks > 2048) blocks = 2048;
+  if (blocks < 1) blocks = 1;
+  return (int)blocks;
+}
+
+}  // namespace
+
+extern "C" {
+
+size_t pfr_workspace_bytes(pfr_op op, const pfr_segments* seg, pfr_dtype dtype) {
+  (void)dtype;
+  SegInfo s;
+  if (check_segments(seg, &s)) return 0;
+  switch (op) {
+    case PFR_OP_MULTINOMIAL:
+    case PFR_OP_STRATIFIED:
+    case PFR_OP_SYSTEMATIC:
+      if (!uses_scan_workspace(s)) return 0;
+      return scan_layout(s.n_total, op == PFR_OP_MULTINOMIAL).total;
+    case PFR_OP_METROPOLIS:
+      return 0;
+    case PFR_OP_REJECTION:
+      return kRejectionWs;
+    case PFR_OP_OFFSPRING_TO_ANCESTORS:
+      return o2a_workspace_bytes(s.n_total);
+    case PFR_OP_PERMUTE:
+      return permute_workspace_bytes(s.n_total);
+  }
+  return 0;
+}
+
+int pfr_workspace_init(void* ws, size_t ws_bytes, void* stream) {
+  if (ws_bytes == 0) return PFR_OK;
+  if (!ws || !aligned256(ws)) return PFR_EWORKSPACE;
+  return launch_result(launch_zero_u32((uint32_t*)ws, ws_bytes / 4, (hipStream_t)stream));
+}
+
+int resample_multinomial(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                         pfr_precision precision, pfr_rng rng, int32_t* ancestors, void* ws,
+                         size_t ws_bytes, uint32_t* dev_flags, void* stream) {
+  return collective(SCHEME_MULTINOMIAL, w, dtype, seg, precision, rng, ancestors, ws, ws_bytes,
+                    dev_flags, stream);
+}
+
+int resample_stratified(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                        pfr_precision precision, pfr_rng rng, int32_t* ancestors, void* ws,
+                        size_t ws_bytes, uint32_t* dev_flags, void* stream) {
+  return collective(SCHEME_STRATIFIED, w, dtype, seg, precision, rng, ancestors, ws, ws_bytes,
+                    dev_flags, stream);
+}
+
+int resample_systematic(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                        pfr_precision precision, pfr_rng rng, int32_t* ancestors, void* ws,
+                        size_t ws_bytes, uint32_t* dev_flags, void* stream) {
+  return collective(SCHEME_SYSTEMATIC, w, dtype, seg, precision, rng, ancestors, ws, ws_bytes,
+                    dev_flags, stream);
+}
+
+int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segments* seg, int32_t B,
+                        const int32_t* B_dev, pfr_rng rng, int32_t* ancestors, void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (dtype != PFR_F32 && dtype != PFR_F64) return PFR_EINVAL;
+  if (B < 0 || B >= (1 << 28)) return PFR_EINVAL;
+  if (s.n_total == 0) return PFR_OK;
+  if (!w || !ancestors) return PFR_EINVAL;
+  if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), ancestors, (size_t)s.n_total * 4))
+    return PFR_EINVAL;
+  return launch_result(launch_metropolis(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters, B,
+                                         B_dev, make_key(rng.seed), rng.offset, rng.filter_base,
+                                         ancestors, (hipStream_t)stream));
+}
+
+int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, double w_max,
+                       const double* w_max_dev, uint32_t max_trials, pfr_rng rng,
+                       int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                       void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (dtype != PFR_F32 && dtype != PFR_F64) return PFR_EINVAL;
+  if (max_trials < 1 || max_trials >= (1u << 28)) return PFR_EINVAL;
+  if (!w_max_dev && !(w_max > 0.0 && w_max < __builtin_huge_val())) return PFR_EINVAL;
+  if (s.n_total == 0) return PFR_OK;
+  if (!w || !ancestors) return PFR_EINVAL;
+  if (!ws || ws_bytes < kRejectionWs || !aligned256(ws)) return PFR_EWORKSPACE;
+  if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), ancestors, (size_t)s.n_total * 4))
+    return PFR_EINVAL;
+  return launch_result(launch_rejection(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters,
+                                        w_max, w_max_dev, max_trials, make_key(rng.seed),
+                                        rng.offset, rng.filter_base, ancestors, (uint32_t*)ws,
+                                        dev_flags, rejection_grid(s.n_total),
+                                        (hipStream_t)stream));
+}
+
+int offspring_to_ancestors(const int32_t* offspring, const pfr_segments* seg, int32_t* ancestors,
+                           void* ws, size_t ws_bytes, uint32_t* dev_flags, void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (s.n_total == 0) return PFR_OK;
+  if (!offspring || !ancestors) return PFR_EINVAL;
+  if (overlaps(offspring, (size_t)s.n_total * 4, ancestors, (size_t)s.n_total * 4))
+    return PFR_EINVAL;
+  const size_t need = o2a_workspace_bytes(s.n_total);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return PFR_EWORKSPACE;
+  return launch_result(launch_offspring_to_ancestors(offspring, s.n_total, s.offsets, s.n_filters,
+                                                     ancestors, ws, dev_flags,
+                                                     (hipStream_t)stream));
+}
+
+int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t sorted_hint,
+                      int32_t* permuted, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                      void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (s.n_total == 0) return PFR_OK;
+  if (!ancestors || !permuted) return PFR_EINVAL;
+  if (overlaps(ancestors, (size_t)s.n_total * 4, permuted, (size_t)s.n_total * 4))
+    return PFR_EINVAL;
+  const size_t need = permute_workspace_bytes(s.n_total);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return PFR_EWORKSPACE;
+  if (overlaps(ws, need, permuted, (size_t)s.n_total * 4) ||
+      overlaps(ws, need, ancestors, (size_t)s.n_total * 4))
+    return PFR_EINVAL;
+  return launch_result(launch_permute(ancestors, s.n_total, s.offsets, s.n_filters,
+                                      sorted_hint != 0, permuted, ws, dev_flags,
+                                      (hipStream_t)stream));
+}
+
+const char* pfr_status_string(int status) {
+  switch (status) {
+    case PFR_OK: return "ok";
+    case PFR_EINVAL: return "invalid argument";
+    case PFR_EWORKSPACE: return "workspace missing, too small or misaligned";
+    case PFR_ELAUNCH: return "kernel launch failed";
+    case PFR_ENOTSUP: return "not supported";
+  }
+  return "unknown status";
+}
+
+const char* pfr_version(void) { return "0.1.0"; }
+
+}  // extern "C"

@@ -1,0 +1,493 @@
+// pfr_aux.hip -- auxiliaries of the resampling step:
+//   offspring_to_ancestors  (Code 11 of the paper after an exclusive scan of
+//                            the offspring counts)
+//   permute_ancestors       (Code 10: Prepermute, chain walk, gather)
+#include "pfr_kernels.h"
+
+namespace pfr {
+
+namespace {
+
+size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
+
+// ================================================================ o2a
+// Single pass with a decoupled look-back (Merrill & Garland, 2016) over tiles
+// of 4096 counts.  Counts are exact integers, so the carry a tile obtains does
+// not depend on how far it had to look back.  Tile ids come from a ticket so
+// that every tile's predecessors are already running.
+//
+// Status word of a tile (64 bits):  [63:35] epoch  [34:33] kind  [32:0] value
+// kind 1 = aggregate of the tile, 2 = inclusive prefix; a word whose epoch is
+// not the current call's is treated as not yet written.  The epoch advances
+// when the last tile of a call finishes, so the status array never needs to
+// be cleared between calls (a zeroed workspace is a valid initial state).
+constexpr int kO2aTile = 4096;
+constexpr uint64_t kKindAgg = 1, kKindInc = 2;
+constexpr uint64_t kValMask = (1ull << 33) - 1;
+
+struct O2aHeader {
+  uint32_t epoch;
+  uint32_t tile_ticket;
+  uint32_t done;
+  uint32_t pad[61];
+};
+
+__device__ __forceinline__ uint64_t pack_status(uint32_t epoch, uint64_t kind, uint64_t value) {
+  return ((uint64_t)(epoch & 0x1FFFFFFFu) << 35) | (kind << 33) | (value & kValMask);
+}
+__device__ __forceinline__ uint64_t status_load(const uint64_t* p) {
+  return __hip_atomic_load(p, __ATOMIC_ACQUIRE, __HIP_MEMORY_SCOPE_AGENT);
+}
+__device__ __forceinline__ void status_store(uint64_t* p, uint64_t v) {
+  __hip_atomic_store(p, v, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_AGENT);
+}
+
+// Offspring values of a tile in (g, lane, v) order per wave; negative counts
+// count as 0 and counts above n as n + 1 (both raise FLAG_BAD_COUNTS), so sums
+// stay far below 2^33 per tile.
+__device__ __forceinline__ void load_counts(const int32_t* __restrict__ o, int64_t n, int64_t base,
+                                            uint64_t (&q)[16], uint32_t& bad) {
+  const int lane = (int)lane_id();
+  const bool aligned = ((reinterpret_cast<uintptr_t>(o + base) & 15u) == 0);
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+    const int64_t idx = base + (int64_t)g * 256 + lane * 4;
+    int32_t v4[4];
+    if (aligned && idx + 4 <= n) {
+      const int4 t = *reinterpret_cast<const int4*>(o + idx);
+      v4[0] = t.x; v4[1] = t.y; v4[2] = t.z; v4[3] = t.w;
+    } else {
+#pragma unroll
+      for (int v = 0; v < 4; ++v) v4[v] = (idx + v < n) ? o[idx + v] : 0;
+    }
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      int64_t x = v4[v];
+      if (x < 0) { bad = FLAG_BAD_COUNTS; x = 0; }
+      if (x > n) { bad = FLAG_BAD_COUNTS; x = n + 1; }
+      q[g * 4 + v] = (uint64_t)x;
+    }
+  }
+}
+
+template <int G, int V>
+__device__ __forceinline__ uint64_t inclusive_scan16(uint64_t (&q)[16]) {
+  uint64_t run = 0;
+#pragma unroll
+  for (int g = 0; g < G; ++g) {
+    uint64_t s = 0;
+#pragma unroll
+    for (int v = 0; v < V; ++v) {
+      s += q[g * V + v];
+      q[g * V + v] = s;
+    }
+    const uint64_t incl = wave_inclusive_scan(s, OpAdd());
+    const uint64_t add = run + (incl - s);
+#pragma unroll
+    for (int v = 0; v < V; ++v) q[g * V + v] += add;
+    run += readlane(incl, kWave - 1);
+  }
+  return run;
+}
+
+// Expansion of one tile: positions s in [lo, hi) get P0 + #{i : O_i <= s},
+// where O (inclusive cumulative counts, saturated at n + 1) sits in LDS.
+__device__ __forceinline__ void expand_tile(const uint32_t* __restrict__ O_lds, int cnt,
+                                            int64_t lo, int64_t hi, int64_t P0,
+                                            int32_t* __restrict__ a, int tid, int nthreads) {
+  for (int64_t s = lo + tid; s < hi; s += nthreads) {
+    int l = 0, h = cnt;
+    while (l < h) {
+      const int m = (l + h) >> 1;
+      if ((int64_t)O_lds[m] <= s) l = m + 1;
+      else h = m;
+    }
+    a[s] = (int32_t)(P0 + l);
+  }
+}
+
+// Builds the tile's cumulative counts in LDS (4 waves x 1024) given its carry
+// and returns through the arguments the tile total.
+__device__ __forceinline__ void tile_counts_to_lds(uint64_t (&q)[16], uint64_t carry, int64_t n,
+                                                   uint32_t* __restrict__ O_lds, int wave,
+                                                   const uint64_t* wave_prefix) {
+  const int lane = (int)lane_id();
+#pragma unroll
+  for (int g = 0; g < 4; ++g) {
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      uint64_t O = carry + wave_prefix[wave] + q[g * 4 + v];
+      if (O > (uint64_t)n + 1) O = (uint64_t)n + 1;
+      O_lds[wave * 1024 + g * 256 + lane * 4 + v] = (uint32_t)O;
+    }
+  }
+}
+
+__global__ __launch_bounds__(256) void k_o2a(const int32_t* __restrict__ o, int64_t n,
+                                             int32_t* __restrict__ a, O2aHeader* __restrict__ hdr,
+                                             uint64_t* __restrict__ status,
+                                             uint32_t* __restrict__ flags, uint32_t ntiles) {
+  __shared__ uint32_t O_lds[kO2aTile];
+  __shared__ uint64_t wave_tot[4], wave_prefix[4];
+  __shared__ uint32_t s_tile, s_epoch, s_bad;
+  __shared__ uint64_t s_carry;
+  const int tid = (int)threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  if (tid == 0) {
+    s_tile = atomicAdd(&hdr->tile_ticket, 1u);
+    s_epoch = __hip_atomic_load(&hdr->epoch, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT);
+    s_bad = 0;
+  }
+  __syncthreads();
+  const uint32_t t = s_tile, epoch = s_epoch;
+  const int64_t P0 = (int64_t)t * kO2aTile;
+  uint64_t q[16];
+  uint32_t bad = 0;
+  load_counts(o, n, P0 + wave * 1024, q, bad);
+  const uint64_t wsum = inclusive_scan16<4, 4>(q);
+  if (lane == 0) wave_tot[wave] = wsum;
+  bad = wave_reduce(bad, OpOr());
+  if (lane == 0 && bad) atomicOr(&s_bad, bad);
+  __syncthreads();
+  if (tid == 0) {
+    uint64_t run = 0;
+    for (int w2 = 0; w2 < 4; ++w2) {
+      wave_prefix[w2] = run;
+      run += wave_tot[w2];
+    }
+    const uint64_t agg = run > (uint64_t)n + 1 ? (uint64_t)n + 1 : run;
+    if (t == 0) {
+      s_carry = 0;
+      status_store(&status[0], pack_status(epoch, kKindInc, agg));
+    } else {
+      status_store(&status[t], pack_status(epoch, kKindAgg, agg));
+    }
+  }
+  __syncthreads();
+  // look-back by wave 0: lane l inspects tile t-1-l
+  if (t > 0 && wave == 0) {
+    uint64_t carry = 0;
+    int64_t pos = (int64_t)t - 1;  // highest tile not yet accounted for
+    while (true) {
+      const int64_t j = pos - lane;
+      uint64_t st = 0, kind = 0;
+      bool ready = true;
+      if (j >= 0) {
+        st = status_load(&status[j]);
+        kind = ((uint32_t)(st >> 35) == (epoch & 0x1FFFFFFFu)) ? ((st >> 33) & 3u) : 0u;
+        ready = kind != 0;
+      }
+      // lanes up to (and including) the nearest inclusive tile must be ready
+      const uint64_t inc_mask = ballot(j >= 0 && kind == kKindInc);
+      const uint64_t end_mask = inc_mask | ballot(j < 0);
+      const int stop = end_mask ? (__ffsll((long long)end_mask) - 1) : kWave;  // first lane that ends the walk
+      const uint64_t need = (stop >= kWave - 1) ? ~0ull : ((2ull << stop) - 1);
+      if ((ballot(!ready) & need) != 0) {
+        __builtin_amdgcn_s_sleep(1);
+        continue;
+      }
+      const uint64_t val = (j >= 0 && lane <= stop) ? (st & kValMask) : 0;
+      carry += wave_reduce(val, OpAdd());
+      if (stop < kWave) break;
+      pos -= kWave;
+    }
+    if (carry > (uint64_t)n + 1) carry = (uint64_t)n + 1;
+    if (lane == 0) {
+      s_carry = carry;
+      uint64_t inc = carry + wave_prefix[3] + wave_tot[3];
+      if (inc > (uint64_t)n + 1) inc = (uint64_t)n + 1;
+      status_store(&status[t], pack_status(epoch, kKindInc, inc));
+    }
+  }
+  __syncthreads();
+  const uint64_t carry = s_carry;
+  tile_counts_to_lds(q, carry, n, O_lds, wave, wave_prefix);
+  __syncthreads();
+  uint64_t total = carry + wave_prefix[3] + wave_tot[3];
+  if (total > (uint64_t)n + 1) total = (uint64_t)n + 1;
+  const int cnt = (int)min((int64_t)kO2aTile, n - P0);
+  const int64_t lo = min((int64_t)carry, n), hi = min((int64_t)total, n);
+  expand_tile(O_lds, cnt, lo, hi, P0, a, tid, 256);
+  uint32_t fl = s_bad;
+  if (t == ntiles - 1) {
+    // positions beyond the last offspring keep the identity
+    for (int64_t s = hi + tid; s < n; s += 256) a[s] = (int32_t)s;
+    if (total != (uint64_t)n) fl |= FLAG_BAD_COUNTS;
+  }
+  if (tid == 0) {
+    if (fl && flags) atomicOr(flags, fl);
+    __threadfence();
+    const uint32_t prev = atomicAdd(&hdr->done, 1u);
+    if (prev == ntiles - 1) {  // last tile out: next call gets a new epoch
+      hdr->tile_ticket = 0;
+      hdr->done = 0;
+      __hip_atomic_store(&hdr->epoch, (epoch + 1) & 0x1FFFFFFFu, __ATOMIC_RELAXED,
+                         __HIP_MEMORY_SCOPE_AGENT);
+      __threadfence();
+    }
+  }
+}
+
+// Ragged batch: one workgroup per segment walks its tiles in order and keeps
+// the carry in a register.
+__global__ __launch_bounds__(256) void k_o2a_batched(const int32_t* __restrict__ o,
+                                                     int64_t n_total,
+                                                     const int64_t* __restrict__ offsets,
+                                                     uint32_t n_filters, int32_t* __restrict__ a,
+                                                     uint32_t* __restrict__ flags) {
+  __shared__ uint32_t O_lds[kO2aTile];
+  __shared__ uint64_t wave_tot[4], wave_prefix[4];
+  __shared__ uint32_t s_bad;
+  const uint32_t f = blockIdx.x;
+  if (f >= n_filters) return;
+  const int tid = (int)threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int64_t base = offsets ? offsets[f] : 0;
+  const int64_t n = offsets ? offsets[f + 1] - base : n_total;
+  const int32_t* __restrict__ os = o + base;
+  int32_t* __restrict__ as = a + base;
+  if (tid == 0) s_bad = 0;
+  uint64_t carry = 0;
+  for (int64_t P0 = 0; P0 < n; P0 += kO2aTile) {
+    uint64_t q[16];
+    uint32_t bad = 0;
+    load_counts(os, n, P0 + wave * 1024, q, bad);
+    const uint64_t wsum = inclusive_scan16<4, 4>(q);
+    if (lane == 0) wave_tot[wave] = wsum;
+    bad = wave_reduce(bad, OpOr());
+    __syncthreads();
+    if (lane == 0 && bad) atomicOr(&s_bad, bad);
+    if (tid == 0) {
+      uint64_t run = 0;
+      for (int w2 = 0; w2 < 4; ++w2) {
+        wave_prefix[w2] = run;
+        run += wave_tot[w2];
+      }
+    }
+    __syncthreads();
+    tile_counts_to_lds(q, carry, n, O_lds, wave, wave_prefix);
+    __syncthreads();
+    uint64_t total = carry + wave_prefix[3] + wave_tot[3];
+    if (total > (uint64_t)n + 1) total = (uint64_t)n + 1;
+    const int cnt = (int)min((int64_t)kO2aTile, n - P0);
+    expand_tile(O_lds, cnt, min((int64_t)carry, n), min((int64_t)total, n), P0, as, tid, 256);
+    carry = total;
+    __syncthreads();
+  }
+  const int64_t hi = min((int64_t)carry, n);
+  for (int64_t s = hi + tid; s < n; s += 256) as[s] = (int32_t)s;
+  __syncthreads();
+  if (tid == 0 && flags) {
+    uint32_t fl = s_bad;
+    if (carry != (uint64_t)n) fl |= FLAG_BAD_COUNTS;
+    if (fl) atomicOr(flags, fl);
+  }
+}
+
+// ================================================================ permute
+// Code 10.  d[j] holds the particle index that claims slot j, or n (unclaimed).
+// Prepermute keeps the lowest claimer of every slot.  For a sorted ancestry
+// (the output of the collective resamplers) the lowest claimer of slot a_i is
+// the first i of its run, so the claim vector is written with plain stores:
+// position i writes slot a_i when it starts a run, and n into every slot
+// strictly between a_{i-1} and a_i, which no position claims.  For an unsorted
+// ancestry the lowest claimer is found with an atomic minimum on d.  After a
+// kernel boundary, every position whose claim failed walks x <- d[x] from x = i
+// to an unclaimed slot and claims it; the walks are disjoint paths (the
+// paper's termination argument), so they read and write disjoint slots.  A
+// final kernel gathers c_i = a_{d_i}.
+struct SegIdx {
+  int64_t base, n, i;
+};
+
+__device__ __forceinline__ SegIdx seg_index(const int64_t* __restrict__ offsets, uint32_t n_filters,
+                                            int64_t n_total, int64_t g) {
+  SegIdx s;
+  if (!offsets) {
+    s.base = 0;
+    s.n = n_total;
+  } else {
+    const uint32_t f = find_segment(offsets, n_filters, g);
+    s.base = offsets[f];
+    s.n = offsets[f + 1] - s.base;
+  }
+  s.i = g - s.base;
+  return s;
+}
+
+// ancestor of local position i, with out-of-range values replaced by i
+__device__ __forceinline__ int64_t anc_at(const int32_t* __restrict__ a, const SegIdx& s, int64_t i,
+                                          bool& bad) {
+  const int64_t v = a[s.base + i];
+  if (v < 0 || v >= s.n) {
+    bad = true;
+    return i;
+  }
+  return v;
+}
+
+__global__ __launch_bounds__(256) void k_claim_sorted(const int32_t* __restrict__ a,
+                                                      int64_t n_total,
+                                                      const int64_t* __restrict__ offsets,
+                                                      uint32_t n_filters, int32_t* __restrict__ d,
+                                                      uint32_t* __restrict__ flags) {
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
+    const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    const int64_t ai = anc_at(a, s, s.i, bad);
+    const int64_t prev = (s.i == 0) ? -1 : anc_at(a, s, s.i - 1, bad);
+    int32_t* ds = d + s.base;
+    if (ai > prev) {
+      ds[ai] = (int32_t)s.i;  // first of its run
+      for (int64_t j = prev + 1; j < ai; ++j) ds[j] = (int32_t)s.n;
+    }
+    if (s.i == s.n - 1) {
+      const int64_t top = ai > prev ? ai : prev;
+      for (int64_t j = top + 1; j < s.n; ++j) ds[j] = (int32_t)s.n;
+    }
+  }
+  if (flags) {
+    const uint32_t b = (uint32_t)wave_reduce((uint32_t)bad, OpOr());
+    if (b && lane_id() == 0) atomicOr(flags, FLAG_BAD_ANCESTOR);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_fill_unclaimed(int32_t* __restrict__ d, int64_t n_total,
+                                                        const int64_t* __restrict__ offsets,
+                                                        uint32_t n_filters) {
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
+    const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    d[g] = (int32_t)s.n;
+  }
+}
+
+__global__ __launch_bounds__(256) void k_claim_min(const int32_t* __restrict__ a, int64_t n_total,
+                                                   const int64_t* __restrict__ offsets,
+                                                   uint32_t n_filters, int32_t* __restrict__ d,
+                                                   uint32_t* __restrict__ flags) {
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
+    const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    const int64_t ai = anc_at(a, s, s.i, bad);
+    atomicMin(&d[s.base + ai], (int32_t)s.i);
+  }
+  if (flags) {
+    const uint32_t b = (uint32_t)wave_reduce((uint32_t)bad, OpOr());
+    if (b && lane_id() == 0) atomicOr(flags, FLAG_BAD_ANCESTOR);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ a, int64_t n_total,
+                                              const int64_t* __restrict__ offsets,
+                                              uint32_t n_filters, int32_t* __restrict__ d,
+                                              uint32_t* __restrict__ flags) {
+  bool bad = false, broken = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
+    const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    int32_t* ds = d + s.base;
+    const int64_t ai = anc_at(a, s, s.i, bad);
+    if (ds[ai] == s.i) continue;  // claim succeeded
+    int64_t x = s.i;
+    int64_t steps = 0;
+    // a chain visits distinct slots, so it ends within n steps
+    while (true) {
+      const int64_t nx = ds[x];
+      if (nx >= s.n || nx < 0) break;
+      x = nx;
+      if (++steps > s.n) {
+        broken = true;
+        break;
+      }
+    }
+    if (!broken) ds[x] = (int32_t)s.i;
+  }
+  if (flags) {
+    const uint32_t b = (uint32_t)wave_reduce((uint32_t)(broken ? FLAG_BAD_ANCESTOR : 0u), OpOr());
+    if (b && lane_id() == 0) atomicOr(flags, b);
+  }
+}
+
+__global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ a, int64_t n_total,
+                                                const int64_t* __restrict__ offsets,
+                                                uint32_t n_filters, const int32_t* __restrict__ d,
+                                                int32_t* __restrict__ c) {
+  bool bad = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
+    const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    const int64_t di = d[g];
+    c[g] = (di >= 0 && di < s.n) ? (int32_t)anc_at(a, s, di, bad) : (int32_t)s.i;
+  }
+}
+
+int grid_for(int64_t n) {
+  int64_t b = (n + 255) / 256;
+  if (b > 65536) b = 65536;
+  if (b < 1) b = 1;
+  return (int)b;
+}
+
+}  // namespace
+
+size_t o2a_workspace_bytes(int64_t n_total) {
+  const size_t tiles = (size_t)((n_total + kO2aTile - 1) / kO2aTile);
+  return 256 + align256(tiles * sizeof(uint64_t));
+}
+
+hipError_t launch_offspring_to_ancestors(const int32_t* o, int64_t n_total, const int64_t* offsets,
+                                         uint32_t n_filters, int32_t* a, void* ws,
+                                         uint32_t* flags, hipStream_t stream) {
+  if (offsets || n_filters > 1 || n_total <= kO2aTile) {
+    hipLaunchKernelGGL(k_o2a_batched, dim3(offsets ? n_filters : 1u), dim3(256), 0, stream, o,
+                       n_total, offsets, offsets ? n_filters : 1u, a, flags);
+    return hipGetLastError();
+  }
+  const uint32_t ntiles = (uint32_t)((n_total + kO2aTile - 1) / kO2aTile);
+  O2aHeader* hdr = (O2aHeader*)ws;
+  uint64_t* status = (uint64_t*)((char*)ws + 256);
+  hipLaunchKernelGGL(k_o2a, dim3(ntiles), dim3(256), 0, stream, o, n_total, a, hdr, status, flags,
+                     ntiles);
+  return hipGetLastError();
+}
+
+size_t permute_workspace_bytes(int64_t n_total) {
+  return align256((size_t)n_total * sizeof(int32_t));
+}
+
+hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offsets,
+                          uint32_t n_filters, bool sorted, int32_t* c, void* ws, uint32_t* flags,
+                          hipStream_t stream) {
+  int32_t* d = (int32_t*)ws;
+  const int grid = grid_for(n_total);
+  if (sorted) {
+    hipLaunchKernelGGL(k_claim_sorted, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
+                       n_filters, d, flags);
+  } else {
+    hipLaunchKernelGGL(k_fill_unclaimed, dim3(grid), dim3(256), 0, stream, d, n_total, offsets,
+                       n_filters);
+    hipLaunchKernelGGL(k_claim_min, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
+                       n_filters, d, flags);
+  }
+  hipLaunchKernelGGL(k_walk, dim3(grid), dim3(256), 0, stream, a, n_total, offsets, n_filters, d,
+                     flags);
+  hipLaunchKernelGGL(k_gather, dim3(grid), dim3(256), 0, stream, a, n_total, offsets, n_filters, d,
+                     c);
+  return hipGetLastError();
+}
+
+__global__ void k_zero_u32(uint32_t* __restrict__ p, size_t count) {
+  const size_t stride = (size_t)gridDim.x * blockDim.x;
+  for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0;
+}
+
+hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t stream) {
+  if (count == 0) return hipSuccess;
+  size_t blocks = (count + 255) / 256;
+  if (blocks > 4096) blocks = 4096;
+  hipLaunchKernelGGL(k_zero_u32, dim3((unsigned)blocks), dim3(256), 0, stream, p, count);
+  return hipGetLastError();
+}
+
+}  // namespace pfr

@@ -1,0 +1,246 @@
+// pfr_device.h -- device-side building blocks of libpfresample (gfx950).
+//
+// Philox4x32-10 counter-based random numbers, the canonical draws every kernel
+// takes from it, the exact accept test of the Metropolis and rejection
+// resamplers, wave64 primitives (shuffle, ballot, scans) and the 128-bit
+// integer helpers of the exact prefix sums.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+namespace pfr {
+
+constexpr int kWave = 64;
+
+// Philox counter word 1 is (domain << 28) | step.
+constexpr uint32_t DOM_STRATA = 0u;  // stratified / systematic offsets
+constexpr uint32_t DOM_EXP = 1u;     // exponential spacings (multinomial)
+constexpr uint32_t DOM_TRIAL = 2u;   // Metropolis steps, rejection trials
+constexpr uint32_t DOM_NOISE = 3u;   // state-space propagation noise
+constexpr uint32_t DOM_INIT = 4u;    // state-space initial state
+
+// Result bits OR-ed into the caller's device flag word.
+constexpr uint32_t FLAG_ZERO_TOTAL = 1u;
+constexpr uint32_t FLAG_TRIAL_CAP = 2u;
+constexpr uint32_t FLAG_BAD_COUNTS = 4u;
+constexpr uint32_t FLAG_BAD_WEIGHTS = 8u;
+constexpr uint32_t FLAG_BAD_ANCESTOR = 16u;
+
+struct Key {
+  uint32_t k0, k1;
+};
+
+// Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11).  Each round
+// forms the 64-bit products of counter words 0 and 2 with two odd multipliers
+// and mixes their high halves with words 1 and 3 and the round key; the key
+// advances by two Weyl increments per round.  The key is uniform across the
+// wave in every kernel, so its schedule stays in scalar registers.
+__device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
+                                        Key key) {
+  uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+  for (int r = 0; r < 10; ++r) {
+    // one v_mad_u64_u32 per product (instead of separate mul_hi / mul_lo)
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    c1 = (uint32_t)p1;
+    c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c3 = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
+}
+
+__device__ __forceinline__ uint4 draw(Key key, uint32_t index, uint32_t domain, uint32_t step,
+                                      uint32_t filter, uint32_t offset) {
+  return philox(index, (domain << 28) | (step & 0x0FFFFFFFu), filter, offset, key);
+}
+
+// u in (0, 1] on the 2^-32 lattice (accept tests).
+__device__ __forceinline__ double u_accept(uint32_t x) { return ((double)x + 1.0) * 0x1p-32; }
+// u in [0, 1) on the 2^-32 lattice (stratum offsets).
+__device__ __forceinline__ double u_offset(uint32_t x) { return (double)x * 0x1p-32; }
+// j uniform on [0, n): high 64 bits of the 64x64-bit product.
+__device__ __forceinline__ uint32_t index_draw(uint32_t x0, uint32_t x1, uint32_t n) {
+  const uint64_t r = ((uint64_t)x1 << 32) | x0;
+  return (uint32_t)__umul64hi(r, (uint64_t)n);
+}
+
+// Exact u * wk <= wj.  The product p = fl(u wk) and its rounding error e
+// (recovered exactly by one fused multiply-add) give u wk = p + e exactly;
+// since |e| is at most half an ulp of p, the comparison is decided by p unless
+// p == wj, in which case the sign of e decides.  Valid while u wk stays in the
+// normal range (always for float32 weights).
+__device__ __forceinline__ bool accept_exact(double u, double wk, double wj) {
+  const double p = u * wk;
+  const double e = __fma_rn(u, wk, -p);
+  return (p < wj) || (p == wj && e <= 0.0);
+}
+
+// ------------------------------------------------------------------ wave64
+__device__ __forceinline__ uint32_t lane_id() {
+  return __builtin_amdgcn_mbcnt_hi(~0u, __builtin_amdgcn_mbcnt_lo(~0u, 0u));
+}
+__device__ __forceinline__ uint64_t ballot(bool p) { return __ballot(p); }
+__device__ __forceinline__ uint64_t lanemask_lt() {
+  const uint32_t l = lane_id();
+  return l == 0 ? 0ull : (~0ull >> (64 - l));
+}
+__device__ __forceinline__ uint32_t shfl_u32(uint32_t v, int src) {
+  return (uint32_t)__builtin_amdgcn_ds_bpermute(src << 2, (int)v);
+}
+__device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_readfirstlane((int)v);
+}
+__device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int lane) {
+  return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+template <typename T>
+__device__ __forceinline__ T shfl(T v, int src) {
+  static_assert(sizeof(T) % 4 == 0, "shfl needs 32-bit words");
+  union U {
+    T t;
+    uint32_t w[sizeof(T) / 4];
+  } a, b;
+  a.t = v;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) b.w[i] = shfl_u32(a.w[i], src);
+  return b.t;
+}
+template <typename T>
+__device__ __forceinline__ T readlane(T v, int lane) {
+  union U {
+    T t;
+    uint32_t w[sizeof(T) / 4];
+  } a, b;
+  a.t = v;
+#pragma unroll
+  for (int i = 0; i < (int)(sizeof(T) / 4); ++i) b.w[i] = readlane_u32(a.w[i], lane);
+  return b.t;
+}
+
+// Inclusive wave scan (Hillis-Steele over 64 lanes) with a binary operator.
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_inclusive_scan(T v, Op op) {
+  const int l = (int)lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) {
+    const T t = shfl(v, l >= d ? l - d : l);
+    if (l >= d) v = op(t, v);
+  }
+  return v;
+}
+template <typename T, typename Op>
+__device__ __forceinline__ T wave_reduce(T v, Op op) {
+  const int l = (int)lane_id();
+#pragma unroll
+  for (int d = 1; d < kWave; d <<= 1) v = op(v, shfl(v, l ^ d));
+  return v;
+}
+
+struct OpAdd {
+  template <typename T>
+  __device__ __forceinline__ T operator()(T a, T b) const { return a + b; }
+};
+struct OpMax {
+  template <typename T>
+  __device__ __forceinline__ T operator()(T a, T b) const { return a > b ? a : b; }
+};
+struct OpMin {
+  template <typename T>
+  __device__ __forceinline__ T operator()(T a, T b) const { return a < b ? a : b; }
+};
+struct OpOr {
+  template <typename T>
+  __device__ __forceinline__ T operator()(T a, T b) const { return a | b; }
+};
+
+// ------------------------------------------------------------------ u128
+typedef unsigned __int128 u128;
+
+// x * 2^sh for a signed shift; bits shifted out to the right are dropped
+// (floor), which is monotone in x.
+__device__ __forceinline__ u128 shift_u128(u128 x, int sh) {
+  if (sh >= 0) return sh >= 128 ? (u128)0 : (x << sh);
+  const int r = -sh;
+  return r >= 128 ? (u128)0 : (x >> r);
+}
+// u128 -> double for values below 2^116: the high word converts exactly, so
+// fl(hi * 2^64 + fl(lo)) is monotone in x and deterministic.
+__device__ __forceinline__ double u128_to_double(u128 x) {
+  const uint64_t hi = (uint64_t)(x >> 64), lo = (uint64_t)x;
+  return (double)hi * 0x1p64 + (double)lo;
+}
+
+// ------------------------------------------------------------------ segments
+// Segment f holds global indices [offsets[f], offsets[f+1]); returns the f
+// with offsets[f] <= g < offsets[f+1] (offsets non-decreasing, g < offsets[F]).
+__device__ __forceinline__ uint32_t find_segment(const int64_t* __restrict__ offsets,
+                                                 uint32_t n_filters, int64_t g) {
+  uint32_t lo = 0, hi = n_filters;  // answer in [lo, hi)
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (offsets[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+// ------------------------------------------------------------------ weights
+// Weight element traits: P = significand bits (with the implicit bit), bias.
+template <typename T>
+struct WTraits;
+template <>
+struct WTraits<float> {
+  typedef uint32_t Bits;
+  static constexpr int P = 24, BIAS = 127, EXP_BITS = 8;
+  __device__ static Bits bits(float v) { return __float_as_uint(v); }
+};
+template <>
+struct WTraits<double> {
+  typedef uint64_t Bits;
+  static constexpr int P = 53, BIAS = 1023, EXP_BITS = 11;
+  __device__ static Bits bits(double v) { return (Bits)__double_as_longlong(v); }
+};
+
+// A weight is usable when it is finite and >= 0 (-0 counts as 0).
+template <typename T>
+__device__ __forceinline__ bool weight_ok(T v) {
+  return v >= (T)0 && v < (T)__builtin_huge_val();
+}
+
+// Biased exponent field of a non-negative finite weight, at least 1 (zero and
+// subnormal weights share the exponent of the smallest normal).
+template <typename T>
+__device__ __forceinline__ int exp_field(T v) {
+  typedef WTraits<T> Tr;
+  const int e = (int)((Tr::bits(v) >> (Tr::P - 1)) & ((1u << Tr::EXP_BITS) - 1));
+  return e < 1 ? 1 : e;
+}
+
+// Fixed-point quantisation of a weight relative to a block's reference
+// exponent e_ref (the exponent field of the block maximum):
+//   q = floor(v * 2^s),  s = 52 + BIAS - e_ref,
+// so that q < 2^53 for every v in the block.  Computed from the bits: the
+// significand (with its implicit bit) shifted by (53 - P) + e - e_ref.
+template <typename T>
+__device__ __forceinline__ uint64_t quantize(T v, int e_ref) {
+  typedef WTraits<T> Tr;
+  const typename Tr::Bits b = Tr::bits(v);
+  const int ef = (int)((b >> (Tr::P - 1)) & ((1u << Tr::EXP_BITS) - 1));
+  const uint64_t frac = (uint64_t)(b & (((typename Tr::Bits)1 << (Tr::P - 1)) - 1));
+  const uint64_t m = ef ? (frac | ((uint64_t)1 << (Tr::P - 1))) : frac;
+  const int sh = (53 - Tr::P) + (ef < 1 ? 1 : ef) - e_ref;
+  if (sh >= 0) return m << sh;  // sh <= 53 - P
+  return sh <= -64 ? 0ull : (m >> (-sh));
+}
+template <typename T>
+__device__ __forceinline__ int scale_of(int e_ref) {
+  return 52 + WTraits<T>::BIAS - e_ref;
+}
+
+}  // namespace pfr

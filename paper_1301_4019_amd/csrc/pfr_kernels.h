@@ -1,0 +1,74 @@
+// pfr_kernels.h -- launchers shared between the kernel files and the C-ABI
+// layer of libpfresample.  Host-side declarations only; no torch types.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stddef.h>
+#include <stdint.h>
+
+#include "pfr_device.h"
+
+namespace pfr {
+
+// Collective schemes handled by the scan kernels.
+enum Scheme : int { SCHEME_MULTINOMIAL = 0, SCHEME_STRATIFIED = 1, SCHEME_SYSTEMATIC = 2 };
+
+// Canonical quantisation block of the exact prefix sums: 1024 weights, one
+// wave (64 lanes x 16 values).  A reduce workgroup covers kBlocksPerWG blocks.
+constexpr int kBlock = 1024;
+constexpr int kBlocksPerWG = 4;
+constexpr int kWGThreads = kWave * kBlocksPerWG;
+
+// Per-block record written by the reduce pass.
+struct BlockRec {
+  uint64_t sum;    // sum of the block's quantised values
+  int32_t scale;   // q = floor(w * 2^scale) inside the block
+  uint32_t bad;    // FLAG_BAD_WEIGHTS if a weight is negative or not finite
+};
+
+// Header at the start of a collective-scheme workspace.
+struct ScanHeader {
+  uint32_t ticket;   // reduce workgroups done (reset by the last one)
+  uint32_t status;   // FLAG_* bits of this call
+  int32_t gscale;    // global fixed-point scale of the carries
+  uint32_t nb;       // weight blocks
+  uint32_t nbe;      // exponential blocks (multinomial)
+  uint32_t pad[59];  // header padded to 256 bytes
+};
+
+struct ScanLayout {
+  size_t recs, carries, erecs, ecarries, total;
+};
+ScanLayout scan_layout(int64_t n, bool multinomial);
+size_t batch_scan_lds_bytes();
+
+hipError_t launch_scan(int scheme, bool f64, const void* w, int64_t n, Key key, uint32_t offset,
+                       uint32_t filter, int32_t* a, void* ws, uint32_t* flags,
+                       hipStream_t stream);
+hipError_t launch_scan_batched(int scheme, bool f64, const void* w, int64_t n_total,
+                               const int64_t* offsets, uint32_t n_filters, Key key,
+                               uint32_t offset, uint32_t filter_base, int32_t* a, uint32_t* flags,
+                               hipStream_t stream);
+
+hipError_t launch_metropolis(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
+                             uint32_t n_filters, int32_t B, const int32_t* B_dev, Key key,
+                             uint32_t offset, uint32_t filter_base, int32_t* a,
+                             hipStream_t stream);
+hipError_t launch_rejection(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
+                            uint32_t n_filters, double w_max, const double* w_max_dev,
+                            uint32_t max_trials, Key key, uint32_t offset, uint32_t filter_base,
+                            int32_t* a, uint32_t* counters, uint32_t* flags, int grid_blocks,
+                            hipStream_t stream);
+
+size_t o2a_workspace_bytes(int64_t n_total);
+hipError_t launch_offspring_to_ancestors(const int32_t* o, int64_t n_total, const int64_t* offsets,
+                                         uint32_t n_filters, int32_t* a, void* ws,
+                                         uint32_t* flags, hipStream_t stream);
+size_t permute_workspace_bytes(int64_t n_total);
+hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offsets,
+                          uint32_t n_filters, bool sorted, int32_t* c, void* ws, uint32_t* flags,
+                          hipStream_t stream);
+
+hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t stream);
+
+}  // namespace pfr

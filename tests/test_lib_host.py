@@ -1,0 +1,101 @@
+"""Host-side checks of libpfresample: it loads without a GPU, exports every
+entry point include/pfresample.h declares, and rejects invalid arguments
+before enqueuing any work (no compute calls here)."""
+import ctypes
+import os
+import re
+
+import pytest
+
+from paper_1301_4019_amd import _lib
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "pfresample.h")
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return re.findall(r"PFR_API\s+[\w\s\*]+?\b(\w+)\s*\(", src)
+
+
+def test_header_declares_the_entry_points():
+    names = set(declared_functions())
+    assert names == set(_lib.EXPORTS)
+
+
+def test_library_exports_every_declared_symbol():
+    lib = _lib.load()
+    for name in declared_functions():
+        assert hasattr(lib, name), name
+    assert lib.pfr_version().decode().count(".") == 2
+    assert lib.pfr_status_string(_lib.PFR_EINVAL).decode() == "invalid argument"
+
+
+def seg(n, nf=1, offsets=None, max_len=0):
+    return _lib.Segments(n, nf, offsets, max_len)
+
+
+def test_workspace_sizes():
+    lib = _lib.load()
+    s_small = seg(1024)
+    s_big = seg(1 << 20)
+    # small single vectors run in one workgroup without workspace
+    assert lib.pfr_workspace_bytes(_lib.OP_STRATIFIED, ctypes.byref(s_small), 0) == 0
+    big = lib.pfr_workspace_bytes(_lib.OP_STRATIFIED, ctypes.byref(s_big), 0)
+    multi = lib.pfr_workspace_bytes(_lib.OP_MULTINOMIAL, ctypes.byref(s_big), 0)
+    assert big > 0 and multi > big and big % 256 == 0
+    # one 16-byte record and one 16-byte carry per 1024-weight block
+    assert big >= 256 + 1024 * 32
+    assert lib.pfr_workspace_bytes(_lib.OP_METROPOLIS, ctypes.byref(s_big), 0) == 0
+    assert lib.pfr_workspace_bytes(_lib.OP_PERMUTE, ctypes.byref(s_big), 0) >= 4 << 20
+    assert lib.pfr_workspace_bytes(_lib.OP_OFFSPRING_TO_ANCESTORS, ctypes.byref(s_big), 0) >= 256 + 256 * 8
+    assert lib.pfr_workspace_bytes(_lib.OP_REJECTION, ctypes.byref(s_big), 0) >= 8
+
+
+def test_invalid_arguments_rejected_on_host():
+    lib = _lib.load()
+    rng = _lib.Rng(0, 0, 0)
+    fake = ctypes.c_void_p(0x10000)  # never dereferenced: every call below fails validation
+    # negative size
+    assert lib.resample_stratified(fake, 0, ctypes.byref(seg(-1)), 0, rng, fake, None, 0, None,
+                                   None) == _lib.PFR_EINVAL
+    # too large
+    assert lib.resample_systematic(fake, 0, ctypes.byref(seg(1 << 31)), 0, rng, fake, None, 0,
+                                   None, None) == _lib.PFR_EINVAL
+    # unknown dtype
+    assert lib.resample_multinomial(fake, 7, ctypes.byref(seg(10)), 0, rng, fake, None, 0, None,
+                                    None) == _lib.PFR_EINVAL
+    # null weights
+    assert lib.resample_stratified(None, 0, ctypes.byref(seg(10)), 0, rng, fake, None, 0, None,
+                                   None) == _lib.PFR_EINVAL
+    # output aliases input
+    assert lib.resample_stratified(fake, 0, ctypes.byref(seg(10)), 0, rng, fake, None, 0, None,
+                                   None) == _lib.PFR_EINVAL
+    # a large single vector needs a workspace
+    out = ctypes.c_void_p(0x10000 + (1 << 30))
+    assert lib.resample_stratified(fake, 0, ctypes.byref(seg(1 << 20)), 0, rng, out, None, 0,
+                                   None, None) == _lib.PFR_EWORKSPACE
+    # batched without offsets
+    assert lib.resample_stratified(fake, 0, ctypes.byref(seg(100, 4, None)), 0, rng, out, None,
+                                   0, None, None) == _lib.PFR_EINVAL
+    # Metropolis step count out of range
+    assert lib.resample_metropolis(fake, 0, ctypes.byref(seg(10)), -1, None, rng, out,
+                                   None) == _lib.PFR_EINVAL
+    # rejection: bad bound, zero trials, missing workspace
+    assert lib.resample_rejection(fake, 0, ctypes.byref(seg(10)), 0.0, None, 16, rng, out, fake,
+                                  256, None, None) == _lib.PFR_EINVAL
+    assert lib.resample_rejection(fake, 0, ctypes.byref(seg(10)), 1.0, None, 0, rng, out, fake,
+                                  256, None, None) == _lib.PFR_EINVAL
+    assert lib.resample_rejection(fake, 0, ctypes.byref(seg(10)), 1.0, None, 16, rng, out, None,
+                                  0, None, None) == _lib.PFR_EWORKSPACE
+    # permute: output aliases input; workspace missing
+    assert lib.permute_ancestors(fake, ctypes.byref(seg(10)), 1, fake, out, 1 << 20, None,
+                                 None) == _lib.PFR_EINVAL
+    assert lib.permute_ancestors(fake, ctypes.byref(seg(10)), 1, out, None, 0, None,
+                                 None) == _lib.PFR_EWORKSPACE
+    # empty input is a no-op
+    assert lib.resample_stratified(None, 0, ctypes.byref(seg(0)), 0, rng, None, None, 0, None,
+                                   None) == _lib.PFR_OK
+    # precision modes other than the exact one are not built yet
+    assert lib.resample_stratified(fake, 0, ctypes.byref(seg(10)), 3, rng, out, None, 0, None,
+                                   None) == _lib.PFR_ENOTSUP

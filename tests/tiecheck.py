@@ -1,0 +1,46 @@
+"""Parity rule for the collective resamplers.
+
+The oracle resolves every point against an r computed in binary128; the GPU
+rounds its r (and, for the multinomial scheme, its points) to binary64 after
+an exact fixed-point prefix sum.  The two may therefore disagree only where a
+point lies within the stated tolerance of a bin boundary.  A disagreement at
+output s is accepted only if every boundary r_j between the two answers lies
+within delta of the point; the number of such ties is reported and bounded.
+"""
+import numpy as np
+
+
+def gpu_r_error_bound(w, n):
+    """Bound on |r_gpu - r_exact| (in offspring units) for n weights w.
+
+    Each weight is quantised with absolute error below max(w) 2^-52 (it is
+    truncated at 2^-s of its block, s set by the block maximum), so a prefix of
+    i weights is off by at most i max(w) 2^-52, i.e. n^2 max(w) 2^-52 / W in r
+    units; the conversion to binary64 and the scaling add four roundings.
+    """
+    w = np.asarray(w, dtype=np.float64)
+    W = w.sum()
+    if n == 0 or W == 0:
+        return 0.0
+    return n * n * w.max() * 2.0**-52 / W + 6.0 * n * 2.0**-53
+
+
+def check_ties(a_gpu, a_or, r, points, delta, max_ties):
+    a_gpu = np.asarray(a_gpu)
+    a_or = np.asarray(a_or)
+    mism = np.nonzero(a_gpu != a_or)[0]
+    for s in mism:
+        lo, hi = sorted((int(a_gpu[s]), int(a_or[s])))
+        gap = np.abs(r[lo:hi] - points[s])
+        assert np.all(gap <= delta), (
+            f"output {s}: gpu {a_gpu[s]} oracle {a_or[s]} point {points[s]!r} "
+            f"max distance to boundaries {gap.max():.3e} > delta {delta:.3e}")
+    assert mism.size <= max_ties, f"{mism.size} ties exceed the bound {max_ties}"
+    return int(mism.size)
+
+
+def strata_points(u):
+    """q_s = s + 1 - u_s (binary64; exact enough for a distance test)."""
+    u = np.asarray(u, dtype=np.float64)
+    s = np.arange(u.size, dtype=np.float64)
+    return (s + 1.0) - u
