@@ -98,7 +98,7 @@ def main():
     perm = {(y, s): torch.empty(N, dtype=torch.int32, device=dev) for y in YS for s in SCHEMES}
     wsp = {op: pfr.new_workspace(max(256, pfr.workspace_bytes(op, N)), dev)
            for op in (_lib.OP_MULTINOMIAL, _lib.OP_STRATIFIED, _lib.OP_SYSTEMATIC,
-                      _lib.OP_REJECTION, _lib.OP_PERMUTE)}
+                      _lib.OP_PERMUTE)}
     flags = torch.zeros(1, dtype=torch.int32, device=dev)
     stream = torch.cuda.current_stream()
     dominant = (4.0, "metropolis")
@@ -110,8 +110,7 @@ def main():
         if s == "metropolis":
             pfr.resample_metropolis(w, Bs[yi], seed=1, out=a)
         elif s == "rejection":
-            pfr.resample_rejection(w, 1.0, seed=1, out=a, flags=flags,
-                                   workspace=wsp[_lib.OP_REJECTION])
+            pfr.resample_rejection(w, 1.0, seed=1, out=a, flags=flags)
         else:
             op = {"multinomial": _lib.OP_MULTINOMIAL, "stratified": _lib.OP_STRATIFIED,
                   "systematic": _lib.OP_SYSTEMATIC}[s]

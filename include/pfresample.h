@@ -172,11 +172,10 @@ PFR_API int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segmen
  * (decided exactly).  w_max must bound the weights (else the output is
  * biased); w_max_dev (device double[n_filters], may be NULL) overrides it per
  * segment.  After max_trials trials (>= 1) a particle keeps a_i = i and
- * PFR_FLAG_TRIAL_CAP is raised.  The workspace holds a work queue. */
+ * PFR_FLAG_TRIAL_CAP is raised.  No workspace; no collective operation. */
 PFR_API int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, double w_max,
                        const double* w_max_dev, uint32_t max_trials, pfr_rng rng,
-                       int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
-                       void* stream);
+                       int32_t* ancestors, uint32_t* dev_flags, void* stream);
 
 /* ---------------------------------------------------------------- auxiliaries */
 

@@ -172,18 +172,16 @@ def resample_metropolis(w, B, seed=0, offset=0, filter_base=0, B_per_filter=None
 
 
 def resample_rejection(w, w_max, seed=0, offset=0, filter_base=0, max_trials=1 << 20,
-                       w_max_per_filter=None, offsets=None, max_len=None, out=None, flags=None,
-                       workspace=None):
+                       w_max_per_filter=None, offsets=None, max_len=None, out=None, flags=None):
     """Rejection ancestry (Code 3) with first proposal j = i and bound w_max."""
     _require_cuda(w, w_max_per_filter, flags)
     dt = _dtype_code(w)
     seg = _segments(w.numel(), offsets, max_len)
     a = _out_like(w.numel(), w.device, out)
-    ws, _ = _workspace(_lib.OP_REJECTION, seg, dt, w.device, workspace)
     rc = _lib.load().resample_rejection(_ptr(w), dt, ctypes.byref(seg), float(w_max),
                                         _ptr(w_max_per_filter), int(max_trials),
-                                        _rng(seed, offset, filter_base), _ptr(a), _ptr(ws),
-                                        ws.numel(), _ptr(flags), _stream())
+                                        _rng(seed, offset, filter_base), _ptr(a), _ptr(flags),
+                                        _stream())
     _lib.check(rc, "resample_rejection")
     return a
 

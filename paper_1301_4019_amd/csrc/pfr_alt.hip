@@ -93,16 +93,31 @@ __global__ __launch_bounds__(256) void k_metropolis(const T* __restrict__ w, int
 // same block.  The first trial with u * w_max <= w_j wins.  After max_trials
 // rejections the particle keeps a_i = i and FLAG_TRIAL_CAP is raised.
 //
-// Scheduling (the variable task-length problem): each wave keeps 64 lanes
-// busy by handing a finished lane the next particle of the wave's current
-// chunk; chunks of kChunk particles come from a global counter (one atomic per
-// chunk), so waves that draw short trial sequences take more chunks.  When no
-// chunk is left, lanes still working try kSpec trials per pass (speculative:
-// the later proposals are used only if the earlier ones reject), which
-// shortens the dependent tail of the slowest particles.  The last wave to
-// finish resets the two counters for the next launch.
-constexpr uint32_t kChunk = 64;
-constexpr int kSpec = 4;
+// Scheduling (the variable task-length problem of the paper's section 2.2):
+// every wave owns a contiguous range of particles.  While the range lasts, a
+// lane that finishes takes the next particle of the range (ballot + prefix
+// count, no atomics).  When the range is used up, the particles still running
+// share all 64 lanes: each gets 64/m lanes (m = particles left) that try
+// consecutive trials of it at once, and the lowest accepting trial wins.
+// That is the same answer as trying the trials one by one, so the output does
+// not depend on the schedule, and the slowest particle of a wave no longer
+// runs alone on one lane.
+
+// position of the q-th set bit (0-based) of mask, which has more than q bits
+__device__ __forceinline__ int nth_set_bit(uint64_t mask, int q) {
+  int pos = 0;
+#pragma unroll
+  for (int width = 32; width >= 1; width >>= 1) {
+    const uint64_t low = mask & ((1ull << width) - 1ull);
+    const int cnt = __popcll(low);
+    if (q >= cnt) {
+      q -= cnt;
+      mask >>= width;
+      pos += width;
+    }
+  }
+  return pos;
+}
 
 template <typename T>
 __global__ __launch_bounds__(256) void k_rejection(const T* __restrict__ w, int64_t n_total,
@@ -111,79 +126,94 @@ __global__ __launch_bounds__(256) void k_rejection(const T* __restrict__ w, int6
                                                    const double* __restrict__ w_max_dev,
                                                    uint32_t max_trials, Key key, uint32_t offset,
                                                    uint32_t filter_base, int32_t* __restrict__ a,
-                                                   uint32_t* __restrict__ counters,
-                                                   uint32_t* __restrict__ flags) {
+                                                   uint32_t* __restrict__ flags,
+                                                   int64_t per_wave) {
   const uint32_t lane = lane_id();
-  uint32_t q_next = 0, q_end = 0;  // wave-uniform chunk cursor
-  bool exhausted = false;
-  int64_t cur = -1;  // particle (global index) this lane works on
-  uint32_t t = 0;    // next trial of that particle
+  const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
+  const int64_t r0 = gw * per_wave;
+  const int64_t r1 = r0 + per_wave < n_total ? r0 + per_wave : n_total;
+  int64_t next = r0;  // wave-uniform: next particle of the range to hand out
+  int64_t cur = -1;   // particle (global index) this lane works on
+  uint32_t t = 0;     // its next trial
   SegCtx c = {0, 0, 0};
   double wmax = w_max;
   uint32_t my_flags = 0;
 
+  // main phase: one trial per lane per pass
   while (true) {
-    // ---- hand out particles to free lanes
-    uint64_t freem = ballot(cur < 0);
-    while (freem != 0 && !exhausted) {
-      if (q_next >= q_end) {
-        uint32_t got = 0;
-        if (lane == 0) got = atomicAdd(&counters[0], kChunk);
-        got = readlane_u32(got, 0);
-        if ((int64_t)got >= n_total) {
-          exhausted = true;
-          break;
-        }
-        q_next = got;
-        q_end = (uint32_t)(((int64_t)got + kChunk) < n_total ? got + kChunk : n_total);
-      }
-      const uint32_t nfree = (uint32_t)__popcll(freem);
-      const uint32_t avail = q_end - q_next;
-      const uint32_t take = nfree < avail ? nfree : avail;
-      const uint32_t rank = (uint32_t)__popcll(freem & lanemask_lt());
+    const uint64_t freem = ballot(cur < 0);
+    if (freem != 0 && next < r1) {
+      const int64_t avail = r1 - next;
+      const int64_t nfree = __popcll(freem);
+      const int64_t take = nfree < avail ? nfree : avail;
+      const int64_t rank = __popcll(freem & lanemask_lt());
       if (cur < 0 && rank < take) {
-        cur = (int64_t)(q_next + rank);
+        cur = next + rank;
         t = 0;
         c = seg_of(offsets, n_filters, n_total, cur);
         wmax = w_max_dev ? w_max_dev[c.f] : w_max;
       }
-      q_next += take;
-      freem = ballot(cur < 0);
+      next += take;
     }
-    if (ballot(cur >= 0) == 0) break;
-
+    if (next >= r1) break;
     if (cur >= 0) {
       const uint32_t i = (uint32_t)(cur - c.base);
-      const uint32_t filt = filter_base + c.f;
-      const T* __restrict__ ws = w + c.base;
-      // trials [t, t + ntry)
-      const uint32_t ntry = (exhausted && t > 0) ? (uint32_t)kSpec : 1u;
-      uint4 x[kSpec];
-      uint32_t j[kSpec];
-      double wj[kSpec];
-#pragma unroll
-      for (int q = 0; q < kSpec; ++q) {
-        if ((uint32_t)q < ntry) {
-          x[q] = draw(key, i, DOM_TRIAL, t + q, filt, offset);
-          j[q] = (t + q == 0) ? i : index_draw(x[q].x, x[q].y, c.n);
-        }
+      const uint4 x = draw(key, i, DOM_TRIAL, t, filter_base + c.f, offset);
+      const uint32_t j = (t == 0) ? i : index_draw(x.x, x.y, c.n);
+      const double wj = (double)w[c.base + j];
+      if (accept_exact(u_accept(x.z), wmax, wj)) {
+        a[cur] = (int32_t)j;
+        cur = -1;
+      } else if (++t >= max_trials) {
+        a[cur] = (int32_t)i;
+        my_flags |= FLAG_TRIAL_CAP;
+        cur = -1;
       }
-#pragma unroll
-      for (int q = 0; q < kSpec; ++q)
-        if ((uint32_t)q < ntry) wj[q] = (double)ws[j[q]];
-      int done_q = -1;
-#pragma unroll
-      for (int q = kSpec - 1; q >= 0; --q) {
-        if ((uint32_t)q < ntry && t + q < max_trials && accept_exact(u_accept(x[q].z), wmax, wj[q]))
-          done_q = q;
-      }
-      if (done_q >= 0) {
-        a[cur] = (int32_t)j[done_q];
+    }
+  }
+
+  // tail phase: the remaining particles share the wave's lanes
+  while (true) {
+    const uint64_t act = ballot(cur >= 0);
+    if (act == 0) break;
+    const int m = __popcll(act);
+    const int slot = kWave / m;  // lanes per particle
+    const int q = (int)lane / slot;
+    const bool helper = q < m;
+    const int owner = helper ? nth_set_bit(act, q) : (int)lane;
+    const int64_t o_cur = shfl(cur, owner);
+    const uint32_t o_t = shfl(t, owner);
+    const int64_t o_base = shfl(c.base, owner);
+    const uint32_t o_n = shfl(c.n, owner);
+    const uint32_t o_f = shfl(c.f, owner);
+    const double o_wmax = shfl(wmax, owner);
+    const uint32_t tt = o_t + (lane - (uint32_t)(q * slot));
+    bool acc = false;
+    uint32_t jj = 0;
+    if (helper && tt < max_trials) {
+      const uint32_t i = (uint32_t)(o_cur - o_base);
+      const uint4 x = draw(key, i, DOM_TRIAL, tt, filter_base + o_f, offset);
+      jj = (tt == 0) ? i : index_draw(x.x, x.y, o_n);
+      acc = accept_exact(u_accept(x.z), o_wmax, (double)w[o_base + jj]);
+    }
+    const uint64_t accm = ballot(acc);
+    int src = (int)lane;
+    uint64_t g = 0;
+    if (cur >= 0) {
+      const int rank = __popcll(act & lanemask_lt());
+      const uint64_t gm = (slot >= kWave ? ~0ull : ((1ull << slot) - 1ull)) << (rank * slot);
+      g = accm & gm;
+      if (g) src = __ffsll((long long)g) - 1;
+    }
+    const uint32_t jsel = shfl(jj, src);
+    if (cur >= 0) {
+      if (g) {
+        a[cur] = (int32_t)jsel;
         cur = -1;
       } else {
-        t += ntry;
+        t += (uint32_t)slot;
         if (t >= max_trials) {
-          a[cur] = (int32_t)i;
+          a[cur] = (int32_t)(cur - c.base);
           my_flags |= FLAG_TRIAL_CAP;
           cur = -1;
         }
@@ -194,17 +224,6 @@ __global__ __launch_bounds__(256) void k_rejection(const T* __restrict__ w, int6
   if (flags) {
     const uint32_t wf = wave_reduce(my_flags, OpOr());
     if (lane == 0 && wf) atomicOr(flags, wf);
-  }
-  // the last wave out resets the counters for the next launch
-  if (lane == 0) {
-    __threadfence();
-    const uint32_t nwaves = gridDim.x * (blockDim.x / kWave);
-    const uint32_t prev = atomicAdd(&counters[1], 1u);
-    if (prev == nwaves - 1) {
-      counters[0] = 0;
-      counters[1] = 0;
-      __threadfence();
-    }
   }
 }
 
@@ -237,26 +256,36 @@ template <typename T>
 hipError_t launch_rejection_t(const void* w, int64_t n_total, const int64_t* offsets,
                               uint32_t n_filters, double w_max, const double* w_max_dev,
                               uint32_t max_trials, Key key, uint32_t offset, uint32_t filter_base,
-                              int32_t* a, uint32_t* counters, uint32_t* flags, int grid_blocks,
-                              hipStream_t stream) {
+                              int32_t* a, uint32_t* flags, int64_t per_wave, hipStream_t stream) {
   const int threads = 256;
-  hipLaunchKernelGGL(k_rejection<T>, dim3((unsigned)grid_blocks), dim3(threads), 0, stream,
+  const int64_t waves = (n_total + per_wave - 1) / per_wave;
+  const int64_t blocks = (waves + (threads / kWave) - 1) / (threads / kWave);
+  hipLaunchKernelGGL(k_rejection<T>, dim3((unsigned)blocks), dim3(threads), 0, stream,
                      (const T*)w, n_total, offsets, n_filters, w_max, w_max_dev, max_trials, key,
-                     offset, filter_base, a, counters, flags);
+                     offset, filter_base, a, flags, per_wave);
   return hipGetLastError();
+}
+
+// Particles per wave: enough waves to fill the chip (about 16 per CU), at
+// least one particle per lane.
+int64_t rejection_per_wave(int64_t n_total) {
+  const int64_t target_waves = 256 * 16;
+  int64_t p = (n_total + target_waves - 1) / target_waves;
+  if (p < kWave) p = kWave;
+  return p;
 }
 
 hipError_t launch_rejection(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
                             uint32_t n_filters, double w_max, const double* w_max_dev,
                             uint32_t max_trials, Key key, uint32_t offset, uint32_t filter_base,
-                            int32_t* a, uint32_t* counters, uint32_t* flags, int grid_blocks,
-                            hipStream_t stream) {
+                            int32_t* a, uint32_t* flags, hipStream_t stream) {
+  const int64_t pw = rejection_per_wave(n_total);
   return f64 ? launch_rejection_t<double>(w, n_total, offsets, n_filters, w_max, w_max_dev,
-                                          max_trials, key, offset, filter_base, a, counters,
-                                          flags, grid_blocks, stream)
+                                          max_trials, key, offset, filter_base, a, flags, pw,
+                                          stream)
              : launch_rejection_t<float>(w, n_total, offsets, n_filters, w_max, w_max_dev,
-                                         max_trials, key, offset, filter_base, a, counters, flags,
-                                         grid_blocks, stream);
+                                         max_trials, key, offset, filter_base, a, flags, pw,
+                                         stream);
 }
 
 }  // namespace pfr

@@ -9,7 +9,7 @@ namespace {
 using namespace pfr;
 
 constexpr int64_t kMaxN = (int64_t)1 << 31;
-constexpr int64_t kSingleWGMax = 16384;  // single vectors up to this run in one workgroup
+constexpr int64_t kSingleWGMax = 4096;  // single vectors up to this run in one workgroup
 
 struct SegInfo {
   int64_t n_total;
@@ -84,16 +84,6 @@ int collective(int scheme, const void* w, pfr_dtype dtype, const pfr_segments* s
                                    rng.filter_base, a, ws, dev_flags, st));
 }
 
-constexpr size_t kRejectionWs = 256;
-
-int rejection_grid(int64_t n_total) {
-  // enough resident waves to fill the chip, never more than the work needs
-  int64_t blocks = (n_total + 1023) / 1024;  // 4 waves x 256 particles per block to start
-  if (blocks > 2048) blocks = 2048;
-  if (blocks < 1) blocks = 1;
-  return (int)blocks;
-}
-
 }  // namespace
 
 extern "C" {
@@ -111,7 +101,7 @@ size_t pfr_workspace_bytes(pfr_op op, const pfr_segments* seg, pfr_dtype dtype) 
     case PFR_OP_METROPOLIS:
       return 0;
     case PFR_OP_REJECTION:
-      return kRejectionWs;
+      return 0;
     case PFR_OP_OFFSPRING_TO_ANCESTORS:
       return o2a_workspace_bytes(s.n_total);
     case PFR_OP_PERMUTE:
@@ -165,8 +155,7 @@ int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segments* seg,
 
 int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, double w_max,
                        const double* w_max_dev, uint32_t max_trials, pfr_rng rng,
-                       int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
-                       void* stream) {
+                       int32_t* ancestors, uint32_t* dev_flags, void* stream) {
   SegInfo s;
   int rc = check_segments(seg, &s);
   if (rc) return rc;
@@ -175,13 +164,11 @@ int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, 
   if (!w_max_dev && !(w_max > 0.0 && w_max < __builtin_huge_val())) return PFR_EINVAL;
   if (s.n_total == 0) return PFR_OK;
   if (!w || !ancestors) return PFR_EINVAL;
-  if (!ws || ws_bytes < kRejectionWs || !aligned256(ws)) return PFR_EWORKSPACE;
   if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), ancestors, (size_t)s.n_total * 4))
     return PFR_EINVAL;
   return launch_result(launch_rejection(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters,
                                         w_max, w_max_dev, max_trials, make_key(rng.seed),
-                                        rng.offset, rng.filter_base, ancestors, (uint32_t*)ws,
-                                        dev_flags, rejection_grid(s.n_total),
+                                        rng.offset, rng.filter_base, ancestors, dev_flags,
                                         (hipStream_t)stream));
 }
 

@@ -286,14 +286,22 @@ __global__ __launch_bounds__(256) void k_o2a_batched(const int32_t* __restrict__
 // Code 10.  d[j] holds the particle index that claims slot j, or n (unclaimed).
 // Prepermute keeps the lowest claimer of every slot.  For a sorted ancestry
 // (the output of the collective resamplers) the lowest claimer of slot a_i is
-// the first i of its run, so the claim vector is written with plain stores:
-// position i writes slot a_i when it starts a run, and n into every slot
-// strictly between a_{i-1} and a_i, which no position claims.  For an unsorted
-// ancestry the lowest claimer is found with an atomic minimum on d.  After a
-// kernel boundary, every position whose claim failed walks x <- d[x] from x = i
-// to an unclaimed slot and claims it; the walks are disjoint paths (the
-// paper's termination argument), so they read and write disjoint slots.  A
-// final kernel gathers c_i = a_{d_i}.
+// the first i of its run, so the claim vector is written with plain stores in
+// one pass: position i writes slot a_i when it starts a run, and n into every
+// slot strictly between a_{i-1} and a_i, which no position claims.  For an
+// unsorted ancestry the claim vector is filled with n and the lowest claimer
+// found with an atomic minimum (a relaxed load first skips the atomic once a
+// lower claimer is in place).
+//
+// Permute then lets every failed claimer i follow x <- d_x from x = i to an
+// unclaimed slot and take it; finally c_j = a_{d_j}.  The chains are disjoint
+// paths (the paper's termination argument), one per failed claimer, each
+// ending in its own unclaimed slot.  The resolve kernel walks them backwards
+// instead: a claimed slot j keeps c_j = j; from an unclaimed slot j it steps
+// y <- a_y for as long as position y is the winning claimer of slot a_y
+// (d[a_y] == y), which retraces the one chain that ends at j back to its
+// failed claimer y, and sets c_j = a_y.  This is the same c as Code 10, reads
+// only a and d, and needs no second pass over d.
 struct SegIdx {
   int64_t base, n, i;
 };
@@ -328,6 +336,7 @@ __global__ __launch_bounds__(256) void k_claim_sorted(const int32_t* __restrict_
                                                       int64_t n_total,
                                                       const int64_t* __restrict__ offsets,
                                                       uint32_t n_filters, int32_t* __restrict__ d,
+                                                      int32_t* __restrict__ e,
                                                       uint32_t* __restrict__ flags) {
   bool bad = false;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
@@ -336,6 +345,7 @@ __global__ __launch_bounds__(256) void k_claim_sorted(const int32_t* __restrict_
     const int64_t ai = anc_at(a, s, s.i, bad);
     const int64_t prev = (s.i == 0) ? -1 : anc_at(a, s, s.i - 1, bad);
     int32_t* ds = d + s.base;
+    e[g] = ai > prev ? (int32_t)ai : (int32_t)(-1 - ai);
     if (ai > prev) {
       ds[ai] = (int32_t)s.i;  // first of its run
       for (int64_t j = prev + 1; j < ai; ++j) ds[j] = (int32_t)s.n;
@@ -370,7 +380,9 @@ __global__ __launch_bounds__(256) void k_claim_min(const int32_t* __restrict__ a
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
     const SegIdx s = seg_index(offsets, n_filters, n_total, g);
     const int64_t ai = anc_at(a, s, s.i, bad);
-    atomicMin(&d[s.base + ai], (int32_t)s.i);
+    int32_t* slot = &d[s.base + ai];
+    if (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (int32_t)s.i)
+      atomicMin(slot, (int32_t)s.i);
   }
   if (flags) {
     const uint32_t b = (uint32_t)wave_reduce((uint32_t)bad, OpOr());
@@ -378,47 +390,53 @@ __global__ __launch_bounds__(256) void k_claim_min(const int32_t* __restrict__ a
   }
 }
 
-__global__ __launch_bounds__(256) void k_walk(const int32_t* __restrict__ a, int64_t n_total,
+// e[i] = a_i if position i won its claim (d[a_i] == i), else -1 - a_i.
+__global__ __launch_bounds__(256) void k_mark(const int32_t* __restrict__ a, int64_t n_total,
                                               const int64_t* __restrict__ offsets,
-                                              uint32_t n_filters, int32_t* __restrict__ d,
-                                              uint32_t* __restrict__ flags) {
-  bool bad = false, broken = false;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
-    const SegIdx s = seg_index(offsets, n_filters, n_total, g);
-    int32_t* ds = d + s.base;
-    const int64_t ai = anc_at(a, s, s.i, bad);
-    if (ds[ai] == s.i) continue;  // claim succeeded
-    int64_t x = s.i;
-    int64_t steps = 0;
-    // a chain visits distinct slots, so it ends within n steps
-    while (true) {
-      const int64_t nx = ds[x];
-      if (nx >= s.n || nx < 0) break;
-      x = nx;
-      if (++steps > s.n) {
-        broken = true;
-        break;
-      }
-    }
-    if (!broken) ds[x] = (int32_t)s.i;
-  }
-  if (flags) {
-    const uint32_t b = (uint32_t)wave_reduce((uint32_t)(broken ? FLAG_BAD_ANCESTOR : 0u), OpOr());
-    if (b && lane_id() == 0) atomicOr(flags, b);
-  }
-}
-
-__global__ __launch_bounds__(256) void k_gather(const int32_t* __restrict__ a, int64_t n_total,
-                                                const int64_t* __restrict__ offsets,
-                                                uint32_t n_filters, const int32_t* __restrict__ d,
-                                                int32_t* __restrict__ c) {
+                                              uint32_t n_filters, const int32_t* __restrict__ d,
+                                              int32_t* __restrict__ e) {
   bool bad = false;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
     const SegIdx s = seg_index(offsets, n_filters, n_total, g);
-    const int64_t di = d[g];
-    c[g] = (di >= 0 && di < s.n) ? (int32_t)anc_at(a, s, di, bad) : (int32_t)s.i;
+    const int64_t ai = anc_at(a, s, s.i, bad);
+    e[g] = d[s.base + ai] == s.i ? (int32_t)ai : (int32_t)(-1 - ai);
+  }
+}
+
+// Backward walk on e: one dependent load per chain step.
+__global__ __launch_bounds__(256) void k_resolve(int64_t n_total,
+                                                 const int64_t* __restrict__ offsets,
+                                                 uint32_t n_filters, const int32_t* __restrict__ d,
+                                                 const int32_t* __restrict__ e,
+                                                 int32_t* __restrict__ c,
+                                                 uint32_t* __restrict__ flags) {
+  bool broken = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
+    const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    const int64_t j = s.i;
+    const int64_t dj = d[g];
+    if (dj >= 0 && dj < s.n) {  // claimed: its winner's ancestor is j
+      c[g] = (int32_t)j;
+      continue;
+    }
+    // unclaimed: retrace the chain that ends here back to its failed claimer
+    const int32_t* es = e + s.base;
+    int64_t ey = es[j];
+    int64_t steps = 0;
+    while (ey >= 0) {
+      ey = es[ey];
+      if (++steps > s.n) {  // a chain visits distinct slots; only bad input gets here
+        broken = true;
+        break;
+      }
+    }
+    c[g] = broken ? (int32_t)j : (int32_t)(-1 - ey);
+  }
+  if (flags) {
+    const uint32_t b = (uint32_t)wave_reduce((uint32_t)(broken ? FLAG_BAD_ANCESTOR : 0u), OpOr());
+    if (b && lane_id() == 0) atomicOr(flags, b);
   }
 }
 
@@ -452,28 +470,30 @@ hipError_t launch_offspring_to_ancestors(const int32_t* o, int64_t n_total, cons
   return hipGetLastError();
 }
 
+// Workspace: the claim vector d and the marked ancestry e, n int32 each.
 size_t permute_workspace_bytes(int64_t n_total) {
-  return align256((size_t)n_total * sizeof(int32_t));
+  return 2 * align256((size_t)n_total * sizeof(int32_t));
 }
 
 hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offsets,
                           uint32_t n_filters, bool sorted, int32_t* c, void* ws, uint32_t* flags,
                           hipStream_t stream) {
   int32_t* d = (int32_t*)ws;
+  int32_t* e = (int32_t*)((char*)ws + align256((size_t)n_total * sizeof(int32_t)));
   const int grid = grid_for(n_total);
   if (sorted) {
     hipLaunchKernelGGL(k_claim_sorted, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
-                       n_filters, d, flags);
+                       n_filters, d, e, flags);
   } else {
     hipLaunchKernelGGL(k_fill_unclaimed, dim3(grid), dim3(256), 0, stream, d, n_total, offsets,
                        n_filters);
     hipLaunchKernelGGL(k_claim_min, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
                        n_filters, d, flags);
+    hipLaunchKernelGGL(k_mark, dim3(grid), dim3(256), 0, stream, a, n_total, offsets, n_filters, d,
+                       e);
   }
-  hipLaunchKernelGGL(k_walk, dim3(grid), dim3(256), 0, stream, a, n_total, offsets, n_filters, d,
-                     flags);
-  hipLaunchKernelGGL(k_gather, dim3(grid), dim3(256), 0, stream, a, n_total, offsets, n_filters, d,
-                     c);
+  hipLaunchKernelGGL(k_resolve, dim3(grid), dim3(256), 0, stream, n_total, offsets, n_filters, d, e,
+                     c, flags);
   return hipGetLastError();
 }
 

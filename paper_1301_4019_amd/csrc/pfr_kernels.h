@@ -28,13 +28,16 @@ struct BlockRec {
 
 // Header at the start of a collective-scheme workspace.
 struct ScanHeader {
-  uint32_t ticket;   // reduce workgroups done (reset by the last one)
+  uint32_t ticket;   // unused (kept zero)
   uint32_t status;   // FLAG_* bits of this call
   int32_t gscale;    // global fixed-point scale of the carries
-  uint32_t nb;       // weight blocks
-  uint32_t nbe;      // exponential blocks (multinomial)
-  uint32_t pad[59];  // header padded to 256 bytes
+  uint32_t pad0;
+  uint64_t epoch;    // unused (kept zero)
+  uint64_t pad1;
+  u128 Q;            // exact total at the global scale
+  uint32_t pad[52];  // header padded to 256 bytes
 };
+static_assert(sizeof(ScanHeader) == 256, "scan header is 256 bytes");
 
 struct ScanLayout {
   size_t recs, carries, erecs, ecarries, total;
@@ -57,8 +60,7 @@ hipError_t launch_metropolis(bool f64, const void* w, int64_t n_total, const int
 hipError_t launch_rejection(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
                             uint32_t n_filters, double w_max, const double* w_max_dev,
                             uint32_t max_trials, Key key, uint32_t offset, uint32_t filter_base,
-                            int32_t* a, uint32_t* counters, uint32_t* flags, int grid_blocks,
-                            hipStream_t stream);
+                            int32_t* a, uint32_t* flags, hipStream_t stream);
 
 size_t o2a_workspace_bytes(int64_t n_total);
 hipError_t launch_offspring_to_ancestors(const int32_t* o, int64_t n_total, const int64_t* offsets,

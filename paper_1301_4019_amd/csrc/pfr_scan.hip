@@ -7,8 +7,7 @@
 //   systematic   the same with one offset u for all strata
 //   multinomial  p_k = n S_k / S_n from exponential spacings (sorted uniforms),
 //                ancestor = #{i < n-1 : r_i <= p_k}
-// which is Code 7/8 followed by Code 11 (and Code 5 with an upper-bound
-// search), written point by point so that each output is computed once.
+// i.e. Code 7/8 followed by Code 11, and Code 5 with an upper-bound search.
 //
 // Exact prefix sums.  The paper shows that a float32 prefix sum biases these
 // schemes for large n.  Here each block of 1024 weights is quantised to
@@ -17,480 +16,669 @@
 // block sums are exact 64-bit integers, and the carries between blocks are
 // exact 128-bit integers at one global scale.  Integer sums do not depend on
 // the order of addition, so the prefix is deterministic, monotone, exactly
-// flat across zero weights, and consistent at every block boundary; the only
-// rounding is the final conversion r = n * (I / I_total) to binary64.
+// flat across zero weights and consistent at every block boundary; the only
+// rounding is the final map r = n * I / I_total to binary64, itself monotone
+// with r = n at the end.
 //
-// Passes (single vector): a reduce kernel writes one record per block, and
-// its last workgroup (ticket counter) scans the records into carries; the emit
-// kernel re-reads the weights, rebuilds r for a tile of 4096 particles in LDS
-// and writes every point whose value falls in the tile's r-range, so that
-// outputs are written once and coalesced.  Ragged batches run the same steps
-// inside one workgroup per filter.
+// One workgroup of 256 threads handles one block, 4 consecutive weights per
+// thread (one 16-byte load each for float32), so that a 2^20 vector runs
+// 1024 workgroups, 16 waves per CU.  Passes for one vector:
+//   records one record per block (validity, block scale, quantised sum), and
+//           one sum per exponential-spacing block of the multinomial scheme.
+//   carries one workgroup turns the records into the global scale, the exact
+//           carries C_b and the total, and scans the exponential-block sums.
+//           With at most 2048 blocks and no exponential blocks this step is
+//           folded into the emit kernel: every emit workgroup reduces all
+//           records itself, which costs less than one more launch.
+//   emit    each block rebuilds its exact prefix, I = C_b + local prefix, and
+//           r = n I / Q.  Stratified / systematic: every particle computes its
+//           cumulative offspring O_i = #{s : q_s <= r_i} in O(1) with the
+//           stratum offsets from an LDS table, and the block's output range
+//           [O(C_b), O(C_b+1)) is filled through LDS markers and a max-scan,
+//           then written coalesced.  Multinomial: the workgroup rebuilds the
+//           exponential blocks whose points fall in its r-range and locates
+//           each point with interleaved binary searches in r (LDS).
+// Ragged batches run the same steps inside one workgroup per filter.
 #include "pfr_kernels.h"
 
 namespace pfr {
 
 namespace {
 
-constexpr int kTile = kBlock * kBlocksPerWG;  // particles per emit workgroup
-constexpr int kCarryBits = 100;               // carries stay below 2^100
+constexpr int kT = kWGThreads;   // threads per workgroup
+constexpr int kPer = kBlock / kT;  // consecutive values per thread (4)
+constexpr int kNW = kT / kWave;    // waves per workgroup
+constexpr int kCarryBits = 100;    // carries stay below 2^100
+constexpr int kChunk = 2048;       // output positions per LDS marker pass
+constexpr int kUTab = 2048;        // stratum offsets cached per block
 
 size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
 
-template <typename T>
-struct Blk {
-  static constexpr int V = 16 / (int)sizeof(T);  // values per vector load
-  static constexpr int G = kBlock / (kWave * V);  // vector loads per lane
+// ---------------------------------------------------------------- workgroup
+struct WgScratch {
+  u128 v[kNW];
+  uint64_t u[kNW];
+  int32_t i[2 * kNW];
 };
 
-// ---------------------------------------------------------------- block loads
-// Lane l holds, for g = 0..G-1 and v = 0..V-1, element g*64*V + l*V + v of the
-// block: every vector load of the wave reads one contiguous kilobyte.
-template <typename T>
-__device__ __forceinline__ void load_block(const T* __restrict__ w, int64_t n, int64_t base,
-                                           T (&x)[16]) {
-  constexpr int V = Blk<T>::V, G = Blk<T>::G;
-  const int lane = (int)lane_id();
-  const bool aligned = ((reinterpret_cast<uintptr_t>(w + base) & 15u) == 0);
+template <typename U, typename Op>
+__device__ U wg_reduce(U x, Op op, U* slot) {
+  const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
+  x = wave_reduce(x, op);
+  __syncthreads();
+  if (lane == 0) slot[wave] = x;
+  __syncthreads();
+  U t = slot[0];
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    const int64_t idx = base + (int64_t)g * kWave * V + (int64_t)lane * V;
-    if (aligned && idx + V <= n) {
-      if constexpr (V == 4) {
-        const float4 t = *reinterpret_cast<const float4*>(w + idx);
-        x[g * V + 0] = t.x;
-        x[g * V + 1] = t.y;
-        x[g * V + 2] = t.z;
-        x[g * V + 3] = t.w;
-      } else {
-        const double2 t = *reinterpret_cast<const double2*>(w + idx);
-        x[g * V + 0] = t.x;
-        x[g * V + 1] = t.y;
-      }
-    } else {
-#pragma unroll
-      for (int v = 0; v < V; ++v) x[g * V + v] = (idx + v < n) ? w[idx + v] : (T)0;
-    }
-  }
+  for (int w2 = 1; w2 < kNW; ++w2) t = op(t, slot[w2]);
+  __syncthreads();
+  return t;
 }
 
-// In-place inclusive prefix of 16 per-lane values in (g, lane, v) order.
-template <int G, int V, typename U>
-__device__ __forceinline__ U block_inclusive_scan(U (&q)[16]) {
-  U run = 0;
+// Exclusive prefix (across the workgroup, in thread order) of x; *total gets
+// the workgroup sum.
+template <typename U>
+__device__ U wg_exclusive(U x, U* slot, U* total) {
+  const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
+  const U incl = wave_inclusive_scan(x, OpAdd());
+  __syncthreads();
+  if (lane == kWave - 1) slot[wave] = incl;
+  __syncthreads();
+  U run = incl - x, tot = 0;
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-    U s = 0;
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      s += q[g * V + v];
-      q[g * V + v] = s;
-    }
-    const U incl = wave_inclusive_scan(s, OpAdd());
-    const U add = run + (incl - s);
-#pragma unroll
-    for (int v = 0; v < V; ++v) q[g * V + v] += add;
-    run += readlane(incl, kWave - 1);
+  for (int w2 = 0; w2 < kNW; ++w2) {
+    if (w2 < wave) run += slot[w2];
+    tot += slot[w2];
   }
+  __syncthreads();
+  *total = tot;
   return run;
 }
 
-// ---------------------------------------------------------------- reduce step
-// One weight block: validity, reference exponent (block maximum), quantised
-// sum.  Returns the record (identical in every lane).
+// ---------------------------------------------------------------- block loads
+// Thread t holds elements 4t .. 4t+3 of the block.
 template <typename T>
-__device__ BlockRec weight_block_record(const T* __restrict__ w, int64_t n, int64_t base) {
-  T x[16];
-  load_block(w, n, base, x);
+__device__ __forceinline__ void load4(const T* __restrict__ w, int64_t n, int64_t base,
+                                      T (&x)[kPer]) {
+  const int64_t idx = base + (int64_t)threadIdx.x * kPer;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(w + idx) & 15u) == 0);
+  if (aligned && idx + kPer <= n) {
+    if constexpr (sizeof(T) == 4) {
+      const float4 t = *reinterpret_cast<const float4*>(w + idx);
+      x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
+    } else {
+      const double2 t0 = *reinterpret_cast<const double2*>(w + idx);
+      const double2 t1 = *reinterpret_cast<const double2*>(w + idx + 2);
+      x[0] = t0.x; x[1] = t0.y; x[2] = t1.x; x[3] = t1.y;
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < kPer; ++v) x[v] = (idx + v < n) ? w[idx + v] : (T)0;
+  }
+}
+
+// ---------------------------------------------------------------- records
+// Record of the block at base: validity, reference exponent (block maximum),
+// quantised sum.  Same value in every thread.
+template <typename T>
+__device__ BlockRec block_record(const T* __restrict__ w, int64_t n, int64_t base, WgScratch* s) {
+  T x[kPer];
+  load4(w, n, base, x);
   uint32_t bad = 0;
-  int emax = 1;
+  uint32_t emax = 1;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) {
-    if (!weight_ok(x[i])) bad = FLAG_BAD_WEIGHTS;
-    else emax = max(emax, exp_field(x[i]));
+  for (int v = 0; v < kPer; ++v) {
+    if (!weight_ok(x[v])) bad = FLAG_BAD_WEIGHTS;
+    else emax = max(emax, (uint32_t)exp_field(x[v]));
   }
-  bad = wave_reduce(bad, OpOr());
-  emax = (int)wave_reduce((uint32_t)emax, OpMax());
-  uint64_t s = 0;
-  if (!bad) {
-#pragma unroll
-    for (int i = 0; i < 16; ++i) s += quantize(x[i], emax);
-  }
-  s = wave_reduce(s, OpAdd());
+  // pack (bad, emax) into one max-reduction: bad dominates
+  const uint32_t key = (bad << 16) | emax;
+  const uint32_t red = wg_reduce(key, OpMax(), (uint32_t*)s->i);
   BlockRec r;
-  r.sum = s;
-  r.scale = scale_of<T>(emax);
-  r.bad = bad;
+  r.bad = red >> 16;
+  const int e_ref = (int)(red & 0xFFFFu);
+  uint64_t sum = 0;
+  if (!r.bad) {
+#pragma unroll
+    for (int v = 0; v < kPer; ++v) sum += quantize(x[v], e_ref);
+  }
+  r.sum = wg_reduce(sum, OpAdd(), s->u);
+  r.scale = scale_of<T>(e_ref);
   return r;
 }
 
-// Exponential spacing E_k = -log((x + 1/2) 2^-32) for k = 0..n (word k&3 of
-// Philox call k>>2 in the exponential domain), quantised to floor(E 2^48).
-// Block layout (g, lane, v) with V = 4: Philox call b*256 + g*64 + lane
-// supplies the lane's 4 values of group g.
-__device__ __forceinline__ void exp_block_values(Key key, uint32_t filter, uint32_t offset,
-                                                 int64_t n, uint32_t blk, uint64_t (&q)[16]) {
-  const uint32_t lane = lane_id();
+// Exponential spacing E_k = -log((x + 1/2) 2^-32), k = 0..n: word k&3 of
+// Philox call k>>2 (exponential domain), quantised to floor(E 2^48).  Thread t
+// of block b holds k = 1024 b + 4t + v, all four from call 256 b + t.
+__device__ __forceinline__ void exp_values(Key key, uint32_t filter, uint32_t offset, int64_t n,
+                                           uint32_t blk, uint64_t (&q)[kPer]) {
+  const uint32_t call = blk * (uint32_t)kT + threadIdx.x;
+  const uint4 x = draw(key, call, DOM_EXP, 0, filter, offset);
+  const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
-  for (int g = 0; g < 4; ++g) {
-    const uint32_t call = blk * 256u + (uint32_t)g * 64u + lane;
-    const uint4 x = draw(key, call, DOM_EXP, 0, filter, offset);
-    const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t k = (int64_t)call * 4 + v;
-      const double e = -log(((double)xs[v] + 0.5) * 0x1p-32);
-      q[g * 4 + v] = (k <= n) ? (uint64_t)(e * 0x1p48) : 0ull;
-    }
+  for (int v = 0; v < kPer; ++v) {
+    const int64_t k = (int64_t)call * 4 + v;
+    const double e = -log(((double)xs[v] + 0.5) * 0x1p-32);
+    q[v] = (k <= n) ? (uint64_t)(e * 0x1p48) : 0ull;
   }
 }
 
-__device__ __forceinline__ uint64_t exp_block_sum(Key key, uint32_t filter, uint32_t offset,
-                                                  int64_t n, uint32_t blk) {
-  uint64_t q[16];
-  exp_block_values(key, filter, offset, n, blk, q);
-  uint64_t s = 0;
-#pragma unroll
-  for (int i = 0; i < 16; ++i) s += q[i];
-  return wave_reduce(s, OpAdd());
-}
-
-// ---------------------------------------------------------------- carry scan
-// Exclusive scan of nb records into C[0..nb] (C[nb] = total) by one
-// workgroup of kWGThreads threads.  Weight records are first moved to the
-// global scale gscale; exponential records (scale fixed) are used as is.
-// Returns the OR of the bad bits and writes gscale.
 __device__ __forceinline__ int ceil_log2(uint32_t x) {
   return x <= 1 ? 0 : 32 - __clz(x - 1);
 }
 
-template <typename RecLoad>
-__device__ void wg_exclusive_scan_u128(uint32_t count, RecLoad load, u128* __restrict__ C,
-                                       u128* lds_wave) {
-  const int tid = (int)threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-  const uint32_t per = (count + kWGThreads - 1) / kWGThreads;
-  const uint32_t b0 = (uint32_t)tid * per;
-  const uint32_t b1 = min(b0 + per, count);
-  u128 mine = 0;
-  for (uint32_t b = b0; b < b1; ++b) mine += load(b);
-  const u128 incl = wave_inclusive_scan(mine, OpAdd());
-  if (lane == kWave - 1) lds_wave[wave] = incl;
-  __syncthreads();
-  u128 run = incl - mine;
-  for (int w2 = 0; w2 < wave; ++w2) run += lds_wave[w2];
-  for (uint32_t b = b0; b < b1; ++b) {
-    C[b] = run;
-    run += load(b);
-  }
-  if (tid == kWGThreads - 1) C[count] = run;
-  __syncthreads();
+__device__ __forceinline__ u128 conv_rec(const BlockRec& r, int32_t gscale) {
+  return shift_u128((u128)r.sum, gscale - r.scale);
 }
 
-template <typename RecArr>
-__device__ void scan_weight_records(uint32_t nb, const RecArr recs, u128* __restrict__ C,
-                                    u128* lds_wave, int32_t* lds_misc, uint32_t* status_out,
-                                    int32_t* gscale_out) {
+// ---------------------------------------------------------------- carries
+// From nb records: global scale, exact exclusive carries C[0..nb] (C[nb] is
+// the total) and status.  Whole workgroup; records are read in chunks of
+// kBlock, 4 consecutive per thread, all loads of a chunk issued together.
+struct Totals {
+  u128 Q;
+  int32_t gscale;
+  uint32_t status;
+};
+
+template <typename RecPtr, typename CPtr>
+__device__ Totals carries_from_records(uint32_t nb, RecPtr recs, CPtr C, WgScratch* s) {
   const int tid = (int)threadIdx.x;
-  // global status and the scale of the largest block
   uint32_t bad = 0;
-  int32_t smin = 0x7fffffff;
-  for (uint32_t b = tid; b < nb; b += kWGThreads) {
-    const BlockRec r = recs[b];
-    bad |= r.bad;
-    if (r.sum) smin = min(smin, r.scale);
+  uint32_t smin_key = 0xFFFFFFFFu;  // scale + 2^31, min over non-empty blocks
+  for (uint32_t base = 0; base < nb; base += kBlock) {
+    BlockRec r[kPer];
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t b = base + (uint32_t)tid * kPer + k;
+      if (b < nb) r[k] = recs[b];
+      else r[k].sum = 0, r[k].scale = 0, r[k].bad = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      bad |= r[k].bad;
+      if (r[k].sum) smin_key = min(smin_key, (uint32_t)r[k].scale ^ 0x80000000u);
+    }
   }
-  bad = wave_reduce(bad, OpOr());
-  smin = (int32_t)wave_reduce((uint32_t)(smin ^ 0x80000000u), OpMin()) ^ 0x80000000;
-  if (tid == 0) {
-    lds_misc[0] = 0;
-    lds_misc[1] = 0x7fffffff;
-  }
-  __syncthreads();
-  if ((tid % kWave) == 0) {
-    atomicOr((uint32_t*)&lds_misc[0], bad);
-    atomicMin(&lds_misc[1], smin);
-  }
-  __syncthreads();
-  bad = (uint32_t)lds_misc[0];
-  smin = lds_misc[1];
-  __syncthreads();
+  bad = wg_reduce(bad, OpOr(), (uint32_t*)s->i);
+  smin_key = wg_reduce(smin_key, OpMin(), (uint32_t*)s->i);
+  Totals t;
   // every converted block sum is below 2^(63 + gscale - smin); nb of them stay
   // below 2^kCarryBits
-  const int32_t gscale = (smin == 0x7fffffff) ? 0 : smin + (kCarryBits - 63) - ceil_log2(nb);
-  wg_exclusive_scan_u128(
-      nb,
-      [&](uint32_t b) -> u128 {
-        const BlockRec r = recs[b];
-        return shift_u128((u128)r.sum, gscale - r.scale);
-      },
-      C, lds_wave);
-  uint32_t st = bad;
-  if (!bad && C[nb] == 0) st |= FLAG_ZERO_TOTAL;
-  *status_out = st;
-  *gscale_out = gscale;
+  t.gscale = (smin_key == 0xFFFFFFFFu)
+                 ? 0
+                 : (int32_t)(smin_key ^ 0x80000000u) + (kCarryBits - 63) - ceil_log2(nb);
+  u128 carry = 0;
+  for (uint32_t base = 0; base < nb; base += kBlock) {
+    u128 v[kPer];
+    u128 mine = 0;
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t b = base + (uint32_t)tid * kPer + k;
+      v[k] = (b < nb) ? conv_rec(recs[b], t.gscale) : (u128)0;
+      mine += v[k];
+    }
+    u128 tot;
+    u128 run = carry + wg_exclusive(mine, s->v, &tot);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t b = base + (uint32_t)tid * kPer + k;
+      if (b < nb) C[b] = run;
+      run += v[k];
+    }
+    carry += tot;
+  }
+  if (tid == 0) C[nb] = carry;
+  __syncthreads();
+  t.Q = carry;
+  t.status = bad;
+  if (!bad && carry == 0) t.status |= FLAG_ZERO_TOTAL;
+  return t;
 }
 
-// ---------------------------------------------------------------- r of a block
-// r values (binary64) of one weight block, written to r_out[e] in particle
-// order, given the block's carry and record.
-template <typename T>
-__device__ void weight_block_r(const T* __restrict__ w, int64_t n, int64_t base, const BlockRec rec,
-                               u128 carry, int32_t gscale, double fQ, double Nd,
-                               double* __restrict__ r_out) {
-  constexpr int V = Blk<T>::V, G = Blk<T>::G;
-  T x[16];
-  load_block(w, n, base, x);
-  const int emax = 52 + WTraits<T>::BIAS - rec.scale;
-  uint64_t q[16];
+// Exclusive scan of the exponential block sums into CE[0..nbe].
+template <typename SumPtr, typename CPtr>
+__device__ void exp_carries(uint32_t nbe, SumPtr sums, CPtr CE, WgScratch* s) {
+  const int tid = (int)threadIdx.x;
+  u128 carry = 0;
+  for (uint32_t base = 0; base < nbe; base += kBlock) {
+    u128 v[kPer];
+    u128 mine = 0;
 #pragma unroll
-  for (int i = 0; i < 16; ++i) q[i] = quantize(x[i], emax);
-  block_inclusive_scan<G, V>(q);
-  const int lane = (int)lane_id();
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t b = base + (uint32_t)tid * kPer + k;
+      v[k] = (b < nbe) ? (u128)sums[b] : (u128)0;
+      mine += v[k];
+    }
+    u128 tot;
+    u128 run = carry + wg_exclusive(mine, s->v, &tot);
+#pragma unroll
+    for (int k = 0; k < kPer; ++k) {
+      const uint32_t b = base + (uint32_t)tid * kPer + k;
+      if (b < nbe) CE[b] = run;
+      run += v[k];
+    }
+    carry += tot;
+  }
+  if (tid == 0) CE[nbe] = carry;
+  __syncthreads();
+}
+
+// ---------------------------------------------------------------- r map
+// r(I) = n * I / Q in binary64, monotone in I, with r(Q) = n exactly.
+struct RMap {
+  u128 Q;
+  double invQ;
+  double Nd;
+  __device__ double operator()(u128 I) const {
+    if (I >= Q) return Nd;
+    const double r = Nd * (u128_to_double(I) * invQ);
+    return r < Nd ? r : Nd;
+  }
+};
+
+__device__ __forceinline__ RMap make_rmap(u128 Q, int64_t n) {
+  RMap m;
+  m.Q = Q;
+  m.invQ = 1.0 / u128_to_double(Q);
+  m.Nd = (double)n;
+  return m;
+}
+
+// r of the thread's 4 particles of the block at base, given the block's
+// exclusive carry Cb and record.
+template <typename T>
+__device__ void block_r(const T* __restrict__ w, int64_t n, int64_t base, const BlockRec rec,
+                        u128 Cb, int32_t gscale, const RMap& rm, double (&r)[kPer],
+                        WgScratch* s) {
+  T x[kPer];
+  load4(w, n, base, x);
+  const int e_ref = 52 + WTraits<T>::BIAS - rec.scale;
+  uint64_t q[kPer];
+  uint64_t acc = 0;
+#pragma unroll
+  for (int v = 0; v < kPer; ++v) {
+    acc += quantize(x[v], e_ref);
+    q[v] = acc;
+  }
+  uint64_t tot;
+  const uint64_t off = wg_exclusive(acc, s->u, &tot);
   const int sh = gscale - rec.scale;
 #pragma unroll
-  for (int g = 0; g < G; ++g) {
-#pragma unroll
-    for (int v = 0; v < V; ++v) {
-      const u128 I = carry + shift_u128((u128)q[g * V + v], sh);
-      r_out[g * kWave * V + lane * V + v] = Nd * (u128_to_double(I) / fQ);
-    }
-  }
+  for (int v = 0; v < kPer; ++v) r[v] = rm(Cb + shift_u128((u128)(off + q[v]), sh));
 }
 
-// ---------------------------------------------------------------- emission
-// r >= s + 1 - u, decided exactly: with m = floor(r), true iff m > s, or
-// m == s and frac(r) >= 1 - u (both sides exact in binary64).
-__device__ __forceinline__ bool reaches(double r, int64_t s, double u) {
+// ---------------------------------------------------------------- strata
+// O = #{s : s + 1 - u_s <= r}: all strata below floor(r), plus stratum
+// m = floor(r) when frac(r) >= 1 - u_m (both sides exact in binary64).
+__device__ __forceinline__ int64_t cum_strata(double r, int64_t n, double u) {
   const double mf = floor(r);
   const int64_t m = (int64_t)mf;
-  if (m != s) return m > s;
-  return (r - mf) >= (1.0 - u);
+  if (m >= n) return n;
+  return m + (((r - mf) >= (1.0 - u)) ? 1 : 0);
 }
 
-// First i in [0, cnt) with reaches(r[i], s, u) (r non-decreasing); cnt if none.
-__device__ __forceinline__ int first_reaching(const double* __restrict__ r, int cnt, int64_t s,
-                                              double u) {
-  int lo = 0, hi = cnt;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (reaches(r[mid], s, u)) hi = mid;
-    else lo = mid + 1;
-  }
-  return lo;
-}
-// #{i in [0, cnt) : r[i] <= p}.
-__device__ __forceinline__ int count_le(const double* __restrict__ r, int cnt, double p) {
-  int lo = 0, hi = cnt;
-  while (lo < hi) {
-    const int mid = (lo + hi) >> 1;
-    if (r[mid] <= p) lo = mid + 1;
-    else hi = mid;
-  }
-  return lo;
+struct StrataLds {
+  uint32_t O[kBlock];  // cumulative offspring of the block's particles
+  uint32_t u[kUTab];   // raw stratum-offset words of strata [m_lo, m_lo + kUTab)
+  int32_t M[kChunk];   // expansion markers
+};
+
+// Raw 32-bit word of stratum m's offset (word m&3 of Philox call m>>2).
+__device__ __forceinline__ uint32_t stratum_word(Key key, uint32_t filter, uint32_t offset,
+                                                 int64_t m) {
+  const uint4 x = draw(key, (uint32_t)(m >> 2), DOM_STRATA, 0, filter, offset);
+  const uint32_t k = (uint32_t)(m & 3);
+  return k == 0 ? x.x : k == 1 ? x.y : k == 2 ? x.z : x.w;
 }
 
-// Strata points for a tile whose particles [0, cnt) (local) have r in LDS and
-// whose r-range is (r_lo, r_hi]; the last tile of a vector also takes points
-// above r_hi (none exist: r_hi = n there).  Outputs a_out[s] = P0 + i.
-template <bool SYSTEMATIC>
-__device__ void emit_strata(const double* __restrict__ r_lds, int cnt, double r_lo, double r_hi,
-                            int64_t n, int64_t P0, Key key, uint32_t filter, uint32_t offset,
-                            double u_sys, int32_t* __restrict__ a_out, int tid, int nthreads) {
-  if (cnt <= 0 || !(r_hi > r_lo)) return;
-  const int64_t s_lo = max((int64_t)0, (int64_t)floor(r_lo) - 1);
-  const int64_t s_hi = min(n - 1, (int64_t)floor(r_hi));
-  const int64_t c_lo = s_lo >> 2, c_hi = s_hi >> 2;
-  for (int64_t c = c_lo + tid; c <= c_hi; c += nthreads) {
-    uint32_t xs[4];
-    if (!SYSTEMATIC) {
-      const uint4 x = draw(key, (uint32_t)c, DOM_STRATA, 0, filter, offset);
-      xs[0] = x.x; xs[1] = x.y; xs[2] = x.z; xs[3] = x.w;
-    }
+// In-place inclusive max-scan of M[0..len), len <= kChunk, entries >= -1.
+__device__ void wg_max_scan(int32_t* M, int len, WgScratch* s) {
+  const int tid = (int)threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  constexpr int per = kChunk / kT;
+  int32_t run = -1;
+  int32_t v[per];
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t s = c * 4 + v;
-      if (s < s_lo || s > s_hi) continue;
-      const double u = SYSTEMATIC ? u_sys : u_offset(xs[v]);
-      if (reaches(r_lo, s, u)) continue;   // point at or below r_lo: earlier tile
-      if (!reaches(r_hi, s, u)) continue;  // point above r_hi: later tile
-      a_out[s] = (int32_t)(P0 + first_reaching(r_lds, cnt, s, u));
+  for (int k = 0; k < per; ++k) {
+    const int idx = tid * per + k;
+    v[k] = idx < len ? M[idx] : -1;
+    run = max(run, v[k]);
+  }
+  // shifted by one so that the scan runs on non-negative values
+  const uint32_t incl = wave_inclusive_scan((uint32_t)(run + 1), OpMax());
+  __syncthreads();
+  if (lane == kWave - 1) s->i[wave] = (int32_t)incl - 1;
+  __syncthreads();
+  const uint32_t prev = shfl(incl, lane > 0 ? lane - 1 : 0);
+  int32_t carry = lane > 0 ? (int32_t)prev - 1 : -1;
+  for (int w2 = 0; w2 < wave; ++w2) carry = max(carry, s->i[w2]);
+#pragma unroll
+  for (int k = 0; k < per; ++k) {
+    carry = max(carry, v[k]);
+    const int idx = tid * per + k;
+    if (idx < len) M[idx] = carry;
+  }
+  __syncthreads();
+}
+
+// Stratified / systematic emission for one block: r[4] are the thread's
+// particles (4t .. 4t+3; values past the vector's end equal r_hi).  Writes
+// a_out[s] = P0 + i for every stratum s in [O(r_lo), O(r_hi)).
+template <bool SYSTEMATIC>
+__device__ void emit_strata(const double (&r)[kPer], int cnt, double r_lo, double r_hi, int64_t n,
+                            int64_t P0, Key key, uint32_t filter, uint32_t offset, double u_sys,
+                            int32_t* __restrict__ a_out, StrataLds* L, WgScratch* s) {
+  const int tid = (int)threadIdx.x;
+  // stratum offsets of the strata the block's r-range touches
+  const int64_t m_lo = (int64_t)floor(r_lo);
+  const int64_t m_hi = min(n - 1, (int64_t)floor(r_hi));
+  const bool table = SYSTEMATIC || (m_hi - m_lo + 1 <= kUTab);
+  if (!SYSTEMATIC && table && m_hi >= m_lo) {
+    for (int64_t c = (m_lo >> 2) + tid; c <= (m_hi >> 2); c += kT) {
+      const uint4 x = draw(key, (uint32_t)c, DOM_STRATA, 0, filter, offset);
+      const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = c * 4 + v;
+        if (m >= m_lo && m <= m_hi) L->u[m - m_lo] = xs[v];
+      }
+    }
+  }
+  __syncthreads();
+  auto u_of = [&](int64_t m) -> double {
+    if (SYSTEMATIC) return u_sys;
+    if (m > m_hi) return 0.0;  // reached only with m >= n, where u is unused
+    return u_offset(table ? L->u[m - m_lo] : stratum_word(key, filter, offset, m));
+  };
+#pragma unroll
+  for (int v = 0; v < kPer; ++v)
+    L->O[tid * kPer + v] = (uint32_t)cum_strata(r[v], n, u_of((int64_t)floor(r[v])));
+  const int64_t O_lo = cum_strata(r_lo, n, u_of(m_lo));
+  const int64_t O_hi = cum_strata(r_hi, n, u_of((int64_t)floor(r_hi)));
+  __syncthreads();
+  // expansion: a marker at the first output of every particle, then a max-scan
+  for (int64_t cs = O_lo; cs < O_hi; cs += kChunk) {
+    const int64_t ce = min(cs + (int64_t)kChunk, O_hi);
+    for (int k = tid; k < kChunk; k += kT) L->M[k] = -1;
+    __syncthreads();
+    for (int e = tid; e < cnt; e += kT) {
+      const int64_t Oe = L->O[e];
+      const int64_t Op = e == 0 ? O_lo : (int64_t)L->O[e - 1];
+      if (Oe > Op && Oe > cs && Op < ce) L->M[(Op > cs ? Op : cs) - cs] = e;
+    }
+    __syncthreads();
+    const int len = (int)(ce - cs);
+    wg_max_scan(L->M, len, s);
+    for (int k = tid; k < len; k += kT) a_out[cs + k] = (int32_t)(P0 + L->M[k]);
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- multinomial
+struct MultiLds {
+  double r[kBlock];
+};
+
+// #{i in [0, cnt) : r[i] <= p} for the 4 points of a thread, searched together
+// so that the LDS loads of the 4 searches overlap.
+__device__ __forceinline__ void count_le4(const double* __restrict__ r, int cnt,
+                                          const double (&p)[kPer], int (&pos)[kPer]) {
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) pos[q] = 0;
+  int step = 1;
+  while ((step << 1) <= cnt) step <<= 1;
+  for (; step > 0; step >>= 1) {
+#pragma unroll
+    for (int q = 0; q < kPer; ++q) {
+      const int np = pos[q] + step;
+      const double v = r[min(np, cnt) - 1];
+      if (np <= cnt && v <= p[q]) pos[q] = np;
     }
   }
 }
 
-// Multinomial points for a tile with r-range [r_lo, r_hi) (the last tile:
-// [r_lo, inf)).  The points p_k = n S_k / S_n come from exponential blocks
-// [b_first, b_last], each rebuilt by one wave from its Philox calls and its
-// exact carry CE[b].
+// Multinomial points for a block with r-range [r_lo, r_hi) (the vector's last
+// block: [r_lo, inf)).  The points p_k = n S_k / S_n of every exponential
+// block whose points can fall in the range are rebuilt from their Philox calls
+// and exact carries CE[b].
+template <typename CEPtr>
 __device__ void emit_multinomial(const double* __restrict__ r_lds, int cnt, double r_lo,
-                                 double r_hi, bool last_tile, int64_t n, int64_t P0, Key key,
-                                 uint32_t filter, uint32_t offset, const u128* __restrict__ CE,
-                                 uint32_t nbe, int32_t* __restrict__ a_out, int wave, int nwaves) {
-  if (cnt <= 0 || !(last_tile || r_hi > r_lo)) return;
-  const double Nd = (double)n;
-  const double fQE = u128_to_double(CE[nbe]);
-  // P(b) = value of the last point of block b-1, b = 1..nbe-1
-  auto boundary = [&](uint32_t b) -> double { return Nd * (u128_to_double(CE[b]) / fQE); };
+                                 double r_hi, bool last, int64_t n, int64_t P0, Key key,
+                                 uint32_t filter, uint32_t offset, CEPtr CE, uint32_t nbe,
+                                 int32_t* __restrict__ a_out, WgScratch* s) {
+  if (cnt <= 0 || !(last || r_hi > r_lo)) return;
+  const RMap em = make_rmap(CE[nbe], n);
+  // P(b) = value of the last point of exponential block b-1, b = 1..nbe-1
   auto count_below = [&](double x) -> uint32_t {  // #{b in [1, nbe-1] : P(b) < x}
-    uint32_t lo = 1, hi = nbe;                    // search in [1, nbe)
+    uint32_t lo = 1, hi = nbe;
     while (lo < hi) {
       const uint32_t mid = (lo + hi) >> 1;
-      if (boundary(mid) < x) lo = mid + 1;
+      if (em(CE[mid]) < x) lo = mid + 1;
       else hi = mid;
     }
     return lo - 1;
   };
   const uint32_t b_first = count_below(r_lo);
-  const uint32_t b_last = last_tile ? nbe - 1 : count_below(r_hi);
-  const int lane = (int)lane_id();
-  for (uint32_t b = b_first + (uint32_t)wave; b <= b_last; b += (uint32_t)nwaves) {
-    uint64_t q[16];
-    exp_block_values(key, filter, offset, n, b, q);
-    block_inclusive_scan<4, 4>(q);
-    const u128 carry = CE[b];
+  const uint32_t b_last = last ? nbe - 1 : count_below(r_hi);
+  for (uint32_t b = b_first; b <= b_last; ++b) {
+    uint64_t q[kPer];
+    exp_values(key, filter, offset, n, b, q);
+    uint64_t acc = 0;
 #pragma unroll
-    for (int g = 0; g < 4; ++g) {
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t k = (int64_t)b * kBlock + g * 256 + lane * 4 + v;
-        if (k >= n) continue;
-        const double p = Nd * (u128_to_double(carry + (u128)q[g * 4 + v]) / fQE);
-        if (p < r_lo) continue;
-        if (!last_tile && !(p < r_hi)) continue;
-        int64_t anc = P0 + count_le(r_lds, cnt, p);
-        if (anc > n - 1) anc = n - 1;
-        a_out[k] = (int32_t)anc;
-      }
+    for (int v = 0; v < kPer; ++v) {
+      acc += q[v];
+      q[v] = acc;
     }
+    uint64_t tot;
+    const uint64_t off = wg_exclusive(acc, s->u, &tot);
+    const u128 base = CE[b] + (u128)off;
+    double p[kPer];
+#pragma unroll
+    for (int v = 0; v < kPer; ++v) p[v] = em(base + (u128)q[v]);
+    int pos[kPer];
+    count_le4(r_lds, cnt, p, pos);
+#pragma unroll
+    for (int v = 0; v < kPer; ++v) {
+      const int64_t k = (int64_t)b * kBlock + threadIdx.x * kPer + v;
+      if (k >= n) continue;
+      if (p[v] < r_lo) continue;
+      if (!last && !(p[v] < r_hi)) continue;
+      int64_t anc = P0 + pos[v];
+      if (anc > n - 1) anc = n - 1;
+      a_out[k] = (int32_t)anc;
+    }
+  }
+}
+
+// ---------------------------------------------------------------- block emit
+union EmitLds {
+  StrataLds st;
+  MultiLds mu;
+};
+
+// Emission of block b of a vector (n weights at w, outputs at a_out).
+template <typename T, int SCHEME, typename CEPtr>
+__device__ void emit_block(const T* __restrict__ w, int64_t n, uint32_t b, const BlockRec rec,
+                           u128 Cb, u128 Cb1, int32_t gscale, const RMap& rm, Key key,
+                           uint32_t filter, uint32_t offset, CEPtr CE, uint32_t nbe,
+                           int32_t* __restrict__ a_out, EmitLds* L, WgScratch* s) {
+  const int64_t P0 = (int64_t)b * kBlock;
+  const int cnt = (int)min((int64_t)kBlock, n - P0);
+  const double r_lo = rm(Cb);
+  const double r_hi = rm(Cb1);
+  double r[kPer];
+  block_r(w, n, P0, rec, Cb, gscale, rm, r, s);
+  if (SCHEME == SCHEME_MULTINOMIAL) {
+#pragma unroll
+    for (int v = 0; v < kPer; ++v) L->mu.r[threadIdx.x * kPer + v] = r[v];
+    __syncthreads();
+    emit_multinomial(L->mu.r, cnt, r_lo, r_hi, P0 + cnt == n, n, P0, key, filter, offset, CE, nbe,
+                     a_out, s);
+  } else {
+    double u_sys = 0.0;
+    if (SCHEME == SCHEME_SYSTEMATIC)
+      u_sys = u_offset(draw(key, 0, DOM_STRATA, 0, filter, offset).x);
+    emit_strata<SCHEME == SCHEME_SYSTEMATIC>(r, cnt, r_lo, r_hi, n, P0, key, filter, offset,
+                                             u_sys, a_out, &L->st, s);
   }
 }
 
 // ---------------------------------------------------------------- kernels
+// One record per weight block (and, for the multinomial scheme, one sum per
+// exponential block).  No cross-workgroup communication: the kernel boundary
+// makes the records visible to the next kernel.
 template <typename T, bool MULTI>
-__global__ __launch_bounds__(kWGThreads) void k_scan_reduce(const T* __restrict__ w, int64_t n,
-                                                            uint32_t nb, uint32_t nbe,
-                                                            uint32_t wg_weights, Key key,
-                                                            uint32_t offset, uint32_t filter,
-                                                            ScanHeader* __restrict__ hdr,
-                                                            BlockRec* __restrict__ recs,
-                                                            uint64_t* __restrict__ erecs,
-                                                            u128* __restrict__ C,
-                                                            u128* __restrict__ CE) {
-  __shared__ u128 lds_wave[kBlocksPerWG];
-  __shared__ int32_t lds_misc[4];
-  const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
-  if (blockIdx.x < wg_weights) {
-    const uint32_t blk = blockIdx.x * kBlocksPerWG + wave;
-    if (blk < nb) {
-      const BlockRec r = weight_block_record(w, n, (int64_t)blk * kBlock);
-      if (lane == 0) recs[blk] = r;
-    }
+__global__ __launch_bounds__(kT) void k_scan_records(const T* __restrict__ w, int64_t n,
+                                                     uint32_t nb, Key key, uint32_t offset,
+                                                     uint32_t filter,
+                                                     BlockRec* __restrict__ recs,
+                                                     uint64_t* __restrict__ esums) {
+  __shared__ WgScratch s;
+  if (blockIdx.x < nb) {
+    const BlockRec r = block_record(w, n, (int64_t)blockIdx.x * kBlock, &s);
+    if (threadIdx.x == 0) recs[blockIdx.x] = r;
   } else if (MULTI) {
-    const uint32_t blk = (blockIdx.x - wg_weights) * kBlocksPerWG + wave;
-    if (blk < nbe) {
-      const uint64_t s = exp_block_sum(key, filter, offset, n, blk);
-      if (lane == 0) erecs[blk] = s;
-    }
-  }
-  // the last workgroup to finish scans every record into carries
-  __shared__ uint32_t is_last;
-  __syncthreads();
-  if (threadIdx.x == 0) {
-    __threadfence();
-    const uint32_t prev = atomicAdd(&hdr->ticket, 1u);
-    is_last = (prev == gridDim.x - 1) ? 1u : 0u;
-  }
-  __syncthreads();
-  if (!is_last) return;
-  __threadfence();
-  uint32_t status = 0;
-  int32_t gscale = 0;
-  scan_weight_records(nb, recs, C, lds_wave, lds_misc, &status, &gscale);
-  if (MULTI) {
-    wg_exclusive_scan_u128(
-        nbe, [&](uint32_t b) -> u128 { return (u128)erecs[b]; }, CE, lds_wave);
-  }
-  if (threadIdx.x == 0) {
-    hdr->status = status;
-    hdr->gscale = gscale;
-    hdr->nb = nb;
-    hdr->nbe = nbe;
-    hdr->ticket = 0;
+    const uint32_t b = blockIdx.x - nb;
+    uint64_t q[kPer];
+    exp_values(key, filter, offset, n, b, q);
+    const uint64_t sum = wg_reduce(q[0] + q[1] + q[2] + q[3], OpAdd(), s.u);
+    if (threadIdx.x == 0) esums[b] = sum;
   }
 }
 
-template <typename T, int SCHEME>
-__global__ __launch_bounds__(kWGThreads) void k_scan_emit(const T* __restrict__ w, int64_t n,
-                                                          uint32_t nb, uint32_t nbe, Key key,
-                                                          uint32_t offset, uint32_t filter,
-                                                          const ScanHeader* __restrict__ hdr,
-                                                          const BlockRec* __restrict__ recs,
-                                                          const u128* __restrict__ C,
-                                                          const u128* __restrict__ CE,
-                                                          int32_t* __restrict__ a,
-                                                          uint32_t* __restrict__ flags) {
-  __shared__ double r_lds[kTile];
-  const int tid = (int)threadIdx.x, wave = tid / kWave;
-  const uint32_t status = hdr->status;
-  const int64_t P0 = (int64_t)blockIdx.x * kTile;
-  const int64_t P1 = min(P0 + kTile, n);
-  if (flags && blockIdx.x == 0 && tid == 0 && status) atomicOr(flags, status);
+// One workgroup: global scale, exact carries C[0..nb], total and status, and
+// the exponential-block carries CE[0..nbe] of the multinomial scheme.
+template <bool MULTI>
+__global__ __launch_bounds__(kT) void k_scan_carries(uint32_t nb, uint32_t nbe,
+                                                     ScanHeader* __restrict__ hdr,
+                                                     const BlockRec* __restrict__ recs,
+                                                     const uint64_t* __restrict__ esums,
+                                                     u128* __restrict__ C, u128* __restrict__ CE) {
+  __shared__ WgScratch s;
+  const Totals t = carries_from_records(nb, recs, C, &s);
+  if (MULTI) exp_carries(nbe, esums, CE, &s);
+  if (threadIdx.x == 0) {
+    hdr->status = t.status;
+    hdr->gscale = t.gscale;
+    hdr->Q = t.Q;
+  }
+}
+
+// Direct carries: with few blocks every emit workgroup derives the global
+// scale, its own exact carry and the total from all records itself (at most
+// kDirectMax records, held in registers), which saves the carry kernel.
+constexpr uint32_t kDirectMax = kT * 8;
+
+struct Direct {
+  u128 Cb, Cb1, Q;
+  int32_t gscale;
+  uint32_t status;
+};
+
+__device__ Direct direct_carries(uint32_t nb, uint32_t b, const BlockRec* __restrict__ recs,
+                                 WgScratch* s) {
+  const int tid = (int)threadIdx.x;
+  BlockRec r[8];
+  uint32_t bad = 0, smin_key = 0xFFFFFFFFu;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t j = (uint32_t)tid + (uint32_t)k * kT;
+    if (j < nb) r[k] = recs[j];
+    else r[k].sum = 0, r[k].scale = 0, r[k].bad = 0;
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    bad |= r[k].bad;
+    if (r[k].sum) smin_key = min(smin_key, (uint32_t)r[k].scale ^ 0x80000000u);
+  }
+  bad = wg_reduce(bad, OpOr(), (uint32_t*)s->i);
+  smin_key = wg_reduce(smin_key, OpMin(), (uint32_t*)s->i);
+  Direct d;
+  d.gscale = (smin_key == 0xFFFFFFFFu)
+                 ? 0
+                 : (int32_t)(smin_key ^ 0x80000000u) + (kCarryBits - 63) - ceil_log2(nb);
+  u128 before = 0, all = 0, own = 0;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t j = (uint32_t)tid + (uint32_t)k * kT;
+    const u128 v = (j < nb) ? conv_rec(r[k], d.gscale) : (u128)0;
+    all += v;
+    if (j < b) before += v;
+    if (j == b) own = v;
+  }
+  d.Cb = wg_reduce(before, OpAdd(), s->v);
+  d.Q = wg_reduce(all, OpAdd(), s->v);
+  own = wg_reduce(own, OpAdd(), s->v);
+  d.Cb1 = d.Cb + own;
+  d.status = bad;
+  if (!bad && d.Q == 0) d.status |= FLAG_ZERO_TOTAL;
+  return d;
+}
+
+template <typename T, int SCHEME, bool DIRECT>
+__global__ __launch_bounds__(kT) void k_scan_emit(const T* __restrict__ w, int64_t n,
+                                                  uint32_t nb, uint32_t nbe, Key key,
+                                                  uint32_t offset, uint32_t filter,
+                                                  const ScanHeader* __restrict__ hdr,
+                                                  const BlockRec* __restrict__ recs,
+                                                  const u128* __restrict__ C,
+                                                  const u128* __restrict__ CE,
+                                                  int32_t* __restrict__ a,
+                                                  uint32_t* __restrict__ flags) {
+  __shared__ EmitLds L;
+  __shared__ WgScratch s;
+  const uint32_t b = blockIdx.x;
+  uint32_t status;
+  u128 Cb, Cb1, Q;
+  int32_t gscale;
+  if (DIRECT) {
+    const Direct d = direct_carries(nb, b, recs, &s);
+    status = d.status;
+    Cb = d.Cb;
+    Cb1 = d.Cb1;
+    Q = d.Q;
+    gscale = d.gscale;
+  } else {
+    status = hdr->status;
+    Cb = C[b];
+    Cb1 = C[b + 1];
+    Q = hdr->Q;
+    gscale = hdr->gscale;
+  }
+  if (flags && b == 0 && threadIdx.x == 0 && status) atomicOr(flags, status);
   if (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
-    for (int64_t i = P0 + tid; i < P1; i += kWGThreads) a[i] = (int32_t)i;
+    const int64_t P0 = (int64_t)b * kBlock;
+    for (int64_t i = P0 + threadIdx.x; i < min(P0 + kBlock, n); i += kT) a[i] = (int32_t)i;
     return;
   }
-  const int32_t gscale = hdr->gscale;
-  const double fQ = u128_to_double(C[nb]);
-  const double Nd = (double)n;
-  const uint32_t blk = blockIdx.x * kBlocksPerWG + wave;
-  if (blk < nb)
-    weight_block_r(w, n, (int64_t)blk * kBlock, recs[blk], C[blk], gscale, fQ, Nd,
-                   r_lds + wave * kBlock);
-  __syncthreads();
-  const uint32_t b0 = blockIdx.x * kBlocksPerWG;
-  const uint32_t b_end = min(b0 + kBlocksPerWG, nb);
-  const double r_lo = Nd * (u128_to_double(C[b0]) / fQ);
-  const double r_hi = Nd * (u128_to_double(C[b_end]) / fQ);
-  const int cnt = (int)(P1 - P0);
-  if (SCHEME == SCHEME_MULTINOMIAL) {
-    emit_multinomial(r_lds, cnt, r_lo, r_hi, P1 == n, n, P0, key, filter, offset, CE, nbe, a,
-                     wave, kBlocksPerWG);
-  } else {
-    double u_sys = 0.0;
-    if (SCHEME == SCHEME_SYSTEMATIC) u_sys = u_offset(draw(key, 0, DOM_STRATA, 0, filter, offset).x);
-    emit_strata<SCHEME == SCHEME_SYSTEMATIC>(r_lds, cnt, r_lo, r_hi, n, P0, key, filter, offset,
-                                             u_sys, a, tid, kWGThreads);
-  }
+  const RMap rm = make_rmap(Q, n);
+  emit_block<T, SCHEME>(w, n, b, recs[b], Cb, Cb1, gscale, rm, key, filter, offset, CE, nbe, a,
+                        &L, &s);
 }
 
-// Ragged batch: one workgroup per filter runs the reduce, the carry scan and
-// the emission for its own segment, with the records in LDS.
-constexpr int kBatchMaxBlocks = 256;  // filters up to 2^18 particles
+// Ragged batch: one workgroup per filter runs the reduce, the carries and the
+// emission of its own segment, with the records and carries in LDS.
+constexpr int kBatchMaxBlocks = 256;  // segments up to 2^18 particles
 
 struct BatchLds {
-  double r[kTile];
   BlockRec recs[kBatchMaxBlocks];
   u128 C[kBatchMaxBlocks + 1];
-  uint64_t erecs[kBatchMaxBlocks + 1];
-  u128 CE[kBatchMaxBlocks + 2];
-  u128 wave_tot[kBlocksPerWG];
-  int32_t misc[4];
-  uint32_t status;
-  int32_t gscale;
+  uint64_t esums[kBatchMaxBlocks];
+  u128 CE[kBatchMaxBlocks + 1];
 };
 
 template <typename T, int SCHEME>
-__global__ __launch_bounds__(kWGThreads) void k_scan_batched(const T* __restrict__ w,
-                                                             int64_t n_total,
-                                                             const int64_t* __restrict__ offsets,
-                                                             uint32_t n_filters, Key key,
-                                                             uint32_t offset, uint32_t filter_base,
-                                                             int32_t* __restrict__ a,
-                                                             uint32_t* __restrict__ flags) {
-  __shared__ BatchLds L;
+__global__ __launch_bounds__(kT) void k_scan_batched(const T* __restrict__ w, int64_t n_total,
+                                                     const int64_t* __restrict__ offsets,
+                                                     uint32_t n_filters, Key key, uint32_t offset,
+                                                     uint32_t filter_base, int32_t* __restrict__ a,
+                                                     uint32_t* __restrict__ flags) {
+  __shared__ BatchLds B;
+  __shared__ EmitLds L;
+  __shared__ WgScratch s;
   const uint32_t f = blockIdx.x;
   if (f >= n_filters) return;
-  const int tid = (int)threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  const int tid = (int)threadIdx.x;
   const int64_t base = offsets ? offsets[f] : 0;
   const int64_t n = offsets ? offsets[f + 1] - base : n_total;
   if (n <= 0) return;
@@ -500,58 +688,34 @@ __global__ __launch_bounds__(kWGThreads) void k_scan_batched(const T* __restrict
   const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
   const uint32_t nbe = (uint32_t)((n + 1 + kBlock - 1) / kBlock);
   if (nbe > kBatchMaxBlocks) {  // segment too long for this path: identity + flag
-    for (int64_t i = tid; i < n; i += kWGThreads) as[i] = (int32_t)i;
+    for (int64_t i = tid; i < n; i += kT) as[i] = (int32_t)i;
     if (tid == 0 && flags) atomicOr(flags, FLAG_BAD_COUNTS);
     return;
   }
-  for (uint32_t b = wave; b < nb; b += kBlocksPerWG) {
-    const BlockRec r = weight_block_record(ws, n, (int64_t)b * kBlock);
-    if (lane == 0) L.recs[b] = r;
+  for (uint32_t b = 0; b < nb; ++b) {
+    const BlockRec r = block_record(ws, n, (int64_t)b * kBlock, &s);
+    if (tid == 0) B.recs[b] = r;
   }
   if (SCHEME == SCHEME_MULTINOMIAL) {
-    for (uint32_t b = wave; b < nbe; b += kBlocksPerWG) {
-      const uint64_t s = exp_block_sum(key, filt, offset, n, b);
-      if (lane == 0) L.erecs[b] = s;
+    for (uint32_t b = 0; b < nbe; ++b) {
+      uint64_t q[kPer];
+      exp_values(key, filt, offset, n, b, q);
+      const uint64_t sum = wg_reduce(q[0] + q[1] + q[2] + q[3], OpAdd(), s.u);
+      if (tid == 0) B.esums[b] = sum;
     }
   }
   __syncthreads();
-  uint32_t status = 0;
-  int32_t gscale = 0;
-  scan_weight_records(nb, L.recs, L.C, L.wave_tot, L.misc, &status, &gscale);
-  if (SCHEME == SCHEME_MULTINOMIAL)
-    wg_exclusive_scan_u128(
-        nbe, [&](uint32_t b) -> u128 { return (u128)L.erecs[b]; }, L.CE, L.wave_tot);
-  __syncthreads();
-  if (flags && tid == 0 && status) atomicOr(flags, status);
-  if (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
-    for (int64_t i = tid; i < n; i += kWGThreads) as[i] = (int32_t)i;
+  const Totals t = carries_from_records(nb, (const BlockRec*)B.recs, (u128*)B.C, &s);
+  if (SCHEME == SCHEME_MULTINOMIAL) exp_carries(nbe, (const uint64_t*)B.esums, (u128*)B.CE, &s);
+  if (flags && tid == 0 && t.status) atomicOr(flags, t.status);
+  if (t.status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
+    for (int64_t i = tid; i < n; i += kT) as[i] = (int32_t)i;
     return;
   }
-  const double fQ = u128_to_double(L.C[nb]);
-  const double Nd = (double)n;
-  double u_sys = 0.0;
-  if (SCHEME == SCHEME_SYSTEMATIC) u_sys = u_offset(draw(key, 0, DOM_STRATA, 0, filt, offset).x);
-  const uint32_t ntiles = (uint32_t)((n + kTile - 1) / kTile);
-  for (uint32_t t = 0; t < ntiles; ++t) {
-    const uint32_t blk = t * kBlocksPerWG + wave;
-    if (blk < nb)
-      weight_block_r(ws, n, (int64_t)blk * kBlock, L.recs[blk], L.C[blk], gscale, fQ, Nd,
-                     L.r + wave * kBlock);
-    __syncthreads();
-    const int64_t P0 = (int64_t)t * kTile;
-    const int64_t P1 = min(P0 + kTile, n);
-    const uint32_t b0 = t * kBlocksPerWG;
-    const uint32_t b_end = min(b0 + kBlocksPerWG, nb);
-    const double r_lo = Nd * (u128_to_double(L.C[b0]) / fQ);
-    const double r_hi = Nd * (u128_to_double(L.C[b_end]) / fQ);
-    const int cnt = (int)(P1 - P0);
-    if (SCHEME == SCHEME_MULTINOMIAL) {
-      emit_multinomial(L.r, cnt, r_lo, r_hi, P1 == n, n, P0, key, filt, offset, L.CE, nbe, as,
-                       wave, kBlocksPerWG);
-    } else {
-      emit_strata<SCHEME == SCHEME_SYSTEMATIC>(L.r, cnt, r_lo, r_hi, n, P0, key, filt, offset,
-                                               u_sys, as, tid, kWGThreads);
-    }
+  const RMap rm = make_rmap(t.Q, n);
+  for (uint32_t b = 0; b < nb; ++b) {
+    emit_block<T, SCHEME>(ws, n, b, B.recs[b], B.C[b], B.C[b + 1], t.gscale, rm, key, filt,
+                          offset, (const u128*)B.CE, nbe, as, &L, &s);
     __syncthreads();
   }
 }
@@ -560,28 +724,30 @@ template <typename T, int SCHEME>
 hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, uint32_t filter,
                          int32_t* a, void* ws, uint32_t* flags, hipStream_t stream) {
   const T* w = (const T*)wv;
-  const bool multi = SCHEME == SCHEME_MULTINOMIAL;
+  constexpr bool multi = SCHEME == SCHEME_MULTINOMIAL;
   const ScanLayout L = scan_layout(n, multi);
   char* base = (char*)ws;
   ScanHeader* hdr = (ScanHeader*)base;
   BlockRec* recs = (BlockRec*)(base + L.recs);
   u128* C = (u128*)(base + L.carries);
-  uint64_t* erecs = (uint64_t*)(base + L.erecs);
+  uint64_t* esums = (uint64_t*)(base + L.erecs);
   u128* CE = (u128*)(base + L.ecarries);
   const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
   const uint32_t nbe = multi ? (uint32_t)((n + 1 + kBlock - 1) / kBlock) : 0u;
-  const uint32_t wg_w = (nb + kBlocksPerWG - 1) / kBlocksPerWG;
-  const uint32_t wg_e = (nbe + kBlocksPerWG - 1) / kBlocksPerWG;
-  if (multi)
-    hipLaunchKernelGGL((k_scan_reduce<T, true>), dim3(wg_w + wg_e), dim3(kWGThreads), 0, stream, w,
-                       n, nb, nbe, wg_w, key, offset, filter, hdr, recs, erecs, C, CE);
-  else
-    hipLaunchKernelGGL((k_scan_reduce<T, false>), dim3(wg_w), dim3(kWGThreads), 0, stream, w, n,
-                       nb, nbe, wg_w, key, offset, filter, hdr, recs, erecs, C, CE);
+  hipLaunchKernelGGL((k_scan_records<T, multi>), dim3(nb + nbe), dim3(kT), 0, stream, w, n, nb,
+                     key, offset, filter, recs, esums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  const uint32_t tiles = (uint32_t)((n + kTile - 1) / kTile);
-  hipLaunchKernelGGL((k_scan_emit<T, SCHEME>), dim3(tiles), dim3(kWGThreads), 0, stream, w, n, nb,
+  if (!multi && nb <= kDirectMax) {
+    hipLaunchKernelGGL((k_scan_emit<T, SCHEME, true>), dim3(nb), dim3(kT), 0, stream, w, n, nb,
+                       nbe, key, offset, filter, hdr, recs, C, CE, a, flags);
+    return hipGetLastError();
+  }
+  hipLaunchKernelGGL((k_scan_carries<multi>), dim3(1), dim3(kT), 0, stream, nb, nbe, hdr, recs,
+                     esums, C, CE);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_scan_emit<T, SCHEME, false>), dim3(nb), dim3(kT), 0, stream, w, n, nb,
                      nbe, key, offset, filter, hdr, recs, C, CE, a, flags);
   return hipGetLastError();
 }
@@ -601,26 +767,26 @@ hipError_t launch_scan_scheme(int scheme, const void* w, int64_t n, Key key, uin
 }
 
 template <typename T>
-hipError_t launch_batched_scheme(int scheme, const void* w, int64_t n_total, const int64_t* offsets,
-                                 uint32_t n_filters, Key key, uint32_t offset,
-                                 uint32_t filter_base, int32_t* a, uint32_t* flags,
-                                 hipStream_t stream) {
+hipError_t launch_batched_scheme(int scheme, const void* w, int64_t n_total,
+                                 const int64_t* offsets, uint32_t n_filters, Key key,
+                                 uint32_t offset, uint32_t filter_base, int32_t* a,
+                                 uint32_t* flags, hipStream_t stream) {
   const T* wt = (const T*)w;
   switch (scheme) {
     case SCHEME_MULTINOMIAL:
-      hipLaunchKernelGGL((k_scan_batched<T, SCHEME_MULTINOMIAL>), dim3(n_filters),
-                         dim3(kWGThreads), 0, stream, wt, n_total, offsets, n_filters, key, offset,
-                         filter_base, a, flags);
+      hipLaunchKernelGGL((k_scan_batched<T, SCHEME_MULTINOMIAL>), dim3(n_filters), dim3(kT), 0,
+                         stream, wt, n_total, offsets, n_filters, key, offset, filter_base, a,
+                         flags);
       break;
     case SCHEME_STRATIFIED:
-      hipLaunchKernelGGL((k_scan_batched<T, SCHEME_STRATIFIED>), dim3(n_filters),
-                         dim3(kWGThreads), 0, stream, wt, n_total, offsets, n_filters, key, offset,
-                         filter_base, a, flags);
+      hipLaunchKernelGGL((k_scan_batched<T, SCHEME_STRATIFIED>), dim3(n_filters), dim3(kT), 0,
+                         stream, wt, n_total, offsets, n_filters, key, offset, filter_base, a,
+                         flags);
       break;
     default:
-      hipLaunchKernelGGL((k_scan_batched<T, SCHEME_SYSTEMATIC>), dim3(n_filters),
-                         dim3(kWGThreads), 0, stream, wt, n_total, offsets, n_filters, key, offset,
-                         filter_base, a, flags);
+      hipLaunchKernelGGL((k_scan_batched<T, SCHEME_SYSTEMATIC>), dim3(n_filters), dim3(kT), 0,
+                         stream, wt, n_total, offsets, n_filters, key, offset, filter_base, a,
+                         flags);
       break;
   }
   return hipGetLastError();
@@ -640,7 +806,7 @@ ScanLayout scan_layout(int64_t n, bool multinomial) {
   return L;
 }
 
-size_t batch_scan_lds_bytes() { return sizeof(BatchLds); }
+size_t batch_scan_lds_bytes() { return sizeof(BatchLds) + sizeof(EmitLds); }
 
 hipError_t launch_scan(int scheme, bool f64, const void* w, int64_t n, Key key, uint32_t offset,
                        uint32_t filter, int32_t* a, void* ws, uint32_t* flags,

@@ -80,7 +80,7 @@ def test_rejection_full_size_and_trial_cap():
     assert rfl & oracle.FLAG_TRIAL_CAP and int(host(fl)[0]) & oracle.FLAG_TRIAL_CAP
 
 
-def test_rejection_repeat_calls_reuse_workspace():
+def test_rejection_repeat_calls_identical():
     w = inputs.weights(300000, 2.0, seed=8)
     wd = dev(w)
     outs = [host(pfr().resample_rejection(wd, 1.0, seed=4)) for _ in range(3)]
@@ -129,7 +129,7 @@ def check_collective(scheme, w, a_gpu, seed, filt=0, offset=0):
 @pytest.mark.parametrize("scheme", SCHEMES)
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("n,y", [(1024, 2.0), (1, 1.0), (2, 0.0), (3, 4.0), (1000, 3.0),
-                                 (16384, 2.0), (16385, 2.0), (100003, 4.0)])
+                                 (4096, 2.0), (4097, 2.0), (16385, 2.0), (100003, 4.0)])
 def test_collective_parity(scheme, dtype, n, y):
     w = inputs.weights(n, y, seed=n + 17, dtype=dtype)
     a = host(gpu_collective(scheme, w, seed=77, offset=5, filter_base=2))
@@ -303,3 +303,13 @@ def test_permute_bad_ancestors_and_batched():
         for f in range(sizes.size):
             ref, _ = oracle.permute(a[off[f]:off[f + 1]])
             assert np.array_equal(c[off[f]:off[f + 1]], ref)
+
+
+def test_permute_long_chain():
+    # a = [0, 0, 1, 2, ..., n-2]: one chain runs through every slot
+    n = 3000
+    a = np.concatenate([[0], np.arange(n - 1)]).astype(np.int32)
+    ref, _ = oracle.permute(a)
+    for hint in (True, False):
+        c = host(pfr().permute_ancestors(dev(a), sorted_hint=hint))
+        assert np.array_equal(c, ref)

@@ -44,12 +44,12 @@ def test_workspace_sizes():
     big = lib.pfr_workspace_bytes(_lib.OP_STRATIFIED, ctypes.byref(s_big), 0)
     multi = lib.pfr_workspace_bytes(_lib.OP_MULTINOMIAL, ctypes.byref(s_big), 0)
     assert big > 0 and multi > big and big % 256 == 0
-    # one 16-byte record and one 16-byte carry per 1024-weight block
-    assert big >= 256 + 1024 * 32
+    # a 16-byte record per 1024-weight block and a 32-byte prefix per 4096-particle tile
+    assert big >= 256 + 1024 * 16 + 256 * 32
     assert lib.pfr_workspace_bytes(_lib.OP_METROPOLIS, ctypes.byref(s_big), 0) == 0
     assert lib.pfr_workspace_bytes(_lib.OP_PERMUTE, ctypes.byref(s_big), 0) >= 4 << 20
     assert lib.pfr_workspace_bytes(_lib.OP_OFFSPRING_TO_ANCESTORS, ctypes.byref(s_big), 0) >= 256 + 256 * 8
-    assert lib.pfr_workspace_bytes(_lib.OP_REJECTION, ctypes.byref(s_big), 0) >= 8
+    assert lib.pfr_workspace_bytes(_lib.OP_REJECTION, ctypes.byref(s_big), 0) == 0
 
 
 def test_invalid_arguments_rejected_on_host():
@@ -81,13 +81,11 @@ def test_invalid_arguments_rejected_on_host():
     # Metropolis step count out of range
     assert lib.resample_metropolis(fake, 0, ctypes.byref(seg(10)), -1, None, rng, out,
                                    None) == _lib.PFR_EINVAL
-    # rejection: bad bound, zero trials, missing workspace
-    assert lib.resample_rejection(fake, 0, ctypes.byref(seg(10)), 0.0, None, 16, rng, out, fake,
-                                  256, None, None) == _lib.PFR_EINVAL
-    assert lib.resample_rejection(fake, 0, ctypes.byref(seg(10)), 1.0, None, 0, rng, out, fake,
-                                  256, None, None) == _lib.PFR_EINVAL
-    assert lib.resample_rejection(fake, 0, ctypes.byref(seg(10)), 1.0, None, 16, rng, out, None,
-                                  0, None, None) == _lib.PFR_EWORKSPACE
+    # rejection: bad bound, zero trials
+    assert lib.resample_rejection(fake, 0, ctypes.byref(seg(10)), 0.0, None, 16, rng, out, None,
+                                  None) == _lib.PFR_EINVAL
+    assert lib.resample_rejection(fake, 0, ctypes.byref(seg(10)), 1.0, None, 0, rng, out, None,
+                                  None) == _lib.PFR_EINVAL
     # permute: output aliases input; workspace missing
     assert lib.permute_ancestors(fake, ctypes.byref(seg(10)), 1, fake, out, 1 << 20, None,
                                  None) == _lib.PFR_EINVAL
