@@ -158,8 +158,10 @@ PFR_API int resample_systematic(const void* w, pfr_dtype dtype, const pfr_segmen
                         int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
                         void* stream);
 
-/* Metropolis resampling (Code 2): lane i starts at k = i and runs B steps;
- * step s draws Philox call (i, 2<<28 | s), j = floor(((x1<<32)|x0) n / 2^64),
+/* Metropolis resampling (Code 2): lane i starts at k = i and runs B steps.
+ * Lane i's words come from Philox calls (i, 2<<28 | c), word m being word
+ * m&3 of call m>>2; step s takes words x0, x1, x2 = 3s, 3s+1, 3s+2 (four steps
+ * per three calls), proposes j = floor(((x1<<32)|x0) n / 2^64) with
  * u = (x2 + 1) 2^-32, and moves to j when u w_k <= w_j (decided exactly).
  * B_dev (device int32[n_filters], may be NULL) overrides B per segment.
  * No workspace; no collective operation. */

@@ -90,11 +90,43 @@ int orc_accept(double u, double w_k, double w_j)
     return lhs <= (q128)w_j;
 }
 
+/* The 32-bit words of lane i's stream in a domain: word k is word k & 3 of   */
+/* the call with step k >> 2.  A one-call cache keeps the oracle from calling  */
+/* Philox again for the next word of the same block.                          */
+typedef struct {
+    uint64_t seed;
+    uint32_t index, domain, filter, offset;
+    int64_t call;
+    uint32_t x[4];
+} word_stream;
+
+static void ws_init(word_stream* s, uint64_t seed, uint32_t index, uint32_t domain,
+                    uint32_t filter, uint32_t offset)
+{
+    s->seed = seed;
+    s->index = index;
+    s->domain = domain;
+    s->filter = filter;
+    s->offset = offset;
+    s->call = -1;
+}
+
+static uint32_t ws_word(word_stream* s, int64_t k)
+{
+    if ((k >> 2) != s->call) {
+        s->call = k >> 2;
+        draw(s->seed, s->index, s->domain, (uint32_t)s->call, s->filter, s->offset, s->x);
+    }
+    return s->x[k & 3];
+}
+
 /* ------------------------------------------------------------------------ */
 /* Code 2: Metropolis-Ancestors.  Each lane i runs an independent Metropolis */
 /* chain started at k = i for B steps; step n proposes j uniformly and moves */
 /* when u <= w_j / w_k (read as u w_k <= w_j, so a chain sitting on a zero   */
-/* weight always moves).  Random numbers: call (i, trial domain, step n).    */
+/* weight always moves).  Random numbers: step n takes words 3n, 3n+1 (for  */
+/* j) and 3n+2 (for u) of lane i's stream in the trial domain, so four steps */
+/* use three Philox calls.                                                   */
 /* ------------------------------------------------------------------------ */
 int orc_resample_metropolis(const double* w, int64_t n, int32_t B, uint64_t seed,
                             uint32_t filter, uint32_t offset, int32_t* a)
@@ -104,13 +136,14 @@ int orc_resample_metropolis(const double* w, int64_t n, int32_t B, uint64_t seed
     for (i = 0; i < n; ++i) {
         int64_t k = i;
         int32_t step;
+        word_stream s;
+        ws_init(&s, seed, (uint32_t)i, ORC_DOM_TRIAL, filter, offset);
         for (step = 0; step < B; ++step) {
-            uint32_t x[4];
-            int64_t j;
-            double u;
-            draw(seed, (uint32_t)i, ORC_DOM_TRIAL, (uint32_t)step, filter, offset, x);
-            j = orc_index(x[0], x[1], n);
-            u = orc_u_accept(x[2]);
+            const int64_t w0 = 3 * (int64_t)step;
+            const uint32_t x0 = ws_word(&s, w0), x1 = ws_word(&s, w0 + 1);
+            const uint32_t x2 = ws_word(&s, w0 + 2);
+            const int64_t j = orc_index(x0, x1, n);
+            const double u = orc_u_accept(x2);
             if (orc_accept(u, w[k], w[j])) k = j;
         }
         a[i] = (int32_t)k;

@@ -54,33 +54,35 @@ __global__ __launch_bounds__(256) void k_metropolis(const T* __restrict__ w, int
     const T* __restrict__ ws = w + c.base;
     uint32_t k = i;
     double wk = (double)ws[i];
-    int32_t s = 0;
-    for (; s + 4 <= steps; s += 4) {
-      uint4 x[4];
+    // steps 4m .. 4m+3 take the 12 words of calls 3m .. 3m+2
+    for (int32_t m = 0; 4 * m < steps; ++m) {
+      uint32_t x[12];
+      const int32_t left = steps - 4 * m;
+      const int ncall = left >= 4 ? 3 : (3 * left + 3) / 4;
+#pragma unroll
+      for (int c3 = 0; c3 < 3; ++c3) {
+        if (c3 < ncall) {
+          const uint4 v = draw(key, i, DOM_TRIAL, (uint32_t)(3 * m + c3), filt, offset);
+          x[4 * c3 + 0] = v.x;
+          x[4 * c3 + 1] = v.y;
+          x[4 * c3 + 2] = v.z;
+          x[4 * c3 + 3] = v.w;
+        }
+      }
+      const int nq = left >= 4 ? 4 : left;
       uint32_t j[4];
       double wj[4];
 #pragma unroll
       for (int q = 0; q < 4; ++q) {
-        x[q] = draw(key, i, DOM_TRIAL, (uint32_t)(s + q), filt, offset);
-        j[q] = index_draw(x[q].x, x[q].y, c.n);
+        j[q] = q < nq ? index_draw(x[3 * q], x[3 * q + 1], c.n) : i;
+        wj[q] = (double)ws[j[q]];
       }
 #pragma unroll
-      for (int q = 0; q < 4; ++q) wj[q] = (double)ws[j[q]];
-#pragma unroll
       for (int q = 0; q < 4; ++q) {
-        if (accept_exact(u_accept(x[q].z), wk, wj[q])) {
+        if (q < nq && accept_exact(u_accept(x[3 * q + 2]), wk, wj[q])) {
           k = j[q];
           wk = wj[q];
         }
-      }
-    }
-    for (; s < steps; ++s) {
-      const uint4 x = draw(key, i, DOM_TRIAL, (uint32_t)s, filt, offset);
-      const uint32_t j = index_draw(x.x, x.y, c.n);
-      const double wj = (double)ws[j];
-      if (accept_exact(u_accept(x.z), wk, wj)) {
-        k = j;
-        wk = wj;
       }
     }
     a[g] = (int32_t)k;

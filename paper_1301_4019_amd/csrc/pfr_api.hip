@@ -64,7 +64,7 @@ int collective(int scheme, const void* w, pfr_dtype dtype, const pfr_segments* s
   int rc = check_segments(seg, &s);
   if (rc) return rc;
   if (dtype != PFR_F32 && dtype != PFR_F64) return PFR_EINVAL;
-  if (precision != PFR_SCAN_EXACT) return PFR_ENOTSUP;
+  if (precision < PFR_SCAN_EXACT || precision > PFR_SCAN_NAIVE_F32) return PFR_EINVAL;
   if (s.n_total == 0) return PFR_OK;
   if (!w || !a) return PFR_EINVAL;
   if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), a, (size_t)s.n_total * 4))
@@ -73,6 +73,10 @@ int collective(int scheme, const void* w, pfr_dtype dtype, const pfr_segments* s
   const Key key = make_key(rng.seed);
   if (!uses_scan_workspace(s)) {
     if (s.n_filters > 1 && s.max_len > PFR_MAX_BATCH_SEGMENT) return PFR_ENOTSUP;
+    if (precision != PFR_SCAN_EXACT)
+      return launch_result(launch_fscan_batched(scheme, (int)precision, dtype == PFR_F64, w,
+                                                s.n_total, s.offsets, s.n_filters, key,
+                                                rng.offset, rng.filter_base, a, dev_flags, st));
     return launch_result(launch_scan_batched(scheme, dtype == PFR_F64, w, s.n_total, s.offsets,
                                              s.n_filters, key, rng.offset, rng.filter_base, a,
                                              dev_flags, st));
@@ -80,6 +84,10 @@ int collective(int scheme, const void* w, pfr_dtype dtype, const pfr_segments* s
   const ScanLayout L = scan_layout(s.n_total, scheme == SCHEME_MULTINOMIAL);
   if (!ws || ws_bytes < L.total) return PFR_EWORKSPACE;
   if (!aligned256(ws)) return PFR_EWORKSPACE;
+  if (overlaps(ws, L.total, a, (size_t)s.n_total * 4)) return PFR_EINVAL;
+  if (precision != PFR_SCAN_EXACT)
+    return launch_result(launch_fscan(scheme, (int)precision, dtype == PFR_F64, w, s.n_total, key,
+                                      rng.offset, rng.filter_base, a, ws, dev_flags, st));
   return launch_result(launch_scan(scheme, dtype == PFR_F64, w, s.n_total, key, rng.offset,
                                    rng.filter_base, a, ws, dev_flags, st));
 }

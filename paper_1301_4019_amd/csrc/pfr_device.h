@@ -36,6 +36,12 @@ struct Key {
 // and mixes their high halves with words 1 and 3 and the round key; the key
 // advances by two Weyl increments per round.  The key is uniform across the
 // wave in every kernel, so its schedule stays in scalar registers.
+// a ^ b ^ k in one VALU instruction (gfx950 three-input bit operation, truth
+// table 0x96 = xor of the three inputs).
+__device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k) {
+  return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
+}
+
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         Key key) {
   uint32_t k0 = key.k0, k1 = key.k1;
@@ -44,9 +50,9 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
     // one v_mad_u64_u32 per product (instead of separate mul_hi / mul_lo)
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
-    c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    c0 = xor3_key((uint32_t)(p1 >> 32), c1, k0);
     c1 = (uint32_t)p1;
-    c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c2 = xor3_key((uint32_t)(p0 >> 32), c3, k1);
     c3 = (uint32_t)p0;
     k0 += 0x9E3779B9u;
     k1 += 0xBB67AE85u;

@@ -34,7 +34,10 @@ struct ScanHeader {
   uint32_t pad0;
   uint64_t epoch;    // unused (kept zero)
   uint64_t pad1;
-  u128 Q;            // exact total at the global scale
+  union {
+    u128 Q;          // exact total at the global scale
+    double W;        // floating-point total (precision modes other than exact)
+  };
   uint32_t pad[52];  // header padded to 256 bytes
 };
 static_assert(sizeof(ScanHeader) == 256, "scan header is 256 bytes");
@@ -52,6 +55,16 @@ hipError_t launch_scan_batched(int scheme, bool f64, const void* w, int64_t n_to
                                const int64_t* offsets, uint32_t n_filters, Key key,
                                uint32_t offset, uint32_t filter_base, int32_t* a, uint32_t* flags,
                                hipStream_t stream);
+
+// Floating-point prefix modes (pfr_precision values 1..3).
+enum Prec : int { PREC_F64 = 1, PREC_COMP_F32 = 2, PREC_NAIVE_F32 = 3 };
+hipError_t launch_fscan(int scheme, int prec, bool f64, const void* w, int64_t n, Key key,
+                        uint32_t offset, uint32_t filter, int32_t* a, void* ws, uint32_t* flags,
+                        hipStream_t stream);
+hipError_t launch_fscan_batched(int scheme, int prec, bool f64, const void* w, int64_t n_total,
+                                const int64_t* offsets, uint32_t n_filters, Key key,
+                                uint32_t offset, uint32_t filter_base, int32_t* a,
+                                uint32_t* flags, hipStream_t stream);
 
 hipError_t launch_metropolis(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
                              uint32_t n_filters, int32_t B, const int32_t* B_dev, Key key,

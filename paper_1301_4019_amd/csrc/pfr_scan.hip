@@ -44,78 +44,8 @@
 namespace pfr {
 
 namespace {
+#include "pfr_scan_common.h"
 
-constexpr int kT = kWGThreads;   // threads per workgroup
-constexpr int kPer = kBlock / kT;  // consecutive values per thread (4)
-constexpr int kNW = kT / kWave;    // waves per workgroup
-constexpr int kCarryBits = 100;    // carries stay below 2^100
-constexpr int kChunk = 2048;       // output positions per LDS marker pass
-constexpr int kUTab = 2048;        // stratum offsets cached per block
-
-size_t align256(size_t x) { return (x + 255) & ~(size_t)255; }
-
-// ---------------------------------------------------------------- workgroup
-struct WgScratch {
-  u128 v[kNW];
-  uint64_t u[kNW];
-  int32_t i[2 * kNW];
-};
-
-template <typename U, typename Op>
-__device__ U wg_reduce(U x, Op op, U* slot) {
-  const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
-  x = wave_reduce(x, op);
-  __syncthreads();
-  if (lane == 0) slot[wave] = x;
-  __syncthreads();
-  U t = slot[0];
-#pragma unroll
-  for (int w2 = 1; w2 < kNW; ++w2) t = op(t, slot[w2]);
-  __syncthreads();
-  return t;
-}
-
-// Exclusive prefix (across the workgroup, in thread order) of x; *total gets
-// the workgroup sum.
-template <typename U>
-__device__ U wg_exclusive(U x, U* slot, U* total) {
-  const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
-  const U incl = wave_inclusive_scan(x, OpAdd());
-  __syncthreads();
-  if (lane == kWave - 1) slot[wave] = incl;
-  __syncthreads();
-  U run = incl - x, tot = 0;
-#pragma unroll
-  for (int w2 = 0; w2 < kNW; ++w2) {
-    if (w2 < wave) run += slot[w2];
-    tot += slot[w2];
-  }
-  __syncthreads();
-  *total = tot;
-  return run;
-}
-
-// ---------------------------------------------------------------- block loads
-// Thread t holds elements 4t .. 4t+3 of the block.
-template <typename T>
-__device__ __forceinline__ void load4(const T* __restrict__ w, int64_t n, int64_t base,
-                                      T (&x)[kPer]) {
-  const int64_t idx = base + (int64_t)threadIdx.x * kPer;
-  const bool aligned = ((reinterpret_cast<uintptr_t>(w + idx) & 15u) == 0);
-  if (aligned && idx + kPer <= n) {
-    if constexpr (sizeof(T) == 4) {
-      const float4 t = *reinterpret_cast<const float4*>(w + idx);
-      x[0] = t.x; x[1] = t.y; x[2] = t.z; x[3] = t.w;
-    } else {
-      const double2 t0 = *reinterpret_cast<const double2*>(w + idx);
-      const double2 t1 = *reinterpret_cast<const double2*>(w + idx + 2);
-      x[0] = t0.x; x[1] = t0.y; x[2] = t1.x; x[3] = t1.y;
-    }
-  } else {
-#pragma unroll
-    for (int v = 0; v < kPer; ++v) x[v] = (idx + v < n) ? w[idx + v] : (T)0;
-  }
-}
 
 // ---------------------------------------------------------------- records
 // Record of the block at base: validity, reference exponent (block maximum),
@@ -147,25 +77,6 @@ __device__ BlockRec block_record(const T* __restrict__ w, int64_t n, int64_t bas
   return r;
 }
 
-// Exponential spacing E_k = -log((x + 1/2) 2^-32), k = 0..n: word k&3 of
-// Philox call k>>2 (exponential domain), quantised to floor(E 2^48).  Thread t
-// of block b holds k = 1024 b + 4t + v, all four from call 256 b + t.
-__device__ __forceinline__ void exp_values(Key key, uint32_t filter, uint32_t offset, int64_t n,
-                                           uint32_t blk, uint64_t (&q)[kPer]) {
-  const uint32_t call = blk * (uint32_t)kT + threadIdx.x;
-  const uint4 x = draw(key, call, DOM_EXP, 0, filter, offset);
-  const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-  for (int v = 0; v < kPer; ++v) {
-    const int64_t k = (int64_t)call * 4 + v;
-    const double e = -log(((double)xs[v] + 0.5) * 0x1p-32);
-    q[v] = (k <= n) ? (uint64_t)(e * 0x1p48) : 0ull;
-  }
-}
-
-__device__ __forceinline__ int ceil_log2(uint32_t x) {
-  return x <= 1 ? 0 : 32 - __clz(x - 1);
-}
 
 __device__ __forceinline__ u128 conv_rec(const BlockRec& r, int32_t gscale) {
   return shift_u128((u128)r.sum, gscale - r.scale);
@@ -236,55 +147,6 @@ __device__ Totals carries_from_records(uint32_t nb, RecPtr recs, CPtr C, WgScrat
   return t;
 }
 
-// Exclusive scan of the exponential block sums into CE[0..nbe].
-template <typename SumPtr, typename CPtr>
-__device__ void exp_carries(uint32_t nbe, SumPtr sums, CPtr CE, WgScratch* s) {
-  const int tid = (int)threadIdx.x;
-  u128 carry = 0;
-  for (uint32_t base = 0; base < nbe; base += kBlock) {
-    u128 v[kPer];
-    u128 mine = 0;
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const uint32_t b = base + (uint32_t)tid * kPer + k;
-      v[k] = (b < nbe) ? (u128)sums[b] : (u128)0;
-      mine += v[k];
-    }
-    u128 tot;
-    u128 run = carry + wg_exclusive(mine, s->v, &tot);
-#pragma unroll
-    for (int k = 0; k < kPer; ++k) {
-      const uint32_t b = base + (uint32_t)tid * kPer + k;
-      if (b < nbe) CE[b] = run;
-      run += v[k];
-    }
-    carry += tot;
-  }
-  if (tid == 0) CE[nbe] = carry;
-  __syncthreads();
-}
-
-// ---------------------------------------------------------------- r map
-// r(I) = n * I / Q in binary64, monotone in I, with r(Q) = n exactly.
-struct RMap {
-  u128 Q;
-  double invQ;
-  double Nd;
-  __device__ double operator()(u128 I) const {
-    if (I >= Q) return Nd;
-    const double r = Nd * (u128_to_double(I) * invQ);
-    return r < Nd ? r : Nd;
-  }
-};
-
-__device__ __forceinline__ RMap make_rmap(u128 Q, int64_t n) {
-  RMap m;
-  m.Q = Q;
-  m.invQ = 1.0 / u128_to_double(Q);
-  m.Nd = (double)n;
-  return m;
-}
-
 // r of the thread's 4 particles of the block at base, given the block's
 // exclusive carry Cb and record.
 template <typename T>
@@ -308,194 +170,6 @@ __device__ void block_r(const T* __restrict__ w, int64_t n, int64_t base, const 
   for (int v = 0; v < kPer; ++v) r[v] = rm(Cb + shift_u128((u128)(off + q[v]), sh));
 }
 
-// ---------------------------------------------------------------- strata
-// O = #{s : s + 1 - u_s <= r}: all strata below floor(r), plus stratum
-// m = floor(r) when frac(r) >= 1 - u_m (both sides exact in binary64).
-__device__ __forceinline__ int64_t cum_strata(double r, int64_t n, double u) {
-  const double mf = floor(r);
-  const int64_t m = (int64_t)mf;
-  if (m >= n) return n;
-  return m + (((r - mf) >= (1.0 - u)) ? 1 : 0);
-}
-
-struct StrataLds {
-  uint32_t O[kBlock];  // cumulative offspring of the block's particles
-  uint32_t u[kUTab];   // raw stratum-offset words of strata [m_lo, m_lo + kUTab)
-  int32_t M[kChunk];   // expansion markers
-};
-
-// Raw 32-bit word of stratum m's offset (word m&3 of Philox call m>>2).
-__device__ __forceinline__ uint32_t stratum_word(Key key, uint32_t filter, uint32_t offset,
-                                                 int64_t m) {
-  const uint4 x = draw(key, (uint32_t)(m >> 2), DOM_STRATA, 0, filter, offset);
-  const uint32_t k = (uint32_t)(m & 3);
-  return k == 0 ? x.x : k == 1 ? x.y : k == 2 ? x.z : x.w;
-}
-
-// In-place inclusive max-scan of M[0..len), len <= kChunk, entries >= -1.
-__device__ void wg_max_scan(int32_t* M, int len, WgScratch* s) {
-  const int tid = (int)threadIdx.x, wave = tid / kWave, lane = tid % kWave;
-  constexpr int per = kChunk / kT;
-  int32_t run = -1;
-  int32_t v[per];
-#pragma unroll
-  for (int k = 0; k < per; ++k) {
-    const int idx = tid * per + k;
-    v[k] = idx < len ? M[idx] : -1;
-    run = max(run, v[k]);
-  }
-  // shifted by one so that the scan runs on non-negative values
-  const uint32_t incl = wave_inclusive_scan((uint32_t)(run + 1), OpMax());
-  __syncthreads();
-  if (lane == kWave - 1) s->i[wave] = (int32_t)incl - 1;
-  __syncthreads();
-  const uint32_t prev = shfl(incl, lane > 0 ? lane - 1 : 0);
-  int32_t carry = lane > 0 ? (int32_t)prev - 1 : -1;
-  for (int w2 = 0; w2 < wave; ++w2) carry = max(carry, s->i[w2]);
-#pragma unroll
-  for (int k = 0; k < per; ++k) {
-    carry = max(carry, v[k]);
-    const int idx = tid * per + k;
-    if (idx < len) M[idx] = carry;
-  }
-  __syncthreads();
-}
-
-// Stratified / systematic emission for one block: r[4] are the thread's
-// particles (4t .. 4t+3; values past the vector's end equal r_hi).  Writes
-// a_out[s] = P0 + i for every stratum s in [O(r_lo), O(r_hi)).
-template <bool SYSTEMATIC>
-__device__ void emit_strata(const double (&r)[kPer], int cnt, double r_lo, double r_hi, int64_t n,
-                            int64_t P0, Key key, uint32_t filter, uint32_t offset, double u_sys,
-                            int32_t* __restrict__ a_out, StrataLds* L, WgScratch* s) {
-  const int tid = (int)threadIdx.x;
-  // stratum offsets of the strata the block's r-range touches
-  const int64_t m_lo = (int64_t)floor(r_lo);
-  const int64_t m_hi = min(n - 1, (int64_t)floor(r_hi));
-  const bool table = SYSTEMATIC || (m_hi - m_lo + 1 <= kUTab);
-  if (!SYSTEMATIC && table && m_hi >= m_lo) {
-    for (int64_t c = (m_lo >> 2) + tid; c <= (m_hi >> 2); c += kT) {
-      const uint4 x = draw(key, (uint32_t)c, DOM_STRATA, 0, filter, offset);
-      const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
-#pragma unroll
-      for (int v = 0; v < 4; ++v) {
-        const int64_t m = c * 4 + v;
-        if (m >= m_lo && m <= m_hi) L->u[m - m_lo] = xs[v];
-      }
-    }
-  }
-  __syncthreads();
-  auto u_of = [&](int64_t m) -> double {
-    if (SYSTEMATIC) return u_sys;
-    if (m > m_hi) return 0.0;  // reached only with m >= n, where u is unused
-    return u_offset(table ? L->u[m - m_lo] : stratum_word(key, filter, offset, m));
-  };
-#pragma unroll
-  for (int v = 0; v < kPer; ++v)
-    L->O[tid * kPer + v] = (uint32_t)cum_strata(r[v], n, u_of((int64_t)floor(r[v])));
-  const int64_t O_lo = cum_strata(r_lo, n, u_of(m_lo));
-  const int64_t O_hi = cum_strata(r_hi, n, u_of((int64_t)floor(r_hi)));
-  __syncthreads();
-  // expansion: a marker at the first output of every particle, then a max-scan
-  for (int64_t cs = O_lo; cs < O_hi; cs += kChunk) {
-    const int64_t ce = min(cs + (int64_t)kChunk, O_hi);
-    for (int k = tid; k < kChunk; k += kT) L->M[k] = -1;
-    __syncthreads();
-    for (int e = tid; e < cnt; e += kT) {
-      const int64_t Oe = L->O[e];
-      const int64_t Op = e == 0 ? O_lo : (int64_t)L->O[e - 1];
-      if (Oe > Op && Oe > cs && Op < ce) L->M[(Op > cs ? Op : cs) - cs] = e;
-    }
-    __syncthreads();
-    const int len = (int)(ce - cs);
-    wg_max_scan(L->M, len, s);
-    for (int k = tid; k < len; k += kT) a_out[cs + k] = (int32_t)(P0 + L->M[k]);
-    __syncthreads();
-  }
-}
-
-// ---------------------------------------------------------------- multinomial
-struct MultiLds {
-  double r[kBlock];
-};
-
-// #{i in [0, cnt) : r[i] <= p} for the 4 points of a thread, searched together
-// so that the LDS loads of the 4 searches overlap.
-__device__ __forceinline__ void count_le4(const double* __restrict__ r, int cnt,
-                                          const double (&p)[kPer], int (&pos)[kPer]) {
-#pragma unroll
-  for (int q = 0; q < kPer; ++q) pos[q] = 0;
-  int step = 1;
-  while ((step << 1) <= cnt) step <<= 1;
-  for (; step > 0; step >>= 1) {
-#pragma unroll
-    for (int q = 0; q < kPer; ++q) {
-      const int np = pos[q] + step;
-      const double v = r[min(np, cnt) - 1];
-      if (np <= cnt && v <= p[q]) pos[q] = np;
-    }
-  }
-}
-
-// Multinomial points for a block with r-range [r_lo, r_hi) (the vector's last
-// block: [r_lo, inf)).  The points p_k = n S_k / S_n of every exponential
-// block whose points can fall in the range are rebuilt from their Philox calls
-// and exact carries CE[b].
-template <typename CEPtr>
-__device__ void emit_multinomial(const double* __restrict__ r_lds, int cnt, double r_lo,
-                                 double r_hi, bool last, int64_t n, int64_t P0, Key key,
-                                 uint32_t filter, uint32_t offset, CEPtr CE, uint32_t nbe,
-                                 int32_t* __restrict__ a_out, WgScratch* s) {
-  if (cnt <= 0 || !(last || r_hi > r_lo)) return;
-  const RMap em = make_rmap(CE[nbe], n);
-  // P(b) = value of the last point of exponential block b-1, b = 1..nbe-1
-  auto count_below = [&](double x) -> uint32_t {  // #{b in [1, nbe-1] : P(b) < x}
-    uint32_t lo = 1, hi = nbe;
-    while (lo < hi) {
-      const uint32_t mid = (lo + hi) >> 1;
-      if (em(CE[mid]) < x) lo = mid + 1;
-      else hi = mid;
-    }
-    return lo - 1;
-  };
-  const uint32_t b_first = count_below(r_lo);
-  const uint32_t b_last = last ? nbe - 1 : count_below(r_hi);
-  for (uint32_t b = b_first; b <= b_last; ++b) {
-    uint64_t q[kPer];
-    exp_values(key, filter, offset, n, b, q);
-    uint64_t acc = 0;
-#pragma unroll
-    for (int v = 0; v < kPer; ++v) {
-      acc += q[v];
-      q[v] = acc;
-    }
-    uint64_t tot;
-    const uint64_t off = wg_exclusive(acc, s->u, &tot);
-    const u128 base = CE[b] + (u128)off;
-    double p[kPer];
-#pragma unroll
-    for (int v = 0; v < kPer; ++v) p[v] = em(base + (u128)q[v]);
-    int pos[kPer];
-    count_le4(r_lds, cnt, p, pos);
-#pragma unroll
-    for (int v = 0; v < kPer; ++v) {
-      const int64_t k = (int64_t)b * kBlock + threadIdx.x * kPer + v;
-      if (k >= n) continue;
-      if (p[v] < r_lo) continue;
-      if (!last && !(p[v] < r_hi)) continue;
-      int64_t anc = P0 + pos[v];
-      if (anc > n - 1) anc = n - 1;
-      a_out[k] = (int32_t)anc;
-    }
-  }
-}
-
-// ---------------------------------------------------------------- block emit
-union EmitLds {
-  StrataLds st;
-  MultiLds mu;
-};
-
 // Emission of block b of a vector (n weights at w, outputs at a_out).
 template <typename T, int SCHEME, typename CEPtr>
 __device__ void emit_block(const T* __restrict__ w, int64_t n, uint32_t b, const BlockRec rec,
@@ -515,11 +189,10 @@ __device__ void emit_block(const T* __restrict__ w, int64_t n, uint32_t b, const
     emit_multinomial(L->mu.r, cnt, r_lo, r_hi, P0 + cnt == n, n, P0, key, filter, offset, CE, nbe,
                      a_out, s);
   } else {
-    double u_sys = 0.0;
-    if (SCHEME == SCHEME_SYSTEMATIC)
-      u_sys = u_offset(draw(key, 0, DOM_STRATA, 0, filter, offset).x);
-    emit_strata<SCHEME == SCHEME_SYSTEMATIC>(r, cnt, r_lo, r_hi, n, P0, key, filter, offset,
-                                             u_sys, a_out, &L->st, s);
+    const uint32_t u_sys =
+        SCHEME == SCHEME_SYSTEMATIC ? draw(key, 0, DOM_STRATA, 0, filter, offset).x : 0u;
+    emit_strata<SCHEME == SCHEME_SYSTEMATIC, false>(r, cnt, r_lo, r_hi, n, P0, key, filter,
+                                                    offset, u_sys, a_out, &L->st, s);
   }
 }
 

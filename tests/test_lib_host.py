@@ -94,6 +94,8 @@ def test_invalid_arguments_rejected_on_host():
     # empty input is a no-op
     assert lib.resample_stratified(None, 0, ctypes.byref(seg(0)), 0, rng, None, None, 0, None,
                                    None) == _lib.PFR_OK
-    # precision modes other than the exact one are not built yet
-    assert lib.resample_stratified(fake, 0, ctypes.byref(seg(10)), 3, rng, out, None, 0, None,
-                                   None) == _lib.PFR_ENOTSUP
+    # unknown precision mode
+    assert lib.resample_stratified(fake, 0, ctypes.byref(seg(10)), 4, rng, out, None, 0, None,
+                                   None) == _lib.PFR_EINVAL
+    assert lib.resample_stratified(fake, 0, ctypes.byref(seg(10)), -1, rng, out, None, 0, None,
+                                   None) == _lib.PFR_EINVAL

@@ -44,3 +44,22 @@ def strata_points(u):
     u = np.asarray(u, dtype=np.float64)
     s = np.arange(u.size, dtype=np.float64)
     return (s + 1.0) - u
+
+
+def float_r_error_bound(n, mode):
+    """Bound on |r_gpu - r_exact| for the floating-point prefix modes.
+
+    Every prefix value passes through at most k = 42 + n / 2^20 roundings (3
+    in a thread's serial sum, 9 in the workgroup scan tree, 3 across waves and
+    within the carries, one per chunk of 2^20 weights in the carry chain, ...),
+    so |W_i' - W_i| <= k eps W and r = n W_i / W is off by at most
+    n (2k + 6) eps, the 6 covering the reciprocal, the two products, the
+    binary32 rounding of float64 weights and, for NAIVE_F32, the binary32 sum
+    r + u and the 24-bit offsets.  eps is the unit roundoff of one addition:
+    2^-53 (F64), 4 * 2^-48 for a double-float addition of non-negative pairs
+    (COMP_F32, Joldes, Muller & Popescu 2017), 2^-24 (NAIVE_F32).  Clamping and
+    the max-scan only replace a value by a neighbour within the same bound.
+    """
+    k = 42.0 + n / float(1 << 20)
+    eps = {"f64": 2.0**-53, "comp_f32": 4.0 * 2.0**-48, "naive_f32": 2.0**-24}[mode]
+    return n * (2.0 * k + 6.0) * eps + 8.0 * n * 2.0**-53
