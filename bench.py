@@ -71,6 +71,72 @@ def cpu_baseline(n_sample: int):
                       f"{n_sample} instead of 2^20; {dt:.1f} s on one host core"}
 
 
+def precision_sweep(args):
+    """Bias of the collective resamplers per prefix-sum precision mode.
+
+    For each n, one weight vector (y = 3, data seed 0) is resampled K times
+    (Philox seeds 1..K) by every collective scheme in every precision mode,
+    with Metropolis (B = 60) and rejection (w_max = 1) as controls.  Offspring
+    are counted on the GPU and accumulated in binary64.  Reported, as in the
+    paper's section 3: ||Bias||^2 = sum_i (mean o_i - n w_i / W)^2, the MSE,
+    their ratio (about 1 / (K + 1) for an unbiased scheme) and MSE / n, plus
+    the noise-corrected excess ||Bias||^2 - tr(Var) / K.
+    """
+    import torch
+    import paper_1301_4019_amd as pfr
+    from paper_1301_4019_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    K = args.replicates
+    y = 3.0
+    modes = {"exact": pfr.SCAN_EXACT, "f64": pfr.SCAN_F64, "comp_f32": pfr.SCAN_COMP_F32,
+             "naive_f32": pfr.SCAN_NAIVE_F32}
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    rows = []
+    t_start = time.perf_counter()
+    for lg in args.sweep_log2n:
+        n = 1 << lg
+        w = torch.from_numpy(inputs.weights(n, y, seed=0)).to(dev)
+        wd = w.double()
+        e = n * wd / wd.sum()
+        a = torch.empty(n, dtype=torch.int32, device=dev)
+        cases = [(s, m) for s in ("multinomial", "stratified", "systematic") for m in modes]
+        cases += [("metropolis", "-"), ("rejection", "-")]
+        for scheme, mode in cases:
+            S1 = torch.zeros(n, dtype=torch.float64, device=dev)
+            S2 = torch.zeros(n, dtype=torch.float64, device=dev)
+            for k in range(K):
+                if scheme == "metropolis":
+                    pfr.resample_metropolis(w, 60, seed=1 + k, out=a)
+                elif scheme == "rejection":
+                    pfr.resample_rejection(w, 1.0, seed=1 + k, out=a, flags=flags)
+                else:
+                    getattr(pfr, "resample_" + scheme)(w, seed=1 + k, precision=modes[mode],
+                                                      out=a, flags=flags)
+                o = torch.bincount(a, minlength=n).double()
+                S1 += o
+                S2 += o * o
+            mean = S1 / K
+            bias2 = float(((mean - e) ** 2).sum())
+            mse = float((S2 / K - 2.0 * e * mean + e * e).sum())
+            var_tr = float(((S2 - K * mean * mean) / (K - 1)).sum())
+            rows.append({"n": n, "scheme": scheme, "precision": mode, "bias2": bias2, "mse": mse,
+                         "bias2_over_mse": bias2 / mse, "mse_over_n": mse / n,
+                         "bias2_excess": bias2 - var_tr / K})
+        log(f"n = 2^{lg} done ({time.perf_counter() - t_start:.0f} s)")
+    if int(flags.cpu()[0]) != 0:
+        raise RuntimeError(f"data flags raised during the sweep: {int(flags.cpu()[0])}")
+    result = {"metric": "bias contribution to the MSE per prefix-sum precision",
+              "unit": "ratio", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+              "config": {"workload": "precision sweep: y = 3 weights (data seed 0), "
+                                     f"{K} Philox seeds per case, n = 2^" +
+                                     ",".join(str(v) for v in args.sweep_log2n),
+                         "replicates": K, "y": y, "unbiased_ratio": 1.0 / (K + 1)},
+              "rows": rows}
+    print(json.dumps(result), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -78,11 +144,19 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 18)
+    ap.add_argument("--workload", choices=("step", "precision"), default="step",
+                    help="step: the timed resampling step (default); precision: the bias "
+                         "sweep over prefix-sum precision modes")
+    ap.add_argument("--replicates", type=int, default=256)
+    ap.add_argument("--sweep-log2n", type=int, nargs="+", default=[16, 18, 20, 22, 24])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the resampling step here runs on a single MI355X "
               "and has no multi-GPU path; run with --gpus 1", file=sys.stderr)
         sys.exit(2)
+    if args.workload == "precision":
+        precision_sweep(args)
+        return
 
     import torch
     import paper_1301_4019_amd as pfr
