@@ -137,6 +137,154 @@ def precision_sweep(args):
     print(json.dumps(result), flush=True)
 
 
+def _time_ms(fn, reps, torch):
+    """Mean milliseconds per call of fn over reps calls (wall clock, synchronised)."""
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return 1e3 * (time.perf_counter() - t0) / reps
+
+
+def batch_workload(args):
+    """Ragged batch: 4096 weight vectors, N_f log-uniform in [2^8, 2^16], y_f ~ U[0,4],
+    float32.  Every resampler runs once over the whole batch (one launch), the
+    collective ones with exact and with compensated binary32 prefix sums;
+    Metropolis takes B_f from the bias bound for y_f, rejection w_max = 1.  The
+    per-filter form runs the systematic resampler filter by filter on float64
+    weights with binary64 prefix sums (4096 calls), eagerly and replayed from a
+    captured graph."""
+    import torch
+    import paper_1301_4019_amd as pfr
+    from paper_1301_4019_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    F = args.filters
+    w_np, off_np, ys = inputs.ragged_batch(n_filters=F, seed=0)
+    total = int(off_np[-1])
+    sizes = np.diff(off_np)
+    max_len = int(sizes.max())
+    w = torch.from_numpy(w_np).to(dev)
+    w64 = w.double()
+    offsets = torch.from_numpy(off_np).to(dev)
+    B = torch.tensor([b_star(float(y)) for y in ys], dtype=torch.int32, device=dev)
+    a = torch.empty(total, dtype=torch.int32, device=dev)
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    log(f"batch: {F} filters, {total} particles, max N_f {max_len}")
+
+    def run(scheme, precision=pfr.SCAN_EXACT):
+        if scheme == "metropolis":
+            return lambda: pfr.resample_metropolis(w, 0, seed=1, B_per_filter=B, offsets=offsets,
+                                                   max_len=max_len, out=a)
+        if scheme == "rejection":
+            return lambda: pfr.resample_rejection(w, 1.0, seed=1, offsets=offsets,
+                                                  max_len=max_len, out=a, flags=flags)
+        fn = getattr(pfr, "resample_" + scheme)
+        return lambda: fn(w, seed=1, precision=precision, offsets=offsets, max_len=max_len,
+                          out=a, flags=flags)
+
+    rows = []
+    cases = [(s, "exact") for s in ("multinomial", "stratified", "systematic")]
+    cases += [(s, "comp_f32") for s in ("multinomial", "stratified", "systematic")]
+    cases += [("metropolis", "-"), ("rejection", "-")]
+    prec = {"exact": pfr.SCAN_EXACT, "comp_f32": pfr.SCAN_COMP_F32, "-": pfr.SCAN_EXACT}
+    for scheme, mode in cases:
+        fn = run(scheme, prec[mode])
+        fn()
+        ms = _time_ms(fn, args.steps, torch)
+        rows.append({"scheme": scheme, "precision": mode, "form": "batched, one launch",
+                     "ms": ms, "filters_per_s": F / (ms * 1e-3),
+                     "particles_per_s": total / (ms * 1e-3),
+                     "hbm_frac_8B_per_particle": 8.0 * total / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)})
+        log(f"  {scheme:12s} {mode:9s} {ms:8.3f} ms")
+
+    # per-filter form: one call per filter, float64 weights, binary64 prefix sums
+    views = [(w64[off_np[f]:off_np[f + 1]], a[off_np[f]:off_np[f + 1]]) for f in range(F)]
+
+    def per_filter():
+        for f, (wf, af) in enumerate(views):
+            pfr.resample_systematic(wf, seed=1, filter_base=f, precision=pfr.SCAN_F64, out=af,
+                                    flags=flags)
+
+    per_filter()
+    ms_eager = _time_ms(per_filter, max(1, args.steps // 4), torch)
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        per_filter()
+    g.replay()
+    ms_graph = _time_ms(g.replay, max(1, args.steps // 4), torch)
+    for form, ms in (("per-filter calls", ms_eager), ("per-filter calls, captured graph",
+                                                      ms_graph)):
+        rows.append({"scheme": "systematic", "precision": "f64", "form": form, "ms": ms,
+                     "filters_per_s": F / (ms * 1e-3), "particles_per_s": total / (ms * 1e-3)})
+        log(f"  systematic   f64 {form}: {ms:8.3f} ms")
+    if int(flags.cpu()[0]) != 0:
+        raise RuntimeError(f"data flags raised: {int(flags.cpu()[0])}")
+    print(json.dumps({"metric": "batched filters/sec", "unit": "filters/s",
+                      "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "ragged batch: 4096 float32 weight vectors, N_f = "
+                                             "2^(8+8v), v ~ U[0,1), y_f ~ U[0,4] (seed 0)",
+                                 "filters": F, "particles": total, "max_len": max_len},
+                      "rows": rows}), flush=True)
+
+
+def filter_workload(args):
+    """Bootstrap filter on x_t = 0.9 x_{t-1} + N(0,1), y_t = x_t + N(0, 0.5^2):
+    1024 filters of 2^14 particles, T = 200 synthetic observations (seed 0); one
+    captured graph of a step (resample, permute, copy, propagate, weight) is
+    replayed T times.  filters/s = 1024 / wall time of the T steps; log Z-hat
+    is compared with the Kalman value."""
+    import torch
+    import oracle
+    import paper_1301_4019_amd as pfr
+    from paper_1301_4019_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    F, n, T = args.filters_ssm, 1 << 14, 200
+    phi, q, r = 0.9, 1.0, 0.5
+    s0 = q / math.sqrt(1 - phi * phi)
+    y = inputs.ssm_data(T, phi=phi, q=q, r=r, seed=0)[1]
+    logZ = oracle.kalman_loglik(y, phi, q, r, s0)
+    rows = []
+    for scheme in SCHEMES:
+        flt = pfr.LGSSMFilter(y, F, n, phi=phi, q=q, r=r, scheme=scheme, seed=1, device=dev)
+        flt.run()  # capture and warm up
+        times = []
+        for _ in range(args.filter_reps):
+            flt.reset()
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            for _ in range(T):
+                flt.graph.replay()
+            torch.cuda.synchronize()
+            times.append(time.perf_counter() - t0)
+        lz = flt.log_z.cpu().numpy()
+        if int(flt.flags.cpu()[0]) != 0:
+            raise RuntimeError(f"data flags raised: {int(flt.flags.cpu()[0])}")
+        ratio = np.exp(lz - logZ)
+        sec = float(np.median(times))
+        rows.append({"scheme": scheme, "seconds_T_steps": sec, "filters_per_s": F / sec,
+                     "us_per_step": 1e6 * sec / T,
+                     "particles_per_s": F * n * T / sec,
+                     "mean_logZhat_minus_logZ": float(lz.mean() - logZ),
+                     "sd_logZhat": float(lz.std(ddof=1)),
+                     "mean_Zhat_over_Z": float(ratio.mean()),
+                     "se_Zhat_over_Z": float(ratio.std(ddof=1) / math.sqrt(F))})
+        log(f"  {scheme:12s} {1e6 * sec / T:8.1f} us/step  {F / sec:10.1f} filters/s  "
+            f"Zhat/Z {ratio.mean():.4f} +- {ratio.std(ddof=1) / math.sqrt(F):.4f}")
+        del flt
+    print(json.dumps({"metric": "batched filters/sec (full bootstrap filter, hipGraph step)",
+                      "unit": "filters/s", "higher_is_better": True, "n_gpus": 1,
+                      "data": "synthetic",
+                      "config": {"workload": "bootstrap filter, 1-D linear-Gaussian SSM "
+                                             "phi=0.9 q=1 r=0.5, y from seed 0",
+                                 "filters": F, "n": n, "T": T, "logZ_kalman": logZ},
+                      "rows": rows}), flush=True)
+
+
 def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
@@ -144,9 +292,14 @@ def main():
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--cpu-sample", type=int, default=1 << 18)
-    ap.add_argument("--workload", choices=("step", "precision"), default="step",
+    ap.add_argument("--workload", choices=("step", "precision", "batch", "filter"),
+                    default="step",
                     help="step: the timed resampling step (default); precision: the bias "
-                         "sweep over prefix-sum precision modes")
+                         "sweep over prefix-sum precision modes; batch: ragged batch of "
+                         "4096 filters; filter: full bootstrap filter, 1024 x 2^14 x 200")
+    ap.add_argument("--filters", type=int, default=4096)
+    ap.add_argument("--filters-ssm", type=int, default=1024)
+    ap.add_argument("--filter-reps", type=int, default=3)
     ap.add_argument("--replicates", type=int, default=256)
     ap.add_argument("--sweep-log2n", type=int, nargs="+", default=[16, 18, 20, 22, 24])
     args = ap.parse_args()
@@ -156,6 +309,12 @@ def main():
         sys.exit(2)
     if args.workload == "precision":
         precision_sweep(args)
+        return
+    if args.workload == "batch":
+        batch_workload(args)
+        return
+    if args.workload == "filter":
+        filter_workload(args)
         return
 
     import torch

@@ -83,6 +83,7 @@ typedef enum {
                                     PFR_MAX_BATCH_SEGMENT (that segment gets the identity) */
 #define PFR_FLAG_BAD_WEIGHTS 8u  /* a weight is negative, NaN or infinite: output is the identity */
 #define PFR_FLAG_BAD_ANCESTOR 16u /* permute: an ancestor outside [0, n) is replaced by its own index */
+#define PFR_FLAG_BAD_STEP 32u    /* lgssm_step: step index t outside [1, T]; the state is left unchanged */
 
 /* Longest segment a batched collective call (n_filters > 1) accepts. */
 #define PFR_MAX_BATCH_SEGMENT (256 * 1024 - 1)
@@ -101,11 +102,14 @@ typedef struct {
 
 /* Philox key and counter words: seed is the 64-bit key, offset the last
  * counter word (e.g. the time step of a filter), filter_base the filter id of
- * segment 0 (segment f uses filter_base + f). */
+ * segment 0 (segment f uses filter_base + f).  offset_dev, if not NULL, is a
+ * DEVICE uint32 read by the kernels when they run, in place of offset: a
+ * captured graph can then advance the offset between replays. */
 typedef struct {
     uint64_t seed;
     uint32_t offset;
     uint32_t filter_base;
+    const uint32_t* offset_dev;
 } pfr_rng;
 
 typedef enum {
@@ -202,6 +206,50 @@ PFR_API int offspring_to_ancestors(const int32_t* offspring, const pfr_segments*
 PFR_API int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t sorted_hint,
                       int32_t* permuted, void* ws, size_t ws_bytes, uint32_t* dev_flags,
                       void* stream);
+
+/* ---------------------------------------------------------------- filter
+ * The bootstrap particle filter of Code 1 (section 1: K_t the transition
+ * and G_t the observation density) for the 1-D linear-Gaussian model
+ *   x_0 ~ N(0, s0^2),  x_t = phi x_{t-1} + q e_t,  y_t = x_t + r v_t,
+ * batched over n_filters independent filters of n particles each (filter f
+ * holds positions [f n, (f+1) n) of x, w, ancestors and permuted).  State x
+ * and weights w are binary32; log Z per filter is binary64.
+ *
+ * Random numbers: x_0 of particle i of filter f takes Philox counter
+ * (i, 4<<28, filter_base + f, offset), its noise at step t the counter
+ * (i, 3<<28 | t, filter_base + f, offset); a standard normal is
+ * sqrt(-2 log u1) cos(2 pi u2) with u1 = (x0 + 1) 2^-32, u2 = x1 2^-32.  The
+ * resampler at step t runs with counter offset t. */
+typedef struct {
+    double phi, q, r, s0;
+} pfr_lgssm;
+
+/* Workspace bytes of lgssm_init / lgssm_step (segment offsets + permutation). */
+PFR_API size_t lgssm_workspace_bytes(int32_t n_filters, int32_t n);
+
+/* x_0 ~ N(0, s0^2), w = 1, log_z = 0, B_dev = 1, *t_dev = 1; writes the
+ * segment offsets into the workspace. */
+PFR_API int lgssm_init(const pfr_lgssm* model, int32_t n_filters, int32_t n, pfr_rng rng,
+                       float* x, float* w, double* log_z, int32_t* B_dev, uint32_t* t_dev,
+                       void* ws, size_t ws_bytes, void* stream);
+
+/* One step t = *t_dev (read on the device) of Code 1 for every filter:
+ *   a = Ancestors(w) by `scheme` (a resampler op; Metropolis takes B_dev,
+ *       rejection the bound 1, which the shifted weights never exceed),
+ *   c = permute_ancestors(a), x_i <- x_{c_i} in place,
+ *   x_i <- phi x_i + q e_i, lw_i = log N(y_t; x_i, r^2) (binary64),
+ *   log_z[f] += m + log(mean exp(lw - m)) with m = max lw, w_i = exp(lw_i - m),
+ *   B_dev[f] = ceil(log(1/100) / log(1 - mean w)) in [1, 65536] (eq. (B)),
+ * then *t_dev += 1.  y is a DEVICE binary64 array of T observations with
+ * y[t-1] = y_t; a step with t outside [1, T] leaves x, w and log_z unchanged
+ * and raises PFR_FLAG_BAD_STEP.  Every argument is read when the kernels run,
+ * so the step can be captured once and replayed T times.  `ancestors` and
+ * `permuted` receive a and c. */
+PFR_API int lgssm_step(const pfr_lgssm* model, pfr_op scheme, pfr_precision precision,
+                       int32_t n_filters, int32_t n, const double* y, int32_t T, uint32_t* t_dev,
+                       pfr_rng rng, float* x, float* w, double* log_z, int32_t* B_dev,
+                       int32_t* ancestors, int32_t* permuted, void* ws, size_t ws_bytes,
+                       uint32_t* dev_flags, void* stream);
 
 /* ---------------------------------------------------------------- misc */
 PFR_API const char* pfr_status_string(int status);

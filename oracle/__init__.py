@@ -73,6 +73,11 @@ def _load():
         "orc_ancestors_to_offspring": (ctypes.c_int, [P, i64, P, P]),
         "orc_permute": (ctypes.c_int, [P, i64, P, P, P]),
         "orc_permute_serial": (ctypes.c_int, [P, i64]),
+        "orc_normal": (dbl, [u64, u32, u32, u32, u32, u32]),
+        "orc_lgssm_init": (None, [i32, i32, dbl, u64, u32, u32, P]),
+        "orc_lgssm_move": (None, [i32, i32, dbl, dbl, dbl, u32, dbl, u64, u32, u32, P, P, P, P,
+                                  P]),
+        "orc_kalman_loglik": (dbl, [P, i64, dbl, dbl, dbl, dbl]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -242,3 +247,39 @@ def permute_serial(a):
     a = np.array(a, dtype=np.int32, copy=True)
     _check(_load().orc_permute_serial(_ptr(a), a.size), "permute_serial")
     return a
+
+
+# ------------------------------------------------------------------ filter
+def normal(seed, index, domain, step, filt=0, offset=0):
+    """Box-Muller standard normal of one canonical Philox draw."""
+    return float(_load().orc_normal(int(seed) & (2**64 - 1), index, domain, step, filt, offset))
+
+
+def lgssm_init(n_filters, n, s0, seed=0, offset=0, filter_base=0):
+    """x_0 (float32, n_filters * n) of the bootstrap filter."""
+    x = np.empty(n_filters * n, dtype=np.float32)
+    _load().orc_lgssm_init(n_filters, n, float(s0), int(seed) & (2**64 - 1), offset, filter_base,
+                           _ptr(x))
+    return x
+
+
+def lgssm_move(c, x, log_z, n_filters, n, phi, q, r, t, y_t, seed=0, offset=0, filter_base=0):
+    """Copy, propagate and weight after resampling (one step of Code 1).
+
+    Returns (x, w, log_z, B) as new arrays; the inputs are not modified."""
+    c = np.ascontiguousarray(c, dtype=np.int32)
+    x = np.array(x, dtype=np.float32, copy=True)
+    lz = np.array(log_z, dtype=np.float64, copy=True)
+    w = np.empty(n_filters * n, dtype=np.float32)
+    B = np.empty(n_filters, dtype=np.int32)
+    _load().orc_lgssm_move(n_filters, n, float(phi), float(q), float(r), int(t), float(y_t),
+                           int(seed) & (2**64 - 1), offset, filter_base, _ptr(c), _ptr(x),
+                           _ptr(w), _ptr(lz), _ptr(B))
+    return x, w, lz, B
+
+
+def kalman_loglik(y, phi, q, r, s0):
+    """Exact log p(y_1..y_T) of the linear-Gaussian model (Kalman filter)."""
+    y = np.ascontiguousarray(y, dtype=np.float64)
+    return float(_load().orc_kalman_loglik(_ptr(y), y.size, float(phi), float(q), float(r),
+                                           float(s0)))

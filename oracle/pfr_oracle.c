@@ -540,3 +540,94 @@ int orc_permute_serial(int32_t* a, int64_t n)
     }
     return 0;
 }
+
+/* ------------------------------------------------------------------------ */
+/* Bootstrap particle filter, Code 1, on the linear-Gaussian model.          */
+/* ------------------------------------------------------------------------ */
+
+/* Box & Muller (1958): for u1 in (0, 1] and u2 in [0, 1),
+ * sqrt(-2 log u1) cos(2 pi u2) is a standard normal. */
+double orc_normal(uint64_t seed, uint32_t index, uint32_t domain, uint32_t step,
+                  uint32_t filter, uint32_t offset)
+{
+    uint32_t x[4];
+    double u1, u2;
+    draw(seed, index, domain, step, filter, offset, x);
+    u1 = ldexp((double)x[0] + 1.0, -32);
+    u2 = ldexp((double)x[1], -32);
+    return sqrt(-2.0 * log(u1)) * cos(6.283185307179586 * u2);
+}
+
+void orc_lgssm_init(int32_t n_filters, int32_t n, double s0, uint64_t seed, uint32_t offset,
+                    uint32_t filter_base, float* x)
+{
+    int32_t f, i;
+    for (f = 0; f < n_filters; ++f)
+        for (i = 0; i < n; ++i)
+            x[(int64_t)f * n + i] = (float)(s0 * orc_normal(seed, (uint32_t)i, ORC_DOM_INIT, 0,
+                                                             filter_base + (uint32_t)f, offset));
+}
+
+void orc_lgssm_move(int32_t n_filters, int32_t n, double phi, double q, double r, uint32_t t,
+                    double y_t, uint64_t seed, uint32_t offset, uint32_t filter_base,
+                    const int32_t* c, float* x, float* w, double* log_z, int32_t* B)
+{
+    /* log of the observation density's normalising constant 1 / (r sqrt(2 pi)) */
+    const double log_norm = -log(r) - 0.5 * log(6.283185307179586);
+    int32_t f, i;
+    for (f = 0; f < n_filters; ++f) {
+        float* xf = x + (int64_t)f * n;
+        float* wf = w + (int64_t)f * n;
+        const int32_t* cf = c + (int64_t)f * n;
+        double m = -HUGE_VAL, sum = 0.0, beta, b;
+        /* copy step before propagation (section 2.3): slots with offspring
+         * keep their particle, the others receive their ancestor's */
+        for (i = 0; i < n; ++i)
+            if (cf[i] != i) xf[i] = xf[cf[i]];
+        /* propagate with the transition density, weight with G_t */
+        for (i = 0; i < n; ++i) {
+            const double e = orc_normal(seed, (uint32_t)i, ORC_DOM_NOISE, t,
+                                        filter_base + (uint32_t)f, offset);
+            double d, lw;
+            xf[i] = (float)(phi * (double)xf[i] + q * e);
+            d = (y_t - (double)xf[i]) / r;
+            lw = -0.5 * d * d + log_norm;
+            if (lw > m) m = lw;
+        }
+        /* renormalisation by the maximum log-weight (appendix E) */
+        for (i = 0; i < n; ++i) {
+            const double d = (y_t - (double)xf[i]) / r;
+            const double e = exp((-0.5 * d * d + log_norm) - m);
+            wf[i] = (float)e;
+            sum += e;
+        }
+        beta = sum / (double)n;
+        log_z[f] += m + log(beta);
+        /* eq. (B) with epsilon = 1/100 and beta = mean(w) / max(w), max(w) = 1 */
+        b = beta >= 1.0 ? 1.0 : ceil(log(0.01) / log1p(-beta));
+        if (b < 1.0) b = 1.0;
+        if (b > 65536.0) b = 65536.0;
+        B[f] = (int32_t)b;
+    }
+}
+
+/* Kalman (1960) filter for the scalar model: predictive mean m and variance P
+ * of x_t given y_1..y_{t-1}; y_t ~ N(m, P + r^2) contributes its log-density
+ * and the update conditions x_t on y_t. */
+double orc_kalman_loglik(const double* y, int64_t T, double phi, double q, double r, double s0)
+{
+    double m = 0.0, P = s0 * s0, ll = 0.0;
+    int64_t t;
+    for (t = 0; t < T; ++t) {
+        double S, K, v;
+        m = phi * m;
+        P = phi * phi * P + q * q;
+        S = P + r * r;
+        v = y[t] - m;
+        ll += -0.5 * (log(6.283185307179586 * S) + v * v / S);
+        K = P / S;
+        m = m + K * v;
+        P = (1.0 - K) * P;
+    }
+    return ll;
+}

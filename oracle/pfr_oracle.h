@@ -96,6 +96,35 @@ int orc_permute(const int32_t* a, int64_t n, int32_t* c, int32_t* d, uint32_t* f
 /* Code 9 (serial in-place Permute), used only as an invariant cross-check. */
 int orc_permute_serial(int32_t* a, int64_t n);
 
+/* ---------------------------------------------------------------------- */
+/* Bootstrap filter on the 1-D linear-Gaussian model (Code 1 with K_t the   */
+/* transition density and G_t the observation density):                   */
+/*   x_0 ~ N(0, s0^2),  x_t = phi x_{t-1} + q e_t,  y_t = x_t + r v_t.      */
+/* Filter f holds particles [f n, (f+1) n).  Normals come from Philox words */
+/* 0 and 1 by the Box-Muller transform (u1 = (x0+1) 2^-32, u2 = x1 2^-32).  */
+/* ---------------------------------------------------------------------- */
+
+/* Standard normal of the canonical draw (index, domain, step, filter, offset). */
+double orc_normal(uint64_t seed, uint32_t index, uint32_t domain, uint32_t step,
+                  uint32_t filter, uint32_t offset);
+
+/* x_0 of every particle (binary32, as the state is stored). */
+void orc_lgssm_init(int32_t n_filters, int32_t n, double s0, uint64_t seed, uint32_t offset,
+                    uint32_t filter_base, float* x);
+
+/* One step t after resampling, for every filter: the in-place copy
+ * x_i <- x_{c_i} (c the permuted ancestry), propagation with noise
+ * (i, NOISE<<28 | t, filter_base + f, offset), the log-weights
+ * lw_i = log N(y_t; x_i, r^2), log_z[f] += m + log(mean exp(lw - m)) with
+ * m = max lw, w_i = exp(lw_i - m) (binary32) and
+ * B[f] = ceil(log(1/100) / log(1 - mean w)) clamped to [1, 65536]. */
+void orc_lgssm_move(int32_t n_filters, int32_t n, double phi, double q, double r, uint32_t t,
+                    double y_t, uint64_t seed, uint32_t offset, uint32_t filter_base,
+                    const int32_t* c, float* x, float* w, double* log_z, int32_t* B);
+
+/* Exact log p(y_1..y_T) of the model by the Kalman filter (binary64). */
+double orc_kalman_loglik(const double* y, int64_t T, double phi, double q, double r, double s0);
+
 #ifdef __cplusplus
 }
 #endif

@@ -16,7 +16,8 @@ from __future__ import annotations
 import ctypes
 
 from . import _lib
-from ._lib import (FLAG_BAD_ANCESTOR, FLAG_BAD_COUNTS, FLAG_BAD_WEIGHTS, FLAG_TRIAL_CAP,
+from ._lib import (FLAG_BAD_ANCESTOR, FLAG_BAD_COUNTS, FLAG_BAD_STEP, FLAG_BAD_WEIGHTS,
+                   FLAG_TRIAL_CAP,
                    FLAG_ZERO_TOTAL, MAX_BATCH_SEGMENT, SCAN_COMP_F32, SCAN_EXACT, SCAN_F64,
                    SCAN_NAIVE_F32, PfrError)
 
@@ -24,9 +25,10 @@ __all__ = [
     "resample_multinomial", "resample_stratified", "resample_systematic",
     "resample_metropolis", "resample_rejection", "offspring_to_ancestors",
     "permute_ancestors", "workspace_bytes", "new_workspace", "version", "PfrError",
+    "LGSSMFilter",
     "SCAN_EXACT", "SCAN_F64", "SCAN_COMP_F32", "SCAN_NAIVE_F32",
     "FLAG_ZERO_TOTAL", "FLAG_TRIAL_CAP", "FLAG_BAD_COUNTS", "FLAG_BAD_WEIGHTS",
-    "FLAG_BAD_ANCESTOR", "MAX_BATCH_SEGMENT",
+    "FLAG_BAD_ANCESTOR", "FLAG_BAD_STEP", "MAX_BATCH_SEGMENT",
 ]
 
 
@@ -74,9 +76,10 @@ def _segments(n_total, offsets=None, max_len=None):
                          int(max_len) if max_len is not None else 0)
 
 
-def _rng(seed, offset, filter_base):
+def _rng(seed, offset, filter_base, offset_dev=None):
     return _lib.Rng(int(seed) & (2**64 - 1), int(offset) & 0xFFFFFFFF,
-                    int(filter_base) & 0xFFFFFFFF)
+                    int(filter_base) & 0xFFFFFFFF,
+                    None if offset_dev is None else offset_dev.data_ptr())
 
 
 # workspaces are zeroed once and reused; calls sharing one must be ordered on
@@ -217,3 +220,85 @@ def permute_ancestors(a, sorted_hint=False, offsets=None, max_len=None, out=None
                                        _ptr(flags), _stream())
     _lib.check(rc, "permute_ancestors")
     return c
+
+
+_SCHEME_OPS = {"multinomial": _lib.OP_MULTINOMIAL, "stratified": _lib.OP_STRATIFIED,
+               "systematic": _lib.OP_SYSTEMATIC, "metropolis": _lib.OP_METROPOLIS,
+               "rejection": _lib.OP_REJECTION}
+
+
+class LGSSMFilter:
+    """Batched bootstrap particle filter on the 1-D linear-Gaussian model
+    x_t = phi x_{t-1} + q e_t, y_t = x_t + r v_t (lgssm_* in the C header).
+
+    Holds the device state of n_filters filters of n particles: x, w (float32),
+    log_z (float64 per filter), the Metropolis step counts B and the device
+    step counter t.  `run` initialises and then advances T steps, replaying one
+    captured graph of a step by default.
+    """
+
+    def __init__(self, y, n_filters, n, phi=0.9, q=1.0, r=0.5, s0=None, scheme="systematic",
+                 precision=SCAN_EXACT, seed=0, offset=0, filter_base=0, device="cuda"):
+        import math
+        torch = _torch()
+        if s0 is None:  # stationary prior of the state
+            s0 = q / math.sqrt(1.0 - phi * phi)
+        self.model = _lib.LGSSM(float(phi), float(q), float(r), float(s0))
+        self.y = torch.as_tensor(y, dtype=torch.float64).to(device).contiguous()
+        self.T = int(self.y.numel())
+        self.F, self.n = int(n_filters), int(n)
+        total = self.F * self.n
+        self.x = torch.empty(total, dtype=torch.float32, device=device)
+        self.w = torch.empty(total, dtype=torch.float32, device=device)
+        self.log_z = torch.zeros(self.F, dtype=torch.float64, device=device)
+        self.B = torch.zeros(self.F, dtype=torch.int32, device=device)
+        self.t = torch.zeros(1, dtype=torch.int32, device=device)
+        self.ancestors = torch.empty(total, dtype=torch.int32, device=device)
+        self.permuted = torch.empty(total, dtype=torch.int32, device=device)
+        self.flags = torch.zeros(1, dtype=torch.int32, device=device)
+        nbytes = int(_lib.load().lgssm_workspace_bytes(self.F, self.n))
+        if nbytes == 0:
+            raise ValueError("invalid filter size")
+        self.ws = new_workspace(nbytes, device)
+        self.scheme = _SCHEME_OPS[scheme]
+        self.precision = int(precision)
+        self.rng = _rng(seed, offset, filter_base)
+        self.graph = None
+
+    def reset(self):
+        rc = _lib.load().lgssm_init(ctypes.byref(self.model), self.F, self.n, self.rng,
+                                    _ptr(self.x), _ptr(self.w), _ptr(self.log_z), _ptr(self.B),
+                                    _ptr(self.t), _ptr(self.ws), self.ws.numel(), _stream())
+        _lib.check(rc, "lgssm_init")
+
+    def step(self):
+        rc = _lib.load().lgssm_step(ctypes.byref(self.model), self.scheme, self.precision, self.F,
+                                    self.n, _ptr(self.y), self.T, _ptr(self.t), self.rng,
+                                    _ptr(self.x), _ptr(self.w), _ptr(self.log_z), _ptr(self.B),
+                                    _ptr(self.ancestors), _ptr(self.permuted), _ptr(self.ws),
+                                    self.ws.numel(), _ptr(self.flags), _stream())
+        _lib.check(rc, "lgssm_step")
+
+    def capture(self):
+        """Capture one step in a HIP graph (every step argument is read on the device)."""
+        torch = _torch()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            self.step()
+        self.graph = g
+        return g
+
+    def run(self, T=None, graph=True):
+        """reset() and T steps (default: all observations); returns log_z."""
+        T = self.T if T is None else int(T)
+        self.reset()
+        if graph:
+            if self.graph is None:
+                _torch().cuda.synchronize()
+                self.capture()
+            for _ in range(T):
+                self.graph.replay()
+        else:
+            for _ in range(T):
+                self.step()
+        return self.log_z

@@ -24,12 +24,14 @@ FLAG_TRIAL_CAP = 2
 FLAG_BAD_COUNTS = 4
 FLAG_BAD_WEIGHTS = 8
 FLAG_BAD_ANCESTOR = 16
+FLAG_BAD_STEP = 32
 MAX_BATCH_SEGMENT = 256 * 1024 - 1
 
 EXPORTS = (
     "pfr_workspace_bytes", "pfr_workspace_init", "resample_multinomial", "resample_stratified",
     "resample_systematic", "resample_metropolis", "resample_rejection", "offspring_to_ancestors",
-    "permute_ancestors", "pfr_status_string", "pfr_version",
+    "permute_ancestors", "lgssm_workspace_bytes", "lgssm_init", "lgssm_step",
+    "pfr_status_string", "pfr_version",
 )
 
 
@@ -40,7 +42,12 @@ class Segments(ctypes.Structure):
 
 class Rng(ctypes.Structure):
     _fields_ = [("seed", ctypes.c_uint64), ("offset", ctypes.c_uint32),
-                ("filter_base", ctypes.c_uint32)]
+                ("filter_base", ctypes.c_uint32), ("offset_dev", ctypes.c_void_p)]
+
+
+class LGSSM(ctypes.Structure):
+    _fields_ = [("phi", ctypes.c_double), ("q", ctypes.c_double), ("r", ctypes.c_double),
+                ("s0", ctypes.c_double)]
 
 
 class PfrError(RuntimeError):
@@ -61,6 +68,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
     P, I, U32, I32, D, SZ = (ctypes.c_void_p, ctypes.c_int, ctypes.c_uint32, ctypes.c_int32,
                              ctypes.c_double, ctypes.c_size_t)
     SEG = ctypes.POINTER(Segments)
+    MODEL = ctypes.POINTER(LGSSM)
     sigs = {
         "pfr_workspace_bytes": (SZ, [I, SEG, I]),
         "pfr_workspace_init": (I, [P, SZ, P]),
@@ -71,6 +79,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "resample_rejection": (I, [P, I, SEG, D, P, U32, Rng, P, P, P]),
         "offspring_to_ancestors": (I, [P, SEG, P, P, SZ, P, P]),
         "permute_ancestors": (I, [P, SEG, I32, P, P, SZ, P, P]),
+        "lgssm_workspace_bytes": (SZ, [I32, I32]),
+        "lgssm_init": (I, [MODEL, I32, I32, Rng, P, P, P, P, P, P, SZ, P]),
+        "lgssm_step": (I, [MODEL, I, I, I32, I32, P, I32, P, Rng, P, P, P, P, P, P, P, SZ, P,
+                           P]),
         "pfr_status_string": (ctypes.c_char_p, [I]),
         "pfr_version": (ctypes.c_char_p, []),
     }

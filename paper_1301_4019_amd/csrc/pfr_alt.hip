@@ -34,10 +34,56 @@ __device__ __forceinline__ SegCtx seg_of(const int64_t* __restrict__ offsets, ui
 
 // ------------------------------------------------------------------ Metropolis
 // Lane i runs B steps of an independent Metropolis chain started at k = i.
-// Step s draws (j, u) from Philox counter (i, TRIAL<<28 | s, filter, offset)
-// and moves to j when u * w_k <= w_j.  The proposals and their weight loads do
-// not depend on the chain state, so groups of 4 steps issue their 4 Philox
-// blocks and 4 gathers together and only the accept decisions run in order.
+// Step s takes (j, u) from words 3s, 3s+1, 3s+2 of the lane's Philox stream
+// (word m = word m&3 of counter (i, TRIAL<<28 | m>>2, filter, offset)) and
+// moves to j when u * w_k <= w_j.  The proposals and their weight loads do not
+// depend on the chain state: a group of 4 steps takes 3 Philox calls and
+// issues its 4 gathers at once, and the gathers of group m+1 are in flight
+// while the accept decisions of group m run in order (two register sets, used
+// alternately, so that no load has to complete before it is consumed).
+struct MGroup {
+  uint32_t j[4];
+  uint32_t u[4];
+  double wj[4];
+  int nq;
+};
+
+template <typename T>
+__device__ __forceinline__ void metropolis_fetch(const T* __restrict__ ws, Key key, uint32_t i,
+                                                 uint32_t filt, uint32_t offset, uint32_t n,
+                                                 int32_t steps, int32_t m, MGroup& g) {
+  uint32_t x[12];
+  const int32_t left = steps - 4 * m;
+  const int ncall = left >= 4 ? 3 : (3 * left + 3) / 4;
+#pragma unroll
+  for (int c3 = 0; c3 < 3; ++c3) {
+    if (c3 < ncall) {
+      const uint4 v = draw(key, i, DOM_TRIAL, (uint32_t)(3 * m + c3), filt, offset);
+      x[4 * c3 + 0] = v.x;
+      x[4 * c3 + 1] = v.y;
+      x[4 * c3 + 2] = v.z;
+      x[4 * c3 + 3] = v.w;
+    }
+  }
+  g.nq = left >= 4 ? 4 : left;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    g.j[q] = q < g.nq ? index_draw(x[3 * q], x[3 * q + 1], n) : i;
+    g.u[q] = x[3 * q + 2];
+    g.wj[q] = (double)ws[g.j[q]];
+  }
+}
+
+__device__ __forceinline__ void metropolis_accept(const MGroup& g, uint32_t& k, double& wk) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q < g.nq && accept_exact(u_accept(g.u[q]), wk, g.wj[q])) {
+      k = g.j[q];
+      wk = g.wj[q];
+    }
+  }
+}
+
 template <typename T>
 __global__ __launch_bounds__(256) void k_metropolis(const T* __restrict__ w, int64_t n_total,
                                                     const int64_t* __restrict__ offsets,
@@ -45,6 +91,7 @@ __global__ __launch_bounds__(256) void k_metropolis(const T* __restrict__ w, int
                                                     const int32_t* __restrict__ B_dev, Key key,
                                                     uint32_t offset, uint32_t filter_base,
                                                     int32_t* __restrict__ a) {
+  offset = counter_offset(key, offset);
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
     const SegCtx c = seg_of(offsets, n_filters, n_total, g);
@@ -54,36 +101,14 @@ __global__ __launch_bounds__(256) void k_metropolis(const T* __restrict__ w, int
     const T* __restrict__ ws = w + c.base;
     uint32_t k = i;
     double wk = (double)ws[i];
-    // steps 4m .. 4m+3 take the 12 words of calls 3m .. 3m+2
-    for (int32_t m = 0; 4 * m < steps; ++m) {
-      uint32_t x[12];
-      const int32_t left = steps - 4 * m;
-      const int ncall = left >= 4 ? 3 : (3 * left + 3) / 4;
-#pragma unroll
-      for (int c3 = 0; c3 < 3; ++c3) {
-        if (c3 < ncall) {
-          const uint4 v = draw(key, i, DOM_TRIAL, (uint32_t)(3 * m + c3), filt, offset);
-          x[4 * c3 + 0] = v.x;
-          x[4 * c3 + 1] = v.y;
-          x[4 * c3 + 2] = v.z;
-          x[4 * c3 + 3] = v.w;
-        }
-      }
-      const int nq = left >= 4 ? 4 : left;
-      uint32_t j[4];
-      double wj[4];
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        j[q] = q < nq ? index_draw(x[3 * q], x[3 * q + 1], c.n) : i;
-        wj[q] = (double)ws[j[q]];
-      }
-#pragma unroll
-      for (int q = 0; q < 4; ++q) {
-        if (q < nq && accept_exact(u_accept(x[3 * q + 2]), wk, wj[q])) {
-          k = j[q];
-          wk = wj[q];
-        }
-      }
+    const int32_t groups = (steps + 3) / 4;
+    MGroup ga, gb;
+    if (groups > 0) metropolis_fetch(ws, key, i, filt, offset, c.n, steps, 0, ga);
+    for (int32_t m = 0; m < groups; m += 2) {
+      if (m + 1 < groups) metropolis_fetch(ws, key, i, filt, offset, c.n, steps, m + 1, gb);
+      metropolis_accept(ga, k, wk);
+      if (m + 2 < groups) metropolis_fetch(ws, key, i, filt, offset, c.n, steps, m + 2, ga);
+      if (m + 1 < groups) metropolis_accept(gb, k, wk);
     }
     a[g] = (int32_t)k;
   }
@@ -130,6 +155,7 @@ __global__ __launch_bounds__(256) void k_rejection(const T* __restrict__ w, int6
                                                    uint32_t filter_base, int32_t* __restrict__ a,
                                                    uint32_t* __restrict__ flags,
                                                    int64_t per_wave) {
+  offset = counter_offset(key, offset);
   const uint32_t lane = lane_id();
   const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
   const int64_t r0 = gw * per_wave;

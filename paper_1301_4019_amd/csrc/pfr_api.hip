@@ -35,10 +35,11 @@ int check_segments(const pfr_segments* seg, SegInfo* info) {
   return PFR_OK;
 }
 
-Key make_key(uint64_t seed) {
+Key make_key(const pfr_rng& rng) {
   Key k;
-  k.k0 = (uint32_t)seed;
-  k.k1 = (uint32_t)(seed >> 32);
+  k.k0 = (uint32_t)rng.seed;
+  k.k1 = (uint32_t)(rng.seed >> 32);
+  k.offset_dev = rng.offset_dev;
   return k;
 }
 
@@ -50,6 +51,10 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
 }
 
 int launch_result(hipError_t e) { return e == hipSuccess ? PFR_OK : PFR_ELAUNCH; }
+
+size_t lgssm_offsets_bytes(int32_t n_filters) {
+  return (((size_t)n_filters + 1) * sizeof(int64_t) + 255) & ~(size_t)255;
+}
 
 size_t dtype_size(pfr_dtype dt) { return dt == PFR_F64 ? 8 : 4; }
 
@@ -70,7 +75,7 @@ int collective(int scheme, const void* w, pfr_dtype dtype, const pfr_segments* s
   if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), a, (size_t)s.n_total * 4))
     return PFR_EINVAL;
   const hipStream_t st = (hipStream_t)stream;
-  const Key key = make_key(rng.seed);
+  const Key key = make_key(rng);
   if (!uses_scan_workspace(s)) {
     if (s.n_filters > 1 && s.max_len > PFR_MAX_BATCH_SEGMENT) return PFR_ENOTSUP;
     if (precision != PFR_SCAN_EXACT)
@@ -157,7 +162,7 @@ int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segments* seg,
   if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), ancestors, (size_t)s.n_total * 4))
     return PFR_EINVAL;
   return launch_result(launch_metropolis(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters, B,
-                                         B_dev, make_key(rng.seed), rng.offset, rng.filter_base,
+                                         B_dev, make_key(rng), rng.offset, rng.filter_base,
                                          ancestors, (hipStream_t)stream));
 }
 
@@ -175,7 +180,7 @@ int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, 
   if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), ancestors, (size_t)s.n_total * 4))
     return PFR_EINVAL;
   return launch_result(launch_rejection(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters,
-                                        w_max, w_max_dev, max_trials, make_key(rng.seed),
+                                        w_max, w_max_dev, max_trials, make_key(rng),
                                         rng.offset, rng.filter_base, ancestors, dev_flags,
                                         (hipStream_t)stream));
 }
@@ -214,6 +219,82 @@ int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t
   return launch_result(launch_permute(ancestors, s.n_total, s.offsets, s.n_filters,
                                       sorted_hint != 0, permuted, ws, dev_flags,
                                       (hipStream_t)stream));
+}
+
+size_t lgssm_workspace_bytes(int32_t n_filters, int32_t n) {
+  if (n_filters < 1 || n < 1 || (int64_t)n_filters * n >= kMaxN) return 0;
+  return lgssm_offsets_bytes(n_filters) + permute_workspace_bytes((int64_t)n_filters * n);
+}
+
+int lgssm_init(const pfr_lgssm* model, int32_t n_filters, int32_t n, pfr_rng rng, float* x,
+               float* w, double* log_z, int32_t* B_dev, uint32_t* t_dev, void* ws,
+               size_t ws_bytes, void* stream) {
+  if (!model || n_filters < 1 || n < 1 || (int64_t)n_filters * n >= kMaxN) return PFR_EINVAL;
+  if (!x || !w || !log_z || !B_dev || !t_dev) return PFR_EINVAL;
+  if (!(model->s0 >= 0.0)) return PFR_EINVAL;
+  if (!ws || !aligned256(ws) || ws_bytes < lgssm_workspace_bytes(n_filters, n))
+    return PFR_EWORKSPACE;
+  Key key = make_key(rng);
+  key.offset_dev = nullptr;
+  return launch_result(launch_lgssm_init(n_filters, n, model->s0, key, rng.offset,
+                                         rng.filter_base, x, w, log_z, B_dev, t_dev,
+                                         (int64_t*)ws, (hipStream_t)stream));
+}
+
+int lgssm_step(const pfr_lgssm* model, pfr_op scheme, pfr_precision precision, int32_t n_filters,
+               int32_t n, const double* y, int32_t T, uint32_t* t_dev, pfr_rng rng, float* x, float* w,
+               double* log_z, int32_t* B_dev, int32_t* ancestors, int32_t* permuted, void* ws,
+               size_t ws_bytes, uint32_t* dev_flags, void* stream) {
+  if (!model || n_filters < 1 || n < 1 || (int64_t)n_filters * n >= kMaxN) return PFR_EINVAL;
+  if (!y || T < 1 || !t_dev || !x || !w || !log_z || !B_dev || !ancestors || !permuted)
+    return PFR_EINVAL;
+  if (!(model->r > 0.0) || !(model->q >= 0.0)) return PFR_EINVAL;
+  if (precision < PFR_SCAN_EXACT || precision > PFR_SCAN_NAIVE_F32) return PFR_EINVAL;
+  if (scheme > PFR_OP_REJECTION || scheme < PFR_OP_MULTINOMIAL) return PFR_EINVAL;
+  const bool collective_scheme = scheme <= PFR_OP_SYSTEMATIC;
+  if (collective_scheme && n > PFR_MAX_BATCH_SEGMENT) return PFR_ENOTSUP;
+  if (!ws || !aligned256(ws) || ws_bytes < lgssm_workspace_bytes(n_filters, n))
+    return PFR_EWORKSPACE;
+  const int64_t total = (int64_t)n_filters * n;
+  if (overlaps(ancestors, (size_t)total * 4, permuted, (size_t)total * 4)) return PFR_EINVAL;
+  const hipStream_t st = (hipStream_t)stream;
+  const int64_t* offsets = (const int64_t*)ws;
+  void* perm_ws = (char*)ws + lgssm_offsets_bytes(n_filters);
+  // the resampler at step t uses counter offset t
+  Key rkey = make_key(rng);
+  rkey.offset_dev = t_dev;
+  const uint32_t nf = (uint32_t)n_filters;
+  hipError_t e;
+  switch (scheme) {
+    case PFR_OP_METROPOLIS:
+      e = launch_metropolis(false, w, total, offsets, nf, 0, B_dev, rkey, 0u, rng.filter_base,
+                            ancestors, st);
+      break;
+    case PFR_OP_REJECTION:
+      e = launch_rejection(false, w, total, offsets, nf, 1.0, nullptr, 1u << 20, rkey, 0u,
+                           rng.filter_base, ancestors, dev_flags, st);
+      break;
+    default: {
+      const int sch = scheme == PFR_OP_MULTINOMIAL   ? SCHEME_MULTINOMIAL
+                      : scheme == PFR_OP_STRATIFIED ? SCHEME_STRATIFIED
+                                                    : SCHEME_SYSTEMATIC;
+      e = precision == PFR_SCAN_EXACT
+              ? launch_scan_batched(sch, false, w, total, offsets, nf, rkey, 0u, rng.filter_base,
+                                    ancestors, dev_flags, st)
+              : launch_fscan_batched(sch, (int)precision, false, w, total, offsets, nf, rkey, 0u,
+                                     rng.filter_base, ancestors, dev_flags, st);
+    }
+  }
+  if (e != hipSuccess) return PFR_ELAUNCH;
+  e = launch_permute(ancestors, total, offsets, nf, collective_scheme, permuted, perm_ws,
+                     dev_flags, st);
+  if (e != hipSuccess) return PFR_ELAUNCH;
+  Key nkey = make_key(rng);
+  nkey.offset_dev = nullptr;
+  return launch_result(launch_lgssm_move(n_filters, n, model->phi, model->q, model->r,
+                                         log(0.01), y, T, t_dev, nkey, rng.offset,
+                                         rng.filter_base, permuted, x, w, log_z, B_dev, dev_flags,
+                                         st));
 }
 
 const char* pfr_status_string(int status) {

@@ -26,10 +26,18 @@ constexpr uint32_t FLAG_TRIAL_CAP = 2u;
 constexpr uint32_t FLAG_BAD_COUNTS = 4u;
 constexpr uint32_t FLAG_BAD_WEIGHTS = 8u;
 constexpr uint32_t FLAG_BAD_ANCESTOR = 16u;
+constexpr uint32_t FLAG_BAD_STEP = 32u;
 
+// Philox key, and optionally the device word that holds the counter offset
+// (read when the kernel runs, so that a captured graph can advance it).
 struct Key {
   uint32_t k0, k1;
+  const uint32_t* offset_dev;
 };
+
+__device__ __forceinline__ uint32_t counter_offset(const Key& key, uint32_t offset) {
+  return key.offset_dev ? *key.offset_dev : offset;
+}
 
 // Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11).  Each round
 // forms the 64-bit products of counter words 0 and 2 with two odd multipliers

@@ -294,6 +294,7 @@ __global__ __launch_bounds__(kT) void k_fscan_records(const T* __restrict__ w, i
                                                       uint32_t nb, Key key, uint32_t offset,
                                                       uint32_t filter, double* __restrict__ sums,
                                                       uint64_t* __restrict__ esums) {
+  offset = counter_offset(key, offset);
   __shared__ WgScratch s;
   if (blockIdx.x < nb) {
     const double d = fblock_sum<T, P>(w, n, (int64_t)blockIdx.x * kBlock, &s);
@@ -332,6 +333,7 @@ __global__ __launch_bounds__(kT) void k_fscan_emit(const T* __restrict__ w, int6
                                                    const u128* __restrict__ CE,
                                                    int32_t* __restrict__ a,
                                                    uint32_t* __restrict__ flags) {
+  offset = counter_offset(key, offset);
   __shared__ EmitLds L;
   __shared__ WgScratch s;
   const uint32_t b = blockIdx.x;
@@ -363,6 +365,7 @@ __global__ __launch_bounds__(kT) void k_fscan_batched(const T* __restrict__ w, i
                                                       uint32_t offset, uint32_t filter_base,
                                                       int32_t* __restrict__ a,
                                                       uint32_t* __restrict__ flags) {
+  offset = counter_offset(key, offset);
   __shared__ FBatchLds B;
   __shared__ EmitLds L;
   __shared__ WgScratch s;

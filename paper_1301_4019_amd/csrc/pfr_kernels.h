@@ -84,6 +84,16 @@ hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offs
                           uint32_t n_filters, bool sorted, int32_t* c, void* ws, uint32_t* flags,
                           hipStream_t stream);
 
+hipError_t launch_lgssm_init(int32_t n_filters, int32_t n, double s0, Key key, uint32_t offset,
+                             uint32_t filter_base, float* x, float* w, double* logz,
+                             int32_t* B_dev, uint32_t* t_dev, int64_t* offsets,
+                             hipStream_t stream);
+hipError_t launch_lgssm_move(int32_t n_filters, int32_t n, double phi, double q, double r,
+                             double log_eps, const double* y, int32_t T, uint32_t* t_dev,
+                             Key key, uint32_t offset, uint32_t filter_base, const int32_t* c,
+                             float* x, float* w, double* logz, int32_t* B_dev, uint32_t* flags,
+                             hipStream_t stream);
+
 hipError_t launch_zero_u32(uint32_t* p, size_t count, hipStream_t stream);
 
 }  // namespace pfr

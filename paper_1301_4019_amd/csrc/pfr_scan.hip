@@ -206,6 +206,7 @@ __global__ __launch_bounds__(kT) void k_scan_records(const T* __restrict__ w, in
                                                      uint32_t filter,
                                                      BlockRec* __restrict__ recs,
                                                      uint64_t* __restrict__ esums) {
+  offset = counter_offset(key, offset);
   __shared__ WgScratch s;
   if (blockIdx.x < nb) {
     const BlockRec r = block_record(w, n, (int64_t)blockIdx.x * kBlock, &s);
@@ -298,6 +299,7 @@ __global__ __launch_bounds__(kT) void k_scan_emit(const T* __restrict__ w, int64
                                                   const u128* __restrict__ CE,
                                                   int32_t* __restrict__ a,
                                                   uint32_t* __restrict__ flags) {
+  offset = counter_offset(key, offset);
   __shared__ EmitLds L;
   __shared__ WgScratch s;
   const uint32_t b = blockIdx.x;
@@ -346,6 +348,7 @@ __global__ __launch_bounds__(kT) void k_scan_batched(const T* __restrict__ w, in
                                                      uint32_t n_filters, Key key, uint32_t offset,
                                                      uint32_t filter_base, int32_t* __restrict__ a,
                                                      uint32_t* __restrict__ flags) {
+  offset = counter_offset(key, offset);
   __shared__ BatchLds B;
   __shared__ EmitLds L;
   __shared__ WgScratch s;
