@@ -33,10 +33,19 @@ N = 1 << 20
 YS = (0.0, 1.0, 2.0, 3.0, 4.0)
 SCHEMES = ("multinomial", "stratified", "systematic", "metropolis", "rejection")
 HBM_PEAK_GBS = 8000.0
-# Philox4x32-10 per call: 20 32x32->64-bit products (one v_mad_u64_u32 each,
-# quarter rate: 4 lane-cycles) and 20 three-input xors (1 lane-cycle each) =
-# 100 lane-cycles; 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-cycles/s.
-PHILOX_PEAK_PER_S = 256 * 4 * 16 * 2.4e9 / 100.0
+# Philox4x32-10 per call: 20 32x32->64-bit products (one v_mad_u64_u32 each)
+# and 20 three-input xors (one v_bitop3_b32 each) = 40 VALU instructions per
+# lane; 256 CUs x 4 SIMDs x 16 lanes x 2.4 GHz = 3.93e13 lane-instructions/s,
+# i.e. 9.83e11 calls/s.  (A Philox-only kernel measures 8.55e11 calls/s.)
+PHILOX_PEAK_PER_S = 256 * 4 * 16 * 2.4e9 / 40.0
+# Random 4-byte loads from a 1-4 MB table, measured with a plain gather kernel
+# (one line per lane from L2): the rate Metropolis' weight loads run into.
+GATHER_CEILING_PER_S = 2.65e11
+
+
+def metropolis_calls_per_lane(B):
+    """Philox calls of a B-step chain: four steps per three calls."""
+    return 3 * (B // 4) + (3 * (B % 4) + 3) // 4
 
 
 def log(msg):
@@ -384,11 +393,16 @@ def main():
     value = particles * args.steps / elapsed
 
     dom_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
-    dom_calls = N * Bs[YS.index(dominant[0])]
+    B_dom = Bs[YS.index(dominant[0])]
+    dom_calls = N * metropolis_calls_per_lane(B_dom)
     achieved = dom_calls / (dom_ms * 1e-3)
-    roofline = {"bound": "alu", "kernel": "k_metropolis<float> (y=4, B=354)",
+    gathers = N * B_dom / (dom_ms * 1e-3)
+    roofline = {"bound": "alu", "kernel": f"Metropolis resample (y=4, B={B_dom})",
                 "achieved": achieved / 1e9, "peak": PHILOX_PEAK_PER_S / 1e9,
                 "unit": "G Philox4x32-10 calls/s", "frac": achieved / PHILOX_PEAK_PER_S,
+                "limiter": f"random weight loads: {gathers / 1e9:.0f} G/s of steps, "
+                           f"{gathers / GATHER_CEILING_PER_S:.2f} of the "
+                           f"{GATHER_CEILING_PER_S / 1e9:.0f} G/s a plain gather kernel reaches",
                 "traffic": None, "avg_launch_ms": dom_ms}
 
     # per-scheme breakdown (untimed pass, events around each call)

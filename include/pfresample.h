@@ -168,9 +168,16 @@ PFR_API int resample_systematic(const void* w, pfr_dtype dtype, const pfr_segmen
  * per three calls), proposes j = floor(((x1<<32)|x0) n / 2^64) with
  * u = (x2 + 1) 2^-32, and moves to j when u w_k <= w_j (decided exactly).
  * B_dev (device int32[n_filters], may be NULL) overrides B per segment.
- * No workspace; no collective operation. */
+ * No collective operation: the chains are independent, so the output does
+ * not depend on the launch shape.  Segments of up to 16K (float32) or 8K
+ * (float64) weights, and with pfr_segments.max_len set up to 32K / 16K, are
+ * staged in LDS.  The workspace (may be NULL, ws_bytes 0) holds, for a single
+ * long vector, a table of power-of-two weight bounds per bucket of particles
+ * that lets most rejected proposals skip the load of w_j; it changes the
+ * speed, never the result. */
 PFR_API int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segments* seg, int32_t B,
-                        const int32_t* B_dev, pfr_rng rng, int32_t* ancestors, void* stream);
+                        const int32_t* B_dev, pfr_rng rng, int32_t* ancestors, void* ws,
+                        size_t ws_bytes, void* stream);
 
 /* Rejection resampling (Code 3): particle i first proposes j = i, then draws
  * j as above from Philox call (i, 2<<28 | t) for trial t >= 1 (every trial
@@ -178,10 +185,12 @@ PFR_API int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segmen
  * (decided exactly).  w_max must bound the weights (else the output is
  * biased); w_max_dev (device double[n_filters], may be NULL) overrides it per
  * segment.  After max_trials trials (>= 1) a particle keeps a_i = i and
- * PFR_FLAG_TRIAL_CAP is raised.  No workspace; no collective operation. */
+ * PFR_FLAG_TRIAL_CAP is raised.  No collective operation; LDS staging and
+ * the optional workspace (weight-bound table) as for resample_metropolis. */
 PFR_API int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, double w_max,
                        const double* w_max_dev, uint32_t max_trials, pfr_rng rng,
-                       int32_t* ancestors, uint32_t* dev_flags, void* stream);
+                       int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                       void* stream);
 
 /* ---------------------------------------------------------------- auxiliaries */
 

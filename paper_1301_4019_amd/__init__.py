@@ -161,29 +161,34 @@ def resample_systematic(w, seed=0, offset=0, filter_base=0, precision=SCAN_EXACT
 
 
 def resample_metropolis(w, B, seed=0, offset=0, filter_base=0, B_per_filter=None, offsets=None,
-                        max_len=None, out=None):
+                        max_len=None, out=None, workspace=None):
     """Metropolis ancestry (Code 2), B steps per lane (or B_per_filter[f])."""
     _require_cuda(w, B_per_filter)
     dt = _dtype_code(w)
     seg = _segments(w.numel(), offsets, max_len)
     a = _out_like(w.numel(), w.device, out)
+    ws, _ = _workspace(_lib.OP_METROPOLIS, seg, dt, w.device, workspace)
     rc = _lib.load().resample_metropolis(_ptr(w), dt, ctypes.byref(seg), int(B),
                                          _ptr(B_per_filter), _rng(seed, offset, filter_base),
-                                         _ptr(a), _stream())
+                                         _ptr(a), _ptr(ws), 0 if ws is None else ws.numel(),
+                                         _stream())
     _lib.check(rc, "resample_metropolis")
     return a
 
 
 def resample_rejection(w, w_max, seed=0, offset=0, filter_base=0, max_trials=1 << 20,
-                       w_max_per_filter=None, offsets=None, max_len=None, out=None, flags=None):
+                       w_max_per_filter=None, offsets=None, max_len=None, out=None, flags=None,
+                       workspace=None):
     """Rejection ancestry (Code 3) with first proposal j = i and bound w_max."""
     _require_cuda(w, w_max_per_filter, flags)
     dt = _dtype_code(w)
     seg = _segments(w.numel(), offsets, max_len)
     a = _out_like(w.numel(), w.device, out)
+    ws, _ = _workspace(_lib.OP_REJECTION, seg, dt, w.device, workspace)
     rc = _lib.load().resample_rejection(_ptr(w), dt, ctypes.byref(seg), float(w_max),
                                         _ptr(w_max_per_filter), int(max_trials),
-                                        _rng(seed, offset, filter_base), _ptr(a), _ptr(flags),
+                                        _rng(seed, offset, filter_base), _ptr(a), _ptr(ws),
+                                        0 if ws is None else ws.numel(), _ptr(flags),
                                         _stream())
     _lib.check(rc, "resample_rejection")
     return a

@@ -75,8 +75,8 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "resample_multinomial": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),
         "resample_stratified": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),
         "resample_systematic": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),
-        "resample_metropolis": (I, [P, I, SEG, I32, P, Rng, P, P]),
-        "resample_rejection": (I, [P, I, SEG, D, P, U32, Rng, P, P, P]),
+        "resample_metropolis": (I, [P, I, SEG, I32, P, Rng, P, P, SZ, P]),
+        "resample_rejection": (I, [P, I, SEG, D, P, U32, Rng, P, P, SZ, P, P]),
         "offspring_to_ancestors": (I, [P, SEG, P, P, SZ, P, P]),
         "permute_ancestors": (I, [P, SEG, I32, P, P, SZ, P, P]),
         "lgssm_workspace_bytes": (SZ, [I32, I32]),

@@ -84,31 +84,287 @@ __device__ __forceinline__ void metropolis_accept(const MGroup& g, uint32_t& k, 
   }
 }
 
+// A workgroup takes the particles [p0, p1) of the global array (chunk per
+// workgroup) and walks the segments that overlap them; a segment of at most
+// CAP weights is first copied into LDS, so that every random weight load of
+// its chains is an LDS read.  Longer segments load from global memory, with
+// the gathers of the next group of steps in flight while the current group
+// is decided.  The chains do not depend on the launch shape.
 template <typename T>
-__global__ __launch_bounds__(256) void k_metropolis(const T* __restrict__ w, int64_t n_total,
-                                                    const int64_t* __restrict__ offsets,
-                                                    uint32_t n_filters, int32_t B,
-                                                    const int32_t* __restrict__ B_dev, Key key,
-                                                    uint32_t offset, uint32_t filter_base,
-                                                    int32_t* __restrict__ a) {
+__device__ __forceinline__ void stage_weights(const T* __restrict__ w, uint32_t n, T* sw) {
+  for (uint32_t k = threadIdx.x; k < n; k += blockDim.x) sw[k] = w[k];
+}
+
+template <typename T>
+__device__ __forceinline__ uint32_t metropolis_chain(const T* ws, Key key, uint32_t i,
+                                                     uint32_t filt, uint32_t offset, uint32_t n,
+                                                     int32_t steps) {
+  uint32_t k = i;
+  double wk = (double)ws[i];
+  const int32_t groups = (steps + 3) / 4;
+  for (int32_t m = 0; m < groups; ++m) {
+    MGroup g;
+    metropolis_fetch(ws, key, i, filt, offset, n, steps, m, g);
+    metropolis_accept(g, k, wk);
+  }
+  return k;
+}
+
+template <typename T, int CAP, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_metropolis_staged(
+    const T* __restrict__ w, int64_t n_total, const int64_t* __restrict__ offsets,
+    uint32_t n_filters, int32_t B, const int32_t* __restrict__ B_dev, Key key, uint32_t offset,
+    uint32_t filter_base, int32_t* __restrict__ a, int64_t chunk) {
+  __shared__ T sw[CAP > 0 ? CAP : 1];
   offset = counter_offset(key, offset);
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
-    const SegCtx c = seg_of(offsets, n_filters, n_total, g);
-    const uint32_t i = (uint32_t)(g - c.base);
-    const int32_t steps = B_dev ? B_dev[c.f] : B;
-    const uint32_t filt = filter_base + c.f;
-    const T* __restrict__ ws = w + c.base;
+  const int64_t p0 = (int64_t)blockIdx.x * chunk;
+  const int64_t p1 = p0 + chunk < n_total ? p0 + chunk : n_total;
+  uint32_t f = offsets ? find_segment(offsets, n_filters, p0) : 0u;
+  for (int64_t g0 = p0; g0 < p1; ++f) {
+    const int64_t base = offsets ? offsets[f] : 0;
+    const int64_t end = offsets ? offsets[f + 1] : n_total;
+    const int64_t q1 = end < p1 ? end : p1;
+    if (q1 <= g0) continue;  // empty segment
+    const uint32_t n = (uint32_t)(end - base);
+    const int32_t steps = B_dev ? B_dev[f] : B;
+    const uint32_t filt = filter_base + f;
+    if (CAP > 0 && n <= (uint32_t)CAP) {
+      __syncthreads();  // the previous segment's chains are done with sw
+      stage_weights(w + base, n, sw);
+      __syncthreads();
+      for (int64_t g = g0 + threadIdx.x; g < q1; g += THREADS)
+        a[g] = (int32_t)metropolis_chain(sw, key, (uint32_t)(g - base), filt, offset, n, steps);
+    } else if (CAP > 0) {  // a long segment in a staged launch: plain chains
+      for (int64_t g = g0 + threadIdx.x; g < q1; g += THREADS)
+        a[g] = (int32_t)metropolis_chain(w + base, key, (uint32_t)(g - base), filt, offset, n,
+                                         steps);
+    } else {
+      for (int64_t g = g0 + threadIdx.x; g < q1; g += THREADS) {
+        const uint32_t i = (uint32_t)(g - base);
+        const T* __restrict__ ws = w + base;
+        uint32_t k = i;
+        double wk = (double)ws[i];
+        const int32_t groups = (steps + 3) / 4;
+        MGroup ga, gb;
+        if (groups > 0) metropolis_fetch(ws, key, i, filt, offset, n, steps, 0, ga);
+        for (int32_t m = 0; m < groups; m += 2) {
+          if (m + 1 < groups) metropolis_fetch(ws, key, i, filt, offset, n, steps, m + 1, gb);
+          metropolis_accept(ga, k, wk);
+          if (m + 2 < groups) metropolis_fetch(ws, key, i, filt, offset, n, steps, m + 2, ga);
+          if (m + 1 < groups) metropolis_accept(gb, k, wk);
+        }
+        a[g] = (int32_t)k;
+      }
+    }
+    g0 = q1;
+  }
+}
+
+// ------------------------------------------------------------------ bound table
+// For a vector too long for LDS, an upper bound of the weights, one per bucket
+// of S = 2^shift consecutive particles, lets most proposals be rejected
+// without loading w_j: if u * w_k > ub >= w_j the step (or trial) rejects.
+// The bound is a power of two, 2^(cM - 127 - c4): cM is the largest bucket
+// code of the vector and c4 = min(15, cM - c) the 4-bit distance of the
+// bucket's code c, where 2^(c - 127) >= the bucket maximum.  Two buckets per
+// LDS byte: 128 KB cover 2^18 buckets.  The skip test compares
+// u * (a lower bound of w_k) with ub after scaling the product down by
+// (1 - 2^-50), which exceeds the rounding of the few products involved, so a
+// skipped step is one that the exact test rejects; the output is the same.
+constexpr int kTableBuckets = 1 << 18;  // nibbles in LDS (128 KB)
+constexpr int kTableThreads = 1024;
+constexpr int kCodeThreads = 256;
+
+__device__ __forceinline__ uint32_t bound_code(float v) {
+  const uint32_t b = __float_as_uint(v);
+  return (b >> 23) + ((b & 0x7FFFFFu) != 0u);  // 0 .. 255 for finite v >= 0
+}
+__device__ __forceinline__ uint32_t bound_code(double v) {
+  const uint64_t b = (uint64_t)__double_as_longlong(v);
+  const int e = (int)((b >> 52) & 0x7FF);
+  if (e == 0) return 0u;  // zero or below 2^-1022
+  const int c = e - 1023 + 127 + (((b & 0xFFFFFFFFFFFFFull) != 0ull) ? 1 : 0);
+  return c < 0 ? 0u : (c > 255 ? 255u : (uint32_t)c);
+}
+
+// One thread per bucket: its 8-bit code; per workgroup the largest code.
+// Invalid weights (negative, non-finite) give code 255, which disables the
+// skips of the vector (the kernels then load every weight).
+template <typename T>
+__global__ __launch_bounds__(kCodeThreads) void k_bound_codes(const T* __restrict__ w, int64_t n,
+                                                              int shift,
+                                                              uint8_t* __restrict__ codes,
+                                                              uint32_t* __restrict__ wg_max) {
+  __shared__ uint32_t slot[kCodeThreads / kWave];
+  const int64_t b = (int64_t)blockIdx.x * kCodeThreads + threadIdx.x;
+  const int64_t S = (int64_t)1 << shift;
+  uint32_t c = 0;
+  if ((b << shift) < n) {
+    const int64_t e = ((b + 1) << shift) < n ? ((b + 1) << shift) : n;
+    for (int64_t k = b << shift; k < e; ++k) {
+      const T v = w[k];
+      const uint32_t ck = weight_ok(v) ? bound_code(v) : 255u;
+      c = ck > c ? ck : c;
+    }
+    codes[b] = (uint8_t)c;
+  }
+  (void)S;
+  c = wave_reduce(c, OpMax());
+  if (lane_id() == 0) slot[threadIdx.x / kWave] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    uint32_t m = slot[0];
+    for (int k = 1; k < kCodeThreads / kWave; ++k) m = slot[k] > m ? slot[k] : m;
+    wg_max[blockIdx.x] = m;
+  }
+}
+
+struct BoundTable {
+  const uint8_t* nib;  // LDS, two 4-bit codes per byte
+  int shift;
+  int cM;
+  bool usable;
+  __device__ __forceinline__ double ub(uint32_t j) const {
+    const uint32_t b = j >> shift;
+    const uint32_t c4 = (nib[b >> 1] >> ((b & 1u) * 4u)) & 15u;
+    return ldexp(1.0, cM - 127 - (int)c4);
+  }
+  // true when u * lb > ub(j), i.e. u * w_k > w_j for every w_k >= lb
+  __device__ __forceinline__ bool rejects(double u, double lb, uint32_t j) const {
+    return usable && (u * lb) * (1.0 - 0x1p-50) > ub(j);
+  }
+};
+
+// Workgroup prologue: the largest code from the per-workgroup maxima and the
+// 4-bit table in LDS.
+__device__ BoundTable load_bound_table(const uint8_t* __restrict__ codes,
+                                       const uint32_t* __restrict__ wg_max, uint32_t n_wg,
+                                       uint32_t nb, int shift, uint8_t* nib, uint32_t* slot) {
+  uint32_t m = 0;
+  for (uint32_t k = threadIdx.x; k < n_wg; k += blockDim.x) m = wg_max[k] > m ? wg_max[k] : m;
+  m = wave_reduce(m, OpMax());
+  if (lane_id() == 0) slot[threadIdx.x / kWave] = m;
+  __syncthreads();
+  uint32_t cM = slot[0];
+  for (uint32_t k = 1; k < blockDim.x / kWave; ++k) cM = slot[k] > cM ? slot[k] : cM;
+  // 8 codes per thread and pass (the code array is padded to a multiple of 8;
+  // the padding is never looked up)
+  const uint2* __restrict__ c8 = reinterpret_cast<const uint2*>(codes);
+  uint32_t* nib32 = reinterpret_cast<uint32_t*>(nib);
+  for (uint32_t p = threadIdx.x; 8 * p < nb; p += blockDim.x) {
+    const uint2 v = c8[p];
+    uint32_t packed = 0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const uint32_t c = ((q < 4 ? v.x : v.y) >> (8 * (q & 3))) & 0xFFu;
+      const uint32_t d = c > cM ? 15u : (cM - c > 15u ? 15u : cM - c);
+      packed |= d << (4 * q);
+    }
+    nib32[p] = packed;
+  }
+  __syncthreads();
+  BoundTable t;
+  t.nib = nib;
+  t.shift = shift;
+  t.cM = (int)cM;
+  t.usable = cM < 255u;
+  return t;
+}
+
+// Metropolis group with skips: step q of the group loads w_j only when the
+// table cannot reject it for the lower bound lb of w_k at that step; lb starts
+// at lb0 and is multiplied by u for every step that may accept (an accepted
+// move lands on w_j >= u * w_k).  prod returns that product.
+struct TGroup {
+  uint32_t j[4];
+  uint32_t u[4];
+  double wj[4];
+  uint32_t skip;
+  double prod;
+  int nq;
+};
+
+template <typename T>
+__device__ __forceinline__ void metropolis_fetch_table(const T* __restrict__ ws,
+                                                       const BoundTable& tab, Key key, uint32_t i,
+                                                       uint32_t filt, uint32_t offset, uint32_t n,
+                                                       int32_t steps, int32_t m, double lb0,
+                                                       TGroup& g) {
+  uint32_t x[12];
+  const int32_t left = steps - 4 * m;
+  const int ncall = left >= 4 ? 3 : (3 * left + 3) / 4;
+#pragma unroll
+  for (int c3 = 0; c3 < 3; ++c3) {
+    if (c3 < ncall) {
+      const uint4 v = draw(key, i, DOM_TRIAL, (uint32_t)(3 * m + c3), filt, offset);
+      x[4 * c3 + 0] = v.x;
+      x[4 * c3 + 1] = v.y;
+      x[4 * c3 + 2] = v.z;
+      x[4 * c3 + 3] = v.w;
+    }
+  }
+  g.nq = left >= 4 ? 4 : left;
+  g.skip = 0;
+  double lb = lb0, prod = 1.0;
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    g.j[q] = q < g.nq ? index_draw(x[3 * q], x[3 * q + 1], n) : i;
+    g.u[q] = x[3 * q + 2];
+    const double u = u_accept(g.u[q]);
+    g.wj[q] = 0.0;
+    if (q < g.nq) {
+      if (tab.rejects(u, lb, g.j[q])) {
+        g.skip |= 1u << q;
+      } else {
+        g.wj[q] = (double)ws[g.j[q]];
+        lb = (lb * u) * (1.0 - 0x1p-50);
+        prod = (prod * u) * (1.0 - 0x1p-50);
+      }
+    }
+  }
+  g.prod = prod;
+}
+
+__device__ __forceinline__ void metropolis_accept_table(const TGroup& g, uint32_t& k, double& wk) {
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    if (q < g.nq && !((g.skip >> q) & 1u) && accept_exact(u_accept(g.u[q]), wk, g.wj[q])) {
+      k = g.j[q];
+      wk = g.wj[q];
+    }
+  }
+}
+
+// One vector (no segments) with the LDS bound table; workgroups take chunks.
+template <typename T>
+__global__ __launch_bounds__(kTableThreads) void k_metropolis_table(
+    const T* __restrict__ w, int64_t n, int32_t B, Key key, uint32_t offset, uint32_t filter,
+    int32_t* __restrict__ a, int64_t chunk, const uint8_t* __restrict__ codes,
+    const uint32_t* __restrict__ wg_max, uint32_t n_wg, uint32_t nb, int shift) {
+  __shared__ uint8_t nib[kTableBuckets / 2];
+  __shared__ uint32_t slot[kTableThreads / kWave];
+  offset = counter_offset(key, offset);
+  const BoundTable tab = load_bound_table(codes, wg_max, n_wg, nb, shift, nib, slot);
+  const int64_t p0 = (int64_t)blockIdx.x * chunk;
+  const int64_t p1 = p0 + chunk < n ? p0 + chunk : n;
+  const int32_t groups = (B + 3) / 4;
+  for (int64_t g = p0 + threadIdx.x; g < p1; g += kTableThreads) {
+    const uint32_t i = (uint32_t)g;
     uint32_t k = i;
-    double wk = (double)ws[i];
-    const int32_t groups = (steps + 3) / 4;
-    MGroup ga, gb;
-    if (groups > 0) metropolis_fetch(ws, key, i, filt, offset, c.n, steps, 0, ga);
+    double wk = (double)w[i];
+    TGroup ga, gb;
+    double lb_a = wk;  // lower bound of w_k at the start of group ga
+    if (groups > 0) metropolis_fetch_table(w, tab, key, i, filter, offset, (uint32_t)n, B, 0, lb_a, ga);
     for (int32_t m = 0; m < groups; m += 2) {
-      if (m + 1 < groups) metropolis_fetch(ws, key, i, filt, offset, c.n, steps, m + 1, gb);
-      metropolis_accept(ga, k, wk);
-      if (m + 2 < groups) metropolis_fetch(ws, key, i, filt, offset, c.n, steps, m + 2, ga);
-      if (m + 1 < groups) metropolis_accept(gb, k, wk);
+      if (m + 1 < groups)
+        metropolis_fetch_table(w, tab, key, i, filter, offset, (uint32_t)n, B, m + 1,
+                               (lb_a * ga.prod) * (1.0 - 0x1p-50), gb);
+      metropolis_accept_table(ga, k, wk);
+      if (m + 2 < groups) {
+        lb_a = (wk * gb.prod) * (1.0 - 0x1p-50);
+        metropolis_fetch_table(w, tab, key, i, filter, offset, (uint32_t)n, B, m + 2, lb_a, ga);
+      }
+      if (m + 1 < groups) metropolis_accept_table(gb, k, wk);
     }
     a[g] = (int32_t)k;
   }
@@ -146,26 +402,19 @@ __device__ __forceinline__ int nth_set_bit(uint64_t mask, int q) {
   return pos;
 }
 
-template <typename T>
-__global__ __launch_bounds__(256) void k_rejection(const T* __restrict__ w, int64_t n_total,
-                                                   const int64_t* __restrict__ offsets,
-                                                   uint32_t n_filters, double w_max,
-                                                   const double* __restrict__ w_max_dev,
-                                                   uint32_t max_trials, Key key, uint32_t offset,
-                                                   uint32_t filter_base, int32_t* __restrict__ a,
-                                                   uint32_t* __restrict__ flags,
-                                                   int64_t per_wave) {
-  offset = counter_offset(key, offset);
+// One wave works through the particles [r0, r1) (global indices) of one
+// segment (weights ws, length n, filter id filt).
+// With TABLE, a trial whose u * w_max exceeds the bucket bound of j is
+// rejected without loading w_j.
+template <bool TABLE, typename T>
+__device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint32_t filt,
+                                     double wmax, int64_t r0, int64_t r1, uint32_t max_trials,
+                                     Key key, uint32_t offset, int32_t* __restrict__ a,
+                                     uint32_t& my_flags, const BoundTable& tab) {
   const uint32_t lane = lane_id();
-  const int64_t gw = (int64_t)blockIdx.x * (blockDim.x / kWave) + threadIdx.x / kWave;
-  const int64_t r0 = gw * per_wave;
-  const int64_t r1 = r0 + per_wave < n_total ? r0 + per_wave : n_total;
   int64_t next = r0;  // wave-uniform: next particle of the range to hand out
   int64_t cur = -1;   // particle (global index) this lane works on
   uint32_t t = 0;     // its next trial
-  SegCtx c = {0, 0, 0};
-  double wmax = w_max;
-  uint32_t my_flags = 0;
 
   // main phase: one trial per lane per pass
   while (true) {
@@ -178,18 +427,17 @@ __global__ __launch_bounds__(256) void k_rejection(const T* __restrict__ w, int6
       if (cur < 0 && rank < take) {
         cur = next + rank;
         t = 0;
-        c = seg_of(offsets, n_filters, n_total, cur);
-        wmax = w_max_dev ? w_max_dev[c.f] : w_max;
       }
       next += take;
     }
     if (next >= r1) break;
     if (cur >= 0) {
-      const uint32_t i = (uint32_t)(cur - c.base);
-      const uint4 x = draw(key, i, DOM_TRIAL, t, filter_base + c.f, offset);
-      const uint32_t j = (t == 0) ? i : index_draw(x.x, x.y, c.n);
-      const double wj = (double)w[c.base + j];
-      if (accept_exact(u_accept(x.z), wmax, wj)) {
+      const uint32_t i = (uint32_t)(cur - base);
+      const uint4 x = draw(key, i, DOM_TRIAL, t, filt, offset);
+      const uint32_t j = (t == 0) ? i : index_draw(x.x, x.y, n);
+      const double u = u_accept(x.z);
+      const bool skip = TABLE && tab.rejects(u, wmax, j);
+      if (!skip && accept_exact(u, wmax, (double)ws[j])) {
         a[cur] = (int32_t)j;
         cur = -1;
       } else if (++t >= max_trials) {
@@ -211,18 +459,15 @@ __global__ __launch_bounds__(256) void k_rejection(const T* __restrict__ w, int6
     const int owner = helper ? nth_set_bit(act, q) : (int)lane;
     const int64_t o_cur = shfl(cur, owner);
     const uint32_t o_t = shfl(t, owner);
-    const int64_t o_base = shfl(c.base, owner);
-    const uint32_t o_n = shfl(c.n, owner);
-    const uint32_t o_f = shfl(c.f, owner);
-    const double o_wmax = shfl(wmax, owner);
     const uint32_t tt = o_t + (lane - (uint32_t)(q * slot));
     bool acc = false;
     uint32_t jj = 0;
     if (helper && tt < max_trials) {
-      const uint32_t i = (uint32_t)(o_cur - o_base);
-      const uint4 x = draw(key, i, DOM_TRIAL, tt, filter_base + o_f, offset);
-      jj = (tt == 0) ? i : index_draw(x.x, x.y, o_n);
-      acc = accept_exact(u_accept(x.z), o_wmax, (double)w[o_base + jj]);
+      const uint32_t i = (uint32_t)(o_cur - base);
+      const uint4 x = draw(key, i, DOM_TRIAL, tt, filt, offset);
+      jj = (tt == 0) ? i : index_draw(x.x, x.y, n);
+      const double u = u_accept(x.z);
+      acc = !(TABLE && tab.rejects(u, wmax, jj)) && accept_exact(u, wmax, (double)ws[jj]);
     }
     const uint64_t accm = ballot(acc);
     int src = (int)lane;
@@ -241,79 +486,284 @@ __global__ __launch_bounds__(256) void k_rejection(const T* __restrict__ w, int6
       } else {
         t += (uint32_t)slot;
         if (t >= max_trials) {
-          a[cur] = (int32_t)(cur - c.base);
+          a[cur] = (int32_t)(cur - base);
           my_flags |= FLAG_TRIAL_CAP;
           cur = -1;
         }
       }
     }
   }
+}
 
+// A workgroup takes the particles [p0, p1) and walks the segments that overlap
+// them; each segment part is split evenly among the workgroup's waves.  A
+// segment of at most CAP weights is first copied into LDS.
+template <typename T, int CAP, int THREADS>
+__global__ __launch_bounds__(THREADS) void k_rejection(
+    const T* __restrict__ w, int64_t n_total, const int64_t* __restrict__ offsets,
+    uint32_t n_filters, double w_max, const double* __restrict__ w_max_dev, uint32_t max_trials,
+    Key key, uint32_t offset, uint32_t filter_base, int32_t* __restrict__ a,
+    uint32_t* __restrict__ flags, int64_t chunk) {
+  __shared__ T sw[CAP > 0 ? CAP : 1];
+  offset = counter_offset(key, offset);
+  constexpr int kWaves = THREADS / kWave;
+  const int wave = (int)threadIdx.x / kWave;
+  const int64_t p0 = (int64_t)blockIdx.x * chunk;
+  const int64_t p1 = p0 + chunk < n_total ? p0 + chunk : n_total;
+  uint32_t my_flags = 0;
+  uint32_t f = offsets ? find_segment(offsets, n_filters, p0) : 0u;
+  for (int64_t g0 = p0; g0 < p1; ++f) {
+    const int64_t base = offsets ? offsets[f] : 0;
+    const int64_t end = offsets ? offsets[f + 1] : n_total;
+    const int64_t q1 = end < p1 ? end : p1;
+    if (q1 <= g0) continue;  // empty segment
+    const uint32_t n = (uint32_t)(end - base);
+    const double wmax = w_max_dev ? w_max_dev[f] : w_max;
+    const int64_t len = q1 - g0;
+    const int64_t r0 = g0 + len * wave / kWaves;
+    const int64_t r1 = g0 + len * (wave + 1) / kWaves;
+    if (CAP > 0 && n <= (uint32_t)CAP) {
+      __syncthreads();  // the previous segment's trials are done with sw
+      stage_weights(w + base, n, sw);
+      __syncthreads();
+      rejection_wave_range<false>(sw, base, n, filter_base + f, wmax, r0, r1, max_trials, key,
+                                  offset, a, my_flags, BoundTable{});
+    } else {
+      rejection_wave_range<false>(w + base, base, n, filter_base + f, wmax, r0, r1, max_trials,
+                                  key, offset, a, my_flags, BoundTable{});
+    }
+    g0 = q1;
+  }
   if (flags) {
     const uint32_t wf = wave_reduce(my_flags, OpOr());
-    if (lane == 0 && wf) atomicOr(flags, wf);
+    if (lane_id() == 0 && wf) atomicOr(flags, wf);
+  }
+}
+
+// One vector with the LDS bound table; the workgroup's chunk is split among
+// its waves.
+template <typename T>
+__global__ __launch_bounds__(kTableThreads) void k_rejection_table(
+    const T* __restrict__ w, int64_t n, double w_max, uint32_t max_trials, Key key,
+    uint32_t offset, uint32_t filter, int32_t* __restrict__ a, uint32_t* __restrict__ flags,
+    int64_t chunk, const uint8_t* __restrict__ codes, const uint32_t* __restrict__ wg_max,
+    uint32_t n_wg, uint32_t nb, int shift) {
+  __shared__ uint8_t nib[kTableBuckets / 2];
+  __shared__ uint32_t slot[kTableThreads / kWave];
+  offset = counter_offset(key, offset);
+  const BoundTable tab = load_bound_table(codes, wg_max, n_wg, nb, shift, nib, slot);
+  constexpr int kWaves = kTableThreads / kWave;
+  const int wave = (int)threadIdx.x / kWave;
+  const int64_t p0 = (int64_t)blockIdx.x * chunk;
+  const int64_t p1 = p0 + chunk < n ? p0 + chunk : n;
+  uint32_t my_flags = 0;
+  if (p0 < p1) {
+    const int64_t len = p1 - p0;
+    rejection_wave_range<true>(w, 0, (uint32_t)n, filter, w_max, p0 + len * wave / kWaves,
+                               p0 + len * (wave + 1) / kWaves, max_trials, key, offset, a,
+                               my_flags, tab);
+  }
+  if (flags) {
+    const uint32_t wf = wave_reduce(my_flags, OpOr());
+    if (lane_id() == 0 && wf) atomicOr(flags, wf);
   }
 }
 
 // ------------------------------------------------------------------ launchers
+// LDS capacity (weights) for the longest segment: 16, 64 or 128 KB, or none
+// when some segment is longer (or the lengths are unknown and the vector is
+// long) -- then every weight load goes to global memory.
 template <typename T>
-hipError_t launch_metropolis_t(const void* w, int64_t n_total, const int64_t* offsets,
-                               uint32_t n_filters, int32_t B, const int32_t* B_dev, Key key,
-                               uint32_t offset, uint32_t filter_base, int32_t* a,
-                               hipStream_t stream) {
-  const int threads = 256;
-  int64_t blocks = (n_total + threads - 1) / threads;
-  if (blocks > (1 << 20)) blocks = 1 << 20;
-  hipLaunchKernelGGL(k_metropolis<T>, dim3((unsigned)blocks), dim3(threads), 0, stream,
-                     (const T*)w, n_total, offsets, n_filters, B, B_dev, key, offset, filter_base,
-                     a);
+int staged_capacity(int64_t max_len, int64_t n_total, uint32_t n_filters) {
+  constexpr int64_t per_kb = 1024 / (int64_t)sizeof(T);
+  if (n_filters == 1) max_len = n_total;
+  if (max_len <= 0) max_len = (int64_t)128 * per_kb;
+  if (max_len <= 16 * per_kb) return (int)(16 * per_kb);
+  if (max_len <= 64 * per_kb) return (int)(64 * per_kb);
+  // batches: longer segments run in the same launch from global memory
+  if (n_filters > 1) return (int)(128 * per_kb);
+  return 0;
+}
+
+template <typename T>
+hipError_t launch_metropolis_t(const void* wv, int64_t n_total, const int64_t* offsets,
+                               uint32_t n_filters, int64_t max_len, int32_t B,
+                               const int32_t* B_dev, Key key, uint32_t offset,
+                               uint32_t filter_base, int32_t* a, hipStream_t stream) {
+  const T* w = (const T*)wv;
+  constexpr int per_kb = 1024 / (int)sizeof(T);
+  const int cap = staged_capacity<T>(max_len, n_total, n_filters);
+  if (cap == 0) {
+    const int64_t chunk = 256;
+    hipLaunchKernelGGL((k_metropolis_staged<T, 0, 256>), dim3((unsigned)((n_total + chunk - 1) / chunk)),
+                       dim3(256), 0, stream, w, n_total, offsets, n_filters, B, B_dev, key, offset,
+                       filter_base, a, chunk);
+    return hipGetLastError();
+  }
+  const int64_t chunk = 4096;
+  const dim3 grid((unsigned)((n_total + chunk - 1) / chunk));
+  if (cap == 16 * per_kb)
+    hipLaunchKernelGGL((k_metropolis_staged<T, 16 * per_kb, 1024>), grid, dim3(1024), 0, stream, w,
+                       n_total, offsets, n_filters, B, B_dev, key, offset, filter_base, a, chunk);
+  else if (cap == 64 * per_kb)
+    hipLaunchKernelGGL((k_metropolis_staged<T, 64 * per_kb, 1024>), grid, dim3(1024), 0, stream, w,
+                       n_total, offsets, n_filters, B, B_dev, key, offset, filter_base, a, chunk);
+  else
+    hipLaunchKernelGGL((k_metropolis_staged<T, 128 * per_kb, 1024>), grid, dim3(1024), 0, stream,
+                       w, n_total, offsets, n_filters, B, B_dev, key, offset, filter_base, a,
+                       chunk);
+  return hipGetLastError();
+}
+
+// Bound-table geometry for one vector of n weights: buckets of 2^shift
+// particles, at most kTableBuckets of them.
+struct TableGeom {
+  int shift;
+  uint32_t nb, n_wg;
+  size_t wg_off, codes_off, bytes;
+};
+
+TableGeom table_geom(int64_t n) {
+  TableGeom g;
+  g.shift = 2;
+  while ((((n - 1) >> g.shift) + 1) > kTableBuckets) ++g.shift;
+  g.nb = (uint32_t)(((n - 1) >> g.shift) + 1);
+  g.n_wg = (g.nb + kCodeThreads - 1) / kCodeThreads;
+  g.wg_off = 0;
+  g.codes_off = ((size_t)g.n_wg * 4 + 255) & ~(size_t)255;
+  g.bytes = g.codes_off + (((size_t)g.nb + 7) / 8 * 8 + 255) / 256 * 256;
+  return g;
+}
+
+// A vector long enough for the table path: not staged in LDS, and long enough
+// that the table prologue pays off.
+template <typename T>
+bool use_table(int64_t n_total, uint32_t n_filters, int64_t max_len) {
+  return n_filters == 1 && n_total >= (1 << 16) &&
+         staged_capacity<T>(max_len, n_total, n_filters) == 0;
+}
+
+size_t alt_workspace_bytes(bool f64, int64_t n_total, uint32_t n_filters, int64_t max_len) {
+  const bool t = f64 ? use_table<double>(n_total, n_filters, max_len)
+                     : use_table<float>(n_total, n_filters, max_len);
+  return t ? table_geom(n_total).bytes : 0;
+}
+
+template <typename T>
+hipError_t launch_bound_codes(const T* w, int64_t n, const TableGeom& g, void* ws,
+                              hipStream_t stream) {
+  char* base = (char*)ws;
+  hipLaunchKernelGGL(k_bound_codes<T>, dim3(g.n_wg), dim3(kCodeThreads), 0, stream, w, n, g.shift,
+                     (uint8_t*)(base + g.codes_off), (uint32_t*)(base + g.wg_off));
+  return hipGetLastError();
+}
+
+// Workgroups of the table kernels: one per CU, each with a chunk of particles.
+constexpr int64_t kTableGrid = 256;
+
+template <typename T>
+hipError_t launch_metropolis_table(const T* w, int64_t n, int32_t B, Key key, uint32_t offset,
+                                   uint32_t filter, int32_t* a, void* ws, hipStream_t stream) {
+  const TableGeom g = table_geom(n);
+  hipError_t e = launch_bound_codes(w, n, g, ws, stream);
+  if (e != hipSuccess) return e;
+  const int64_t chunk = (n + kTableGrid - 1) / kTableGrid;
+  char* base = (char*)ws;
+  hipLaunchKernelGGL(k_metropolis_table<T>, dim3((unsigned)((n + chunk - 1) / chunk)),
+                     dim3(kTableThreads), 0, stream, w, n, B, key, offset, filter, a, chunk,
+                     (const uint8_t*)(base + g.codes_off), (const uint32_t*)(base + g.wg_off),
+                     g.n_wg, g.nb, g.shift);
   return hipGetLastError();
 }
 
 hipError_t launch_metropolis(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
-                             uint32_t n_filters, int32_t B, const int32_t* B_dev, Key key,
-                             uint32_t offset, uint32_t filter_base, int32_t* a,
-                             hipStream_t stream) {
-  return f64 ? launch_metropolis_t<double>(w, n_total, offsets, n_filters, B, B_dev, key, offset,
-                                           filter_base, a, stream)
-             : launch_metropolis_t<float>(w, n_total, offsets, n_filters, B, B_dev, key, offset,
-                                          filter_base, a, stream);
+                             uint32_t n_filters, int64_t max_len, int32_t B, const int32_t* B_dev,
+                             Key key, uint32_t offset, uint32_t filter_base, int32_t* a, void* ws,
+                             size_t ws_bytes, hipStream_t stream) {
+  if (ws && !B_dev && ws_bytes >= alt_workspace_bytes(f64, n_total, n_filters, max_len) &&
+      (f64 ? use_table<double>(n_total, n_filters, max_len)
+           : use_table<float>(n_total, n_filters, max_len)))
+    return f64 ? launch_metropolis_table((const double*)w, n_total, B, key, offset, filter_base,
+                                         a, ws, stream)
+               : launch_metropolis_table((const float*)w, n_total, B, key, offset, filter_base, a,
+                                         ws, stream);
+  return f64 ? launch_metropolis_t<double>(w, n_total, offsets, n_filters, max_len, B, B_dev, key,
+                                           offset, filter_base, a, stream)
+             : launch_metropolis_t<float>(w, n_total, offsets, n_filters, max_len, B, B_dev, key,
+                                          offset, filter_base, a, stream);
 }
 
+// Particles per wave of the rejection schedule.
+constexpr int64_t kRejectionPerWave = 256;
+
 template <typename T>
-hipError_t launch_rejection_t(const void* w, int64_t n_total, const int64_t* offsets,
-                              uint32_t n_filters, double w_max, const double* w_max_dev,
-                              uint32_t max_trials, Key key, uint32_t offset, uint32_t filter_base,
-                              int32_t* a, uint32_t* flags, int64_t per_wave, hipStream_t stream) {
-  const int threads = 256;
-  const int64_t waves = (n_total + per_wave - 1) / per_wave;
-  const int64_t blocks = (waves + (threads / kWave) - 1) / (threads / kWave);
-  hipLaunchKernelGGL(k_rejection<T>, dim3((unsigned)blocks), dim3(threads), 0, stream,
-                     (const T*)w, n_total, offsets, n_filters, w_max, w_max_dev, max_trials, key,
-                     offset, filter_base, a, flags, per_wave);
+hipError_t launch_rejection_t(const void* wv, int64_t n_total, const int64_t* offsets,
+                              uint32_t n_filters, int64_t max_len, double w_max,
+                              const double* w_max_dev, uint32_t max_trials, Key key,
+                              uint32_t offset, uint32_t filter_base, int32_t* a, uint32_t* flags,
+                              hipStream_t stream) {
+  const T* w = (const T*)wv;
+  constexpr int per_kb = 1024 / (int)sizeof(T);
+  const int cap = staged_capacity<T>(max_len, n_total, n_filters);
+  if (cap == 0) {
+    const int64_t chunk = kRejectionPerWave * 4;
+    hipLaunchKernelGGL((k_rejection<T, 0, 256>), dim3((unsigned)((n_total + chunk - 1) / chunk)),
+                       dim3(256), 0, stream, w, n_total, offsets, n_filters, w_max, w_max_dev,
+                       max_trials, key, offset, filter_base, a, flags, chunk);
+    return hipGetLastError();
+  }
+  const int64_t chunk = kRejectionPerWave * 16;
+  const dim3 grid((unsigned)((n_total + chunk - 1) / chunk));
+  if (cap == 16 * per_kb)
+    hipLaunchKernelGGL((k_rejection<T, 16 * per_kb, 1024>), grid, dim3(1024), 0, stream, w,
+                       n_total, offsets, n_filters, w_max, w_max_dev, max_trials, key, offset,
+                       filter_base, a, flags, chunk);
+  else if (cap == 64 * per_kb)
+    hipLaunchKernelGGL((k_rejection<T, 64 * per_kb, 1024>), grid, dim3(1024), 0, stream, w,
+                       n_total, offsets, n_filters, w_max, w_max_dev, max_trials, key, offset,
+                       filter_base, a, flags, chunk);
+  else
+    hipLaunchKernelGGL((k_rejection<T, 128 * per_kb, 1024>), grid, dim3(1024), 0, stream, w,
+                       n_total, offsets, n_filters, w_max, w_max_dev, max_trials, key, offset,
+                       filter_base, a, flags, chunk);
   return hipGetLastError();
 }
 
-// Particles per wave: enough waves to fill the chip (about 16 per CU), at
-// least one particle per lane.
-int64_t rejection_per_wave(int64_t n_total) {
-  const int64_t target_waves = 256 * 16;
-  int64_t p = (n_total + target_waves - 1) / target_waves;
-  if (p < kWave) p = kWave;
-  return p;
+template <typename T>
+hipError_t launch_rejection_table(const T* w, int64_t n, double w_max, uint32_t max_trials,
+                                  Key key, uint32_t offset, uint32_t filter, int32_t* a,
+                                  uint32_t* flags, void* ws, hipStream_t stream) {
+  const TableGeom g = table_geom(n);
+  hipError_t e = launch_bound_codes(w, n, g, ws, stream);
+  if (e != hipSuccess) return e;
+  // chunks of 16 waves x kRejectionPerWave particles, several per CU
+  const int64_t chunk = kRejectionPerWave * (kTableThreads / kWave);
+  char* base = (char*)ws;
+  hipLaunchKernelGGL(k_rejection_table<T>, dim3((unsigned)((n + chunk - 1) / chunk)),
+                     dim3(kTableThreads), 0, stream, w, n, w_max, max_trials, key, offset, filter,
+                     a, flags, chunk, (const uint8_t*)(base + g.codes_off),
+                     (const uint32_t*)(base + g.wg_off), g.n_wg, g.nb, g.shift);
+  return hipGetLastError();
 }
 
 hipError_t launch_rejection(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
-                            uint32_t n_filters, double w_max, const double* w_max_dev,
-                            uint32_t max_trials, Key key, uint32_t offset, uint32_t filter_base,
-                            int32_t* a, uint32_t* flags, hipStream_t stream) {
-  const int64_t pw = rejection_per_wave(n_total);
-  return f64 ? launch_rejection_t<double>(w, n_total, offsets, n_filters, w_max, w_max_dev,
-                                          max_trials, key, offset, filter_base, a, flags, pw,
-                                          stream)
-             : launch_rejection_t<float>(w, n_total, offsets, n_filters, w_max, w_max_dev,
-                                         max_trials, key, offset, filter_base, a, flags, pw,
-                                         stream);
+                            uint32_t n_filters, int64_t max_len, double w_max,
+                            const double* w_max_dev, uint32_t max_trials, Key key,
+                            uint32_t offset, uint32_t filter_base, int32_t* a, uint32_t* flags,
+                            void* ws, size_t ws_bytes, hipStream_t stream) {
+  if (ws && !w_max_dev && ws_bytes >= alt_workspace_bytes(f64, n_total, n_filters, max_len) &&
+      (f64 ? use_table<double>(n_total, n_filters, max_len)
+           : use_table<float>(n_total, n_filters, max_len)))
+    return f64 ? launch_rejection_table((const double*)w, n_total, w_max, max_trials, key, offset,
+                                        filter_base, a, flags, ws, stream)
+               : launch_rejection_table((const float*)w, n_total, w_max, max_trials, key, offset,
+                                        filter_base, a, flags, ws, stream);
+  return f64 ? launch_rejection_t<double>(w, n_total, offsets, n_filters, max_len, w_max,
+                                          w_max_dev, max_trials, key, offset, filter_base, a,
+                                          flags, stream)
+             : launch_rejection_t<float>(w, n_total, offsets, n_filters, max_len, w_max,
+                                         w_max_dev, max_trials, key, offset, filter_base, a,
+                                         flags, stream);
 }
 
 }  // namespace pfr

@@ -102,7 +102,6 @@ int collective(int scheme, const void* w, pfr_dtype dtype, const pfr_segments* s
 extern "C" {
 
 size_t pfr_workspace_bytes(pfr_op op, const pfr_segments* seg, pfr_dtype dtype) {
-  (void)dtype;
   SegInfo s;
   if (check_segments(seg, &s)) return 0;
   switch (op) {
@@ -112,9 +111,8 @@ size_t pfr_workspace_bytes(pfr_op op, const pfr_segments* seg, pfr_dtype dtype) 
       if (!uses_scan_workspace(s)) return 0;
       return scan_layout(s.n_total, op == PFR_OP_MULTINOMIAL).total;
     case PFR_OP_METROPOLIS:
-      return 0;
     case PFR_OP_REJECTION:
-      return 0;
+      return alt_workspace_bytes(dtype == PFR_F64, s.n_total, s.n_filters, s.max_len);
     case PFR_OP_OFFSPRING_TO_ANCESTORS:
       return o2a_workspace_bytes(s.n_total);
     case PFR_OP_PERMUTE:
@@ -151,7 +149,8 @@ int resample_systematic(const void* w, pfr_dtype dtype, const pfr_segments* seg,
 }
 
 int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segments* seg, int32_t B,
-                        const int32_t* B_dev, pfr_rng rng, int32_t* ancestors, void* stream) {
+                        const int32_t* B_dev, pfr_rng rng, int32_t* ancestors, void* ws,
+                        size_t ws_bytes, void* stream) {
   SegInfo s;
   int rc = check_segments(seg, &s);
   if (rc) return rc;
@@ -161,14 +160,17 @@ int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segments* seg,
   if (!w || !ancestors) return PFR_EINVAL;
   if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), ancestors, (size_t)s.n_total * 4))
     return PFR_EINVAL;
-  return launch_result(launch_metropolis(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters, B,
-                                         B_dev, make_key(rng), rng.offset, rng.filter_base,
-                                         ancestors, (hipStream_t)stream));
+  if (ws && !aligned256(ws)) return PFR_EWORKSPACE;
+  return launch_result(launch_metropolis(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters,
+                                         s.max_len, B, B_dev, make_key(rng), rng.offset,
+                                         rng.filter_base, ancestors, ws, ws ? ws_bytes : 0,
+                                         (hipStream_t)stream));
 }
 
 int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, double w_max,
                        const double* w_max_dev, uint32_t max_trials, pfr_rng rng,
-                       int32_t* ancestors, uint32_t* dev_flags, void* stream) {
+                       int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                       void* stream) {
   SegInfo s;
   int rc = check_segments(seg, &s);
   if (rc) return rc;
@@ -179,9 +181,11 @@ int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, 
   if (!w || !ancestors) return PFR_EINVAL;
   if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), ancestors, (size_t)s.n_total * 4))
     return PFR_EINVAL;
+  if (ws && !aligned256(ws)) return PFR_EWORKSPACE;
   return launch_result(launch_rejection(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters,
-                                        w_max, w_max_dev, max_trials, make_key(rng),
-                                        rng.offset, rng.filter_base, ancestors, dev_flags,
+                                        s.max_len, w_max, w_max_dev, max_trials, make_key(rng),
+                                        rng.offset, rng.filter_base, ancestors, dev_flags, ws,
+                                        ws ? ws_bytes : 0,
                                         (hipStream_t)stream));
 }
 
@@ -216,7 +220,7 @@ int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t
   if (overlaps(ws, need, permuted, (size_t)s.n_total * 4) ||
       overlaps(ws, need, ancestors, (size_t)s.n_total * 4))
     return PFR_EINVAL;
-  return launch_result(launch_permute(ancestors, s.n_total, s.offsets, s.n_filters,
+  return launch_result(launch_permute(ancestors, s.n_total, s.offsets, s.n_filters, s.max_len,
                                       sorted_hint != 0, permuted, ws, dev_flags,
                                       (hipStream_t)stream));
 }
@@ -267,12 +271,12 @@ int lgssm_step(const pfr_lgssm* model, pfr_op scheme, pfr_precision precision, i
   hipError_t e;
   switch (scheme) {
     case PFR_OP_METROPOLIS:
-      e = launch_metropolis(false, w, total, offsets, nf, 0, B_dev, rkey, 0u, rng.filter_base,
-                            ancestors, st);
+      e = launch_metropolis(false, w, total, offsets, nf, n, 0, B_dev, rkey, 0u, rng.filter_base,
+                            ancestors, nullptr, 0, st);
       break;
     case PFR_OP_REJECTION:
-      e = launch_rejection(false, w, total, offsets, nf, 1.0, nullptr, 1u << 20, rkey, 0u,
-                           rng.filter_base, ancestors, dev_flags, st);
+      e = launch_rejection(false, w, total, offsets, nf, n, 1.0, nullptr, 1u << 20, rkey, 0u,
+                           rng.filter_base, ancestors, dev_flags, nullptr, 0, st);
       break;
     default: {
       const int sch = scheme == PFR_OP_MULTINOMIAL   ? SCHEME_MULTINOMIAL
@@ -286,7 +290,7 @@ int lgssm_step(const pfr_lgssm* model, pfr_op scheme, pfr_precision precision, i
     }
   }
   if (e != hipSuccess) return PFR_ELAUNCH;
-  e = launch_permute(ancestors, total, offsets, nf, collective_scheme, permuted, perm_ws,
+  e = launch_permute(ancestors, total, offsets, nf, n, collective_scheme, permuted, perm_ws,
                      dev_flags, st);
   if (e != hipSuccess) return PFR_ELAUNCH;
   Key nkey = make_key(rng);

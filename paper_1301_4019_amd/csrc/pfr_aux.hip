@@ -335,13 +335,15 @@ __device__ __forceinline__ int64_t anc_at(const int32_t* __restrict__ a, const S
 __global__ __launch_bounds__(256) void k_claim_sorted(const int32_t* __restrict__ a,
                                                       int64_t n_total,
                                                       const int64_t* __restrict__ offsets,
-                                                      uint32_t n_filters, int32_t* __restrict__ d,
+                                                      uint32_t n_filters, int64_t min_len,
+                                                      int32_t* __restrict__ d,
                                                       int32_t* __restrict__ e,
                                                       uint32_t* __restrict__ flags) {
   bool bad = false;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
     const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    if (s.n < min_len) continue;  // permuted in LDS by k_permute_staged
     const int64_t ai = anc_at(a, s, s.i, bad);
     const int64_t prev = (s.i == 0) ? -1 : anc_at(a, s, s.i - 1, bad);
     int32_t* ds = d + s.base;
@@ -363,22 +365,25 @@ __global__ __launch_bounds__(256) void k_claim_sorted(const int32_t* __restrict_
 
 __global__ __launch_bounds__(256) void k_fill_unclaimed(int32_t* __restrict__ d, int64_t n_total,
                                                         const int64_t* __restrict__ offsets,
-                                                        uint32_t n_filters) {
+                                                        uint32_t n_filters, int64_t min_len) {
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
     const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    if (s.n < min_len) continue;
     d[g] = (int32_t)s.n;
   }
 }
 
 __global__ __launch_bounds__(256) void k_claim_min(const int32_t* __restrict__ a, int64_t n_total,
                                                    const int64_t* __restrict__ offsets,
-                                                   uint32_t n_filters, int32_t* __restrict__ d,
+                                                   uint32_t n_filters, int64_t min_len,
+                                                   int32_t* __restrict__ d,
                                                    uint32_t* __restrict__ flags) {
   bool bad = false;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
     const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    if (s.n < min_len) continue;
     const int64_t ai = anc_at(a, s, s.i, bad);
     int32_t* slot = &d[s.base + ai];
     if (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (int32_t)s.i)
@@ -393,12 +398,14 @@ __global__ __launch_bounds__(256) void k_claim_min(const int32_t* __restrict__ a
 // e[i] = a_i if position i won its claim (d[a_i] == i), else -1 - a_i.
 __global__ __launch_bounds__(256) void k_mark(const int32_t* __restrict__ a, int64_t n_total,
                                               const int64_t* __restrict__ offsets,
-                                              uint32_t n_filters, const int32_t* __restrict__ d,
+                                              uint32_t n_filters, int64_t min_len,
+                                              const int32_t* __restrict__ d,
                                               int32_t* __restrict__ e) {
   bool bad = false;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
     const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    if (s.n < min_len) continue;
     const int64_t ai = anc_at(a, s, s.i, bad);
     e[g] = d[s.base + ai] == s.i ? (int32_t)ai : (int32_t)(-1 - ai);
   }
@@ -407,7 +414,8 @@ __global__ __launch_bounds__(256) void k_mark(const int32_t* __restrict__ a, int
 // Backward walk on e: one dependent load per chain step.
 __global__ __launch_bounds__(256) void k_resolve(int64_t n_total,
                                                  const int64_t* __restrict__ offsets,
-                                                 uint32_t n_filters, const int32_t* __restrict__ d,
+                                                 uint32_t n_filters, int64_t min_len,
+                                                 const int32_t* __restrict__ d,
                                                  const int32_t* __restrict__ e,
                                                  int32_t* __restrict__ c,
                                                  uint32_t* __restrict__ flags) {
@@ -415,6 +423,7 @@ __global__ __launch_bounds__(256) void k_resolve(int64_t n_total,
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
   for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
     const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    if (s.n < min_len) continue;
     const int64_t j = s.i;
     const int64_t dj = d[g];
     if (dj >= 0 && dj < s.n) {  // claimed: its winner's ancestor is j
@@ -436,6 +445,96 @@ __global__ __launch_bounds__(256) void k_resolve(int64_t n_total,
   }
   if (flags) {
     const uint32_t b = (uint32_t)wave_reduce((uint32_t)(broken ? FLAG_BAD_ANCESTOR : 0u), OpOr());
+    if (b && lane_id() == 0) atomicOr(flags, b);
+  }
+}
+
+// Segments of at most CAP particles, one workgroup each, entirely in LDS: the
+// claim vector d (minimum claimer per slot, by LDS atomic minimum), then the
+// marked ancestry e overwrites d (a claimed-slot bitmap keeps what resolve
+// needs of d), then every slot resolves as in k_resolve.  Global traffic is
+// the ancestry read and the permutation written.
+constexpr int kPermThreads = 1024;
+
+template <int CAP>
+__global__ __launch_bounds__(kPermThreads) void k_permute_staged(
+    const int32_t* __restrict__ a, int64_t n_total, const int64_t* __restrict__ offsets,
+    uint32_t n_filters, int32_t* __restrict__ c, uint32_t* __restrict__ flags) {
+  __shared__ int32_t de[CAP];
+  __shared__ uint32_t claimed[CAP / 32];
+  constexpr int kPer = CAP / kPermThreads;  // particles per thread
+  const uint32_t f = blockIdx.x;
+  const int64_t base = offsets ? offsets[f] : 0;
+  const int64_t n64 = offsets ? offsets[f + 1] - base : n_total;
+  if (n64 <= 0 || n64 > CAP) return;  // long segments: global kernels
+  const int32_t n = (int32_t)n64;
+  const int tid = (int)threadIdx.x;
+  bool bad = false;
+  // ancestor of local position i; out-of-range values count as i
+  auto anc = [&](int32_t i) -> int32_t {
+    const int32_t v = a[base + i];
+    return (v < 0 || v >= n) ? i : v;
+  };
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int32_t i = tid + q * kPermThreads;
+    de[i] = n;
+    if (q * kPermThreads < CAP / 32 && i < CAP / 32) claimed[i] = 0u;
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int32_t i = tid + q * kPermThreads;
+    if (i < n) {
+      const int32_t v = a[base + i];
+      if (v < 0 || v >= n) bad = true;
+      atomicMin(&de[(v < 0 || v >= n) ? i : v], i);
+    }
+  }
+  __syncthreads();
+  int32_t ev[kPer];
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int32_t i = tid + q * kPermThreads;
+    ev[q] = 0;
+    if (i < n) {
+      const int32_t ai = anc(i);
+      ev[q] = de[ai] == i ? ai : -1 - ai;
+      if (de[i] < n) atomicOr(&claimed[i >> 5], 1u << (i & 31));
+    }
+  }
+  __syncthreads();
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int32_t i = tid + q * kPermThreads;
+    if (i < n) de[i] = ev[q];
+  }
+  __syncthreads();
+  bool broken = false;
+#pragma unroll
+  for (int q = 0; q < kPer; ++q) {
+    const int32_t j = tid + q * kPermThreads;
+    if (j >= n) continue;
+    if ((claimed[j >> 5] >> (j & 31)) & 1u) {
+      c[base + j] = j;
+      continue;
+    }
+    int32_t ey = de[j];
+    int32_t steps = 0;
+    bool br = false;
+    while (ey >= 0) {
+      ey = de[ey];
+      if (++steps > n) {
+        br = true;
+        break;
+      }
+    }
+    broken |= br;
+    c[base + j] = br ? j : -1 - ey;
+  }
+  if (flags) {
+    const uint32_t fl = (bad || broken) ? FLAG_BAD_ANCESTOR : 0u;
+    const uint32_t b = wave_reduce(fl, OpOr());
     if (b && lane_id() == 0) atomicOr(flags, b);
   }
 }
@@ -475,25 +574,37 @@ size_t permute_workspace_bytes(int64_t n_total) {
   return 2 * align256((size_t)n_total * sizeof(int32_t));
 }
 
+// Batches whose segments fit in LDS are permuted there (k_permute_staged, one
+// workgroup per segment); longer segments, and single vectors, go through the
+// global kernels.  max_len: longest segment (0 = unknown).
 hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offsets,
-                          uint32_t n_filters, bool sorted, int32_t* c, void* ws, uint32_t* flags,
-                          hipStream_t stream) {
+                          uint32_t n_filters, int64_t max_len, bool sorted, int32_t* c, void* ws,
+                          uint32_t* flags, hipStream_t stream) {
   int32_t* d = (int32_t*)ws;
   int32_t* e = (int32_t*)((char*)ws + align256((size_t)n_total * sizeof(int32_t)));
   const int grid = grid_for(n_total);
+  int64_t min_len = 0;  // shorter segments are done in LDS
+  if (offsets && n_filters > 1) {
+    hipLaunchKernelGGL(k_permute_staged<16384>, dim3(n_filters), dim3(kPermThreads), 0, stream, a,
+                       n_total, offsets, n_filters, c, flags);
+    hipError_t e0 = hipGetLastError();
+    if (e0 != hipSuccess) return e0;
+    if (max_len > 0 && max_len <= 16384) return hipSuccess;
+    min_len = 16385;
+  }
   if (sorted) {
     hipLaunchKernelGGL(k_claim_sorted, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
-                       n_filters, d, e, flags);
+                       n_filters, min_len, d, e, flags);
   } else {
     hipLaunchKernelGGL(k_fill_unclaimed, dim3(grid), dim3(256), 0, stream, d, n_total, offsets,
-                       n_filters);
+                       n_filters, min_len);
     hipLaunchKernelGGL(k_claim_min, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
-                       n_filters, d, flags);
-    hipLaunchKernelGGL(k_mark, dim3(grid), dim3(256), 0, stream, a, n_total, offsets, n_filters, d,
-                       e);
+                       n_filters, min_len, d, flags);
+    hipLaunchKernelGGL(k_mark, dim3(grid), dim3(256), 0, stream, a, n_total, offsets, n_filters,
+                       min_len, d, e);
   }
-  hipLaunchKernelGGL(k_resolve, dim3(grid), dim3(256), 0, stream, n_total, offsets, n_filters, d, e,
-                     c, flags);
+  hipLaunchKernelGGL(k_resolve, dim3(grid), dim3(256), 0, stream, n_total, offsets, n_filters,
+                     min_len, d, e, c, flags);
   return hipGetLastError();
 }
 

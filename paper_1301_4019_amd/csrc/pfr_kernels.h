@@ -66,14 +66,18 @@ hipError_t launch_fscan_batched(int scheme, int prec, bool f64, const void* w, i
                                 uint32_t offset, uint32_t filter_base, int32_t* a,
                                 uint32_t* flags, hipStream_t stream);
 
+// max_len: longest segment (0 = unknown); segments that fit in LDS are staged.
+// ws (may be NULL) holds the weight-bound table of a long single vector.
+size_t alt_workspace_bytes(bool f64, int64_t n_total, uint32_t n_filters, int64_t max_len);
 hipError_t launch_metropolis(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
-                             uint32_t n_filters, int32_t B, const int32_t* B_dev, Key key,
-                             uint32_t offset, uint32_t filter_base, int32_t* a,
-                             hipStream_t stream);
+                             uint32_t n_filters, int64_t max_len, int32_t B, const int32_t* B_dev,
+                             Key key, uint32_t offset, uint32_t filter_base, int32_t* a, void* ws,
+                             size_t ws_bytes, hipStream_t stream);
 hipError_t launch_rejection(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
-                            uint32_t n_filters, double w_max, const double* w_max_dev,
-                            uint32_t max_trials, Key key, uint32_t offset, uint32_t filter_base,
-                            int32_t* a, uint32_t* flags, hipStream_t stream);
+                            uint32_t n_filters, int64_t max_len, double w_max,
+                            const double* w_max_dev, uint32_t max_trials, Key key,
+                            uint32_t offset, uint32_t filter_base, int32_t* a, uint32_t* flags,
+                            void* ws, size_t ws_bytes, hipStream_t stream);
 
 size_t o2a_workspace_bytes(int64_t n_total);
 hipError_t launch_offspring_to_ancestors(const int32_t* o, int64_t n_total, const int64_t* offsets,
@@ -81,8 +85,8 @@ hipError_t launch_offspring_to_ancestors(const int32_t* o, int64_t n_total, cons
                                          uint32_t* flags, hipStream_t stream);
 size_t permute_workspace_bytes(int64_t n_total);
 hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offsets,
-                          uint32_t n_filters, bool sorted, int32_t* c, void* ws, uint32_t* flags,
-                          hipStream_t stream);
+                          uint32_t n_filters, int64_t max_len, bool sorted, int32_t* c, void* ws,
+                          uint32_t* flags, hipStream_t stream);
 
 hipError_t launch_lgssm_init(int32_t n_filters, int32_t n, double s0, Key key, uint32_t offset,
                              uint32_t filter_base, float* x, float* w, double* logz,

@@ -228,6 +228,77 @@ def test_alternatives_batched_match_single_calls():
                               oracle.rejection(seg, 1.0, seed=3, filt=10 + f)[0])
 
 
+# segment lengths that land in every LDS capacity tier (16, 64, 128 KB of
+# weights) and beyond it, with empty segments in between
+TIER_LENGTHS = [5, 0, 300, 4096, 4097, 1, 16384, 0, 16385, 32768, 32769, 70000, 2, 999]
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("max_len", ["exact", "unknown", "small_cap"])
+def test_alternatives_batched_all_capacity_tiers(dtype, max_len):
+    lens = TIER_LENGTHS
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    w = np.concatenate([inputs.weights(m, 1.0 + (f % 4), seed=200 + f, dtype=dtype)
+                        for f, m in enumerate(lens)])
+    nf = len(lens)
+    ml = {"exact": max(lens), "unknown": None, "small_cap": 3000}[max_len]
+    B = np.array([3 + (f % 9) for f in range(nf)], dtype=np.int32)
+    am = host(pfr().resample_metropolis(dev(w), 0, seed=8, offset=1, filter_base=4,
+                                        B_per_filter=dev(B), offsets=dev(off), max_len=ml))
+    ar = host(pfr().resample_rejection(dev(w), 1.0, seed=8, offset=1, filter_base=4,
+                                       offsets=dev(off), max_len=ml))
+    for f in range(nf):
+        if lens[f] == 0:
+            continue
+        seg = w[off[f]:off[f + 1]]
+        assert np.array_equal(am[off[f]:off[f + 1]],
+                              oracle.metropolis(seg, int(B[f]), seed=8, filt=4 + f, offset=1)), f
+        assert np.array_equal(ar[off[f]:off[f + 1]],
+                              oracle.rejection(seg, 1.0, seed=8, filt=4 + f, offset=1)[0]), f
+
+
+@pytest.mark.parametrize("n", [100, 4096, 16384, 16385, 40000])
+def test_alternatives_single_vector_each_tier(n):
+    w = inputs.weights(n, 3.0, seed=n + 5)
+    a = host(pfr().resample_metropolis(dev(w), 13, seed=2))
+    assert np.array_equal(a, oracle.metropolis(w, 13, seed=2))
+    a = host(pfr().resample_rejection(dev(w), 1.0, seed=2))
+    assert np.array_equal(a, oracle.rejection(w, 1.0, seed=2)[0])
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+@pytest.mark.parametrize("n,y,B", [(65536, 4.0, 354), (100003, 3.0, 60), (1 << 20, 4.0, 41),
+                                   (1 << 20, 0.5, 9), (3 << 20, 2.0, 16)])
+def test_alternatives_bound_table(dtype, n, y, B):
+    """Long single vectors use the bound table when given a workspace; the
+    result is the same as without one, and bit-exact against the oracle."""
+    w = inputs.weights(n, y, seed=n + 9, dtype=dtype)
+    wd = dev(w)
+    am = host(pfr().resample_metropolis(wd, B, seed=6, offset=2))
+    ar = host(pfr().resample_rejection(wd, 1.0, seed=6, offset=2))
+    torch_ws = torch.empty(256, dtype=torch.uint8, device="cuda")  # too small: no table
+    am0 = host(pfr().resample_metropolis(wd, B, seed=6, offset=2, workspace=torch_ws))
+    ar0 = host(pfr().resample_rejection(wd, 1.0, seed=6, offset=2, workspace=torch_ws))
+    assert np.array_equal(am, am0) and np.array_equal(ar, ar0)
+    if n <= (1 << 20):
+        assert np.array_equal(am, oracle.metropolis(w, B, seed=6, offset=2))
+        assert np.array_equal(ar, oracle.rejection(w, 1.0, seed=6, offset=2)[0])
+
+
+def test_bound_table_with_zero_and_huge_weights():
+    n = 1 << 17
+    w = inputs.weights(n, 3.0, seed=1).astype(np.float64)
+    w[::7] = 0.0
+    w[5] = 1e300  # beyond binary32 codes: the table is switched off for this vector
+    a = host(pfr().resample_metropolis(dev(w), 30, seed=3))
+    assert np.array_equal(a, oracle.metropolis(w, 30, seed=3))
+    w[5] = 1.0
+    a = host(pfr().resample_metropolis(dev(w), 30, seed=3))
+    assert np.array_equal(a, oracle.metropolis(w, 30, seed=3))
+    a = host(pfr().resample_rejection(dev(w), 1.0, seed=3))
+    assert np.array_equal(a, oracle.rejection(w, 1.0, seed=3)[0])
+
+
 # ----------------------------------------------------------------- auxiliaries
 @pytest.mark.parametrize("n", [1, 7, 4096, 4097, 50000, 1 << 20])
 def test_offspring_to_ancestors_bit_exact(n):
@@ -286,6 +357,40 @@ def test_permute_unsorted_bit_exact(n):
     a = g.integers(0, n, n).astype(np.int32)
     c = host(pfr().permute_ancestors(dev(a)))
     assert np.array_equal(c, oracle.permute(a)[0])
+
+
+@pytest.mark.parametrize("hint", [True, False])
+@pytest.mark.parametrize("max_len", [None, "exact"])
+def test_permute_batched_lds_and_global_segments(hint, max_len):
+    g = np.random.default_rng(7)
+    sizes = [5, 20000, 0, 16384, 16385, 700, 1, 40000]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    parts = []
+    for s in sizes:
+        p = g.random(s) ** 6 if s else np.zeros(0)
+        a = g.choice(s, size=s, p=p / p.sum()).astype(np.int32) if s else np.zeros(0, np.int32)
+        parts.append(np.sort(a) if hint else a)
+    a = np.concatenate(parts).astype(np.int32)
+    a[3] = 99  # out of range: treated as its own index, flagged
+    fl = new_flags()
+    c = host(pfr().permute_ancestors(dev(a), sorted_hint=hint and False, offsets=dev(off),
+                                     max_len=max(sizes) if max_len else None, flags=fl))
+    for f, s in enumerate(sizes):
+        if s == 0:
+            continue
+        ref, _ = oracle.permute(a[off[f]:off[f + 1]])
+        assert np.array_equal(c[off[f]:off[f + 1]], ref), f
+    assert int(host(fl)[0]) == pfr().FLAG_BAD_ANCESTOR
+    if hint:  # sorted input through the atomic-free claim (segment 0 has the bad value)
+        a2 = a.copy()
+        a2[3] = 0
+        a2[off[0]:off[1]] = np.sort(a2[off[0]:off[1]])
+        c2 = host(pfr().permute_ancestors(dev(a2), sorted_hint=True, offsets=dev(off),
+                                          max_len=max(sizes) if max_len else None))
+        for f, s in enumerate(sizes):
+            if s:
+                ref, _ = oracle.permute(a2[off[f]:off[f + 1]])
+                assert np.array_equal(c2[off[f]:off[f + 1]], ref), f
 
 
 def test_permute_bad_ancestors_and_batched():

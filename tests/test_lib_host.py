@@ -46,10 +46,14 @@ def test_workspace_sizes():
     assert big > 0 and multi > big and big % 256 == 0
     # a 16-byte record per 1024-weight block and a 32-byte prefix per 4096-particle tile
     assert big >= 256 + 1024 * 16 + 256 * 32
-    assert lib.pfr_workspace_bytes(_lib.OP_METROPOLIS, ctypes.byref(s_big), 0) == 0
+    # Metropolis / rejection: optional bound table for a long single vector
+    # (2^18 buckets of 4 particles: one code byte each plus per-workgroup maxima)
+    tab = lib.pfr_workspace_bytes(_lib.OP_METROPOLIS, ctypes.byref(s_big), 0)
+    assert tab >= (1 << 18) and tab % 256 == 0
+    assert lib.pfr_workspace_bytes(_lib.OP_METROPOLIS, ctypes.byref(s_small), 0) == 0
     assert lib.pfr_workspace_bytes(_lib.OP_PERMUTE, ctypes.byref(s_big), 0) >= 4 << 20
     assert lib.pfr_workspace_bytes(_lib.OP_OFFSPRING_TO_ANCESTORS, ctypes.byref(s_big), 0) >= 256 + 256 * 8
-    assert lib.pfr_workspace_bytes(_lib.OP_REJECTION, ctypes.byref(s_big), 0) == 0
+    assert lib.pfr_workspace_bytes(_lib.OP_REJECTION, ctypes.byref(s_big), 0) == tab
 
 
 def test_invalid_arguments_rejected_on_host():
@@ -79,13 +83,16 @@ def test_invalid_arguments_rejected_on_host():
     assert lib.resample_stratified(fake, 0, ctypes.byref(seg(100, 4, None)), 0, rng, out, None,
                                    0, None, None) == _lib.PFR_EINVAL
     # Metropolis step count out of range
-    assert lib.resample_metropolis(fake, 0, ctypes.byref(seg(10)), -1, None, rng, out,
+    assert lib.resample_metropolis(fake, 0, ctypes.byref(seg(10)), -1, None, rng, out, None, 0,
                                    None) == _lib.PFR_EINVAL
     # rejection: bad bound, zero trials
     assert lib.resample_rejection(fake, 0, ctypes.byref(seg(10)), 0.0, None, 16, rng, out, None,
-                                  None) == _lib.PFR_EINVAL
+                                  0, None, None) == _lib.PFR_EINVAL
     assert lib.resample_rejection(fake, 0, ctypes.byref(seg(10)), 1.0, None, 0, rng, out, None,
-                                  None) == _lib.PFR_EINVAL
+                                  0, None, None) == _lib.PFR_EINVAL
+    # misaligned optional workspace
+    assert lib.resample_metropolis(fake, 0, ctypes.byref(seg(1 << 20)), 4, None, rng, out,
+                                   ctypes.c_void_p(0x10008), 1 << 20, None) == _lib.PFR_EWORKSPACE
     # permute: output aliases input; workspace missing
     assert lib.permute_ancestors(fake, ctypes.byref(seg(10)), 1, fake, out, 1 << 20, None,
                                  None) == _lib.PFR_EINVAL
