@@ -43,6 +43,12 @@ PHILOX_PEAK_PER_S = 256 * 4 * 16 * 2.4e9 / 40.0
 GATHER_CEILING_PER_S = 2.65e11
 
 
+# HBM bytes per launch of the dominant kernel (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from
+# two rocprofv3 --pmc passes, scaled by a 256 MiB copy; profiles/metropolis_table_n2p20_pmc.md).
+# Set to None when the kernel changes until the counters are taken again.
+DOMINANT_TRAFFIC_BYTES = (43.0 + 4.0) * (1 << 20)
+
+
 def metropolis_calls_per_lane(B):
     """Philox calls of a B-step chain: four steps per three calls."""
     return 3 * (B // 4) + (3 * (B % 4) + 3) // 4
@@ -300,6 +306,9 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--copy-calibration-mb", type=int, default=0,
+                    help="first run one device-to-device copy of this many MiB, a kernel of "
+                         "known traffic for scaling hardware byte counters")
     ap.add_argument("--cpu-sample", type=int, default=1 << 18)
     ap.add_argument("--workload", choices=("step", "precision", "batch", "filter"),
                     default="step",
@@ -334,6 +343,14 @@ def main():
     torch.cuda.set_device(dev)
     log(f"libpfresample {pfr.version()} on {torch.cuda.get_device_name(0)}")
 
+    if args.copy_calibration_mb > 0:
+        nbytes = args.copy_calibration_mb << 20
+        src = torch.ones(nbytes // 4, dtype=torch.float32, device=dev)
+        dst = torch.empty_like(src)
+        dst.copy_(src)
+        torch.cuda.synchronize()
+        log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
+        del src, dst
     ws_ = [torch.from_numpy(inputs.weights(N, y, seed=100 + int(y))).to(dev) for y in YS]
     Bs = [b_star(y) for y in YS]
     out = {(y, s): torch.empty(N, dtype=torch.int32, device=dev) for y in YS for s in SCHEMES}
@@ -403,7 +420,8 @@ def main():
                 "limiter": f"random weight loads: {gathers / 1e9:.0f} G/s of steps, "
                            f"{gathers / GATHER_CEILING_PER_S:.2f} of the "
                            f"{GATHER_CEILING_PER_S / 1e9:.0f} G/s a plain gather kernel reaches",
-                "traffic": None, "avg_launch_ms": dom_ms}
+                "traffic": DOMINANT_TRAFFIC_BYTES, "traffic_unit": "bytes per launch",
+                "algorithmic_bytes": 8.0 * N, "avg_launch_ms": dom_ms}
 
     # per-scheme breakdown (untimed pass, events around each call)
     breakdown = {}

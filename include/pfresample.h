@@ -260,6 +260,35 @@ PFR_API int lgssm_step(const pfr_lgssm* model, pfr_op scheme, pfr_precision prec
                        int32_t* ancestors, int32_t* permuted, void* ws, size_t ws_bytes,
                        uint32_t* dev_flags, void* stream);
 
+/* ---------------------------------------------------------------- tuning
+ * Launch parameters of the library, chosen per machine by the autotuner
+ * (paper_1301_4019_amd/autotune.py) and loaded at start-up.  None of them
+ * changes a result: random numbers are drawn per particle and the exact
+ * prefix sums do not depend on how they are split, so every setting gives the
+ * same bits.  Process-wide; set them before launching work. */
+#define PFR_TUNING_VERSION 1
+typedef struct {
+    int32_t version;                /* PFR_TUNING_VERSION */
+    int32_t single_wg_max;          /* collective: single vectors up to this length run in one
+                                       workgroup, without workspace [0, PFR_MAX_BATCH_SEGMENT] */
+    int32_t direct_max_blocks;      /* exact collective: up to this many 1024-weight blocks every
+                                       emit workgroup forms its own carries [0, 2048] */
+    int32_t metropolis_table_min_B; /* long single vectors: the bound-table Metropolis kernel
+                                       from this many steps on (0 = never) */
+    int32_t rejection_table;        /* long single vectors: rejection with the bound table (0/1) */
+    int32_t rejection_per_wave;     /* particles per wave of the rejection schedule [64, 4096] */
+    int32_t metropolis_chunk;       /* particles per workgroup of the global-memory Metropolis
+                                       kernel, a multiple of 256 in [256, 8192] */
+} pfr_tuning;
+
+PFR_API void pfr_tuning_defaults(pfr_tuning* t);
+PFR_API int pfr_get_tuning(pfr_tuning* t);
+/* PFR_EINVAL (nothing changed) if a field is out of range or the version differs. */
+PFR_API int pfr_set_tuning(const pfr_tuning* t);
+/* Loads a flat JSON object with the fields above (absent ones keep their
+ * value); PFR_EINVAL if the file is unreadable or a value is invalid. */
+PFR_API int pfr_load_tuning(const char* path);
+
 /* ---------------------------------------------------------------- misc */
 PFR_API const char* pfr_status_string(int status);
 /* Library version, e.g. "0.1.0". */

@@ -25,7 +25,7 @@ __all__ = [
     "resample_multinomial", "resample_stratified", "resample_systematic",
     "resample_metropolis", "resample_rejection", "offspring_to_ancestors",
     "permute_ancestors", "workspace_bytes", "new_workspace", "version", "PfrError",
-    "LGSSMFilter",
+    "LGSSMFilter", "get_tuning", "set_tuning", "default_tuning",
     "SCAN_EXACT", "SCAN_F64", "SCAN_COMP_F32", "SCAN_NAIVE_F32",
     "FLAG_ZERO_TOTAL", "FLAG_TRIAL_CAP", "FLAG_BAD_COUNTS", "FLAG_BAD_WEIGHTS",
     "FLAG_BAD_ANCESTOR", "FLAG_BAD_STEP", "MAX_BATCH_SEGMENT",
@@ -39,6 +39,30 @@ def _torch():
 
 def version() -> str:
     return _lib.load().pfr_version().decode()
+
+
+def get_tuning() -> dict:
+    """The library's launch parameters (pfr_tuning in the C header)."""
+    t = _lib.Tuning()
+    _lib.check(_lib.load().pfr_get_tuning(ctypes.byref(t)), "get_tuning")
+    return {name: int(getattr(t, name)) for name, _ in _lib.Tuning._fields_ if name != "version"}
+
+
+def set_tuning(**fields) -> None:
+    """Change launch parameters (results do not depend on them)."""
+    t = _lib.Tuning()
+    _lib.check(_lib.load().pfr_get_tuning(ctypes.byref(t)), "get_tuning")
+    for k, v in fields.items():
+        if k not in dict(_lib.Tuning._fields_) or k == "version":
+            raise KeyError(k)
+        setattr(t, k, int(v))
+    _lib.check(_lib.load().pfr_set_tuning(ctypes.byref(t)), "set_tuning")
+
+
+def default_tuning() -> dict:
+    t = _lib.Tuning()
+    _lib.load().pfr_tuning_defaults(ctypes.byref(t))
+    return {name: int(getattr(t, name)) for name, _ in _lib.Tuning._fields_ if name != "version"}
 
 
 def _stream():

@@ -31,8 +31,13 @@ EXPORTS = (
     "pfr_workspace_bytes", "pfr_workspace_init", "resample_multinomial", "resample_stratified",
     "resample_systematic", "resample_metropolis", "resample_rejection", "offspring_to_ancestors",
     "permute_ancestors", "lgssm_workspace_bytes", "lgssm_init", "lgssm_step",
+    "pfr_tuning_defaults", "pfr_get_tuning", "pfr_set_tuning", "pfr_load_tuning",
     "pfr_status_string", "pfr_version",
 )
+
+TUNING_VERSION = 1
+# tuning chosen for this machine by autotune.py; PFR_TUNING overrides the path
+TUNING_PATH = os.environ.get("PFR_TUNING", os.path.join(HERE, "tuning.json"))
 
 
 class Segments(ctypes.Structure):
@@ -48,6 +53,14 @@ class Rng(ctypes.Structure):
 class LGSSM(ctypes.Structure):
     _fields_ = [("phi", ctypes.c_double), ("q", ctypes.c_double), ("r", ctypes.c_double),
                 ("s0", ctypes.c_double)]
+
+
+class Tuning(ctypes.Structure):
+    _fields_ = [("version", ctypes.c_int32), ("single_wg_max", ctypes.c_int32),
+                ("direct_max_blocks", ctypes.c_int32),
+                ("metropolis_table_min_B", ctypes.c_int32),
+                ("rejection_table", ctypes.c_int32), ("rejection_per_wave", ctypes.c_int32),
+                ("metropolis_chunk", ctypes.c_int32)]
 
 
 class PfrError(RuntimeError):
@@ -83,6 +96,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "lgssm_init": (I, [MODEL, I32, I32, Rng, P, P, P, P, P, P, SZ, P]),
         "lgssm_step": (I, [MODEL, I, I, I32, I32, P, I32, P, Rng, P, P, P, P, P, P, P, SZ, P,
                            P]),
+        "pfr_tuning_defaults": (None, [ctypes.POINTER(Tuning)]),
+        "pfr_get_tuning": (I, [ctypes.POINTER(Tuning)]),
+        "pfr_set_tuning": (I, [ctypes.POINTER(Tuning)]),
+        "pfr_load_tuning": (I, [ctypes.c_char_p]),
         "pfr_status_string": (ctypes.c_char_p, [I]),
         "pfr_version": (ctypes.c_char_p, []),
     }
@@ -91,6 +108,10 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         fn.restype = res
         fn.argtypes = args
     _lib = lib
+    if os.path.exists(TUNING_PATH):
+        rc = lib.pfr_load_tuning(TUNING_PATH.encode())
+        if rc != PFR_OK:
+            raise PfrError(f"invalid tuning file {TUNING_PATH} (status {rc})")
     return lib
 
 

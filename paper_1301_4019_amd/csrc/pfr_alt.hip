@@ -271,72 +271,13 @@ __device__ BoundTable load_bound_table(const uint8_t* __restrict__ codes,
   return t;
 }
 
-// Metropolis group with skips: step q of the group loads w_j only when the
-// table cannot reject it for the lower bound lb of w_k at that step; lb starts
-// at lb0 and is multiplied by u for every step that may accept (an accepted
-// move lands on w_j >= u * w_k).  prod returns that product.
-struct TGroup {
-  uint32_t j[4];
-  uint32_t u[4];
-  double wj[4];
-  uint32_t skip;
-  double prod;
-  int nq;
-};
-
-template <typename T>
-__device__ __forceinline__ void metropolis_fetch_table(const T* __restrict__ ws,
-                                                       const BoundTable& tab, Key key, uint32_t i,
-                                                       uint32_t filt, uint32_t offset, uint32_t n,
-                                                       int32_t steps, int32_t m, double lb0,
-                                                       TGroup& g) {
-  uint32_t x[12];
-  const int32_t left = steps - 4 * m;
-  const int ncall = left >= 4 ? 3 : (3 * left + 3) / 4;
-#pragma unroll
-  for (int c3 = 0; c3 < 3; ++c3) {
-    if (c3 < ncall) {
-      const uint4 v = draw(key, i, DOM_TRIAL, (uint32_t)(3 * m + c3), filt, offset);
-      x[4 * c3 + 0] = v.x;
-      x[4 * c3 + 1] = v.y;
-      x[4 * c3 + 2] = v.z;
-      x[4 * c3 + 3] = v.w;
-    }
-  }
-  g.nq = left >= 4 ? 4 : left;
-  g.skip = 0;
-  double lb = lb0, prod = 1.0;
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    g.j[q] = q < g.nq ? index_draw(x[3 * q], x[3 * q + 1], n) : i;
-    g.u[q] = x[3 * q + 2];
-    const double u = u_accept(g.u[q]);
-    g.wj[q] = 0.0;
-    if (q < g.nq) {
-      if (tab.rejects(u, lb, g.j[q])) {
-        g.skip |= 1u << q;
-      } else {
-        g.wj[q] = (double)ws[g.j[q]];
-        lb = (lb * u) * (1.0 - 0x1p-50);
-        prod = (prod * u) * (1.0 - 0x1p-50);
-      }
-    }
-  }
-  g.prod = prod;
-}
-
-__device__ __forceinline__ void metropolis_accept_table(const TGroup& g, uint32_t& k, double& wk) {
-#pragma unroll
-  for (int q = 0; q < 4; ++q) {
-    if (q < g.nq && !((g.skip >> q) & 1u) && accept_exact(u_accept(g.u[q]), wk, g.wj[q])) {
-      k = g.j[q];
-      wk = g.wj[q];
-    }
-  }
-}
-
-// One vector (no segments) with the LDS bound table; workgroups take chunks.
-template <typename T>
+// Metropolis with the bound table.  A skip needs the exact current w_k, so
+// the gathers cannot be issued ahead of the decisions of earlier steps;
+// instead each lane runs K independent chains in lockstep: at every step the
+// chains whose proposal the table cannot reject issue their loads together
+// and the K decisions follow.  Particles of the chunk: lane l runs
+// p0 + l + c * kTableThreads for c < K.
+template <typename T, int K>
 __global__ __launch_bounds__(kTableThreads) void k_metropolis_table(
     const T* __restrict__ w, int64_t n, int32_t B, Key key, uint32_t offset, uint32_t filter,
     int32_t* __restrict__ a, int64_t chunk, const uint8_t* __restrict__ codes,
@@ -347,26 +288,62 @@ __global__ __launch_bounds__(kTableThreads) void k_metropolis_table(
   const BoundTable tab = load_bound_table(codes, wg_max, n_wg, nb, shift, nib, slot);
   const int64_t p0 = (int64_t)blockIdx.x * chunk;
   const int64_t p1 = p0 + chunk < n ? p0 + chunk : n;
-  const int32_t groups = (B + 3) / 4;
-  for (int64_t g = p0 + threadIdx.x; g < p1; g += kTableThreads) {
-    const uint32_t i = (uint32_t)g;
-    uint32_t k = i;
-    double wk = (double)w[i];
-    TGroup ga, gb;
-    double lb_a = wk;  // lower bound of w_k at the start of group ga
-    if (groups > 0) metropolis_fetch_table(w, tab, key, i, filter, offset, (uint32_t)n, B, 0, lb_a, ga);
-    for (int32_t m = 0; m < groups; m += 2) {
-      if (m + 1 < groups)
-        metropolis_fetch_table(w, tab, key, i, filter, offset, (uint32_t)n, B, m + 1,
-                               (lb_a * ga.prod) * (1.0 - 0x1p-50), gb);
-      metropolis_accept_table(ga, k, wk);
-      if (m + 2 < groups) {
-        lb_a = (wk * gb.prod) * (1.0 - 0x1p-50);
-        metropolis_fetch_table(w, tab, key, i, filter, offset, (uint32_t)n, B, m + 2, lb_a, ga);
-      }
-      if (m + 1 < groups) metropolis_accept_table(gb, k, wk);
+  for (int64_t gb = p0 + threadIdx.x; gb < p1; gb += (int64_t)K * kTableThreads) {
+    uint32_t idx[K], k[K];
+    double wk[K];
+    bool live[K];
+#pragma unroll
+    for (int c = 0; c < K; ++c) {
+      const int64_t g = gb + (int64_t)c * kTableThreads;
+      live[c] = g < p1;
+      idx[c] = (uint32_t)(live[c] ? g : gb);
+      k[c] = idx[c];
+      wk[c] = (double)w[idx[c]];
     }
-    a[g] = (int32_t)k;
+    for (int32_t m = 0; 4 * m < B; ++m) {
+      const int32_t left = B - 4 * m;
+      const int ncall = left >= 4 ? 3 : (3 * left + 3) / 4;
+      const int nq = left >= 4 ? 4 : left;
+      uint32_t x[K][12];
+#pragma unroll
+      for (int c = 0; c < K; ++c) {
+#pragma unroll
+        for (int c3 = 0; c3 < 3; ++c3) {
+          if (c3 < ncall) {
+            const uint4 v = draw(key, idx[c], DOM_TRIAL, (uint32_t)(3 * m + c3), filter, offset);
+            x[c][4 * c3 + 0] = v.x;
+            x[c][4 * c3 + 1] = v.y;
+            x[c][4 * c3 + 2] = v.z;
+            x[c][4 * c3 + 3] = v.w;
+          }
+        }
+      }
+#pragma unroll
+      for (int q = 0; q < 4; ++q) {
+        if (q < nq) {
+          uint32_t j[K];
+          double u[K], v[K];
+          bool need[K];
+#pragma unroll
+          for (int c = 0; c < K; ++c) {
+            j[c] = index_draw(x[c][3 * q], x[c][3 * q + 1], (uint32_t)n);
+            u[c] = u_accept(x[c][3 * q + 2]);
+            need[c] = live[c] && !tab.rejects(u[c], wk[c], j[c]);
+            v[c] = need[c] ? (double)w[j[c]] : 0.0;
+          }
+#pragma unroll
+          for (int c = 0; c < K; ++c) {
+            if (need[c] && accept_exact(u[c], wk[c], v[c])) {
+              k[c] = j[c];
+              wk[c] = v[c];
+            }
+          }
+        }
+      }
+    }
+#pragma unroll
+    for (int c = 0; c < K; ++c)
+      if (live[c]) a[gb + (int64_t)c * kTableThreads] = (int32_t)k[c];
   }
 }
 
@@ -406,6 +383,7 @@ __device__ __forceinline__ int nth_set_bit(uint64_t mask, int q) {
 // segment (weights ws, length n, filter id filt).
 // With TABLE, a trial whose u * w_max exceeds the bucket bound of j is
 // rejected without loading w_j.
+constexpr int kRejBatch = 4;  // trials per lane and pass after trial 0
 template <bool TABLE, typename T>
 __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint32_t filt,
                                      double wmax, int64_t r0, int64_t r1, uint32_t max_trials,
@@ -416,7 +394,8 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
   int64_t cur = -1;   // particle (global index) this lane works on
   uint32_t t = 0;     // its next trial
 
-  // main phase: one trial per lane per pass
+  // main phase: trial 0 (j = i) alone, then four trials per lane and pass,
+  // of which the lowest accepting one counts (as if they ran one by one)
   while (true) {
     const uint64_t freem = ballot(cur < 0);
     if (freem != 0 && next < r1) {
@@ -433,17 +412,49 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
     if (next >= r1) break;
     if (cur >= 0) {
       const uint32_t i = (uint32_t)(cur - base);
-      const uint4 x = draw(key, i, DOM_TRIAL, t, filt, offset);
-      const uint32_t j = (t == 0) ? i : index_draw(x.x, x.y, n);
-      const double u = u_accept(x.z);
-      const bool skip = TABLE && tab.rejects(u, wmax, j);
-      if (!skip && accept_exact(u, wmax, (double)ws[j])) {
-        a[cur] = (int32_t)j;
-        cur = -1;
-      } else if (++t >= max_trials) {
-        a[cur] = (int32_t)i;
-        my_flags |= FLAG_TRIAL_CAP;
-        cur = -1;
+      if (t == 0) {
+        const uint4 x = draw(key, i, DOM_TRIAL, 0, filt, offset);
+        const double u = u_accept(x.z);
+        const bool skip = TABLE && tab.rejects(u, wmax, i);
+        if (!skip && accept_exact(u, wmax, (double)ws[i])) {
+          a[cur] = (int32_t)i;
+          cur = -1;
+        } else if (++t >= max_trials) {
+          a[cur] = (int32_t)i;
+          my_flags |= FLAG_TRIAL_CAP;
+          cur = -1;
+        }
+      } else {
+        uint32_t jq[kRejBatch];
+        bool accq[kRejBatch];
+#pragma unroll
+        for (int q = 0; q < kRejBatch; ++q) {
+          const uint32_t tt = t + (uint32_t)q;
+          const uint4 x = draw(key, i, DOM_TRIAL, tt, filt, offset);
+          jq[q] = index_draw(x.x, x.y, n);
+          const double u = u_accept(x.z);
+          const bool live = tt < max_trials && !(TABLE && tab.rejects(u, wmax, jq[q]));
+          accq[q] = live && accept_exact(u, wmax, (double)ws[live ? jq[q] : i]);
+        }
+        int first = -1;
+#pragma unroll
+        for (int q = kRejBatch - 1; q >= 0; --q)
+          if (accq[q]) first = q;
+        if (first >= 0) {
+          uint32_t jsel = jq[0];
+#pragma unroll
+          for (int q = 1; q < kRejBatch; ++q)
+            if (q == first) jsel = jq[q];
+          a[cur] = (int32_t)jsel;
+          cur = -1;
+        } else {
+          t += kRejBatch;
+          if (t >= max_trials) {
+            a[cur] = (int32_t)i;
+            my_flags |= FLAG_TRIAL_CAP;
+            cur = -1;
+          }
+        }
       }
     }
   }
@@ -594,7 +605,7 @@ hipError_t launch_metropolis_t(const void* wv, int64_t n_total, const int64_t* o
   constexpr int per_kb = 1024 / (int)sizeof(T);
   const int cap = staged_capacity<T>(max_len, n_total, n_filters);
   if (cap == 0) {
-    const int64_t chunk = 256;
+    const int64_t chunk = tuning().metropolis_chunk;
     hipLaunchKernelGGL((k_metropolis_staged<T, 0, 256>), dim3((unsigned)((n_total + chunk - 1) / chunk)),
                        dim3(256), 0, stream, w, n_total, offsets, n_filters, B, B_dev, key, offset,
                        filter_base, a, chunk);
@@ -669,7 +680,7 @@ hipError_t launch_metropolis_table(const T* w, int64_t n, int32_t B, Key key, ui
   if (e != hipSuccess) return e;
   const int64_t chunk = (n + kTableGrid - 1) / kTableGrid;
   char* base = (char*)ws;
-  hipLaunchKernelGGL(k_metropolis_table<T>, dim3((unsigned)((n + chunk - 1) / chunk)),
+  hipLaunchKernelGGL((k_metropolis_table<T, 4>), dim3((unsigned)((n + chunk - 1) / chunk)),
                      dim3(kTableThreads), 0, stream, w, n, B, key, offset, filter, a, chunk,
                      (const uint8_t*)(base + g.codes_off), (const uint32_t*)(base + g.wg_off),
                      g.n_wg, g.nb, g.shift);
@@ -680,7 +691,10 @@ hipError_t launch_metropolis(bool f64, const void* w, int64_t n_total, const int
                              uint32_t n_filters, int64_t max_len, int32_t B, const int32_t* B_dev,
                              Key key, uint32_t offset, uint32_t filter_base, int32_t* a, void* ws,
                              size_t ws_bytes, hipStream_t stream) {
-  if (ws && !B_dev && ws_bytes >= alt_workspace_bytes(f64, n_total, n_filters, max_len) &&
+  // the table pays off once chains are long (small beta, most proposals rejected)
+  const int32_t min_B = tuning().metropolis_table_min_B;
+  if (ws && !B_dev && min_B > 0 && B >= min_B &&
+      ws_bytes >= alt_workspace_bytes(f64, n_total, n_filters, max_len) &&
       (f64 ? use_table<double>(n_total, n_filters, max_len)
            : use_table<float>(n_total, n_filters, max_len)))
     return f64 ? launch_metropolis_table((const double*)w, n_total, B, key, offset, filter_base,
@@ -693,8 +707,6 @@ hipError_t launch_metropolis(bool f64, const void* w, int64_t n_total, const int
                                           offset, filter_base, a, stream);
 }
 
-// Particles per wave of the rejection schedule.
-constexpr int64_t kRejectionPerWave = 256;
 
 template <typename T>
 hipError_t launch_rejection_t(const void* wv, int64_t n_total, const int64_t* offsets,
@@ -706,13 +718,13 @@ hipError_t launch_rejection_t(const void* wv, int64_t n_total, const int64_t* of
   constexpr int per_kb = 1024 / (int)sizeof(T);
   const int cap = staged_capacity<T>(max_len, n_total, n_filters);
   if (cap == 0) {
-    const int64_t chunk = kRejectionPerWave * 4;
+    const int64_t chunk = (int64_t)tuning().rejection_per_wave * 4;
     hipLaunchKernelGGL((k_rejection<T, 0, 256>), dim3((unsigned)((n_total + chunk - 1) / chunk)),
                        dim3(256), 0, stream, w, n_total, offsets, n_filters, w_max, w_max_dev,
                        max_trials, key, offset, filter_base, a, flags, chunk);
     return hipGetLastError();
   }
-  const int64_t chunk = kRejectionPerWave * 16;
+  const int64_t chunk = (int64_t)tuning().rejection_per_wave * 16;
   const dim3 grid((unsigned)((n_total + chunk - 1) / chunk));
   if (cap == 16 * per_kb)
     hipLaunchKernelGGL((k_rejection<T, 16 * per_kb, 1024>), grid, dim3(1024), 0, stream, w,
@@ -736,8 +748,8 @@ hipError_t launch_rejection_table(const T* w, int64_t n, double w_max, uint32_t 
   const TableGeom g = table_geom(n);
   hipError_t e = launch_bound_codes(w, n, g, ws, stream);
   if (e != hipSuccess) return e;
-  // chunks of 16 waves x kRejectionPerWave particles, several per CU
-  const int64_t chunk = kRejectionPerWave * (kTableThreads / kWave);
+  // chunks of 16 waves x rejection_per_wave particles, several per CU
+  const int64_t chunk = (int64_t)tuning().rejection_per_wave * (kTableThreads / kWave);
   char* base = (char*)ws;
   hipLaunchKernelGGL(k_rejection_table<T>, dim3((unsigned)((n + chunk - 1) / chunk)),
                      dim3(kTableThreads), 0, stream, w, n, w_max, max_trials, key, offset, filter,
@@ -751,7 +763,8 @@ hipError_t launch_rejection(bool f64, const void* w, int64_t n_total, const int6
                             const double* w_max_dev, uint32_t max_trials, Key key,
                             uint32_t offset, uint32_t filter_base, int32_t* a, uint32_t* flags,
                             void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (ws && !w_max_dev && ws_bytes >= alt_workspace_bytes(f64, n_total, n_filters, max_len) &&
+  if (ws && !w_max_dev && tuning().rejection_table &&
+      ws_bytes >= alt_workspace_bytes(f64, n_total, n_filters, max_len) &&
       (f64 ? use_table<double>(n_total, n_filters, max_len)
            : use_table<float>(n_total, n_filters, max_len)))
     return f64 ? launch_rejection_table((const double*)w, n_total, w_max, max_trials, key, offset,

@@ -1,15 +1,28 @@
 // pfr_api.hip -- the C ABI of libpfresample (declared in include/pfresample.h):
 // argument checks, workspace sizing and kernel launches.  Nothing here
 // allocates, frees or synchronises.
+#include <stdio.h>
+#include <stdlib.h>
+#include <string.h>
+
 #include "pfresample.h"
 #include "pfr_kernels.h"
+
+namespace pfr {
+
+namespace {
+Tuning g_tuning = {4096, 2048, 32, 1, 256, 256};
+}  // namespace
+
+const Tuning& tuning() { return g_tuning; }
+
+}  // namespace pfr
 
 namespace {
 
 using namespace pfr;
 
 constexpr int64_t kMaxN = (int64_t)1 << 31;
-constexpr int64_t kSingleWGMax = 4096;  // single vectors up to this run in one workgroup
 
 struct SegInfo {
   int64_t n_total;
@@ -59,7 +72,7 @@ size_t lgssm_offsets_bytes(int32_t n_filters) {
 size_t dtype_size(pfr_dtype dt) { return dt == PFR_F64 ? 8 : 4; }
 
 bool uses_scan_workspace(const SegInfo& s) {
-  return s.n_filters == 1 && s.n_total > kSingleWGMax;
+  return s.n_filters == 1 && s.n_total > tuning().single_wg_max;
 }
 
 int collective(int scheme, const void* w, pfr_dtype dtype, const pfr_segments* seg,
@@ -82,6 +95,16 @@ int collective(int scheme, const void* w, pfr_dtype dtype, const pfr_segments* s
       return launch_result(launch_fscan_batched(scheme, (int)precision, dtype == PFR_F64, w,
                                                 s.n_total, s.offsets, s.n_filters, key,
                                                 rng.offset, rng.filter_base, a, dev_flags, st));
+    // a batch with a workspace runs block-parallel, without one in one
+    // workgroup per segment; the results are the same
+    if (s.n_filters > 1 && ws) {
+      const SegLayout SL = seg_layout(s.n_total, s.n_filters, scheme == SCHEME_MULTINOMIAL);
+      if (ws_bytes < SL.total || !aligned256(ws)) return PFR_EWORKSPACE;
+      if (overlaps(ws, SL.total, a, (size_t)s.n_total * 4)) return PFR_EINVAL;
+      return launch_result(launch_scan_segmented(scheme, dtype == PFR_F64, w, s.n_total,
+                                                 s.offsets, s.n_filters, key, rng.offset,
+                                                 rng.filter_base, a, ws, dev_flags, st));
+    }
     return launch_result(launch_scan_batched(scheme, dtype == PFR_F64, w, s.n_total, s.offsets,
                                              s.n_filters, key, rng.offset, rng.filter_base, a,
                                              dev_flags, st));
@@ -108,6 +131,7 @@ size_t pfr_workspace_bytes(pfr_op op, const pfr_segments* seg, pfr_dtype dtype) 
     case PFR_OP_MULTINOMIAL:
     case PFR_OP_STRATIFIED:
     case PFR_OP_SYSTEMATIC:
+      if (s.n_filters > 1) return seg_layout(s.n_total, s.n_filters, op == PFR_OP_MULTINOMIAL).total;
       if (!uses_scan_workspace(s)) return 0;
       return scan_layout(s.n_total, op == PFR_OP_MULTINOMIAL).total;
     case PFR_OP_METROPOLIS:
@@ -227,7 +251,10 @@ int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t
 
 size_t lgssm_workspace_bytes(int32_t n_filters, int32_t n) {
   if (n_filters < 1 || n < 1 || (int64_t)n_filters * n >= kMaxN) return 0;
-  return lgssm_offsets_bytes(n_filters) + permute_workspace_bytes((int64_t)n_filters * n);
+  const int64_t total = (int64_t)n_filters * n;
+  const size_t perm = permute_workspace_bytes(total);
+  const size_t seg = seg_layout(total, (uint32_t)n_filters, true).total;
+  return lgssm_offsets_bytes(n_filters) + (perm > seg ? perm : seg);
 }
 
 int lgssm_init(const pfr_lgssm* model, int32_t n_filters, int32_t n, pfr_rng rng, float* x,
@@ -282,9 +309,10 @@ int lgssm_step(const pfr_lgssm* model, pfr_op scheme, pfr_precision precision, i
       const int sch = scheme == PFR_OP_MULTINOMIAL   ? SCHEME_MULTINOMIAL
                       : scheme == PFR_OP_STRATIFIED ? SCHEME_STRATIFIED
                                                     : SCHEME_SYSTEMATIC;
+      // the resampler's workspace is free again before the permutation uses it
       e = precision == PFR_SCAN_EXACT
-              ? launch_scan_batched(sch, false, w, total, offsets, nf, rkey, 0u, rng.filter_base,
-                                    ancestors, dev_flags, st)
+              ? launch_scan_segmented(sch, false, w, total, offsets, nf, rkey, 0u,
+                                      rng.filter_base, ancestors, perm_ws, dev_flags, st)
               : launch_fscan_batched(sch, (int)precision, false, w, total, offsets, nf, rkey, 0u,
                                      rng.filter_base, ancestors, dev_flags, st);
     }
@@ -299,6 +327,107 @@ int lgssm_step(const pfr_lgssm* model, pfr_op scheme, pfr_precision precision, i
                                          log(0.01), y, T, t_dev, nkey, rng.offset,
                                          rng.filter_base, permuted, x, w, log_z, B_dev, dev_flags,
                                          st));
+}
+
+void pfr_tuning_defaults(pfr_tuning* t) {
+  if (!t) return;
+  t->version = PFR_TUNING_VERSION;
+  t->single_wg_max = 4096;
+  t->direct_max_blocks = 2048;
+  t->metropolis_table_min_B = 32;
+  t->rejection_table = 1;
+  t->rejection_per_wave = 256;
+  t->metropolis_chunk = 256;
+}
+
+int pfr_get_tuning(pfr_tuning* t) {
+  if (!t) return PFR_EINVAL;
+  const Tuning& g = tuning();
+  t->version = PFR_TUNING_VERSION;
+  t->single_wg_max = g.single_wg_max;
+  t->direct_max_blocks = g.direct_max_blocks;
+  t->metropolis_table_min_B = g.metropolis_table_min_B;
+  t->rejection_table = g.rejection_table;
+  t->rejection_per_wave = g.rejection_per_wave;
+  t->metropolis_chunk = g.metropolis_chunk;
+  return PFR_OK;
+}
+
+int pfr_set_tuning(const pfr_tuning* t) {
+  if (!t || t->version != PFR_TUNING_VERSION) return PFR_EINVAL;
+  if (t->single_wg_max < 0 || t->single_wg_max > PFR_MAX_BATCH_SEGMENT) return PFR_EINVAL;
+  if (t->direct_max_blocks < 0 || t->direct_max_blocks > 2048) return PFR_EINVAL;
+  if (t->metropolis_table_min_B < 0) return PFR_EINVAL;
+  if (t->rejection_table != 0 && t->rejection_table != 1) return PFR_EINVAL;
+  if (t->rejection_per_wave < 64 || t->rejection_per_wave > 4096) return PFR_EINVAL;
+  if (t->metropolis_chunk < 256 || t->metropolis_chunk > 8192 || t->metropolis_chunk % 256)
+    return PFR_EINVAL;
+  g_tuning.single_wg_max = t->single_wg_max;
+  g_tuning.direct_max_blocks = t->direct_max_blocks;
+  g_tuning.metropolis_table_min_B = t->metropolis_table_min_B;
+  g_tuning.rejection_table = t->rejection_table;
+  g_tuning.rejection_per_wave = t->rejection_per_wave;
+  g_tuning.metropolis_chunk = t->metropolis_chunk;
+  return PFR_OK;
+}
+
+// Reads the integer fields named like pfr_tuning's from the top level of a
+// JSON object (nested objects and other fields are skipped); fields that are
+// absent keep their current value.
+int pfr_load_tuning(const char* path) {
+  if (!path) return PFR_EINVAL;
+  FILE* f = fopen(path, "rb");
+  if (!f) return PFR_EINVAL;
+  static char buf[1 << 16];
+  const size_t len = fread(buf, 1, sizeof(buf) - 1, f);
+  fclose(f);
+  buf[len] = 0;
+  pfr_tuning t;
+  pfr_get_tuning(&t);
+  struct Field {
+    const char* name;
+    int32_t* slot;
+  } fields[] = {{"version", &t.version},
+                {"single_wg_max", &t.single_wg_max},
+                {"direct_max_blocks", &t.direct_max_blocks},
+                {"metropolis_table_min_B", &t.metropolis_table_min_B},
+                {"rejection_table", &t.rejection_table},
+                {"rejection_per_wave", &t.rejection_per_wave},
+                {"metropolis_chunk", &t.metropolis_chunk}};
+  int depth = 0;
+  const char* key = nullptr;  // last string seen at depth 1
+  size_t key_len = 0;
+  for (const char* p = buf; *p; ++p) {
+    const char ch = *p;
+    if (ch == '"') {  // a string: find its end (backslash escapes skipped)
+      const char* q = p + 1;
+      while (*q && *q != '"') q += (*q == '\\' && q[1]) ? 2 : 1;
+      if (!*q) return PFR_EINVAL;
+      if (depth == 1) {
+        key = p + 1;
+        key_len = (size_t)(q - p - 1);
+      }
+      p = q;
+    } else if (ch == '{' || ch == '[') {
+      ++depth;
+      key = nullptr;
+    } else if (ch == '}' || ch == ']') {
+      --depth;
+      key = nullptr;
+    } else if (ch == ':' && depth == 1 && key) {
+      for (const Field& fd : fields) {
+        if (strlen(fd.name) == key_len && strncmp(fd.name, key, key_len) == 0) {
+          char* end = nullptr;
+          const long v = strtol(p + 1, &end, 10);
+          if (end == p + 1) return PFR_EINVAL;
+          *fd.slot = (int32_t)v;
+        }
+      }
+      key = nullptr;
+    }
+  }
+  if (depth != 0) return PFR_EINVAL;
+  return pfr_set_tuning(&t);
 }
 
 const char* pfr_status_string(int status) {

@@ -10,6 +10,19 @@
 
 namespace pfr {
 
+// Launch parameters chosen by the autotuner.  None of them changes a result:
+// every kernel draws its random numbers by particle, and the exact prefix
+// sums do not depend on how they are split.
+struct Tuning {
+  int32_t single_wg_max;           // collective: single vectors up to this length in one workgroup
+  int32_t direct_max_blocks;       // exact collective: emit forms its own carries up to this many blocks
+  int32_t metropolis_table_min_B;  // long vectors: bound-table Metropolis from this many steps (0 = never)
+  int32_t rejection_table;         // long vectors: rejection with the bound table (0 / 1)
+  int32_t rejection_per_wave;      // particles per wave of the rejection schedule
+  int32_t metropolis_chunk;        // particles per workgroup of the global-memory Metropolis kernel
+};
+const Tuning& tuning();
+
 // Collective schemes handled by the scan kernels.
 enum Scheme : int { SCHEME_MULTINOMIAL = 0, SCHEME_STRATIFIED = 1, SCHEME_SYSTEMATIC = 2 };
 
@@ -46,6 +59,18 @@ struct ScanLayout {
   size_t recs, carries, erecs, ecarries, total;
 };
 ScanLayout scan_layout(int64_t n, bool multinomial);
+
+// Workspace of a block-parallel batch (exact prefix): block prefixes per
+// segment, one record per weight block, one sum per exponential block.
+struct SegLayout {
+  uint32_t grid_b, grid_e;  // launch bounds on the block counts
+  size_t bstart, estart, recs, esums, total;
+};
+SegLayout seg_layout(int64_t n_total, uint32_t n_filters, bool multinomial);
+hipError_t launch_scan_segmented(int scheme, bool f64, const void* w, int64_t n_total,
+                                 const int64_t* offsets, uint32_t n_filters, Key key,
+                                 uint32_t offset, uint32_t filter_base, int32_t* a, void* ws,
+                                 uint32_t* flags, hipStream_t stream);
 size_t batch_scan_lds_bytes();
 
 hipError_t launch_scan(int scheme, bool f64, const void* w, int64_t n, Key key, uint32_t offset,

@@ -396,6 +396,130 @@ __global__ __launch_bounds__(kT) void k_scan_batched(const T* __restrict__ w, in
   }
 }
 
+// ---------------------------------------------------------------- segmented batches
+// A batch with a workspace runs block-parallel: every 1024-weight block of
+// every segment is one workgroup of the records and of the emit kernel, so a
+// long segment no longer runs through one workgroup.  Blocks start at each
+// segment's first weight (the same blocks as a single call on the segment),
+// and every emit workgroup forms its segment's carries from the segment's
+// records directly, so the result is that of one call per segment.
+constexpr int kSegMaxBlocks = 2048;  // direct carries: segments up to 2^21 weights
+
+// Exclusive block prefixes over the segments: bstart[f] (weight blocks) and,
+// for the multinomial scheme, estart[f] (exponential blocks).  One workgroup.
+__global__ __launch_bounds__(kT) void k_seg_prefix(const int64_t* __restrict__ offsets,
+                                                   uint32_t n_filters,
+                                                   uint32_t* __restrict__ bstart,
+                                                   uint32_t* __restrict__ estart) {
+  __shared__ WgScratch s;
+  uint64_t carry_b = 0, carry_e = 0;
+  for (uint32_t base = 0; base < n_filters; base += kT) {
+    const uint32_t f = base + threadIdx.x;
+    uint64_t nb = 0, ne = 0;
+    if (f < n_filters) {
+      const int64_t n = offsets[f + 1] - offsets[f];
+      nb = n > 0 ? (uint64_t)((n + kBlock - 1) / kBlock) : 0;
+      ne = n > 0 ? (uint64_t)((n + 1 + kBlock - 1) / kBlock) : 0;
+    }
+    uint64_t tb, te;
+    const uint64_t xb = wg_exclusive(nb, s.u, &tb);
+    const uint64_t xe = wg_exclusive(ne, s.u, &te);
+    if (f < n_filters) {
+      bstart[f] = (uint32_t)(carry_b + xb);
+      if (estart) estart[f] = (uint32_t)(carry_e + xe);
+    }
+    carry_b += tb;
+    carry_e += te;
+  }
+  if (threadIdx.x == 0) {
+    bstart[n_filters] = (uint32_t)carry_b;
+    if (estart) estart[n_filters] = (uint32_t)carry_e;
+  }
+}
+
+// segment f of global block g: the last f with start[f] <= g (start non-decreasing)
+__device__ __forceinline__ uint32_t seg_of_block(const uint32_t* __restrict__ start,
+                                                 uint32_t n_filters, uint32_t g) {
+  uint32_t lo = 0, hi = n_filters;
+  while (hi - lo > 1) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (start[mid] <= g) lo = mid;
+    else hi = mid;
+  }
+  return lo;
+}
+
+template <typename T, bool MULTI>
+__global__ __launch_bounds__(kT) void k_seg_records(
+    const T* __restrict__ w, const int64_t* __restrict__ offsets, uint32_t n_filters,
+    uint32_t grid_b, Key key, uint32_t offset, uint32_t filter_base,
+    const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ estart,
+    BlockRec* __restrict__ recs, uint64_t* __restrict__ esums) {
+  __shared__ WgScratch s;
+  offset = counter_offset(key, offset);
+  if (blockIdx.x < grid_b) {
+    const uint32_t g = blockIdx.x;
+    if (g >= bstart[n_filters]) return;
+    const uint32_t f = seg_of_block(bstart, n_filters, g);
+    const int64_t base = offsets[f];
+    const int64_t n = offsets[f + 1] - base;
+    const BlockRec r = block_record(w + base, n, (int64_t)(g - bstart[f]) * kBlock, &s);
+    if (threadIdx.x == 0) recs[g] = r;
+  } else if (MULTI) {
+    const uint32_t g = blockIdx.x - grid_b;
+    if (g >= estart[n_filters]) return;
+    const uint32_t f = seg_of_block(estart, n_filters, g);
+    const int64_t n = offsets[f + 1] - offsets[f];
+    uint64_t q[kPer];
+    exp_values(key, filter_base + f, offset, n, g - estart[f], q);
+    const uint64_t sum = wg_reduce(q[0] + q[1] + q[2] + q[3], OpAdd(), s.u);
+    if (threadIdx.x == 0) esums[g] = sum;
+  }
+}
+
+template <typename T, int SCHEME>
+__global__ __launch_bounds__(kT) void k_seg_emit(
+    const T* __restrict__ w, const int64_t* __restrict__ offsets, uint32_t n_filters, Key key,
+    uint32_t offset, uint32_t filter_base, const uint32_t* __restrict__ bstart,
+    const uint32_t* __restrict__ estart, const BlockRec* __restrict__ recs,
+    const uint64_t* __restrict__ esums, int32_t* __restrict__ a, uint32_t* __restrict__ flags) {
+  __shared__ EmitLds L;
+  __shared__ WgScratch s;
+  // exponential-block carries of the segment (multinomial only)
+  __shared__ u128 CE[SCHEME == SCHEME_MULTINOMIAL ? kSegMaxBlocks + 2 : 1];
+  offset = counter_offset(key, offset);
+  const uint32_t g = blockIdx.x;
+  if (g >= bstart[n_filters]) return;
+  const uint32_t f = seg_of_block(bstart, n_filters, g);
+  const int64_t base = offsets[f];
+  const int64_t n = offsets[f + 1] - base;
+  const uint32_t nb = bstart[f + 1] - bstart[f];
+  const uint32_t b = g - bstart[f];
+  int32_t* __restrict__ as = a + base;
+  if (nb > kSegMaxBlocks) {  // longer than the direct carries allow: identity + flag
+    for (int64_t i = (int64_t)b * kBlock + threadIdx.x; i < min((int64_t)(b + 1) * kBlock, n);
+         i += kT)
+      as[i] = (int32_t)i;
+    if (flags && b == 0 && threadIdx.x == 0) atomicOr(flags, FLAG_BAD_COUNTS);
+    return;
+  }
+  const Direct d = direct_carries(nb, b, recs + bstart[f], &s);
+  if (flags && b == 0 && threadIdx.x == 0 && d.status) atomicOr(flags, d.status);
+  if (d.status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
+    const int64_t P0 = (int64_t)b * kBlock;
+    for (int64_t i = P0 + threadIdx.x; i < min(P0 + kBlock, n); i += kT) as[i] = (int32_t)i;
+    return;
+  }
+  uint32_t nbe = 0;
+  if (SCHEME == SCHEME_MULTINOMIAL) {
+    nbe = estart[f + 1] - estart[f];
+    exp_carries(nbe, esums + estart[f], (u128*)CE, &s);
+  }
+  const RMap rm = make_rmap(d.Q, n);
+  emit_block<T, SCHEME>(w + base, n, b, recs[bstart[f] + b], d.Cb, d.Cb1, d.gscale, rm, key,
+                        filter_base + f, offset, (const u128*)CE, nbe, as, &L, &s);
+}
+
 template <typename T, int SCHEME>
 hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, uint32_t filter,
                          int32_t* a, void* ws, uint32_t* flags, hipStream_t stream) {
@@ -414,7 +538,7 @@ hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, ui
                      key, offset, filter, recs, esums);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (!multi && nb <= kDirectMax) {
+  if (!multi && nb <= (uint32_t)tuning().direct_max_blocks && nb <= kDirectMax) {
     hipLaunchKernelGGL((k_scan_emit<T, SCHEME, true>), dim3(nb), dim3(kT), 0, stream, w, n, nb,
                        nbe, key, offset, filter, hdr, recs, C, CE, a, flags);
     return hipGetLastError();
@@ -468,7 +592,74 @@ hipError_t launch_batched_scheme(int scheme, const void* w, int64_t n_total,
   return hipGetLastError();
 }
 
+template <typename T, int SCHEME>
+hipError_t launch_segmented_t(const T* w, int64_t n_total, const int64_t* offsets,
+                              uint32_t n_filters, Key key, uint32_t offset, uint32_t filter_base,
+                              int32_t* a, void* ws, uint32_t* flags, hipStream_t stream) {
+  constexpr bool multi = SCHEME == SCHEME_MULTINOMIAL;
+  const SegLayout L = seg_layout(n_total, n_filters, multi);
+  char* base = (char*)ws;
+  uint32_t* bstart = (uint32_t*)(base + L.bstart);
+  uint32_t* estart = multi ? (uint32_t*)(base + L.estart) : nullptr;
+  BlockRec* recs = (BlockRec*)(base + L.recs);
+  uint64_t* esums = (uint64_t*)(base + L.esums);
+  hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(kT), 0, stream, offsets, n_filters, bstart,
+                     estart);
+  hipError_t e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_seg_records<T, multi>), dim3(L.grid_b + (multi ? L.grid_e : 0u)),
+                     dim3(kT), 0, stream, w, offsets, n_filters, L.grid_b, key, offset,
+                     filter_base, bstart, estart, recs, esums);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
+  hipLaunchKernelGGL((k_seg_emit<T, SCHEME>), dim3(L.grid_b), dim3(kT), 0, stream, w, offsets,
+                     n_filters, key, offset, filter_base, bstart, estart, recs, esums, a, flags);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_segmented_scheme(int scheme, const void* w, int64_t n_total,
+                                   const int64_t* offsets, uint32_t n_filters, Key key,
+                                   uint32_t offset, uint32_t filter_base, int32_t* a, void* ws,
+                                   uint32_t* flags, hipStream_t stream) {
+  const T* wt = (const T*)w;
+  switch (scheme) {
+    case SCHEME_MULTINOMIAL:
+      return launch_segmented_t<T, SCHEME_MULTINOMIAL>(wt, n_total, offsets, n_filters, key,
+                                                       offset, filter_base, a, ws, flags, stream);
+    case SCHEME_STRATIFIED:
+      return launch_segmented_t<T, SCHEME_STRATIFIED>(wt, n_total, offsets, n_filters, key,
+                                                      offset, filter_base, a, ws, flags, stream);
+    default:
+      return launch_segmented_t<T, SCHEME_SYSTEMATIC>(wt, n_total, offsets, n_filters, key,
+                                                      offset, filter_base, a, ws, flags, stream);
+  }
+}
+
 }  // namespace
+
+SegLayout seg_layout(int64_t n_total, uint32_t n_filters, bool multinomial) {
+  SegLayout L;
+  // upper bounds of the block counts: each segment adds at most one partial block
+  L.grid_b = (uint32_t)(n_total / kBlock + n_filters);
+  L.grid_e = multinomial ? (uint32_t)((n_total + n_filters) / kBlock + n_filters) : 0u;
+  L.bstart = 0;
+  L.estart = align256(((size_t)n_filters + 1) * sizeof(uint32_t));
+  L.recs = L.estart + (multinomial ? align256(((size_t)n_filters + 1) * sizeof(uint32_t)) : 0);
+  L.esums = L.recs + align256((size_t)L.grid_b * sizeof(BlockRec));
+  L.total = L.esums + align256((size_t)L.grid_e * sizeof(uint64_t));
+  return L;
+}
+
+hipError_t launch_scan_segmented(int scheme, bool f64, const void* w, int64_t n_total,
+                                 const int64_t* offsets, uint32_t n_filters, Key key,
+                                 uint32_t offset, uint32_t filter_base, int32_t* a, void* ws,
+                                 uint32_t* flags, hipStream_t stream) {
+  return f64 ? launch_segmented_scheme<double>(scheme, w, n_total, offsets, n_filters, key,
+                                               offset, filter_base, a, ws, flags, stream)
+             : launch_segmented_scheme<float>(scheme, w, n_total, offsets, n_filters, key,
+                                              offset, filter_base, a, ws, flags, stream);
+}
 
 ScanLayout scan_layout(int64_t n, bool multinomial) {
   const size_t nb = (size_t)((n + kBlock - 1) / kBlock);

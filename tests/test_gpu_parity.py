@@ -211,6 +211,44 @@ def test_collective_batched_matches_single_calls(scheme):
         check_collective(scheme, seg, a[off[f]:off[f + 1]], seed=13, filt=100 + f, offset=2)
 
 
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_collective_batched_block_parallel_equals_one_workgroup(scheme, dtype):
+    """With a workspace a batch runs block-parallel; without one, one workgroup
+    per segment.  Both use the same blocks and exact sums: identical bits."""
+    lens = [1, 1023, 1024, 1025, 0, 5000, 65536, 3, 100003, 2048]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    w = np.concatenate([inputs.weights(m, 0.5 + (f % 4), seed=300 + f, dtype=dtype)
+                        for f, m in enumerate(lens)])
+    w[off[5] + 17] = 0.0
+    fn = getattr(pfr(), "resample_" + scheme)
+    kw = dict(seed=21, offset=3, filter_base=7, offsets=dev(off), max_len=max(lens))
+    a_seg = host(fn(dev(w), **kw))
+    none = torch.empty(0, dtype=torch.uint8, device="cuda")
+    a_one = host(fn(dev(w), workspace=none, **kw))
+    assert np.array_equal(a_seg, a_one)
+    for f in (0, 3, 6, 8):
+        seg = w[off[f]:off[f + 1]]
+        check_collective(scheme, seg, a_seg[off[f]:off[f + 1]], seed=21, filt=7 + f, offset=3)
+
+
+def test_collective_batched_bad_and_zero_segments():
+    lens = [3000, 2000, 70000, 10]
+    off = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+    w = np.concatenate([inputs.weights(m, 1.0, seed=f) for f, m in enumerate(lens)])
+    w[off[1]:off[2]] = 0.0            # all-zero segment: identity
+    w[off[2] + 40000] = -1.0          # invalid weight: identity
+    fl = new_flags()
+    a = host(pfr().resample_systematic(dev(w), seed=2, offsets=dev(off), max_len=max(lens),
+                                       flags=fl))
+    assert np.array_equal(a[off[1]:off[2]], np.arange(lens[1]))
+    assert np.array_equal(a[off[2]:off[3]], np.arange(lens[2]))
+    assert int(host(fl)[0]) == pfr().FLAG_ZERO_TOTAL | pfr().FLAG_BAD_WEIGHTS
+    for f in (0, 3):
+        check_collective("systematic", w[off[f]:off[f + 1]], a[off[f]:off[f + 1]], seed=2,
+                         filt=f)
+
+
 def test_alternatives_batched_match_single_calls():
     w, off, ys = ragged(nf=40, seed=5)
     nf = off.size - 1

@@ -1,0 +1,67 @@
+"""The tuning parameters only change how work is split: every setting gives
+the same bits (and the oracle's, where the parity tests already pin them)."""
+import numpy as np
+import pytest
+
+from paper_1301_4019_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SETTINGS = [
+    {"single_wg_max": 0, "direct_max_blocks": 0, "metropolis_table_min_B": 0,
+     "rejection_table": 0, "rejection_per_wave": 64, "metropolis_chunk": 256},
+    {"single_wg_max": 65536, "direct_max_blocks": 2048, "metropolis_table_min_B": 1,
+     "rejection_table": 1, "rejection_per_wave": 4096, "metropolis_chunk": 8192},
+    {"single_wg_max": 1000, "direct_max_blocks": 7, "metropolis_table_min_B": 20,
+     "rejection_table": 1, "rejection_per_wave": 192, "metropolis_chunk": 768},
+]
+
+
+def pfr():
+    import paper_1301_4019_amd as m
+    return m
+
+
+def run_all(w, off=None, max_len=None):
+    m = pfr()
+    outs = []
+    for s in ("stratified", "systematic", "multinomial"):
+        outs.append(getattr(m, "resample_" + s)(w, seed=5, offsets=off, max_len=max_len))
+    outs.append(m.resample_metropolis(w, 37, seed=5, offsets=off, max_len=max_len))
+    outs.append(m.resample_rejection(w, 1.0, seed=5, offsets=off, max_len=max_len))
+    torch.cuda.synchronize()
+    return [o.cpu().numpy() for o in outs]
+
+
+@pytest.mark.parametrize("n", [3000, 5000, 70000, 1 << 20])
+def test_results_do_not_depend_on_tuning(n):
+    m = pfr()
+    saved = m.get_tuning()
+    w = torch.from_numpy(inputs.weights(n, 3.0, seed=n)).cuda()
+    try:
+        ref = run_all(w)
+        for st in SETTINGS:
+            m.set_tuning(**st)
+            got = run_all(w)
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), st
+    finally:
+        m.set_tuning(**saved)
+
+
+def test_batched_results_do_not_depend_on_tuning():
+    m = pfr()
+    saved = m.get_tuning()
+    lens = [300, 5000, 17000, 1, 0, 40000]
+    off = torch.tensor(np.concatenate([[0], np.cumsum(lens)]), dtype=torch.int64).cuda()
+    w = torch.from_numpy(np.concatenate([inputs.weights(k, 2.5, seed=k + 1) for k in lens])).cuda()
+    try:
+        ref = run_all(w, off, max(lens))
+        for st in SETTINGS:
+            m.set_tuning(**st)
+            got = run_all(w, off, max(lens))
+            for a, b in zip(ref, got):
+                assert np.array_equal(a, b), st
+    finally:
+        m.set_tuning(**saved)

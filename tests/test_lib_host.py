@@ -106,3 +106,34 @@ def test_invalid_arguments_rejected_on_host():
                                    None) == _lib.PFR_EINVAL
     assert lib.resample_stratified(fake, 0, ctypes.byref(seg(10)), -1, rng, out, None, 0, None,
                                    None) == _lib.PFR_EINVAL
+
+
+def test_tuning_set_get_load_roundtrip(tmp_path):
+    import paper_1301_4019_amd as pfr
+    saved = pfr.get_tuning()
+    try:
+        d = pfr.default_tuning()
+        assert d["single_wg_max"] > 0 and d["rejection_per_wave"] >= 64
+        pfr.set_tuning(rejection_per_wave=512, metropolis_chunk=1024, direct_max_blocks=0)
+        t = pfr.get_tuning()
+        assert (t["rejection_per_wave"], t["metropolis_chunk"], t["direct_max_blocks"]) == (512, 1024, 0)
+        # out-of-range values leave everything unchanged
+        for bad in ({"rejection_per_wave": 32}, {"metropolis_chunk": 300},
+                    {"direct_max_blocks": 4096}, {"rejection_table": 2},
+                    {"single_wg_max": -1}):
+            with pytest.raises(pfr.PfrError):
+                pfr.set_tuning(**bad)
+            assert pfr.get_tuning() == t
+        # JSON file: top-level integers, unknown keys ignored, absent keys kept
+        f = tmp_path / "tuning.json"
+        f.write_text('{"version": 1, "rejection_per_wave": 128, "device": "x", '
+                     '"measured_ms": {"metropolis_chunk": 7}}')
+        lib = _lib.load()
+        assert lib.pfr_load_tuning(str(f).encode()) == _lib.PFR_OK
+        t2 = pfr.get_tuning()
+        assert t2["rejection_per_wave"] == 128 and t2["metropolis_chunk"] == 1024
+        f.write_text('{"version": 2, "rejection_per_wave": 128}')
+        assert lib.pfr_load_tuning(str(f).encode()) == _lib.PFR_EINVAL
+        assert lib.pfr_load_tuning(str(tmp_path / "missing.json").encode()) == _lib.PFR_EINVAL
+    finally:
+        pfr.set_tuning(**saved)
