@@ -114,7 +114,8 @@ template <typename T, int CAP, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_metropolis_staged(
     const T* __restrict__ w, int64_t n_total, const int64_t* __restrict__ offsets,
     uint32_t n_filters, int32_t B, const int32_t* __restrict__ B_dev, Key key, uint32_t offset,
-    uint32_t filter_base, int32_t* __restrict__ a, int64_t chunk) {
+    uint32_t filter_base, int32_t* __restrict__ a, int64_t chunk, int64_t min_len,
+    int64_t max_len) {
   __shared__ T sw[CAP > 0 ? CAP : 1];
   offset = counter_offset(key, offset);
   const int64_t p0 = (int64_t)blockIdx.x * chunk;
@@ -126,6 +127,10 @@ __global__ __launch_bounds__(THREADS) void k_metropolis_staged(
     const int64_t q1 = end < p1 ? end : p1;
     if (q1 <= g0) continue;  // empty segment
     const uint32_t n = (uint32_t)(end - base);
+    if (end - base < min_len || end - base > max_len) {  // another launch runs this segment
+      g0 = q1;
+      continue;
+    }
     const int32_t steps = B_dev ? B_dev[f] : B;
     const uint32_t filt = filter_base + f;
     if (CAP > 0 && n <= (uint32_t)CAP) {
@@ -604,25 +609,33 @@ hipError_t launch_metropolis_t(const void* wv, int64_t n_total, const int64_t* o
   const T* w = (const T*)wv;
   constexpr int per_kb = 1024 / (int)sizeof(T);
   const int cap = staged_capacity<T>(max_len, n_total, n_filters);
-  if (cap == 0) {
+  constexpr int64_t kAll = INT64_MAX;
+  auto global_launch = [&](int64_t min_len) {
     const int64_t chunk = tuning().metropolis_chunk;
     hipLaunchKernelGGL((k_metropolis_staged<T, 0, 256>), dim3((unsigned)((n_total + chunk - 1) / chunk)),
                        dim3(256), 0, stream, w, n_total, offsets, n_filters, B, B_dev, key, offset,
-                       filter_base, a, chunk);
+                       filter_base, a, chunk, min_len, kAll);
     return hipGetLastError();
-  }
+  };
+  if (cap == 0) return global_launch(0);
+  // segments longer than the LDS tier run in the same launch, from global
+  // memory (a second, pipelined launch for them measured slower on ragged
+  // batches: its chunks hold several long chains per lane)
+  const int64_t hi = kAll;
   const int64_t chunk = 4096;
   const dim3 grid((unsigned)((n_total + chunk - 1) / chunk));
   if (cap == 16 * per_kb)
     hipLaunchKernelGGL((k_metropolis_staged<T, 16 * per_kb, 1024>), grid, dim3(1024), 0, stream, w,
-                       n_total, offsets, n_filters, B, B_dev, key, offset, filter_base, a, chunk);
+                       n_total, offsets, n_filters, B, B_dev, key, offset, filter_base, a, chunk,
+                       (int64_t)0, hi);
   else if (cap == 64 * per_kb)
     hipLaunchKernelGGL((k_metropolis_staged<T, 64 * per_kb, 1024>), grid, dim3(1024), 0, stream, w,
-                       n_total, offsets, n_filters, B, B_dev, key, offset, filter_base, a, chunk);
+                       n_total, offsets, n_filters, B, B_dev, key, offset, filter_base, a, chunk,
+                       (int64_t)0, hi);
   else
     hipLaunchKernelGGL((k_metropolis_staged<T, 128 * per_kb, 1024>), grid, dim3(1024), 0, stream,
                        w, n_total, offsets, n_filters, B, B_dev, key, offset, filter_base, a,
-                       chunk);
+                       chunk, (int64_t)0, hi);
   return hipGetLastError();
 }
 

@@ -386,7 +386,9 @@ __global__ __launch_bounds__(256) void k_claim_min(const int32_t* __restrict__ a
     if (s.n < min_len) continue;
     const int64_t ai = anc_at(a, s, s.i, bad);
     int32_t* slot = &d[s.base + ai];
-    if (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_AGENT) > (int32_t)s.i)
+    // d only decreases, so a stale (cached) value that is already <= i proves
+    // the claim lost; only a larger one needs the atomic
+    if (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > (int32_t)s.i)
       atomicMin(slot, (int32_t)s.i);
   }
   if (flags) {

@@ -24,7 +24,7 @@ namespace pfr {
 
 namespace {
 
-constexpr int kFT = 256;  // threads per filter workgroup
+constexpr int kFT = 512;  // threads per filter workgroup
 
 __device__ __forceinline__ double normal_bm(uint32_t x0, uint32_t x1) {
   const double u1 = ((double)x0 + 1.0) * 0x1p-32;

@@ -64,7 +64,7 @@ ScanLayout scan_layout(int64_t n, bool multinomial);
 // segment, one record per weight block, one sum per exponential block.
 struct SegLayout {
   uint32_t grid_b, grid_e;  // launch bounds on the block counts
-  size_t bstart, estart, recs, esums, total;
+  size_t bstart, estart, recs, esums, carries, ecarries, hdr, total;
 };
 SegLayout seg_layout(int64_t n_total, uint32_t n_filters, bool multinomial);
 hipError_t launch_scan_segmented(int scheme, bool f64, const void* w, int64_t n_total,

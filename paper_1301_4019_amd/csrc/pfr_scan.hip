@@ -401,9 +401,8 @@ __global__ __launch_bounds__(kT) void k_scan_batched(const T* __restrict__ w, in
 // every segment is one workgroup of the records and of the emit kernel, so a
 // long segment no longer runs through one workgroup.  Blocks start at each
 // segment's first weight (the same blocks as a single call on the segment),
-// and every emit workgroup forms its segment's carries from the segment's
-// records directly, so the result is that of one call per segment.
-constexpr int kSegMaxBlocks = 2048;  // direct carries: segments up to 2^21 weights
+// and one workgroup per segment forms the segment's exact carries, so the
+// result is that of one call per segment.
 
 // Exclusive block prefixes over the segments: bstart[f] (weight blocks) and,
 // for the multinomial scheme, estart[f] (exponential blocks).  One workgroup.
@@ -477,47 +476,71 @@ __global__ __launch_bounds__(kT) void k_seg_records(
   }
 }
 
+// Per segment (one workgroup each): global scale, exact carries C (nb + 1 per
+// segment, at cstart = bstart[f] + f), total and status, and the
+// exponential-block carries of the multinomial scheme (at estart[f] + f).
+struct SegHdr {
+  u128 Q;
+  int32_t gscale;
+  uint32_t status;
+  uint64_t pad;
+};
+
+template <bool MULTI>
+__global__ __launch_bounds__(kT) void k_seg_carries(uint32_t n_filters,
+                                                    const uint32_t* __restrict__ bstart,
+                                                    const uint32_t* __restrict__ estart,
+                                                    const BlockRec* __restrict__ recs,
+                                                    const uint64_t* __restrict__ esums,
+                                                    u128* __restrict__ C, u128* __restrict__ CE,
+                                                    SegHdr* __restrict__ hdr) {
+  __shared__ WgScratch s;
+  const uint32_t f = blockIdx.x;
+  if (f >= n_filters) return;
+  const uint32_t b0 = bstart[f], nb = bstart[f + 1] - b0;
+  if (nb == 0) return;
+  const Totals t = carries_from_records(nb, recs + b0, C + b0 + f, &s);
+  if (MULTI) {
+    const uint32_t e0 = estart[f];
+    exp_carries(estart[f + 1] - e0, esums + e0, CE + e0 + f, &s);
+  }
+  if (threadIdx.x == 0) {
+    hdr[f].Q = t.Q;
+    hdr[f].gscale = t.gscale;
+    hdr[f].status = t.status;
+  }
+}
+
 template <typename T, int SCHEME>
 __global__ __launch_bounds__(kT) void k_seg_emit(
     const T* __restrict__ w, const int64_t* __restrict__ offsets, uint32_t n_filters, Key key,
     uint32_t offset, uint32_t filter_base, const uint32_t* __restrict__ bstart,
     const uint32_t* __restrict__ estart, const BlockRec* __restrict__ recs,
-    const uint64_t* __restrict__ esums, int32_t* __restrict__ a, uint32_t* __restrict__ flags) {
+    const u128* __restrict__ C, const u128* __restrict__ CE, const SegHdr* __restrict__ hdr,
+    int32_t* __restrict__ a, uint32_t* __restrict__ flags) {
   __shared__ EmitLds L;
   __shared__ WgScratch s;
-  // exponential-block carries of the segment (multinomial only)
-  __shared__ u128 CE[SCHEME == SCHEME_MULTINOMIAL ? kSegMaxBlocks + 2 : 1];
   offset = counter_offset(key, offset);
   const uint32_t g = blockIdx.x;
   if (g >= bstart[n_filters]) return;
   const uint32_t f = seg_of_block(bstart, n_filters, g);
   const int64_t base = offsets[f];
   const int64_t n = offsets[f + 1] - base;
-  const uint32_t nb = bstart[f + 1] - bstart[f];
   const uint32_t b = g - bstart[f];
   int32_t* __restrict__ as = a + base;
-  if (nb > kSegMaxBlocks) {  // longer than the direct carries allow: identity + flag
-    for (int64_t i = (int64_t)b * kBlock + threadIdx.x; i < min((int64_t)(b + 1) * kBlock, n);
-         i += kT)
-      as[i] = (int32_t)i;
-    if (flags && b == 0 && threadIdx.x == 0) atomicOr(flags, FLAG_BAD_COUNTS);
-    return;
-  }
-  const Direct d = direct_carries(nb, b, recs + bstart[f], &s);
-  if (flags && b == 0 && threadIdx.x == 0 && d.status) atomicOr(flags, d.status);
-  if (d.status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
+  const uint32_t status = hdr[f].status;
+  if (flags && b == 0 && threadIdx.x == 0 && status) atomicOr(flags, status);
+  if (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
     const int64_t P0 = (int64_t)b * kBlock;
     for (int64_t i = P0 + threadIdx.x; i < min(P0 + kBlock, n); i += kT) as[i] = (int32_t)i;
     return;
   }
-  uint32_t nbe = 0;
-  if (SCHEME == SCHEME_MULTINOMIAL) {
-    nbe = estart[f + 1] - estart[f];
-    exp_carries(nbe, esums + estart[f], (u128*)CE, &s);
-  }
-  const RMap rm = make_rmap(d.Q, n);
-  emit_block<T, SCHEME>(w + base, n, b, recs[bstart[f] + b], d.Cb, d.Cb1, d.gscale, rm, key,
-                        filter_base + f, offset, (const u128*)CE, nbe, as, &L, &s);
+  const u128* Cs = C + bstart[f] + f;
+  const uint32_t nbe = SCHEME == SCHEME_MULTINOMIAL ? estart[f + 1] - estart[f] : 0u;
+  const u128* CEs = SCHEME == SCHEME_MULTINOMIAL ? CE + estart[f] + f : CE;
+  const RMap rm = make_rmap(hdr[f].Q, n);
+  emit_block<T, SCHEME>(w + base, n, b, recs[g], Cs[b], Cs[b + 1], hdr[f].gscale, rm, key,
+                        filter_base + f, offset, CEs, nbe, as, &L, &s);
 }
 
 template <typename T, int SCHEME>
@@ -612,8 +635,16 @@ hipError_t launch_segmented_t(const T* w, int64_t n_total, const int64_t* offset
                      filter_base, bstart, estart, recs, esums);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
+  u128* C = (u128*)(base + L.carries);
+  u128* CE = (u128*)(base + L.ecarries);
+  SegHdr* hdr = (SegHdr*)(base + L.hdr);
+  hipLaunchKernelGGL((k_seg_carries<multi>), dim3(n_filters), dim3(kT), 0, stream, n_filters,
+                     bstart, estart, recs, esums, C, CE, hdr);
+  e = hipGetLastError();
+  if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_seg_emit<T, SCHEME>), dim3(L.grid_b), dim3(kT), 0, stream, w, offsets,
-                     n_filters, key, offset, filter_base, bstart, estart, recs, esums, a, flags);
+                     n_filters, key, offset, filter_base, bstart, estart, recs, C, CE, hdr, a,
+                     flags);
   return hipGetLastError();
 }
 
@@ -647,7 +678,11 @@ SegLayout seg_layout(int64_t n_total, uint32_t n_filters, bool multinomial) {
   L.estart = align256(((size_t)n_filters + 1) * sizeof(uint32_t));
   L.recs = L.estart + (multinomial ? align256(((size_t)n_filters + 1) * sizeof(uint32_t)) : 0);
   L.esums = L.recs + align256((size_t)L.grid_b * sizeof(BlockRec));
-  L.total = L.esums + align256((size_t)L.grid_e * sizeof(uint64_t));
+  L.carries = L.esums + align256((size_t)L.grid_e * sizeof(uint64_t));
+  L.ecarries = L.carries + align256(((size_t)L.grid_b + n_filters) * sizeof(u128));
+  L.hdr = L.ecarries +
+          (multinomial ? align256(((size_t)L.grid_e + n_filters) * sizeof(u128)) : 0);
+  L.total = L.hdr + align256((size_t)n_filters * sizeof(SegHdr));
   return L;
 }
 
