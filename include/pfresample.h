@@ -136,6 +136,11 @@ PFR_API int pfr_workspace_init(void* ws, size_t ws_bytes, void* stream);
  * block maximum and summed exactly, so the result is deterministic and the
  * only rounding is the final scaling r_i = n W_i / W_n to binary64.  Zero
  * weights are never selected.  Output ancestry is sorted (non-decreasing).
+ * Workspace: a single vector longer than the tuned single-workgroup length
+ * needs one (PFR_EWORKSPACE without); a batch (n_filters > 1) runs
+ * block-parallel with one and one workgroup per segment without one (a NULL
+ * workspace), with identical results.  The floating-point precision modes
+ * ignore a batch workspace.
  */
 
 /* Multinomial resampling (Code 5): draws the order statistics of n uniforms

@@ -1,0 +1,116 @@
+"""Parity at the benchmark workloads' full sizes, on sampled outputs.
+
+The 4096-vector ragged batch and the 1024 x 2^14 filter step run whole on the
+GPU, in the launch configuration the benchmark uses; the oracle recomputes a
+sample of segments (the shortest, the longest and a spread of others).  The
+collective schemes are also checked on one 2^22 vector.
+"""
+import math
+
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_4019_amd import inputs
+from tiecheck import check_ties, gpu_r_error_bound, strata_points
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+
+def pfr():
+    import paper_1301_4019_amd as m
+    return m
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def b_star(y):
+    return math.ceil(math.log(0.01) / math.log(1.0 - inputs.expected_weight(y)))
+
+
+def check_collective(scheme, w, a_gpu, seed, filt, offset=0):
+    n = w.size
+    if scheme == "multinomial":
+        a_or, fl, r, pts = oracle.multinomial(w, seed=seed, filt=filt, offset=offset,
+                                              return_rp=True)
+        delta = gpu_r_error_bound(w, n) + n * 2.0**-44
+    else:
+        a_or, fl, r = getattr(oracle, scheme)(w, seed=seed, filt=filt, offset=offset,
+                                              return_r=True)
+        if scheme == "stratified":
+            u = oracle.stratum_offsets(n, seed=seed, filt=filt, offset=offset)
+        else:
+            u = np.full(n, oracle.systematic_offset(seed=seed, filt=filt, offset=offset))
+        pts = strata_points(u)
+        delta = gpu_r_error_bound(w, n)
+    assert fl == 0
+    assert np.all(np.diff(a_gpu) >= 0)
+    check_ties(a_gpu, a_or, r, pts, delta, max_ties=5 + int(20 * delta * n))
+
+
+@pytest.fixture(scope="module")
+def batch():
+    w, off, ys = inputs.ragged_batch(n_filters=4096, seed=0)
+    return w, off, ys
+
+
+def test_ragged_batch_full_size_sampled(batch):
+    w, off, ys = batch
+    sizes = np.diff(off)
+    F = sizes.size
+    wd = torch.from_numpy(w).cuda()
+    od = torch.from_numpy(off).cuda()
+    B = np.array([b_star(float(y)) for y in ys], dtype=np.int32)
+    ml = int(sizes.max())
+    outs = {s: host(getattr(pfr(), "resample_" + s)(wd, seed=1, offsets=od, max_len=ml))
+            for s in ("systematic", "stratified", "multinomial")}
+    am = host(pfr().resample_metropolis(wd, 0, seed=1, B_per_filter=torch.from_numpy(B).cuda(),
+                                        offsets=od, max_len=ml))
+    fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    ar = host(pfr().resample_rejection(wd, 1.0, seed=1, offsets=od, max_len=ml, flags=fl))
+    assert int(host(fl)[0]) == 0
+    sample = sorted({0, 1, 2, 777, 2047, 3000, F - 1, int(sizes.argmin()), int(sizes.argmax())})
+    for f in sample:
+        seg = w[off[f]:off[f + 1]].astype(np.float64)
+        sl = slice(off[f], off[f + 1])
+        for s, a in outs.items():
+            check_collective(s, seg, a[sl], seed=1, filt=f)
+        assert np.array_equal(am[sl], oracle.metropolis(seg, int(B[f]), seed=1, filt=f)), f
+        assert np.array_equal(ar[sl], oracle.rejection(seg, 1.0, seed=1, filt=f)[0]), f
+
+
+@pytest.mark.parametrize("scheme", ["systematic", "stratified"])
+def test_collective_2p22(scheme):
+    n = 1 << 22
+    w = inputs.weights(n, 3.0, seed=0)
+    a = host(getattr(pfr(), "resample_" + scheme)(torch.from_numpy(w).cuda(), seed=5))
+    check_collective(scheme, w.astype(np.float64), a, seed=5, filt=0)
+
+
+def test_filter_step_full_size_sampled():
+    F, n, T = 1024, 1 << 14, 3
+    phi, q, r = 0.9, 1.0, 0.5
+    y = inputs.ssm_data(T, phi=phi, q=q, r=r, seed=0)[1]
+    flt = pfr().LGSSMFilter(y, F, n, phi=phi, q=q, r=r, scheme="systematic", seed=3)
+    flt.reset()
+    flt.step()  # t = 1 on uniform weights
+    x0, lz0 = host(flt.x), host(flt.log_z)
+    w0 = host(flt.w)
+    flt.step()  # t = 2, the step checked
+    a, c = host(flt.ancestors), host(flt.permuted)
+    x1, w1, lz1 = host(flt.x), host(flt.w), host(flt.log_z)
+    for f in (0, 511, 1023):
+        sl = slice(f * n, (f + 1) * n)
+        check_collective("systematic", w0[sl].astype(np.float64), a[sl], seed=3, filt=f,
+                         offset=2)
+        assert np.array_equal(c[sl], oracle.permute(a[sl])[0])
+        xo, wo, lzo, _ = oracle.lgssm_move(c[sl], x0[sl], lz0[f:f + 1], 1, n, phi, q, r, 2,
+                                           y[1], seed=3, filter_base=f)
+        gap = np.abs(x1[sl].astype(np.float64) - xo.astype(np.float64))
+        assert np.all(gap <= 2 * np.spacing(np.abs(xo)).astype(np.float64) + 1e-30)
+        np.testing.assert_allclose(w1[sl], wo, rtol=6e-7, atol=0)
+        assert lz1[f] == pytest.approx(lzo[0], rel=1e-12, abs=1e-12)
