@@ -72,6 +72,8 @@ def _load():
         "orc_offspring_to_ancestors": (ctypes.c_int, [P, i64, P, P]),
         "orc_ancestors_to_offspring": (ctypes.c_int, [P, i64, P, P]),
         "orc_permute": (ctypes.c_int, [P, i64, P, P, P]),
+        "orc_ess": (ctypes.c_int, [P, i64, P, P]),
+        "orc_copy_rows": (ctypes.c_int, [P, i64, i64, P, P, P]),
         "orc_permute_serial": (ctypes.c_int, [P, i64]),
         "orc_normal": (dbl, [u64, u32, u32, u32, u32, u32]),
         "orc_lgssm_init": (None, [i32, i32, dbl, u64, u32, u32, P]),
@@ -232,6 +234,29 @@ def ancestors_to_offspring(a):
     _check(_load().orc_ancestors_to_offspring(_ptr(a), a.size, _ptr(o), _ptr(fl)),
            "ancestors_to_offspring")
     return o, int(fl[0])
+
+
+def ess(w):
+    """Effective sample size Sum(w)^2 / w^T w -> (ess, flags)."""
+    w = _w(w)
+    out = np.zeros(1, dtype=np.float64)
+    fl = np.zeros(1, dtype=np.uint32)
+    _check(_load().orc_ess(_ptr(w), w.size, _ptr(out), _ptr(fl)), "ess")
+    return float(out[0]), int(fl[0])
+
+
+def copy_rows(c, x):
+    """Copy step of section 2.3 out of place: x (n, dim) float64 -> (x', flags)."""
+    c = np.ascontiguousarray(c, dtype=np.int32)
+    x = np.ascontiguousarray(x, dtype=np.float64)
+    if x.ndim == 1:
+        x = x.reshape(-1, 1)
+    assert x.shape[0] == c.size
+    out = np.empty_like(x)
+    fl = np.zeros(1, dtype=np.uint32)
+    _check(_load().orc_copy_rows(_ptr(c), c.size, x.shape[1], _ptr(x), _ptr(out), _ptr(fl)),
+           "copy_rows")
+    return out, int(fl[0])
 
 
 def permute(a, return_d=False):

@@ -473,6 +473,56 @@ int orc_ancestors_to_offspring(const int32_t* a, int64_t n, int32_t* o, uint32_t
 }
 
 /* ------------------------------------------------------------------------ */
+/* Effective sample size (section 3.4): the square of the weight sum over    */
+/* the sum of squared weights.  Sums in binary128, so neither the squares of */
+/* large binary64 weights nor the rounding of a long sum matter here.        */
+/* ------------------------------------------------------------------------ */
+int orc_ess(const double* w, int64_t n, double* ess, uint32_t* flags)
+{
+    int64_t i;
+    q128 s1 = 0, s2 = 0;
+    if (n < 0 || !ess || (n > 0 && !w)) return -1;
+    for (i = 0; i < n; ++i) {
+        if (!(w[i] >= 0.0) || isinf(w[i])) {
+            if (flags) *flags |= ORC_FLAG_BAD_WEIGHTS;
+            *ess = NAN;
+            return 0;
+        }
+        s1 += (q128)w[i];
+        s2 += (q128)w[i] * (q128)w[i];
+    }
+    if (s2 == 0) {
+        if (n > 0 && flags) *flags |= ORC_FLAG_ZERO_TOTAL;
+        *ess = 0.0;
+        return 0;
+    }
+    *ess = (double)(s1 * s1 / s2);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
+/* Copy step of section 2.3, out of place (see the header for the reading of */
+/* an ancestry that breaks the in-place predicate).                          */
+/* ------------------------------------------------------------------------ */
+int orc_copy_rows(const int32_t* c, int64_t n, int64_t dim, const double* x_in, double* x_out,
+                  uint32_t* flags)
+{
+    int64_t i, k;
+    uint32_t fl = 0;
+    if (n < 0 || dim < 1 || (n > 0 && (!c || !x_in || !x_out))) return -1;
+    for (i = 0; i < n; ++i) {
+        int64_t src = i;
+        if (c[i] != i) {
+            if (c[i] < 0 || c[i] >= n || c[c[i]] != c[i]) fl |= ORC_FLAG_BAD_ANCESTOR;
+            else src = c[i];
+        }
+        for (k = 0; k < dim; ++k) x_out[i * dim + k] = x_in[src * dim + k];
+    }
+    if (flags) *flags |= fl;
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Code 10: Prepermute then Permute.                                         */
 /*   Prepermute: d_j = n (unclaimed) for all j; then every i claims slot a_i */
 /*   and the lowest index wins, d_{a_i} = min(d_{a_i}, i).                   */

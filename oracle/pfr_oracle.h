@@ -90,6 +90,22 @@ int orc_offspring_to_ancestors(const int32_t* o, int64_t n, int32_t* a, uint32_t
 /* Code 12 (Ancestors-to-Offspring). */
 int orc_ancestors_to_offspring(const int32_t* a, int64_t n, int32_t* o, uint32_t* flags);
 
+/* Effective sample size Sum(w)^2 / w^T w (section 3.4, after Liu 1995),
+ * both sums in binary128.  An empty or all-zero vector gives 0 (all-zero
+ * raises ORC_FLAG_ZERO_TOTAL); a negative or non-finite weight gives NaN and
+ * ORC_FLAG_BAD_WEIGHTS. */
+int orc_ess(const double* w, int64_t n, double* ess, uint32_t* flags);
+
+/* The copy step of section 2.3 written out of place: x_out row i is x_in row
+ * c_i when c_i != i, else x_in row i (rows of `dim` doubles).  It reads only
+ * slots that are not written when c satisfies the in-place predicate of
+ * section 2.3 (c_{c_i} = c_i for every copied i).  Reading for other input: a
+ * particle whose c_i lies outside [0, n), or whose source slot is itself
+ * overwritten (c_{c_i} != c_i), keeps its own row and ORC_FLAG_BAD_ANCESTOR is
+ * raised. */
+int orc_copy_rows(const int32_t* c, int64_t n, int64_t dim, const double* x_in, double* x_out,
+                  uint32_t* flags);
+
 /* Code 10 (Prepermute + Permute); c receives the permuted ancestry, d (may be
  * NULL) the final claim vector (n = unclaimed). */
 int orc_permute(const int32_t* a, int64_t n, int32_t* c, int32_t* d, uint32_t* flags);
