@@ -119,7 +119,9 @@ typedef enum {
     PFR_OP_METROPOLIS = 3,
     PFR_OP_REJECTION = 4,
     PFR_OP_OFFSPRING_TO_ANCESTORS = 5,
-    PFR_OP_PERMUTE = 6
+    PFR_OP_PERMUTE = 6,
+    PFR_OP_ANCESTORS_TO_OFFSPRING = 7,
+    PFR_OP_ESS = 8
 } pfr_op;
 
 /* Bytes of workspace the operation needs for these segments (0 if none). */
@@ -220,6 +222,45 @@ PFR_API int offspring_to_ancestors(const int32_t* offspring, const pfr_segments*
 PFR_API int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t sorted_hint,
                       int32_t* permuted, void* ws, size_t ws_bytes, uint32_t* dev_flags,
                       void* stream);
+
+/* Ancestors to offspring counts (appendix D, Code 12): o_j = #{i : a_i = j}.
+ * With sorted_hint != 0 the ancestry must be non-decreasing (as produced by
+ * the collective resamplers; otherwise the counts are unspecified) and the
+ * counts are formed without atomics, from the first and last position of each
+ * run; otherwise any ancestry is counted (atomic additions, as in Code 12).
+ * An ancestor outside [0, n) is not counted and raises PFR_FLAG_BAD_ANCESTOR.
+ * No workspace. */
+PFR_API int ancestors_to_offspring(const int32_t* ancestors, const pfr_segments* seg,
+                                   int32_t sorted_hint, int32_t* offspring, uint32_t* dev_flags,
+                                   void* stream);
+
+/* Effective sample size (section 3.4): ess[f] = (sum w)^2 / (w^T w) for every
+ * segment f (ess: DEVICE double[n_filters]).  Binary64 sums of weights scaled
+ * by powers of two (exact), in an order fixed by the segment length, so the
+ * result is reproducible and free of overflow for any finite weights; its
+ * relative error is below (3d + 8) 2^-53 with d = 31 + ceil(P / 64), P the
+ * number of 4096-weight chunks of the segment.  An empty or all-zero segment
+ * gives 0 (all-zero raises PFR_FLAG_ZERO_TOTAL); a negative or non-finite
+ * weight gives NaN and PFR_FLAG_BAD_WEIGHTS.  Workspace required
+ * (pfr_workspace_bytes(PFR_OP_ESS, ...); it needs no initialisation). */
+PFR_API int effective_sample_size(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                                  double* ess, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                                  void* stream);
+
+/* The copy step of section 2.3, in place: x_i <- x_{c_i} for every particle i
+ * with c_i != i, c = `permuted` (the output of permute_ancestors, local to its
+ * segment).  The state of particle g (global index) has `dim` components of
+ * elem_bytes bytes each (1, 2, 4, 8 or 16), component k at element
+ * g * particle_stride + k * component_stride of x (strides in elements, >= 1;
+ * either component_stride == 1 and particle_stride >= dim, or particle_stride
+ * == 1 and component_stride >= n_total, or dim == 1).  x must be aligned to
+ * elem_bytes.  A particle whose c_i lies outside [0, n) or whose source is
+ * itself overwritten (c_{c_i} != c_i, which the in-place predicate forbids)
+ * keeps its state and raises PFR_FLAG_BAD_ANCESTOR, so the step never races.
+ * No workspace. */
+PFR_API int copy_particles(const int32_t* permuted, const pfr_segments* seg, void* x,
+                           size_t elem_bytes, int32_t dim, int64_t particle_stride,
+                           int64_t component_stride, uint32_t* dev_flags, void* stream);
 
 /* ---------------------------------------------------------------- filter
  * The bootstrap particle filter of Code 1 (section 1: K_t the transition

@@ -251,6 +251,63 @@ def permute_ancestors(a, sorted_hint=False, offsets=None, max_len=None, out=None
     return c
 
 
+def ancestors_to_offspring(a, sorted_hint=False, offsets=None, max_len=None, out=None,
+                           flags=None):
+    """Offspring counts o_j = #{i : a_i = j} (Code 12); atomic-free when
+    sorted_hint says the ancestry is non-decreasing."""
+    torch = _torch()
+    _require_cuda(a, flags)
+    if a.dtype != torch.int32:
+        raise TypeError("ancestors must be int32")
+    seg = _segments(a.numel(), offsets, max_len)
+    o = _out_like(a.numel(), a.device, out)
+    rc = _lib.load().ancestors_to_offspring(_ptr(a), ctypes.byref(seg), 1 if sorted_hint else 0,
+                                            _ptr(o), _ptr(flags), _stream())
+    _lib.check(rc, "ancestors_to_offspring")
+    return o
+
+
+def effective_sample_size(w, offsets=None, max_len=None, out=None, flags=None, workspace=None):
+    """ESS (sum w)^2 / w^T w per segment (section 3.4) -> float64 [n_filters]."""
+    torch = _torch()
+    _require_cuda(w, flags, out)
+    dt = _dtype_code(w)
+    seg = _segments(w.numel(), offsets, max_len)
+    nf = seg.n_filters
+    if out is None:
+        out = torch.empty(nf, dtype=torch.float64, device=w.device)
+    elif out.dtype != torch.float64 or out.numel() != nf:
+        raise ValueError("out must be a float64 tensor with one entry per segment")
+    ws, _ = _workspace(_lib.OP_ESS, seg, dt, w.device, workspace)
+    rc = _lib.load().effective_sample_size(_ptr(w), dt, ctypes.byref(seg), _ptr(out), _ptr(ws),
+                                           0 if ws is None else ws.numel(), _ptr(flags),
+                                           _stream())
+    _lib.check(rc, "effective_sample_size")
+    return out
+
+
+def copy_particles(c, x, offsets=None, max_len=None, flags=None):
+    """In-place copy step x_i <- x_{c_i} for c_i != i (section 2.3).
+
+    x has one row per particle, shape (n,) or (n, D), with any strides that
+    keep either the rows or the columns contiguous (an (n, D) tensor, or the
+    transpose of a (D, n) one)."""
+    torch = _torch()
+    _require_cuda(c, flags)
+    if c.dtype != torch.int32:
+        raise TypeError("permuted ancestors must be int32")
+    if not x.is_cuda or x.dim() not in (1, 2) or x.shape[0] != c.numel():
+        raise ValueError("x must be a GPU tensor with one row per particle")
+    dim = 1 if x.dim() == 1 else x.shape[1]
+    ps = x.stride(0)
+    cs = 1 if x.dim() == 1 else x.stride(1)
+    seg = _segments(c.numel(), offsets, max_len)
+    rc = _lib.load().copy_particles(_ptr(c), ctypes.byref(seg), _ptr(x), x.element_size(),
+                                    int(dim), int(ps), int(cs), _ptr(flags), _stream())
+    _lib.check(rc, "copy_particles")
+    return x
+
+
 _SCHEME_OPS = {"multinomial": _lib.OP_MULTINOMIAL, "stratified": _lib.OP_STRATIFIED,
                "systematic": _lib.OP_SYSTEMATIC, "metropolis": _lib.OP_METROPOLIS,
                "rejection": _lib.OP_REJECTION}

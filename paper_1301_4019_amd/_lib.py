@@ -17,7 +17,7 @@ PFR_OK, PFR_EINVAL, PFR_EWORKSPACE, PFR_ELAUNCH, PFR_ENOTSUP = range(5)
 PFR_F32, PFR_F64 = 0, 1
 SCAN_EXACT, SCAN_F64, SCAN_COMP_F32, SCAN_NAIVE_F32 = 0, 1, 2, 3
 (OP_MULTINOMIAL, OP_STRATIFIED, OP_SYSTEMATIC, OP_METROPOLIS, OP_REJECTION,
- OP_OFFSPRING_TO_ANCESTORS, OP_PERMUTE) = range(7)
+ OP_OFFSPRING_TO_ANCESTORS, OP_PERMUTE, OP_ANCESTORS_TO_OFFSPRING, OP_ESS) = range(9)
 
 FLAG_ZERO_TOTAL = 1
 FLAG_TRIAL_CAP = 2
@@ -30,7 +30,8 @@ MAX_BATCH_SEGMENT = 256 * 1024 - 1
 EXPORTS = (
     "pfr_workspace_bytes", "pfr_workspace_init", "resample_multinomial", "resample_stratified",
     "resample_systematic", "resample_metropolis", "resample_rejection", "offspring_to_ancestors",
-    "permute_ancestors", "lgssm_workspace_bytes", "lgssm_init", "lgssm_step",
+    "permute_ancestors", "ancestors_to_offspring", "effective_sample_size", "copy_particles",
+    "lgssm_workspace_bytes", "lgssm_init", "lgssm_step",
     "pfr_tuning_defaults", "pfr_get_tuning", "pfr_set_tuning", "pfr_load_tuning",
     "pfr_status_string", "pfr_version",
 )
@@ -92,6 +93,9 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "resample_rejection": (I, [P, I, SEG, D, P, U32, Rng, P, P, SZ, P, P]),
         "offspring_to_ancestors": (I, [P, SEG, P, P, SZ, P, P]),
         "permute_ancestors": (I, [P, SEG, I32, P, P, SZ, P, P]),
+        "ancestors_to_offspring": (I, [P, SEG, I32, P, P, P]),
+        "effective_sample_size": (I, [P, I, SEG, P, P, SZ, P, P]),
+        "copy_particles": (I, [P, SEG, P, SZ, I32, ctypes.c_int64, ctypes.c_int64, P, P]),
         "lgssm_workspace_bytes": (SZ, [I32, I32]),
         "lgssm_init": (I, [MODEL, I32, I32, Rng, P, P, P, P, P, P, SZ, P]),
         "lgssm_step": (I, [MODEL, I, I, I32, I32, P, I32, P, Rng, P, P, P, P, P, P, P, SZ, P,

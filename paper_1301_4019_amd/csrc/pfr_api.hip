@@ -141,6 +141,10 @@ size_t pfr_workspace_bytes(pfr_op op, const pfr_segments* seg, pfr_dtype dtype) 
       return o2a_workspace_bytes(s.n_total);
     case PFR_OP_PERMUTE:
       return permute_workspace_bytes(s.n_total);
+    case PFR_OP_ANCESTORS_TO_OFFSPRING:
+      return 0;
+    case PFR_OP_ESS:
+      return ess_workspace_bytes(s.n_total, s.n_filters);
   }
   return 0;
 }
@@ -247,6 +251,64 @@ int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t
   return launch_result(launch_permute(ancestors, s.n_total, s.offsets, s.n_filters, s.max_len,
                                       sorted_hint != 0, permuted, ws, dev_flags,
                                       (hipStream_t)stream));
+}
+
+int ancestors_to_offspring(const int32_t* ancestors, const pfr_segments* seg, int32_t sorted_hint,
+                           int32_t* offspring, uint32_t* dev_flags, void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (s.n_total == 0) return PFR_OK;
+  if (!ancestors || !offspring) return PFR_EINVAL;
+  if (overlaps(ancestors, (size_t)s.n_total * 4, offspring, (size_t)s.n_total * 4))
+    return PFR_EINVAL;
+  return launch_result(launch_ancestors_to_offspring(ancestors, s.n_total, s.offsets,
+                                                     s.n_filters, s.max_len, sorted_hint != 0,
+                                                     offspring, dev_flags,
+                                                     (hipStream_t)stream));
+}
+
+int effective_sample_size(const void* w, pfr_dtype dtype, const pfr_segments* seg, double* ess,
+                          void* ws, size_t ws_bytes, uint32_t* dev_flags, void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (dtype != PFR_F32 && dtype != PFR_F64) return PFR_EINVAL;
+  if (!ess || (s.n_total > 0 && !w)) return PFR_EINVAL;
+  const size_t need = ess_workspace_bytes(s.n_total, s.n_filters);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return PFR_EWORKSPACE;
+  const size_t ebytes = (size_t)s.n_filters * sizeof(double);
+  if (overlaps(ws, need, ess, ebytes) ||
+      (s.n_total > 0 && overlaps(w, (size_t)s.n_total * dtype_size(dtype), ess, ebytes)))
+    return PFR_EINVAL;
+  return launch_result(launch_ess(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters, ess, ws,
+                                  dev_flags, (hipStream_t)stream));
+}
+
+int copy_particles(const int32_t* permuted, const pfr_segments* seg, void* x, size_t elem_bytes,
+                   int32_t dim, int64_t particle_stride, int64_t component_stride,
+                   uint32_t* dev_flags, void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (elem_bytes != 1 && elem_bytes != 2 && elem_bytes != 4 && elem_bytes != 8 &&
+      elem_bytes != 16)
+    return PFR_EINVAL;
+  if (dim < 1 || particle_stride < 1 || component_stride < 1) return PFR_EINVAL;
+  // distinct (particle, component) pairs must address distinct elements
+  const bool rows = component_stride == 1 && particle_stride >= dim;
+  const bool cols = particle_stride == 1 && component_stride >= s.n_total;
+  if (!(dim == 1 || rows || cols)) return PFR_EINVAL;
+  if (s.n_total == 0) return PFR_OK;
+  if (!permuted || !x) return PFR_EINVAL;
+  if ((reinterpret_cast<uintptr_t>(x) & (elem_bytes - 1)) != 0) return PFR_EINVAL;
+  const double span = ((double)(s.n_total - 1) * (double)particle_stride +
+                       (double)(dim - 1) * (double)component_stride + 1.0) * (double)elem_bytes;
+  if (span >= 0x1p62) return PFR_EINVAL;
+  if (overlaps(x, (size_t)span, permuted, (size_t)s.n_total * 4)) return PFR_EINVAL;
+  return launch_result(launch_copy(permuted, s.n_total, s.offsets, s.n_filters, x, elem_bytes, dim,
+                                   particle_stride, dim == 1 ? 1 : component_stride, dev_flags,
+                                   (hipStream_t)stream));
 }
 
 size_t lgssm_workspace_bytes(int32_t n_filters, int32_t n) {

@@ -113,6 +113,18 @@ hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offs
                           uint32_t n_filters, int64_t max_len, bool sorted, int32_t* c, void* ws,
                           uint32_t* flags, hipStream_t stream);
 
+// Code 12; max_len as for launch_permute.
+hipError_t launch_ancestors_to_offspring(const int32_t* a, int64_t n_total, const int64_t* offsets,
+                                         uint32_t n_filters, int64_t max_len, bool sorted,
+                                         int32_t* o, uint32_t* flags, hipStream_t stream);
+size_t ess_workspace_bytes(int64_t n_total, uint32_t n_filters);
+hipError_t launch_ess(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
+                      uint32_t n_filters, double* ess, void* ws, uint32_t* flags,
+                      hipStream_t stream);
+hipError_t launch_copy(const int32_t* c, int64_t n_total, const int64_t* offsets,
+                       uint32_t n_filters, void* x, size_t elem_bytes, int32_t dim, int64_t ps,
+                       int64_t cs, uint32_t* flags, hipStream_t stream);
+
 hipError_t launch_lgssm_init(int32_t n_filters, int32_t n, double s0, Key key, uint32_t offset,
                              uint32_t filter_base, float* x, float* w, double* logz,
                              int32_t* B_dev, uint32_t* t_dev, int64_t* offsets,

@@ -54,6 +54,54 @@ def test_workspace_sizes():
     assert lib.pfr_workspace_bytes(_lib.OP_PERMUTE, ctypes.byref(s_big), 0) >= 4 << 20
     assert lib.pfr_workspace_bytes(_lib.OP_OFFSPRING_TO_ANCESTORS, ctypes.byref(s_big), 0) >= 256 + 256 * 8
     assert lib.pfr_workspace_bytes(_lib.OP_REJECTION, ctypes.byref(s_big), 0) == tab
+    # ESS: a 32-byte partial per 4096-weight chunk (plus one per segment)
+    ess_big = lib.pfr_workspace_bytes(_lib.OP_ESS, ctypes.byref(s_big), 0)
+    assert ess_big >= 256 * 32 and ess_big % 256 == 0
+    assert lib.pfr_workspace_bytes(_lib.OP_ESS, ctypes.byref(seg(0)), 0) > 0
+    assert lib.pfr_workspace_bytes(_lib.OP_ANCESTORS_TO_OFFSPRING, ctypes.byref(s_big), 0) == 0
+
+
+def test_auxiliary_arguments_rejected_on_host():
+    lib = _lib.load()
+    fake = ctypes.c_void_p(0x10000)
+    out = ctypes.c_void_p(0x10000 + (1 << 30))
+    ws = ctypes.c_void_p(0x10000 + (2 << 30))
+    # Code 12: output aliases input, null pointers, batch without offsets
+    assert lib.ancestors_to_offspring(fake, ctypes.byref(seg(10)), 1, fake, None,
+                                      None) == _lib.PFR_EINVAL
+    assert lib.ancestors_to_offspring(None, ctypes.byref(seg(10)), 0, out, None,
+                                      None) == _lib.PFR_EINVAL
+    assert lib.ancestors_to_offspring(fake, ctypes.byref(seg(10, 3, None)), 0, out, None,
+                                      None) == _lib.PFR_EINVAL
+    # ESS: workspace missing or small, null output, unknown dtype
+    assert lib.effective_sample_size(fake, 0, ctypes.byref(seg(10)), out, None, 0, None,
+                                     None) == _lib.PFR_EWORKSPACE
+    assert lib.effective_sample_size(fake, 0, ctypes.byref(seg(1 << 20)), out, ws, 256, None,
+                                     None) == _lib.PFR_EWORKSPACE
+    assert lib.effective_sample_size(fake, 0, ctypes.byref(seg(10)), None, ws, 1 << 20, None,
+                                     None) == _lib.PFR_EINVAL
+    assert lib.effective_sample_size(fake, 5, ctypes.byref(seg(10)), out, ws, 1 << 20, None,
+                                     None) == _lib.PFR_EINVAL
+    # copy: element size, strides that alias elements, misaligned state
+    I64 = ctypes.c_int64
+    assert lib.copy_particles(fake, ctypes.byref(seg(10)), out, 3, 1, I64(1), I64(1), None,
+                              None) == _lib.PFR_EINVAL
+    assert lib.copy_particles(fake, ctypes.byref(seg(10)), out, 4, 4, I64(2), I64(1), None,
+                              None) == _lib.PFR_EINVAL
+    assert lib.copy_particles(fake, ctypes.byref(seg(10)), out, 4, 2, I64(1), I64(5), None,
+                              None) == _lib.PFR_EINVAL
+    assert lib.copy_particles(fake, ctypes.byref(seg(10)), out, 4, 0, I64(1), I64(1), None,
+                              None) == _lib.PFR_EINVAL
+    assert lib.copy_particles(fake, ctypes.byref(seg(10)), ctypes.c_void_p(0x10000 + (1 << 30) + 2),
+                              4, 1, I64(1), I64(1), None, None) == _lib.PFR_EINVAL
+    # the state overlaps the permutation
+    assert lib.copy_particles(fake, ctypes.byref(seg(10)), fake, 4, 1, I64(1), I64(1), None,
+                              None) == _lib.PFR_EINVAL
+    # empty input is a no-op
+    assert lib.copy_particles(None, ctypes.byref(seg(0)), None, 4, 3, I64(3), I64(1), None,
+                              None) == _lib.PFR_OK
+    assert lib.ancestors_to_offspring(None, ctypes.byref(seg(0)), 1, None, None,
+                                      None) == _lib.PFR_OK
 
 
 def test_invalid_arguments_rejected_on_host():
