@@ -63,6 +63,8 @@ def _load():
         "orc_resample_metropolis": (ctypes.c_int, [P, i64, i32, u64, u32, u32, P]),
         "orc_resample_rejection": (ctypes.c_int, [P, i64, dbl, u32, u64, u32, u32, P, P, P]),
         "orc_stratified_u": (ctypes.c_int, [P, i64, P, P, P, P]),
+        "orc_resample_partial_rejection": (ctypes.c_int, [P, i64, dbl, u32, u64, u32, u32, P, P,
+                                                          P]),
         "orc_resample_stratified": (ctypes.c_int, [P, i64, u64, u32, u32, P, P, P]),
         "orc_resample_systematic": (ctypes.c_int, [P, i64, u64, u32, u32, P, P, P]),
         "orc_systematic_offset": (dbl, [u64, u32, u32]),
@@ -205,6 +207,18 @@ def multinomial(w, seed=0, filt=0, offset=0, return_rp=False):
     _check(_load().orc_resample_multinomial(_ptr(w), w.size, seed, filt, offset, _ptr(a),
                                             _ptr(r), _ptr(p), _ptr(fl)), "multinomial")
     return (a, int(fl[0]), r, p) if return_rp else (a, int(fl[0]))
+
+
+def partial_rejection(w, v_max, seed=0, filt=0, offset=0, max_trials=1 << 20):
+    """Partial rejection control -> (ancestors, importance weights (float64), flags)."""
+    w = _w(w)
+    a = np.empty(w.size, dtype=np.int32)
+    wo = np.empty(w.size, dtype=np.float64)
+    fl = np.zeros(1, dtype=np.uint32)
+    _check(_load().orc_resample_partial_rejection(_ptr(w), w.size, float(v_max), max_trials,
+                                                  int(seed) & (2**64 - 1), filt, offset, _ptr(a),
+                                                  _ptr(wo), _ptr(fl)), "partial_rejection")
+    return a, wo, int(fl[0])
 
 
 def multinomial_points(w, p):

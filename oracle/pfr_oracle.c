@@ -194,6 +194,33 @@ int orc_resample_rejection(const double* w, int64_t n, double w_max, uint32_t ma
 }
 
 /* ------------------------------------------------------------------------ */
+/* Partial rejection control: Code 3 on the clipped weights, then the        */
+/* importance weight of each particle's ancestor.                            */
+/* ------------------------------------------------------------------------ */
+int orc_resample_partial_rejection(const double* w, int64_t n, double v_max, uint32_t max_trials,
+                                   uint64_t seed, uint32_t filter, uint32_t offset, int32_t* a,
+                                   double* w_out, uint32_t* flags)
+{
+    int64_t i;
+    double* v;
+    int rc;
+    if (n < 0 || max_trials == 0 || !(v_max > 0.0) || (n > 0 && (!w || !a || !w_out))) return -1;
+    if (n == 0) return 0;
+    v = (double*)malloc((size_t)n * sizeof(double));
+    if (!v) return -1;
+    for (i = 0; i < n; ++i) v[i] = (w[i] > v_max) ? v_max : w[i];
+    rc = orc_resample_rejection(v, n, v_max, max_trials, seed, filter, offset, a, NULL, flags);
+    if (rc == 0) {
+        for (i = 0; i < n; ++i) {
+            const double va = v[a[i]];
+            w_out[i] = (va > 0.0) ? w[a[i]] / va : 0.0;
+        }
+    }
+    free(v);
+    return rc;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Shared pieces of the collective schemes (appendix B).                     */
 /* ------------------------------------------------------------------------ */
 

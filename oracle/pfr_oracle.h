@@ -59,6 +59,16 @@ int orc_resample_rejection(const double* w, int64_t n, double w_max, uint32_t ma
                            uint64_t seed, uint32_t filter, uint32_t offset, int32_t* a,
                            uint32_t* trials, uint32_t* flags);
 
+/* Partial rejection control (section 2.2, after Liu et al. 1998): for a bound
+ * v_max, the clipped weights v_i = min(w_i, v_max) are resampled by Code 3
+ * with bound v_max, and particle i receives the importance weight
+ * w_out[i] = w_{a_i} / v_{a_i} (computed in binary64).  Reading: v_i keeps a
+ * NaN or negative w_i (which Code 3 never accepts); a lane that reaches the
+ * trial cap keeps a_i = i and gets w_i / v_i, or 0 when v_i is not positive. */
+int orc_resample_partial_rejection(const double* w, int64_t n, double v_max, uint32_t max_trials,
+                                   uint64_t seed, uint32_t filter, uint32_t offset, int32_t* a,
+                                   double* w_out, uint32_t* flags);
+
 /* Code 7 (stratified) with explicit stratum offsets u[0..n) in [0,1).
  * r_out (may be NULL) receives the scaled prefix r_i = n W_i / W_n (rounded
  * to double from the oracle's binary128 value). */
