@@ -245,6 +245,232 @@ def batch_workload(args):
                       "rows": rows}), flush=True)
 
 
+def decision_workload(args):
+    """Fastest resampler per (N, y), and the Metropolis bias / time trade-off.
+
+    Decision matrix (section 3.4): for N = 2^4 .. 2^22 and y = 0, 1/2, .., 4,
+    float32 weights w = exp(-(x - y)^2 / 2), x ~ N(0, 1) (data seed 0), every
+    resampler is timed until it has delivered an ancestry satisfying the
+    in-place predicate -- the resample followed by permute_ancestors -- with
+    HIP events around --decision-reps back-to-back calls; the cell takes the
+    scheme of least mean time.  Metropolis takes B = B* from the bias bound
+    with beta = mean(w) / w_max of the weight vector itself, rejection w_max = 1
+    (the bound of these weights).
+
+    Metropolis trade-off (section 3.3): y = 4, B = ceil(B* / C) for C = 1, 2,
+    4, 8, with multinomial as the unbiased reference: ||Bias||^2 / MSE and
+    MSE / N over --replicates Philox seeds, and the time per resample.
+    """
+    import torch
+    import paper_1301_4019_amd as pfr
+    from paper_1301_4019_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    reps = args.decision_reps
+    lgs = list(range(args.decision_log2n[0], args.decision_log2n[1] + 1))
+    ys = [0.5 * k for k in range(9)]
+    nmax = 1 << lgs[-1]
+    a = torch.empty(nmax, dtype=torch.int32, device=dev)
+    c = torch.empty(nmax, dtype=torch.int32, device=dev)
+
+    def b_of(wn):
+        beta = float(np.mean(wn, dtype=np.float64)) / float(wn.max())
+        if beta >= 1.0:
+            return 1
+        return max(1, math.ceil(math.log(0.01) / math.log(1.0 - beta)))
+
+    def call(scheme, w, n, B):
+        out, perm = a[:n], c[:n]
+        if scheme == "metropolis":
+            pfr.resample_metropolis(w, B, seed=1, out=out)
+        elif scheme == "rejection":
+            pfr.resample_rejection(w, 1.0, seed=1, out=out, flags=flags)
+        else:
+            getattr(pfr, "resample_" + scheme)(w, seed=1, out=out, flags=flags)
+        pfr.permute_ancestors(out, sorted_hint=scheme not in ("metropolis", "rejection"),
+                              out=perm, flags=flags)
+
+    cells = []
+    t_start = time.perf_counter()
+    for lg in lgs:
+        n = 1 << lg
+        for y in ys:
+            wn = inputs.weights(n, y, seed=0)
+            w = torch.from_numpy(wn).to(dev)
+            B = b_of(wn)
+            times, eager = {}, {}
+            for scheme in SCHEMES:
+                call(scheme, w, n, B)  # warm-up, workspaces
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                for _ in range(reps):
+                    call(scheme, w, n, B)
+                e1.record(stream)
+                e1.synchronize()
+                eager[scheme] = 1e3 * e0.elapsed_time(e1) / reps
+                # device time alone: the same calls replayed from a captured graph
+                g = torch.cuda.CUDAGraph()
+                with torch.cuda.graph(g):
+                    for _ in range(reps):
+                        call(scheme, w, n, B)
+                g.replay()
+                e0.record(stream)
+                g.replay()
+                e1.record(stream)
+                e1.synchronize()
+                times[scheme] = 1e3 * e0.elapsed_time(e1) / reps
+                del g
+            best = min(times, key=times.get)
+            cells.append({"log2n": lg, "y": y, "B": B, "us": times, "eager_us": eager,
+                          "fastest": best, "fastest_eager": min(eager, key=eager.get)})
+        log(f"decision n = 2^{lg} done ({time.perf_counter() - t_start:.0f} s)")
+
+    # Metropolis B = B*/C against multinomial, y = 4
+    K = args.replicates
+    y = 4.0
+    trade = []
+    for lg in args.tradeoff_log2n:
+        n = 1 << lg
+        wn = inputs.weights(n, y, seed=0)
+        w = torch.from_numpy(wn).to(dev)
+        wd = w.double()
+        e = n * wd / wd.sum()
+        Bs = b_of(wn)
+        out = a[:n]
+        cases = [("multinomial", None)] + [("metropolis", C) for C in (1, 2, 4, 8)]
+        for scheme, C in cases:
+            B = None if C is None else max(1, math.ceil(Bs / C))
+            S1 = torch.zeros(n, dtype=torch.float64, device=dev)
+            S2 = torch.zeros(n, dtype=torch.float64, device=dev)
+            t_ms = 0.0
+            for k in range(K):
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                if scheme == "metropolis":
+                    pfr.resample_metropolis(w, B, seed=1 + k, out=out)
+                else:
+                    pfr.resample_multinomial(w, seed=1 + k, out=out, flags=flags)
+                e1.record(stream)
+                o = torch.bincount(out, minlength=n).double()
+                S1 += o
+                S2 += o * o
+                e1.synchronize()
+                t_ms += e0.elapsed_time(e1)
+            mean = S1 / K
+            bias2 = float(((mean - e) ** 2).sum())
+            mse = float((S2 / K - 2.0 * e * mean + e * e).sum())
+            trade.append({"log2n": lg, "scheme": scheme, "C": C, "B": B,
+                          "bias2_over_mse": bias2 / mse, "mse_over_n": mse / n,
+                          "resample_us": 1e3 * t_ms / K})
+        log(f"trade-off n = 2^{lg} done ({time.perf_counter() - t_start:.0f} s)")
+    if int(flags.cpu()[0]) != 0:
+        raise RuntimeError(f"data flags raised: {int(flags.cpu()[0])}")
+
+    letters = {"multinomial": "M", "stratified": "S", "systematic": "Y", "metropolis": "P",
+               "rejection": "R"}
+    grid, grid_eager = [], []
+    for lg in lgs:
+        row = "".join(letters[cl["fastest"]] for cl in cells if cl["log2n"] == lg)
+        grid.append(f"2^{lg:<2d} {row}")
+        row = "".join(letters[cl["fastest_eager"]] for cl in cells if cl["log2n"] == lg)
+        grid_eager.append(f"2^{lg:<2d} {row}")
+    print(json.dumps({"metric": "fastest resampler per (N, y) incl. permutation; Metropolis "
+                                "bias/time at B = B*/C",
+                      "unit": "us", "higher_is_better": False, "n_gpus": 1,
+                      "data": "synthetic",
+                      "config": {"workload": "decision matrix: N = 2^" + str(lgs[0]) + "..2^" +
+                                             str(lgs[-1]) + ", y = 0..4 step 1/2, float32 "
+                                             "weights (data seed 0); trade-off at y = 4",
+                                 "reps": reps, "replicates": K,
+                                 "legend": "M multinomial, S stratified, Y systematic, "
+                                           "P Metropolis, R rejection; columns y = 0..4"},
+                      "matrix": grid, "matrix_eager": grid_eager, "cells": cells,
+                      "tradeoff": trade}), flush=True)
+
+
+def aux_workload(args):
+    """Auxiliary exports on float32 / int32 data resident in HBM, HIP-event timed
+    (mean over --steps calls after a warm-up), against their algorithmic bytes:
+      ancestors_to_offspring  read a, write o                 8 B / particle
+      effective_sample_size   read w                           4 B / particle
+      copy_particles          read c, read + write the copied state rows
+    for a single vector of 2^20 and 2^24 particles (systematic ancestry of
+    y = 2 weights; Metropolis ancestry for the unsorted count) and the
+    4096-vector ragged batch."""
+    import torch
+    import paper_1301_4019_amd as pfr
+    from paper_1301_4019_amd import inputs
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    rows = []
+
+    def timed(fn):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(args.steps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / args.steps
+
+    def add(case, what, ms, n, nbytes):
+        rows.append({"case": case, "op": what, "us": 1e3 * ms, "particles_per_s": n / (ms * 1e-3),
+                     "algorithmic_bytes": nbytes, "GB_per_s": nbytes / (ms * 1e-3) / 1e9,
+                     "hbm_frac": nbytes / (ms * 1e-3) / (HBM_PEAK_GBS * 1e9)})
+        log(f"  {case:22s} {what:30s} {1e3 * ms:9.1f} us  {nbytes / (ms * 1e-3) / 1e9:7.0f} GB/s")
+
+    cases = []
+    for lg in (20, 24):
+        n = 1 << lg
+        w = torch.from_numpy(inputs.weights(n, 2.0, seed=lg)).to(dev)
+        cases.append((f"single n=2^{lg}", w, None, n))
+    wb, offb, _ = inputs.ragged_batch(n_filters=4096, seed=0)
+    cases.append(("batch 4096 ragged", torch.from_numpy(wb).to(dev),
+                  torch.from_numpy(offb).to(dev), int(np.diff(offb).max())))
+    for case, w, off, ml in cases:
+        n = w.numel()
+        kw = {} if off is None else {"offsets": off, "max_len": ml}
+        a = pfr.resample_systematic(w, seed=1, flags=flags, **kw)
+        am = pfr.resample_metropolis(w, 16, seed=1, **kw)
+        cperm = pfr.permute_ancestors(a, sorted_hint=True, flags=flags, **kw)
+        o = torch.empty(n, dtype=torch.int32, device=dev)
+        copied = int((cperm != torch.arange(n, device=dev, dtype=torch.int32)).sum()) \
+            if off is None else None
+        add(case, "a2o sorted", timed(lambda: pfr.ancestors_to_offspring(
+            a, sorted_hint=True, out=o, flags=flags, **kw)), n, 8 * n)
+        add(case, "a2o unsorted (Metropolis)", timed(lambda: pfr.ancestors_to_offspring(
+            am, out=o, flags=flags, **kw)), n, 8 * n)
+        e = pfr.effective_sample_size(w, flags=flags, **kw)
+        add(case, "ess", timed(lambda: pfr.effective_sample_size(w, out=e, flags=flags, **kw)),
+            n, 4 * n)
+        if off is None:
+            for D, layout in ((1, "rows"), (4, "rows"), (4, "columns")):
+                x = torch.zeros(n, D, dtype=torch.float32, device=dev)
+                if layout == "columns":
+                    x = torch.zeros(D, n, dtype=torch.float32, device=dev).t()
+                add(case, f"copy D={D} {layout} ({copied} moved)",
+                    timed(lambda: pfr.copy_particles(cperm, x, flags=flags)), n,
+                    4 * n + 8 * D * copied)
+    if int(flags.cpu()[0]) != 0:
+        raise RuntimeError(f"data flags raised: {int(flags.cpu()[0])}")
+    print(json.dumps({"metric": "auxiliary exports: time and HBM fraction of algorithmic bytes",
+                      "unit": "us", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "ancestors_to_offspring, effective_sample_size, "
+                                             "copy_particles; n = 2^20, 2^24 and the 4096-vector "
+                                             "ragged batch", "steps": args.steps},
+                      "rows": rows}), flush=True)
+
+
 def filter_workload(args):
     """Bootstrap filter on x_t = 0.9 x_{t-1} + N(0,1), y_t = x_t + N(0, 0.5^2):
     1024 filters of 2^14 particles, T = 200 synthetic observations (seed 0); one
@@ -310,16 +536,22 @@ def main():
                     help="first run one device-to-device copy of this many MiB, a kernel of "
                          "known traffic for scaling hardware byte counters")
     ap.add_argument("--cpu-sample", type=int, default=1 << 18)
-    ap.add_argument("--workload", choices=("step", "precision", "batch", "filter"),
+    ap.add_argument("--workload", choices=("step", "precision", "batch", "filter", "decision",
+                                              "aux"),
                     default="step",
                     help="step: the timed resampling step (default); precision: the bias "
                          "sweep over prefix-sum precision modes; batch: ragged batch of "
-                         "4096 filters; filter: full bootstrap filter, 1024 x 2^14 x 200")
+                         "4096 filters; filter: full bootstrap filter, 1024 x 2^14 x 200; "
+                         "decision: fastest scheme per (N, y) and the Metropolis B*/C "
+                         "trade-off; aux: the auxiliary exports")
     ap.add_argument("--filters", type=int, default=4096)
     ap.add_argument("--filters-ssm", type=int, default=1024)
     ap.add_argument("--filter-reps", type=int, default=3)
     ap.add_argument("--replicates", type=int, default=256)
     ap.add_argument("--sweep-log2n", type=int, nargs="+", default=[16, 18, 20, 22, 24])
+    ap.add_argument("--decision-log2n", type=int, nargs=2, default=[4, 22])
+    ap.add_argument("--decision-reps", type=int, default=20)
+    ap.add_argument("--tradeoff-log2n", type=int, nargs="+", default=[12, 16, 20])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the resampling step here runs on a single MI355X "
@@ -333,6 +565,12 @@ def main():
         return
     if args.workload == "filter":
         filter_workload(args)
+        return
+    if args.workload == "decision":
+        decision_workload(args)
+        return
+    if args.workload == "aux":
+        aux_workload(args)
         return
 
     import torch

@@ -199,6 +199,23 @@ PFR_API int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segment
                        int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
                        void* stream);
 
+/* Partial rejection control (section 2.2, after Liu et al. 1998): with a
+ * bound v_max that need not bound the weights, the clipped weights
+ * v_i = min(w_i, v_max) are resampled as by resample_rejection with bound
+ * v_max -- which accepts exactly when u v_max <= w_j, so the ancestors are
+ * those of resample_rejection(w, v_max) -- and the outcome is weighted:
+ * weights_out[i] (same type as w) = w_{a_i} / v_{a_i}, i.e. w_{a_i} / v_max
+ * where w_{a_i} > v_max and 1 elsewhere (binary64 quotient, rounded); a lane
+ * that hits max_trials keeps a_i = i, gets w_i / v_i (0 if w_i is not
+ * positive) and raises PFR_FLAG_TRIAL_CAP.  v_max_dev (device
+ * double[n_filters], may be NULL) overrides v_max per segment.  Workspace as
+ * for resample_rejection.  weights_out must not alias w or ancestors. */
+PFR_API int resample_partial_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                                       double v_max, const double* v_max_dev,
+                                       uint32_t max_trials, pfr_rng rng, int32_t* ancestors,
+                                       void* weights_out, void* ws, size_t ws_bytes,
+                                       uint32_t* dev_flags, void* stream);
+
 /* ---------------------------------------------------------------- auxiliaries */
 
 /* Offspring counts to ancestors (appendix D, Code 11 after an inclusive prefix

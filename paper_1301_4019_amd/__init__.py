@@ -100,6 +100,17 @@ def _segments(n_total, offsets=None, max_len=None):
                          int(max_len) if max_len is not None else 0)
 
 
+def _per_segment(t, dtype, seg, what):
+    """A per-segment device array must have the C type the library reads and
+    one entry per segment."""
+    if t is None:
+        return
+    torch = _torch()
+    want = {"int32": torch.int32, "float64": torch.float64}[dtype]
+    if t.dtype != want or t.numel() < seg.n_filters:
+        raise TypeError(f"{what} must be a {dtype} tensor with one entry per segment")
+
+
 def _rng(seed, offset, filter_base, offset_dev=None):
     return _lib.Rng(int(seed) & (2**64 - 1), int(offset) & 0xFFFFFFFF,
                     int(filter_base) & 0xFFFFFFFF,
@@ -190,6 +201,7 @@ def resample_metropolis(w, B, seed=0, offset=0, filter_base=0, B_per_filter=None
     _require_cuda(w, B_per_filter)
     dt = _dtype_code(w)
     seg = _segments(w.numel(), offsets, max_len)
+    _per_segment(B_per_filter, "int32", seg, "B_per_filter")
     a = _out_like(w.numel(), w.device, out)
     ws, _ = _workspace(_lib.OP_METROPOLIS, seg, dt, w.device, workspace)
     rc = _lib.load().resample_metropolis(_ptr(w), dt, ctypes.byref(seg), int(B),
@@ -207,6 +219,7 @@ def resample_rejection(w, w_max, seed=0, offset=0, filter_base=0, max_trials=1 <
     _require_cuda(w, w_max_per_filter, flags)
     dt = _dtype_code(w)
     seg = _segments(w.numel(), offsets, max_len)
+    _per_segment(w_max_per_filter, "float64", seg, "w_max_per_filter")
     a = _out_like(w.numel(), w.device, out)
     ws, _ = _workspace(_lib.OP_REJECTION, seg, dt, w.device, workspace)
     rc = _lib.load().resample_rejection(_ptr(w), dt, ctypes.byref(seg), float(w_max),
@@ -216,6 +229,33 @@ def resample_rejection(w, w_max, seed=0, offset=0, filter_base=0, max_trials=1 <
                                         _stream())
     _lib.check(rc, "resample_rejection")
     return a
+
+
+def resample_partial_rejection(w, v_max, seed=0, offset=0, filter_base=0, max_trials=1 << 20,
+                               v_max_per_filter=None, offsets=None, max_len=None, out=None,
+                               weights_out=None, flags=None, workspace=None):
+    """Partial rejection control: rejection ancestry on min(w, v_max) with
+    bound v_max and the importance weights w_{a_i} / min(w_{a_i}, v_max).
+    Returns (ancestors, weights)."""
+    torch = _torch()
+    _require_cuda(w, v_max_per_filter, flags, weights_out)
+    dt = _dtype_code(w)
+    seg = _segments(w.numel(), offsets, max_len)
+    _per_segment(v_max_per_filter, "float64", seg, "v_max_per_filter")
+    a = _out_like(w.numel(), w.device, out)
+    if weights_out is None:
+        weights_out = torch.empty_like(w)
+    elif weights_out.dtype != w.dtype or weights_out.numel() != w.numel():
+        raise ValueError("weights_out must match the weights' type and size")
+    ws, _ = _workspace(_lib.OP_REJECTION, seg, dt, w.device, workspace)
+    rc = _lib.load().resample_partial_rejection(_ptr(w), dt, ctypes.byref(seg), float(v_max),
+                                                _ptr(v_max_per_filter), int(max_trials),
+                                                _rng(seed, offset, filter_base), _ptr(a),
+                                                _ptr(weights_out), _ptr(ws),
+                                                0 if ws is None else ws.numel(), _ptr(flags),
+                                                _stream())
+    _lib.check(rc, "resample_partial_rejection")
+    return a, weights_out
 
 
 def offspring_to_ancestors(o, offsets=None, max_len=None, out=None, flags=None, workspace=None):

@@ -29,7 +29,8 @@ MAX_BATCH_SEGMENT = 256 * 1024 - 1
 
 EXPORTS = (
     "pfr_workspace_bytes", "pfr_workspace_init", "resample_multinomial", "resample_stratified",
-    "resample_systematic", "resample_metropolis", "resample_rejection", "offspring_to_ancestors",
+    "resample_systematic", "resample_metropolis", "resample_rejection",
+    "resample_partial_rejection", "offspring_to_ancestors",
     "permute_ancestors", "ancestors_to_offspring", "effective_sample_size", "copy_particles",
     "lgssm_workspace_bytes", "lgssm_init", "lgssm_step",
     "pfr_tuning_defaults", "pfr_get_tuning", "pfr_set_tuning", "pfr_load_tuning",
@@ -91,6 +92,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "resample_systematic": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),
         "resample_metropolis": (I, [P, I, SEG, I32, P, Rng, P, P, SZ, P]),
         "resample_rejection": (I, [P, I, SEG, D, P, U32, Rng, P, P, SZ, P, P]),
+        "resample_partial_rejection": (I, [P, I, SEG, D, P, U32, Rng, P, P, P, SZ, P, P]),
         "offspring_to_ancestors": (I, [P, SEG, P, P, SZ, P, P]),
         "permute_ancestors": (I, [P, SEG, I32, P, P, SZ, P, P]),
         "ancestors_to_offspring": (I, [P, SEG, I32, P, P, P]),

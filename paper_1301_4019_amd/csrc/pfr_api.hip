@@ -217,6 +217,29 @@ int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, 
                                         (hipStream_t)stream));
 }
 
+int resample_partial_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                               double v_max, const double* v_max_dev, uint32_t max_trials,
+                               pfr_rng rng, int32_t* ancestors, void* weights_out, void* ws,
+                               size_t ws_bytes, uint32_t* dev_flags, void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (dtype != PFR_F32 && dtype != PFR_F64) return PFR_EINVAL;
+  if (s.n_total > 0 && !weights_out) return PFR_EINVAL;
+  if (s.n_total > 0) {
+    const size_t wb = (size_t)s.n_total * dtype_size(dtype);
+    if (overlaps(weights_out, wb, ancestors, (size_t)s.n_total * 4) ||
+        (w && overlaps(weights_out, wb, w, wb)))
+      return PFR_EINVAL;
+  }
+  rc = resample_rejection(w, dtype, seg, v_max, v_max_dev, max_trials, rng, ancestors, ws,
+                          ws_bytes, dev_flags, stream);
+  if (rc || s.n_total == 0) return rc;
+  return launch_result(launch_prc_weights(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters,
+                                          v_max, v_max_dev, ancestors, weights_out,
+                                          (hipStream_t)stream));
+}
+
 int offspring_to_ancestors(const int32_t* offspring, const pfr_segments* seg, int32_t* ancestors,
                            void* ws, size_t ws_bytes, uint32_t* dev_flags, void* stream) {
   SegInfo s;

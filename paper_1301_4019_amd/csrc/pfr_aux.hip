@@ -457,6 +457,12 @@ __global__ __launch_bounds__(256) void k_resolve(int64_t n_total,
 // needs of d), then every slot resolves as in k_resolve.  Global traffic is
 // the ancestry read and the permutation written.
 constexpr int kPermThreads = 1024;
+// Single vectors up to these lengths are permuted in LDS by one workgroup
+// (one launch instead of two to four); beyond them the multi-workgroup
+// kernels are faster (measured on MI355X: the crossover lies near 2^11
+// particles for a sorted ancestry and 2^12 for an unsorted one).
+constexpr int kPermSingleMax = 4096;
+constexpr int kPermSingleMaxSorted = 2048;
 
 template <int CAP>
 __global__ __launch_bounds__(kPermThreads) void k_permute_staged(
@@ -576,9 +582,9 @@ size_t permute_workspace_bytes(int64_t n_total) {
   return 2 * align256((size_t)n_total * sizeof(int32_t));
 }
 
-// Batches whose segments fit in LDS are permuted there (k_permute_staged, one
-// workgroup per segment); longer segments, and single vectors, go through the
-// global kernels.  max_len: longest segment (0 = unknown).
+// Batches whose segments fit in LDS, and short single vectors, are permuted
+// there (k_permute_staged, one workgroup per segment); longer segments go
+// through the global kernels.  max_len: longest segment (0 = unknown).
 hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offsets,
                           uint32_t n_filters, int64_t max_len, bool sorted, int32_t* c, void* ws,
                           uint32_t* flags, hipStream_t stream) {
@@ -586,6 +592,12 @@ hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offs
   int32_t* e = (int32_t*)((char*)ws + align256((size_t)n_total * sizeof(int32_t)));
   const int grid = grid_for(n_total);
   int64_t min_len = 0;  // shorter segments are done in LDS
+  if (!(offsets && n_filters > 1) && n_total <= (sorted ? kPermSingleMaxSorted : kPermSingleMax)) {
+    // a short single vector: one workgroup, one launch
+    hipLaunchKernelGGL(k_permute_staged<kPermSingleMax>, dim3(1), dim3(kPermThreads), 0, stream,
+                       a, n_total, nullptr, 1u, c, flags);
+    return hipGetLastError();
+  }
   if (offsets && n_filters > 1) {
     hipLaunchKernelGGL(k_permute_staged<16384>, dim3(n_filters), dim3(kPermThreads), 0, stream, a,
                        n_total, offsets, n_filters, c, flags);

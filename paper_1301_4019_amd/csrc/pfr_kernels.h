@@ -125,6 +125,12 @@ hipError_t launch_copy(const int32_t* c, int64_t n_total, const int64_t* offsets
                        uint32_t n_filters, void* x, size_t elem_bytes, int32_t dim, int64_t ps,
                        int64_t cs, uint32_t* flags, hipStream_t stream);
 
+// Importance weights of partial rejection control (after a rejection launch
+// with bound v_max).
+hipError_t launch_prc_weights(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
+                              uint32_t n_filters, double v_max, const double* v_max_dev,
+                              const int32_t* a, void* w_out, hipStream_t stream);
+
 hipError_t launch_lgssm_init(int32_t n_filters, int32_t n, double s0, Key key, uint32_t offset,
                              uint32_t filter_base, float* x, float* w, double* logz,
                              int32_t* B_dev, uint32_t* t_dev, int64_t* offsets,

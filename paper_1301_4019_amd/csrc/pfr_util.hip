@@ -63,19 +63,19 @@ uint32_t slot_count(int64_t n_total, uint32_t n_filters) {
 // slots: a tile finds the range of positions holding its values with two
 // wave-wide 64-ary searches, runs the two phases over that range into an LDS
 // count array and writes its slots once.  An unsorted ancestry goes through
-// counting (LDS atomic adds for short segments; a zero pass then global
-// atomic adds, as in Code 12, for long ones).
+// counting: LDS histograms over windows of values for segments of up to
+// kA2oWinMax particles, a zero pass then atomic additions in global memory,
+// as in Code 12, for longer ones.
 constexpr int kA2oCap = 16384;
 constexpr int kA2oStagedThreads = 1024;
 constexpr int kA2oTile = 4096;
 constexpr int kA2oThreads = 256;
 
-template <bool SORTED>
 __global__ __launch_bounds__(kA2oStagedThreads) void k_a2o_staged(
     const int32_t* __restrict__ a, const int64_t* __restrict__ offsets, uint32_t n_filters,
     int32_t* __restrict__ o, uint32_t* __restrict__ flags) {
   __shared__ int32_t cnt[kA2oCap];
-  __shared__ int32_t as[SORTED ? kA2oCap : 1];
+  __shared__ int32_t as[kA2oCap];
   __shared__ uint32_t s_bad;
   const uint32_t f = blockIdx.x;
   if (f >= n_filters) return;
@@ -87,41 +87,66 @@ __global__ __launch_bounds__(kA2oStagedThreads) void k_a2o_staged(
   if (tid == 0) s_bad = 0;
   bool bad = false;
   for (int j = tid; j < n; j += kA2oStagedThreads) cnt[j] = 0;
-  if (SORTED) {
-    for (int i = tid; i < n; i += kA2oStagedThreads) as[i] = a[base + i];
-    __syncthreads();
-    // phase 1: run ends
-    for (int i = tid; i < n; i += kA2oStagedThreads) {
-      const int v = as[i];
-      if (v < 0 || v >= n) {
-        bad = true;
-        continue;
-      }
-      if (i == n - 1 || as[i + 1] != v) cnt[v] = i + 1;
+  for (int i = tid; i < n; i += kA2oStagedThreads) as[i] = a[base + i];
+  __syncthreads();
+  // phase 1: run ends
+  for (int i = tid; i < n; i += kA2oStagedThreads) {
+    const int v = as[i];
+    if (v < 0 || v >= n) {
+      bad = true;
+      continue;
     }
-    __syncthreads();
-    // phase 2: run starts
-    for (int i = tid; i < n; i += kA2oStagedThreads) {
-      const int v = as[i];
-      if (v < 0 || v >= n) continue;
-      if (i == 0 || as[i - 1] != v) cnt[v] -= i;
-    }
-  } else {
-    __syncthreads();
-    for (int i = tid; i < n; i += kA2oStagedThreads) {
-      const int v = a[base + i];
-      if (v < 0 || v >= n) {
-        bad = true;
-        continue;
-      }
-      atomicAdd(&cnt[v], 1);
-    }
+    if (i == n - 1 || as[i + 1] != v) cnt[v] = i + 1;
+  }
+  __syncthreads();
+  // phase 2: run starts
+  for (int i = tid; i < n; i += kA2oStagedThreads) {
+    const int v = as[i];
+    if (v < 0 || v >= n) continue;
+    if (i == 0 || as[i - 1] != v) cnt[v] -= i;
   }
   __syncthreads();
   for (int j = tid; j < n; j += kA2oStagedThreads) o[base + j] = cnt[j];
   if (ballot(bad) != 0 && lane_id() == 0) atomicOr(&s_bad, 1u);
   __syncthreads();
   if (tid == 0 && s_bad && flags) atomicOr(flags, FLAG_BAD_ANCESTOR);
+}
+
+// Unsorted segments of up to kA2oWinMax particles: the workgroup of slot
+// (f, p) counts values [p W, (p + 1) W) of segment f in an LDS histogram
+// (W = kA2oWin), reading the whole segment; a segment is read
+// ceil(n_f / W) times, which for these lengths costs less than atomics in
+// global memory.
+constexpr int kA2oWin = 32768;
+constexpr int kA2oWinMax = 4 * kA2oWin;
+
+__global__ __launch_bounds__(kA2oStagedThreads) void k_a2o_window(
+    const int32_t* __restrict__ a, int64_t n_total, const int64_t* __restrict__ offsets,
+    uint32_t n_filters, int32_t* __restrict__ o, uint32_t* __restrict__ flags) {
+  __shared__ int32_t cnt[kA2oWin];
+  SlotSeg s;
+  if (!slot_segment<kA2oWin>(offsets, n_filters, n_total, blockIdx.x, s)) return;
+  if (s.n > kA2oWinMax) return;  // global atomics
+  const int tid = (int)threadIdx.x;
+  const int64_t j0 = s.p * kA2oWin;
+  const int win = (int)min((int64_t)kA2oWin, s.n - j0);
+  for (int j = tid; j < win; j += kA2oStagedThreads) cnt[j] = 0;
+  __syncthreads();
+  bool bad = false;
+  const int32_t* __restrict__ as = a + s.base;
+  for (int64_t i = tid; i < s.n; i += kA2oStagedThreads) {
+    const int64_t v = as[i];
+    if (v < 0 || v >= s.n) {
+      bad = true;
+      continue;
+    }
+    const int64_t r = v - j0;
+    if (r >= 0 && r < win) atomicAdd(&cnt[r], 1);
+  }
+  __syncthreads();
+  for (int j = tid; j < win; j += kA2oStagedThreads) o[s.base + j0 + j] = cnt[j];
+  // every window sees every out-of-range value; the first one reports it
+  if (flags && s.p == 0 && ballot(bad) != 0 && lane_id() == 0) atomicOr(flags, FLAG_BAD_ANCESTOR);
 }
 
 // First position p in [0, n) with a[p] >= v (n if none), for a non-decreasing
@@ -186,42 +211,39 @@ __global__ __launch_bounds__(kA2oThreads) void k_a2o_sorted_tiles(
   for (int j = tid; j < tile; j += kA2oThreads) o[s.base + j0 + j] = cnt[j];
 }
 
-__global__ __launch_bounds__(256) void k_a2o_zero(int64_t n_total,
-                                                  const int64_t* __restrict__ offsets,
-                                                  uint32_t n_filters, int64_t min_len,
-                                                  int32_t* __restrict__ o) {
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
-    if (offsets) {
-      const uint32_t f = find_segment(offsets, n_filters, g);
-      if (offsets[f + 1] - offsets[f] < min_len) continue;
-    }
-    o[g] = 0;
-  }
+// Unsorted segments longer than kA2oWinMax: zero pass, then one atomic
+// addition per ancestor, both over tiles of kA2oTile positions per workgroup.
+__global__ __launch_bounds__(kA2oThreads) void k_a2o_zero(int64_t n_total,
+                                                          const int64_t* __restrict__ offsets,
+                                                          uint32_t n_filters, int64_t min_len,
+                                                          int32_t* __restrict__ o) {
+  SlotSeg s;
+  if (!slot_segment<kA2oTile>(offsets, n_filters, n_total, blockIdx.x, s)) return;
+  if (s.n < min_len) return;
+  const int64_t j0 = s.p * kA2oTile;
+  const int tile = (int)min((int64_t)kA2oTile, s.n - j0);
+  for (int j = (int)threadIdx.x; j < tile; j += kA2oThreads) o[s.base + j0 + j] = 0;
 }
 
-__global__ __launch_bounds__(256) void k_a2o_atomic(const int32_t* __restrict__ a,
-                                                    int64_t n_total,
-                                                    const int64_t* __restrict__ offsets,
-                                                    uint32_t n_filters, int64_t min_len,
-                                                    int32_t* __restrict__ o,
-                                                    uint32_t* __restrict__ flags) {
+__global__ __launch_bounds__(kA2oThreads) void k_a2o_atomic(const int32_t* __restrict__ a,
+                                                            int64_t n_total,
+                                                            const int64_t* __restrict__ offsets,
+                                                            uint32_t n_filters, int64_t min_len,
+                                                            int32_t* __restrict__ o,
+                                                            uint32_t* __restrict__ flags) {
+  SlotSeg s;
+  if (!slot_segment<kA2oTile>(offsets, n_filters, n_total, blockIdx.x, s)) return;
+  if (s.n < min_len) return;
+  const int64_t i0 = s.p * kA2oTile;
+  const int tile = (int)min((int64_t)kA2oTile, s.n - i0);
   bool bad = false;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
-    int64_t base = 0, n = n_total;
-    if (offsets) {
-      const uint32_t f = find_segment(offsets, n_filters, g);
-      base = offsets[f];
-      n = offsets[f + 1] - base;
-      if (n < min_len) continue;
-    }
-    const int64_t v = a[g];
-    if (v < 0 || v >= n) {
+  for (int i = (int)threadIdx.x; i < tile; i += kA2oThreads) {
+    const int64_t v = a[s.base + i0 + i];
+    if (v < 0 || v >= s.n) {
       bad = true;
       continue;
     }
-    atomicAdd(&o[base + v], 1);
+    atomicAdd(&o[s.base + v], 1);
   }
   if (flags && ballot(bad) != 0 && lane_id() == 0) atomicOr(flags, FLAG_BAD_ANCESTOR);
 }
@@ -373,49 +395,88 @@ __global__ __launch_bounds__(256) void k_ess_finish(int64_t n_total,
 // is never written); a particle whose source is out of range or is itself
 // overwritten (c_{c_i} != c_i) is left alone and flagged, which keeps the
 // step race-free for any input.  Element (g, k) of the state (particle g,
-// component k) sits at x[g * ps + k * cs]; consecutive threads take
-// consecutive components when cs == 1 (rows), consecutive particles
-// otherwise (columns), so both layouts are coalesced.
+// component k) sits at x[g * ps + k * cs].  A workgroup takes a tile of
+// kCopyTile particles of one segment: with contiguous rows (cs == 1)
+// consecutive threads take consecutive elements of the tile's rows; with
+// contiguous columns a thread takes one particle and walks its components,
+// consecutive threads taking consecutive particles.  Either way the stores
+// are coalesced and the ancestry is read once per particle.
+constexpr int kCopyTile = 1024;
+
+template <typename E>
+__device__ __forceinline__ bool copy_source(const int32_t* __restrict__ cs_, int64_t i, int64_t n,
+                                            int64_t& ci, bool& bad) {
+  ci = cs_[i];
+  if (ci == i) return false;
+  if (ci < 0 || ci >= n || cs_[ci] != ci) {
+    bad = true;
+    return false;
+  }
+  return true;
+}
+
 template <typename E>
 __global__ __launch_bounds__(256) void k_copy(const int32_t* __restrict__ c, int64_t n_total,
                                               const int64_t* __restrict__ offsets,
                                               uint32_t n_filters, E* __restrict__ x, int32_t dim,
                                               int64_t ps, int64_t cs, bool rows,
                                               uint32_t* __restrict__ flags) {
+  SlotSeg s;
+  if (!slot_segment<kCopyTile>(offsets, n_filters, n_total, blockIdx.x, s)) return;
+  const int64_t p0 = s.p * kCopyTile;
+  const int tile = (int)min((int64_t)kCopyTile, s.n - p0);
+  const int32_t* __restrict__ cseg = c + s.base;
+  E* __restrict__ xs = x + s.base * ps;
   bool bad = false;
-  const int64_t total = n_total * dim;
-  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < total; t += stride) {
-    int64_t g, k;
-    if (rows) {
-      g = t / dim;
-      k = t - g * dim;
-    } else {
-      k = t / n_total;
-      g = t - k * n_total;
+  if (rows) {
+    const int64_t total = (int64_t)tile * dim;
+    for (int64_t t = threadIdx.x; t < total; t += 256) {
+      const int64_t il = t / dim;
+      const int64_t k = t - il * dim;
+      const int64_t i = p0 + il;
+      int64_t ci;
+      bool b = false;
+      if (copy_source<E>(cseg, i, s.n, ci, b)) xs[i * ps + k] = xs[ci * ps + k];
+      bad |= b && k == 0;
     }
-    int64_t base = 0, n = n_total;
-    if (offsets) {
-      const uint32_t f = find_segment(offsets, n_filters, g);
-      base = offsets[f];
-      n = offsets[f + 1] - base;
+  } else {
+    for (int il = (int)threadIdx.x; il < tile; il += 256) {
+      const int64_t i = p0 + il;
+      int64_t ci;
+      if (!copy_source<E>(cseg, i, s.n, ci, bad)) continue;
+      for (int k = 0; k < dim; ++k) xs[i * ps + k * cs] = xs[ci * ps + k * cs];
     }
-    const int64_t i = g - base;
-    const int64_t ci = c[g];
-    if (ci == i) continue;
-    if (ci < 0 || ci >= n || c[base + ci] != ci) {
-      bad |= (k == 0);
-      continue;
-    }
-    x[g * ps + k * cs] = x[(base + ci) * ps + k * cs];
   }
   if (flags && ballot(bad) != 0 && lane_id() == 0) atomicOr(flags, FLAG_BAD_ANCESTOR);
 }
 
-int grid_for_total(int64_t total) {
-  int64_t g = (total + 255) / 256;
-  if (g > 8192) g = 8192;
-  return g < 1 ? 1 : (int)g;
+// ================================================================ PRC weights
+// Importance weight of each particle after partial rejection control:
+// w_{a_i} / min(w_{a_i}, v_max), i.e. w_{a_i} / v_max above the bound, 1 at
+// or below it, and 0 where the ancestor's weight is not positive (only a
+// lane that hit the trial cap keeps such an ancestor).  The quotient is a
+// binary64 division rounded to the weight type.
+template <typename T>
+__global__ __launch_bounds__(256) void k_prc_weights(const T* __restrict__ w, int64_t n_total,
+                                                     const int64_t* __restrict__ offsets,
+                                                     uint32_t n_filters, double v_max,
+                                                     const double* __restrict__ v_max_dev,
+                                                     const int32_t* __restrict__ a,
+                                                     T* __restrict__ w_out) {
+  SlotSeg s;
+  if (!slot_segment<kCopyTile>(offsets, n_filters, n_total, blockIdx.x, s)) return;
+  const double vm = v_max_dev ? v_max_dev[s.f] : v_max;
+  const int64_t p0 = s.p * kCopyTile;
+  const int tile = (int)min((int64_t)kCopyTile, s.n - p0);
+  for (int il = (int)threadIdx.x; il < tile; il += 256) {
+    const int64_t g = s.base + p0 + il;
+    const int64_t ai = a[g];
+    const double wa = (ai >= 0 && ai < s.n) ? (double)w[s.base + ai] : 0.0;
+    double r = 0.0;
+    if (wa > vm) r = wa / vm;
+    else if (wa > 0.0) r = 1.0;
+    w_out[g] = (T)r;
+  }
 }
 
 }  // namespace
@@ -424,32 +485,43 @@ int grid_for_total(int64_t total) {
 hipError_t launch_ancestors_to_offspring(const int32_t* a, int64_t n_total, const int64_t* offsets,
                                          uint32_t n_filters, int64_t max_len, bool sorted,
                                          int32_t* o, uint32_t* flags, hipStream_t stream) {
-  int64_t min_len = 0;  // shorter segments are converted in LDS
-  if (offsets && n_filters > 1) {
-    if (sorted)
-      hipLaunchKernelGGL(k_a2o_staged<true>, dim3(n_filters), dim3(kA2oStagedThreads), 0, stream,
-                         a, offsets, n_filters, o, flags);
-    else
-      hipLaunchKernelGGL(k_a2o_staged<false>, dim3(n_filters), dim3(kA2oStagedThreads), 0,
-                         stream, a, offsets, n_filters, o, flags);
-    const hipError_t e = hipGetLastError();
-    if (e != hipSuccess) return e;
-    if (max_len > 0 && max_len <= kA2oCap) return hipSuccess;
-    min_len = kA2oCap + 1;
-  } else {
+  if (!(offsets && n_filters > 1)) {
     offsets = nullptr;  // one segment covers [0, n_total)
+    n_filters = 1;
+    max_len = n_total;
   }
   if (sorted) {
-    const uint32_t slots = slot_count<kA2oTile>(n_total, offsets ? n_filters : 1u);
+    int64_t min_len = 0;  // shorter segments are converted in LDS
+    if (offsets) {
+      hipLaunchKernelGGL(k_a2o_staged, dim3(n_filters), dim3(kA2oStagedThreads), 0, stream, a,
+                         offsets, n_filters, o, flags);
+      const hipError_t e = hipGetLastError();
+      if (e != hipSuccess) return e;
+      if (max_len > 0 && max_len <= kA2oCap) return hipSuccess;
+      min_len = kA2oCap + 1;
+    }
+    const uint32_t slots = slot_count<kA2oTile>(n_total, n_filters);
     hipLaunchKernelGGL(k_a2o_sorted_tiles, dim3(slots), dim3(kA2oThreads), 0, stream, a, n_total,
-                       offsets, offsets ? n_filters : 1u, min_len, o, flags);
-  } else {
-    const int grid = grid_for_total(n_total);
-    hipLaunchKernelGGL(k_a2o_zero, dim3(grid), dim3(256), 0, stream, n_total, offsets,
-                       offsets ? n_filters : 1u, min_len, o);
-    hipLaunchKernelGGL(k_a2o_atomic, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
-                       offsets ? n_filters : 1u, min_len, o, flags);
+                       offsets, n_filters, min_len, o, flags);
+    return hipGetLastError();
   }
+  // a batch may hold both kinds of segment; each kernel skips the other kind
+  const bool any_short = offsets ? true : n_total <= kA2oWinMax;
+  const bool any_long = offsets ? (max_len <= 0 || max_len > kA2oWinMax) : n_total > kA2oWinMax;
+  if (any_short) {
+    const uint32_t slots = slot_count<kA2oWin>(n_total, n_filters);
+    hipLaunchKernelGGL(k_a2o_window, dim3(slots), dim3(kA2oStagedThreads), 0, stream, a, n_total,
+                       offsets, n_filters, o, flags);
+    const hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
+  }
+  if (!any_long) return hipSuccess;
+  const int64_t min_len = kA2oWinMax + 1;
+  const uint32_t slots = slot_count<kA2oTile>(n_total, n_filters);
+  hipLaunchKernelGGL(k_a2o_zero, dim3(slots), dim3(kA2oThreads), 0, stream, n_total, offsets,
+                     n_filters, min_len, o);
+  hipLaunchKernelGGL(k_a2o_atomic, dim3(slots), dim3(kA2oThreads), 0, stream, a, n_total,
+                     offsets, n_filters, min_len, o, flags);
   return hipGetLastError();
 }
 
@@ -483,7 +555,7 @@ hipError_t launch_copy(const int32_t* c, int64_t n_total, const int64_t* offsets
                        int64_t cs, uint32_t* flags, hipStream_t stream) {
   if (n_filters == 1) offsets = nullptr;
   const bool rows = (cs == 1);
-  const int grid = grid_for_total(n_total * dim);
+  const uint32_t grid = slot_count<kCopyTile>(n_total, n_filters);
   switch (elem_bytes) {
     case 1:
       hipLaunchKernelGGL(k_copy<uint8_t>, dim3(grid), dim3(256), 0, stream, c, n_total, offsets,
@@ -508,6 +580,20 @@ hipError_t launch_copy(const int32_t* c, int64_t n_total, const int64_t* offsets
     default:
       return hipErrorInvalidValue;
   }
+  return hipGetLastError();
+}
+
+hipError_t launch_prc_weights(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
+                              uint32_t n_filters, double v_max, const double* v_max_dev,
+                              const int32_t* a, void* w_out, hipStream_t stream) {
+  if (n_filters == 1) offsets = nullptr;
+  const uint32_t grid = slot_count<kCopyTile>(n_total, n_filters);
+  if (f64)
+    hipLaunchKernelGGL(k_prc_weights<double>, dim3(grid), dim3(256), 0, stream, (const double*)w,
+                       n_total, offsets, n_filters, v_max, v_max_dev, a, (double*)w_out);
+  else
+    hipLaunchKernelGGL(k_prc_weights<float>, dim3(grid), dim3(256), 0, stream, (const float*)w,
+                       n_total, offsets, n_filters, v_max, v_max_dev, a, (float*)w_out);
   return hipGetLastError();
 }
 

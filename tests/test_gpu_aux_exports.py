@@ -97,7 +97,7 @@ def test_a2o_out_of_range_ancestors(hint):
 @pytest.mark.parametrize("with_max_len", [True, False])
 def test_a2o_ragged_batch(hint, with_max_len):
     rng = np.random.default_rng(7)
-    sizes = np.array([0, 1, 5, 300, 4096, 16384, 16385, 0, 20000, 777, 70000, 2])
+    sizes = np.array([0, 1, 5, 300, 4096, 16384, 16385, 0, 20000, 777, 70000, 2, 140001])
     off = ragged_offsets(sizes)
     parts = []
     for f, n in enumerate(sizes):

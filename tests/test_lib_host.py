@@ -97,6 +97,14 @@ def test_auxiliary_arguments_rejected_on_host():
     # the state overlaps the permutation
     assert lib.copy_particles(fake, ctypes.byref(seg(10)), fake, 4, 1, I64(1), I64(1), None,
                               None) == _lib.PFR_EINVAL
+    # partial rejection control: no weight output, weight output aliasing the ancestry
+    rng = _lib.Rng(0, 0, 0)
+    assert lib.resample_partial_rejection(fake, 0, ctypes.byref(seg(10)), 1.0, None, 16, rng, out,
+                                          None, None, 0, None, None) == _lib.PFR_EINVAL
+    assert lib.resample_partial_rejection(fake, 0, ctypes.byref(seg(10)), 1.0, None, 16, rng, out,
+                                          out, None, 0, None, None) == _lib.PFR_EINVAL
+    assert lib.resample_partial_rejection(fake, 0, ctypes.byref(seg(10)), 0.0, None, 16, rng, out,
+                                          ws, None, 0, None, None) == _lib.PFR_EINVAL
     # empty input is a no-op
     assert lib.copy_particles(None, ctypes.byref(seg(0)), None, 4, 3, I64(3), I64(1), None,
                               None) == _lib.PFR_OK
