@@ -459,10 +459,10 @@ __global__ __launch_bounds__(256) void k_resolve(int64_t n_total,
 constexpr int kPermThreads = 1024;
 // Single vectors up to these lengths are permuted in LDS by one workgroup
 // (one launch instead of two to four); beyond them the multi-workgroup
-// kernels are faster (measured on MI355X: the crossover lies near 2^11
+// kernels are faster (measured on MI355X: the crossover lies near 2^10
 // particles for a sorted ancestry and 2^12 for an unsorted one).
 constexpr int kPermSingleMax = 4096;
-constexpr int kPermSingleMaxSorted = 2048;
+constexpr int kPermSingleMaxSorted = 1024;
 
 template <int CAP>
 __global__ __launch_bounds__(kPermThreads) void k_permute_staged(
