@@ -27,7 +27,7 @@ FLAG_BAD_COUNTS = 4
 FLAG_BAD_WEIGHTS = 8
 FLAG_BAD_ANCESTOR = 16
 
-DOM_STRATA, DOM_EXP, DOM_TRIAL, DOM_NOISE, DOM_INIT = 0, 1, 2, 3, 4
+DOM_STRATA, DOM_EXP, DOM_TRIAL, DOM_NOISE, DOM_INIT, DOM_UNIFORM = 0, 1, 2, 3, 4, 5
 
 
 def build(force: bool = True) -> str:
@@ -71,6 +71,7 @@ def _load():
         "orc_stratum_offsets": (None, [i64, u64, u32, u32, P]),
         "orc_resample_multinomial": (ctypes.c_int, [P, i64, u64, u32, u32, P, P, P, P]),
         "orc_multinomial_points": (ctypes.c_int, [P, i64, P, P, P]),
+        "orc_resample_multinomial_iid": (ctypes.c_int, [P, i64, u64, u32, u32, P, P, P, P]),
         "orc_offspring_to_ancestors": (ctypes.c_int, [P, i64, P, P]),
         "orc_ancestors_to_offspring": (ctypes.c_int, [P, i64, P, P]),
         "orc_permute": (ctypes.c_int, [P, i64, P, P, P]),
@@ -219,6 +220,19 @@ def partial_rejection(w, v_max, seed=0, filt=0, offset=0, max_trials=1 << 20):
                                                   int(seed) & (2**64 - 1), filt, offset, _ptr(a),
                                                   _ptr(wo), _ptr(fl)), "partial_rejection")
     return a, wo, int(fl[0])
+
+
+def multinomial_iid(w, seed=0, filt=0, offset=0, return_rp=False):
+    """Code 5 with one independent uniform per particle (unsorted output)."""
+    w = _w(w)
+    a = np.empty(w.size, dtype=np.int32)
+    r = np.empty(w.size, dtype=np.float64)
+    p = np.empty(w.size, dtype=np.float64)
+    fl = np.zeros(1, dtype=np.uint32)
+    _check(_load().orc_resample_multinomial_iid(_ptr(w), w.size, int(seed) & (2**64 - 1), filt,
+                                                offset, _ptr(a), _ptr(r), _ptr(p), _ptr(fl)),
+           "multinomial_iid")
+    return (a, int(fl[0]), r, p) if return_rp else (a, int(fl[0]))
 
 
 def multinomial_points(w, p):

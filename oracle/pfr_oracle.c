@@ -459,6 +459,49 @@ int orc_resample_multinomial(const double* w, int64_t n, uint64_t seed, uint32_t
 }
 
 /* ------------------------------------------------------------------------ */
+/* Code 5 with independent uniforms: each particle draws u on [0, 1) and    */
+/* takes the upper bound of n u among the scaled prefix r.                   */
+/* ------------------------------------------------------------------------ */
+int orc_resample_multinomial_iid(const double* w, int64_t n, uint64_t seed, uint32_t filter,
+                                 uint32_t offset, int32_t* a, double* r_out, double* p_out,
+                                 uint32_t* flags)
+{
+    q128 *W, *p;
+    int64_t i;
+    uint32_t fl;
+    if (n < 0 || (n > 0 && (!w || !a))) return -1;
+    if (n == 0) return 0;
+    W = (q128*)malloc(sizeof(q128) * (size_t)n);
+    p = (q128*)malloc(sizeof(q128) * (size_t)n);
+    if (!W || !p) { free(W); free(p); return -1; }
+    fl = inclusive_prefix_sum(w, n, W);
+    if (!fl && !(W[n - 1] > 0)) fl |= ORC_FLAG_ZERO_TOTAL;
+    if (fl) {
+        identity(n, a);
+        if (r_out) for (i = 0; i < n; ++i) r_out[i] = NAN;
+        if (p_out) for (i = 0; i < n; ++i) p_out[i] = NAN;
+    } else {
+        for (i = 0; i < n; ++i) {
+            uint32_t x[4];
+            uint64_t m;
+            double u, pi;
+            draw(seed, (uint32_t)i, ORC_DOM_UNIFORM, 0, filter, offset, x);
+            m = ((uint64_t)(x[0] >> 11) << 32) | (uint64_t)x[1]; /* 53 random bits */
+            u = ldexp((double)m, -53);                            /* exact */
+            pi = (double)n * u;                                   /* one rounding */
+            p[i] = (q128)pi;
+            if (p_out) p_out[i] = pi;
+        }
+        multinomial_core(W, n, p, a);
+        if (r_out) for (i = 0; i < n; ++i) r_out[i] = (double)scaled(W[i], W[n - 1], n);
+    }
+    if (flags) *flags |= fl;
+    free(W);
+    free(p);
+    return 0;
+}
+
+/* ------------------------------------------------------------------------ */
 /* Code 11 from offspring counts: O = Inclusive-Prefix-Sum(o), then          */
 /* a[O_{i-1} .. O_i) = i.  Readings for invalid input: a negative count is   */
 /* used as 0; positions at or beyond n are dropped; if the counts sum to     */

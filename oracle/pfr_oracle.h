@@ -38,6 +38,7 @@ extern "C" {
 #define ORC_DOM_TRIAL  2u /* Metropolis steps, rejection trials */
 #define ORC_DOM_NOISE  3u /* state-space model propagation     */
 #define ORC_DOM_INIT   4u /* state-space model initial state   */
+#define ORC_DOM_UNIFORM 5u /* independent uniforms (Code 5)     */
 
 /* Philox4x32 with 10 rounds (Salmon et al., SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
@@ -91,6 +92,14 @@ void orc_stratum_offsets(int64_t n, uint64_t seed, uint32_t filter, uint32_t off
 int orc_resample_multinomial(const double* w, int64_t n, uint64_t seed, uint32_t filter,
                              uint32_t offset, int32_t* a, double* r_out, double* p_out,
                              uint32_t* flags);
+/* Code 5 as printed: particle i draws its own uniform and searches the
+ * prefix.  u_i = m 2^-53 with m = (word 0 >> 11) 2^32 + word 1 of Philox call
+ * (i, UNIFORM<<28, filter, offset), p_i = n u_i rounded to binary64, and
+ * a[i] = #{k < n-1 : r_k <= p_i}.  The output is not sorted.  p_out (may be
+ * NULL) gets p. */
+int orc_resample_multinomial_iid(const double* w, int64_t n, uint64_t seed, uint32_t filter,
+                                 uint32_t offset, int32_t* a, double* r_out, double* p_out,
+                                 uint32_t* flags);
 /* The same search with caller-given sorted points p[0..n) in [0,n]. */
 int orc_multinomial_points(const double* w, int64_t n, const double* p, int32_t* a,
                            uint32_t* flags);
