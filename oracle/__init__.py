@@ -57,6 +57,8 @@ def _load():
     P = ctypes.c_void_p
     sig = {
         "orc_philox4x32_10": (None, [P, P, P]),
+        "orc_philox4x32_r": (None, [P, P, ctypes.c_int, P]),
+        "orc_set_philox_rounds": (ctypes.c_int, [ctypes.c_int]),
         "orc_u_accept": (dbl, [u32]),
         "orc_index": (i64, [u32, u32, i64]),
         "orc_accept": (ctypes.c_int, [dbl, dbl, dbl]),
@@ -115,12 +117,44 @@ def philox4x32_10(ctr, key):
     return out
 
 
+def philox4x32_r(ctr, key, rounds):
+    """One Philox4x32 block with the given round count."""
+    c = np.ascontiguousarray(ctr, dtype=np.uint32)
+    k = np.ascontiguousarray(key, dtype=np.uint32)
+    out = np.zeros(4, dtype=np.uint32)
+    _load().orc_philox4x32_r(_ptr(c), _ptr(k), int(rounds), _ptr(out))
+    return out
+
+
+_ROUNDS = 10  # round count of draw(), kept equal to the C side's
+
+
+class philox_rounds:
+    """Context manager: every draw of the oracle uses this many Philox rounds
+    (the round-count study), 10 again on exit."""
+
+    def __init__(self, rounds):
+        self.rounds = int(rounds)
+
+    def __enter__(self):
+        global _ROUNDS
+        _check(_load().orc_set_philox_rounds(self.rounds), "philox_rounds")
+        _ROUNDS = self.rounds
+        return self
+
+    def __exit__(self, *exc):
+        global _ROUNDS
+        _load().orc_set_philox_rounds(10)
+        _ROUNDS = 10
+        return False
+
+
 def draw(seed, index, domain, step, filt=0, offset=0):
     """The canonical Philox call for (index, domain, step, filter, offset)."""
     ctr = [index & 0xFFFFFFFF, ((domain << 28) | (step & 0x0FFFFFFF)) & 0xFFFFFFFF,
            filt & 0xFFFFFFFF, offset & 0xFFFFFFFF]
     key = [seed & 0xFFFFFFFF, (seed >> 32) & 0xFFFFFFFF]
-    return philox4x32_10(ctr, key)
+    return philox4x32_r(ctr, key, _ROUNDS)
 
 
 def u_accept(x):

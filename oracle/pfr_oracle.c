@@ -31,14 +31,14 @@ typedef __float128 q128;
 /* halves, and mixes the high halves with the other two counter words and the */
 /* round key; the key is bumped by two Weyl constants between rounds.         */
 /* ------------------------------------------------------------------------ */
-void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+void orc_philox4x32_r(const uint32_t ctr[4], const uint32_t key[2], int rounds, uint32_t out[4])
 {
     const uint32_t M0 = 0xD2511F53u, M1 = 0xCD9E8D57u;
     const uint32_t W0 = 0x9E3779B9u, W1 = 0xBB67AE85u;
     uint32_t x0 = ctr[0], x1 = ctr[1], x2 = ctr[2], x3 = ctr[3];
     uint32_t k0 = key[0], k1 = key[1];
     int round;
-    for (round = 0; round < 10; ++round) {
+    for (round = 0; round < rounds; ++round) {
         uint64_t p0, p1;
         uint32_t y0, y1, y2, y3;
         if (round > 0) {
@@ -56,6 +56,22 @@ void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t ou
     out[0] = x0; out[1] = x1; out[2] = x2; out[3] = x3;
 }
 
+void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4])
+{
+    orc_philox4x32_r(ctr, key, 10, out);
+}
+
+/* Round count of every draw below: 10 (Philox4x32-10) unless a round-count
+ * study sets another. */
+static int g_rounds = 10;
+
+int orc_set_philox_rounds(int rounds)
+{
+    if (rounds < 1 || rounds > 16) return -1;
+    g_rounds = rounds;
+    return 0;
+}
+
 static void draw(uint64_t seed, uint32_t index, uint32_t domain, uint32_t step,
                  uint32_t filter, uint32_t offset, uint32_t out[4])
 {
@@ -66,7 +82,7 @@ static void draw(uint64_t seed, uint32_t index, uint32_t domain, uint32_t step,
     ctr[3] = offset;
     key[0] = (uint32_t)seed;
     key[1] = (uint32_t)(seed >> 32);
-    orc_philox4x32_10(ctr, key, out);
+    orc_philox4x32_r(ctr, key, g_rounds, out);
 }
 
 /* u in (0, 1]: the paper draws u ~ U[0,1] in Codes 2 and 3; the 32-bit

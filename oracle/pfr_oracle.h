@@ -42,6 +42,11 @@ extern "C" {
 
 /* Philox4x32 with 10 rounds (Salmon et al., SC'11). */
 void orc_philox4x32_10(const uint32_t ctr[4], const uint32_t key[2], uint32_t out[4]);
+/* Philox4x32 with `rounds` rounds (1..16); 10 gives the function above. */
+void orc_philox4x32_r(const uint32_t ctr[4], const uint32_t key[2], int rounds, uint32_t out[4]);
+/* Round count used by every draw of the oracle (default 10); -1 if out of
+ * range.  For the round-count study only. */
+int orc_set_philox_rounds(int rounds);
 
 /* Canonical draws shared by definition with the HIP library.                  */
 /* u in (0,1]: ((x + 1) * 2^-32); index in [0,n): floor(((x1<<32)|x0) * n / 2^64) */

@@ -3,6 +3,7 @@ import os
 from fractions import Fraction
 
 import numpy as np
+import pytest
 
 import oracle
 from philox_np import philox4x32
@@ -91,3 +92,35 @@ def test_accept_is_exact():
         assert oracle.accept(u, wk, wj) == (Fraction(u) * Fraction(wk) <= Fraction(wj))
     assert oracle.accept(1.0, 0.0, 0.0)
     assert not oracle.accept(2.0**-32, 1.0, 0.0)
+
+
+def test_round_count_variants_match_the_numpy_implementation():
+    """The round-count study's generator: the oracle's r-round Philox equals
+    the independent numpy one for several round counts, and r = 10 is the
+    pinned Philox4x32-10."""
+    import philox_np
+    g = np.random.default_rng(11)
+    ctr = g.integers(0, 2**32, size=(64, 4), dtype=np.uint64).astype(np.uint32)
+    key = g.integers(0, 2**32, size=(64, 2), dtype=np.uint64).astype(np.uint32)
+    for rounds in (1, 7, 10, 12):
+        ref = philox_np.philox4x32(ctr, key, rounds=rounds)
+        got = np.array([oracle.philox4x32_r(c, k, rounds) for c, k in zip(ctr, key)])
+        assert np.array_equal(got, ref), rounds
+    assert np.array_equal(oracle.philox4x32_r(ctr[0], key[0], 10),
+                          oracle.philox4x32_10(ctr[0], key[0]))
+
+
+def test_round_count_setting_is_scoped():
+    w = np.random.default_rng(1).random(50)
+    a10 = oracle.metropolis(w, 8, seed=3)
+    with oracle.philox_rounds(7):
+        a7 = oracle.metropolis(w, 8, seed=3)
+        x7 = oracle.draw(3, 5, 2, 0)
+    assert not np.array_equal(a7, a10)
+    assert np.array_equal(oracle.metropolis(w, 8, seed=3), a10)
+    import philox_np
+    ref = philox_np.philox4x32(np.array([[5, 2 << 28, 0, 0]]), np.array([[3, 0]]), rounds=7)[0]
+    assert np.array_equal(x7, ref)
+    with pytest.raises(ValueError):
+        with oracle.philox_rounds(0):
+            pass
