@@ -260,6 +260,10 @@ def decision_workload(args):
     Metropolis trade-off (section 3.3): y = 4, B = ceil(B* / C) for C = 1, 2,
     4, 8, with multinomial as the unbiased reference: ||Bias||^2 / MSE and
     MSE / N over --replicates Philox seeds, and the time per resample.
+
+    Multinomial forms: Code 5 as printed (one independent uniform and one
+    search per particle, unsorted output) against the sorted-uniform merge,
+    y = 2, device time with and without the permutation.
     """
     import torch
     import paper_1301_4019_amd as pfr
@@ -290,8 +294,24 @@ def decision_workload(args):
             pfr.resample_rejection(w, 1.0, seed=1, out=out, flags=flags)
         else:
             getattr(pfr, "resample_" + scheme)(w, seed=1, out=out, flags=flags)
-        pfr.permute_ancestors(out, sorted_hint=scheme not in ("metropolis", "rejection"),
+        pfr.permute_ancestors(out, sorted_hint=scheme not in ("metropolis", "rejection",
+                                                               "multinomial_iid"),
                               out=perm, flags=flags)
+
+    def device_us(fn):
+        fn()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                fn()
+        g.replay()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+        e1.synchronize()
+        return 1e3 * e0.elapsed_time(e1) / reps
 
     cells = []
     t_start = time.perf_counter()
@@ -368,6 +388,25 @@ def decision_workload(args):
                           "bias2_over_mse": bias2 / mse, "mse_over_n": mse / n,
                           "resample_us": 1e3 * t_ms / K})
         log(f"trade-off n = 2^{lg} done ({time.perf_counter() - t_start:.0f} s)")
+    # the two multinomial forms: Code 5 as printed (independent uniforms, a
+    # search per particle, unsorted output) against the sorted-uniform merge
+    forms = []
+    for lg in args.forms_log2n:
+        n = 1 << lg
+        if n > nmax:
+            a = torch.empty(n, dtype=torch.int32, device=dev)
+            c = torch.empty(n, dtype=torch.int32, device=dev)
+            nmax = n
+        w = torch.from_numpy(inputs.weights(n, 2.0, seed=0)).to(dev)
+        out, perm = a[:n], c[:n]
+        row = {"log2n": lg}
+        for scheme in ("multinomial", "multinomial_iid"):
+            fn = getattr(pfr, "resample_" + scheme)
+            row[scheme + "_us"] = device_us(lambda: fn(w, seed=1, out=out, flags=flags))
+            row[scheme + "_with_permute_us"] = device_us(lambda: call(scheme, w, n, 0))
+        forms.append(row)
+        log(f"multinomial forms n = 2^{lg}: sorted {row['multinomial_us']:.1f} us, "
+            f"independent {row['multinomial_iid_us']:.1f} us")
     if int(flags.cpu()[0]) != 0:
         raise RuntimeError(f"data flags raised: {int(flags.cpu()[0])}")
 
@@ -390,7 +429,7 @@ def decision_workload(args):
                                  "legend": "M multinomial, S stratified, Y systematic, "
                                            "P Metropolis, R rejection; columns y = 0..4"},
                       "matrix": grid, "matrix_eager": grid_eager, "cells": cells,
-                      "tradeoff": trade}), flush=True)
+                      "tradeoff": trade, "multinomial_forms": forms}), flush=True)
 
 
 def aux_workload(args):
@@ -471,6 +510,99 @@ def aux_workload(args):
                       "rows": rows}), flush=True)
 
 
+def philox_workload(args):
+    """Philox round-count study: the product build (Philox4x32-10) against the
+    study build with 7 rounds (libpfresample_philox7.so), same kernels
+    otherwise.  Speed: device time of each resampler at n = 2^20 for
+    y = 0, 2, 4 (captured graph, mean of --decision-reps calls).  Quality: the
+    bias share ||Bias||^2 / MSE and MSE / n at n = 2^16, y = 3 over
+    --replicates Philox seeds (about 1 / (K + 1) when unbiased)."""
+    import torch
+    import paper_1301_4019_amd as pfr
+    from paper_1301_4019_amd import inputs, build as pbuild
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    reps = args.decision_reps
+    K = args.replicates
+    n = 1 << 20
+    ws = {y: torch.from_numpy(inputs.weights(n, y, seed=100 + int(y))).to(dev) for y in (0.0, 2.0, 4.0)}
+    out = torch.empty(n, dtype=torch.int32, device=dev)
+
+    def resample(scheme, w, y, seed=1, a=out):
+        if scheme == "metropolis":
+            pfr.resample_metropolis(w, b_star(y), seed=seed, out=a)
+        elif scheme == "rejection":
+            pfr.resample_rejection(w, 1.0, seed=seed, out=a, flags=flags)
+        else:
+            getattr(pfr, "resample_" + scheme)(w, seed=seed, out=a, flags=flags)
+
+    def device_us(fn):
+        fn()
+        g = torch.cuda.CUDAGraph()
+        with torch.cuda.graph(g):
+            for _ in range(reps):
+                fn()
+        g.replay()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        g.replay()
+        e1.record(stream)
+        e1.synchronize()
+        return 1e3 * e0.elapsed_time(e1) / reps
+
+    def measure(rounds):
+        speed = []
+        for y, w in ws.items():
+            for scheme in SCHEMES:
+                speed.append({"rounds": rounds, "y": y, "scheme": scheme,
+                              "us": device_us(lambda: resample(scheme, w, y))})
+        nq = 1 << 16
+        wq = torch.from_numpy(inputs.weights(nq, 3.0, seed=0)).to(dev)
+        wd = wq.double()
+        e = nq * wd / wd.sum()
+        aq = torch.empty(nq, dtype=torch.int32, device=dev)
+        quality = []
+        for scheme in ("multinomial", "systematic", "metropolis", "rejection"):
+            S1 = torch.zeros(nq, dtype=torch.float64, device=dev)
+            S2 = torch.zeros(nq, dtype=torch.float64, device=dev)
+            for k in range(K):
+                resample(scheme, wq, 3.0, seed=1 + k, a=aq)
+                o = torch.bincount(aq, minlength=nq).double()
+                S1 += o
+                S2 += o * o
+            mean = S1 / K
+            bias2 = float(((mean - e) ** 2).sum())
+            mse = float((S2 / K - 2.0 * e * mean + e * e).sum())
+            quality.append({"rounds": rounds, "scheme": scheme, "bias2_over_mse": bias2 / mse,
+                            "mse_over_n": mse / nq})
+        return speed, quality
+
+    assert pfr._lib.load().pfr_philox_rounds() == 10
+    sp10, q10 = measure(10)
+    log("10 rounds measured")
+    with pfr._lib.use_library(pbuild.variant_path(7)) as lib7:
+        assert lib7.pfr_philox_rounds() == 7
+        sp7, q7 = measure(7)
+    log("7 rounds measured")
+    if int(flags.cpu()[0]) != 0:
+        raise RuntimeError(f"data flags raised: {int(flags.cpu()[0])}")
+    for a, b in zip(sp10, sp7):
+        log(f"  y={a['y']:.0f} {a['scheme']:12s} 10 rounds {a['us']:8.1f} us   7 rounds "
+            f"{b['us']:8.1f} us   ratio {a['us'] / b['us']:.2f}")
+    for a, b in zip(q10, q7):
+        log(f"  quality {a['scheme']:12s} bias2/mse {a['bias2_over_mse']:.4f} / "
+            f"{b['bias2_over_mse']:.4f}   mse/n {a['mse_over_n']:.4f} / {b['mse_over_n']:.4f}")
+    print(json.dumps({"metric": "resampler time and bias with Philox4x32-10 vs 7 rounds",
+                      "unit": "us", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "n = 2^20, y = 0, 2, 4 (speed); n = 2^16, y = 3, "
+                                             f"{K} seeds (quality)", "reps": reps},
+                      "speed": sp10 + sp7, "quality": q10 + q7}), flush=True)
+
+
 def filter_workload(args):
     """Bootstrap filter on x_t = 0.9 x_{t-1} + N(0,1), y_t = x_t + N(0, 0.5^2):
     1024 filters of 2^14 particles, T = 200 synthetic observations (seed 0); one
@@ -537,13 +669,14 @@ def main():
                          "known traffic for scaling hardware byte counters")
     ap.add_argument("--cpu-sample", type=int, default=1 << 18)
     ap.add_argument("--workload", choices=("step", "precision", "batch", "filter", "decision",
-                                              "aux"),
+                                              "aux", "philox"),
                     default="step",
                     help="step: the timed resampling step (default); precision: the bias "
                          "sweep over prefix-sum precision modes; batch: ragged batch of "
                          "4096 filters; filter: full bootstrap filter, 1024 x 2^14 x 200; "
                          "decision: fastest scheme per (N, y) and the Metropolis B*/C "
-                         "trade-off; aux: the auxiliary exports")
+                         "trade-off; aux: the auxiliary exports; philox: 10 vs 7 Philox "
+                         "rounds")
     ap.add_argument("--filters", type=int, default=4096)
     ap.add_argument("--filters-ssm", type=int, default=1024)
     ap.add_argument("--filter-reps", type=int, default=3)
@@ -552,6 +685,7 @@ def main():
     ap.add_argument("--decision-log2n", type=int, nargs=2, default=[4, 22])
     ap.add_argument("--decision-reps", type=int, default=20)
     ap.add_argument("--tradeoff-log2n", type=int, nargs="+", default=[12, 16, 20])
+    ap.add_argument("--forms-log2n", type=int, nargs="+", default=[10, 14, 18, 20, 22, 24])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the resampling step here runs on a single MI355X "
@@ -571,6 +705,9 @@ def main():
         return
     if args.workload == "aux":
         aux_workload(args)
+        return
+    if args.workload == "philox":
+        philox_workload(args)
         return
 
     import torch

@@ -121,7 +121,8 @@ typedef enum {
     PFR_OP_OFFSPRING_TO_ANCESTORS = 5,
     PFR_OP_PERMUTE = 6,
     PFR_OP_ANCESTORS_TO_OFFSPRING = 7,
-    PFR_OP_ESS = 8
+    PFR_OP_ESS = 8,
+    PFR_OP_MULTINOMIAL_IID = 9
 } pfr_op;
 
 /* Bytes of workspace the operation needs for these segments (0 if none). */
@@ -153,6 +154,18 @@ PFR_API int resample_multinomial(const void* w, pfr_dtype dtype, const pfr_segme
                          pfr_precision precision, pfr_rng rng,
                          int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
                          void* stream);
+
+/* Multinomial resampling as Code 5 prints it, with one independent uniform
+ * per particle: u_i = m 2^-53, m = (word 0 >> 11) 2^32 + word 1 of Philox call
+ * (i, 5<<28, filter, offset), p_i = n u_i (binary64), and
+ * a_i = #{k < n-1 : r_k <= p_i} over the same exact prefix r as
+ * resample_multinomial.  Same law as resample_multinomial, but the output is
+ * NOT sorted (permute it with sorted_hint = 0), and each particle pays a
+ * search over r.  Single vectors only (PFR_ENOTSUP for n_filters > 1);
+ * workspace required (the scan records plus r, 8 bytes per particle). */
+PFR_API int resample_multinomial_iid(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                                     pfr_rng rng, int32_t* ancestors, void* ws, size_t ws_bytes,
+                                     uint32_t* dev_flags, void* stream);
 
 /* Stratified resampling (Code 7 then Code 11): stratum s takes the point
  * s + 1 - u_s with u_s = word s&3 of Philox call s>>2 (domain 0) times 2^-32,
@@ -356,6 +369,10 @@ PFR_API int pfr_load_tuning(const char* path);
 PFR_API const char* pfr_status_string(int status);
 /* Library version, e.g. "0.1.0". */
 PFR_API const char* pfr_version(void);
+
+/* Rounds of the Philox4x32 generator this library was built with: 10 (the
+ * generator named above) unless a study build chose another count. */
+PFR_API int pfr_philox_rounds(void);
 
 #ifdef __cplusplus
 }

@@ -181,6 +181,23 @@ def resample_multinomial(w, seed=0, offset=0, filter_base=0, precision=SCAN_EXAC
                        precision, offsets, max_len, out, flags, workspace)
 
 
+def resample_multinomial_iid(w, seed=0, offset=0, filter_base=0, out=None, flags=None,
+                             workspace=None):
+    """Multinomial ancestry as Code 5 prints it: one independent uniform and
+    one search per particle (unsorted output; single vectors)."""
+    _require_cuda(w, flags)
+    dt = _dtype_code(w)
+    seg = _segments(w.numel())
+    a = _out_like(w.numel(), w.device, out)
+    ws, _ = _workspace(_lib.OP_MULTINOMIAL_IID, seg, dt, w.device, workspace)
+    rc = _lib.load().resample_multinomial_iid(_ptr(w), dt, ctypes.byref(seg),
+                                              _rng(seed, offset, filter_base), _ptr(a), _ptr(ws),
+                                              0 if ws is None else ws.numel(), _ptr(flags),
+                                              _stream())
+    _lib.check(rc, "resample_multinomial_iid")
+    return a
+
+
 def resample_stratified(w, seed=0, offset=0, filter_base=0, precision=SCAN_EXACT, offsets=None,
                         max_len=None, out=None, flags=None, workspace=None):
     """Stratified ancestry (Code 7 + Code 11)."""

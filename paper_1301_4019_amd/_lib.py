@@ -17,7 +17,8 @@ PFR_OK, PFR_EINVAL, PFR_EWORKSPACE, PFR_ELAUNCH, PFR_ENOTSUP = range(5)
 PFR_F32, PFR_F64 = 0, 1
 SCAN_EXACT, SCAN_F64, SCAN_COMP_F32, SCAN_NAIVE_F32 = 0, 1, 2, 3
 (OP_MULTINOMIAL, OP_STRATIFIED, OP_SYSTEMATIC, OP_METROPOLIS, OP_REJECTION,
- OP_OFFSPRING_TO_ANCESTORS, OP_PERMUTE, OP_ANCESTORS_TO_OFFSPRING, OP_ESS) = range(9)
+ OP_OFFSPRING_TO_ANCESTORS, OP_PERMUTE, OP_ANCESTORS_TO_OFFSPRING, OP_ESS,
+ OP_MULTINOMIAL_IID) = range(10)
 
 FLAG_ZERO_TOTAL = 1
 FLAG_TRIAL_CAP = 2
@@ -28,13 +29,14 @@ FLAG_BAD_STEP = 32
 MAX_BATCH_SEGMENT = 256 * 1024 - 1
 
 EXPORTS = (
-    "pfr_workspace_bytes", "pfr_workspace_init", "resample_multinomial", "resample_stratified",
+    "pfr_workspace_bytes", "pfr_workspace_init", "resample_multinomial",
+    "resample_multinomial_iid", "resample_stratified",
     "resample_systematic", "resample_metropolis", "resample_rejection",
     "resample_partial_rejection", "offspring_to_ancestors",
     "permute_ancestors", "ancestors_to_offspring", "effective_sample_size", "copy_particles",
     "lgssm_workspace_bytes", "lgssm_init", "lgssm_step",
     "pfr_tuning_defaults", "pfr_get_tuning", "pfr_set_tuning", "pfr_load_tuning",
-    "pfr_status_string", "pfr_version",
+    "pfr_status_string", "pfr_version", "pfr_philox_rounds",
 )
 
 TUNING_VERSION = 1
@@ -72,11 +74,9 @@ class PfrError(RuntimeError):
 _lib = None
 
 
-def load(path: str = LIB_PATH) -> ctypes.CDLL:
-    """Load the shared library and declare every signature."""
-    global _lib
-    if _lib is not None:
-        return _lib
+def open_library(path: str) -> ctypes.CDLL:
+    """Open a build of the library, declare every signature and load the
+    tuning file into it."""
     if not os.path.exists(path):
         raise ImportError(f"{path} is not built; run `python -m paper_1301_4019_amd.build`")
     lib = ctypes.CDLL(path)
@@ -88,6 +88,7 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pfr_workspace_bytes": (SZ, [I, SEG, I]),
         "pfr_workspace_init": (I, [P, SZ, P]),
         "resample_multinomial": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),
+        "resample_multinomial_iid": (I, [P, I, SEG, Rng, P, P, SZ, P, P]),
         "resample_stratified": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),
         "resample_systematic": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),
         "resample_metropolis": (I, [P, I, SEG, I32, P, Rng, P, P, SZ, P]),
@@ -108,17 +109,45 @@ def load(path: str = LIB_PATH) -> ctypes.CDLL:
         "pfr_load_tuning": (I, [ctypes.c_char_p]),
         "pfr_status_string": (ctypes.c_char_p, [I]),
         "pfr_version": (ctypes.c_char_p, []),
+        "pfr_philox_rounds": (I, []),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    _lib = lib
     if os.path.exists(TUNING_PATH):
         rc = lib.pfr_load_tuning(TUNING_PATH.encode())
         if rc != PFR_OK:
             raise PfrError(f"invalid tuning file {TUNING_PATH} (status {rc})")
     return lib
+
+
+def load(path: str = LIB_PATH) -> ctypes.CDLL:
+    """The library every binding call goes through (opened once)."""
+    global _lib
+    if _lib is None:
+        _lib = open_library(path)
+    return _lib
+
+
+class use_library:
+    """Context manager: route the binding through another build of the
+    library (the Philox round-count study's variant), then back."""
+
+    def __init__(self, path: str):
+        self.path = path
+        self.saved = None
+
+    def __enter__(self):
+        global _lib
+        self.saved = load()
+        _lib = open_library(self.path)
+        return _lib
+
+    def __exit__(self, *exc):
+        global _lib
+        _lib = self.saved
+        return False
 
 
 def check(rc: int, what: str) -> None:

@@ -47,30 +47,49 @@ def hipcc() -> str:
     raise RuntimeError("hipcc not found")
 
 
-def _compile(src: str) -> str:
-    obj = os.path.join(BUILD_DIR, os.path.splitext(src)[0] + ".o")
-    cmd = [hipcc(), *HIPCC_FLAGS, "-c", os.path.join(CSRC, src), "-o", obj]
+# The product library uses Philox4x32-10.  build_philox_variant() compiles a
+# second copy with another round count, for the round-count study only.
+VARIANT_ROUNDS = 7
+
+
+def variant_path(rounds: int = VARIANT_ROUNDS) -> str:
+    return os.path.join(HERE, f"libpfresample_philox{rounds}.so")
+
+
+def _compile(src: str, build_dir: str, defines=()) -> str:
+    obj = os.path.join(build_dir, os.path.splitext(src)[0] + ".o")
+    cmd = [hipcc(), *HIPCC_FLAGS, *defines, "-c", os.path.join(CSRC, src), "-o", obj]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"hipcc failed for {src}:\n{res.stdout}\n{res.stderr}")
     return obj
 
 
-def build(verbose: bool = False) -> str:
-    os.makedirs(BUILD_DIR, exist_ok=True)
+def _build(out: str, build_dir: str, defines=(), verbose: bool = False) -> str:
+    os.makedirs(build_dir, exist_ok=True)
     with cf.ThreadPoolExecutor(max_workers=min(4, len(SOURCES))) as ex:
-        objs = list(ex.map(_compile, SOURCES))
-    tmp = LIB + ".tmp"
+        objs = list(ex.map(lambda src: _compile(src, build_dir, defines), SOURCES))
+    tmp = out + ".tmp"
     cmd = [hipcc(), f"--offload-arch={ARCH}", "-shared", "-fPIC", "-o", tmp, *objs]
     res = subprocess.run(cmd, capture_output=True, text=True)
     if res.returncode != 0:
         raise RuntimeError(f"link failed:\n{res.stdout}\n{res.stderr}")
-    os.replace(tmp, LIB)
+    os.replace(tmp, out)
     if verbose:
-        print("built", LIB)
-    return LIB
+        print("built", out)
+    return out
+
+
+def build(verbose: bool = False) -> str:
+    return _build(LIB, BUILD_DIR, (), verbose)
+
+
+def build_philox_variant(rounds: int = VARIANT_ROUNDS, verbose: bool = False) -> str:
+    return _build(variant_path(rounds), BUILD_DIR + f"_philox{rounds}",
+                  (f"-DPFR_PHILOX_ROUNDS={rounds}",), verbose)
 
 
 if __name__ == "__main__":
     build(verbose=True)
+    build_philox_variant(verbose=True)
     sys.exit(0)

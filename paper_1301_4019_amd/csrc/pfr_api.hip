@@ -145,6 +145,8 @@ size_t pfr_workspace_bytes(pfr_op op, const pfr_segments* seg, pfr_dtype dtype) 
       return 0;
     case PFR_OP_ESS:
       return ess_workspace_bytes(s.n_total, s.n_filters);
+    case PFR_OP_MULTINOMIAL_IID:
+      return multinomial_iid_workspace_bytes(s.n_total);
   }
   return 0;
 }
@@ -160,6 +162,28 @@ int resample_multinomial(const void* w, pfr_dtype dtype, const pfr_segments* seg
                          size_t ws_bytes, uint32_t* dev_flags, void* stream) {
   return collective(SCHEME_MULTINOMIAL, w, dtype, seg, precision, rng, ancestors, ws, ws_bytes,
                     dev_flags, stream);
+}
+
+int resample_multinomial_iid(const void* w, pfr_dtype dtype, const pfr_segments* seg, pfr_rng rng,
+                             int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                             void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (dtype != PFR_F32 && dtype != PFR_F64) return PFR_EINVAL;
+  if (s.n_filters > 1) return PFR_ENOTSUP;
+  if (s.n_total == 0) return PFR_OK;
+  if (!w || !ancestors) return PFR_EINVAL;
+  if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), ancestors, (size_t)s.n_total * 4))
+    return PFR_EINVAL;
+  const size_t need = multinomial_iid_workspace_bytes(s.n_total);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return PFR_EWORKSPACE;
+  if (overlaps(ws, need, ancestors, (size_t)s.n_total * 4) ||
+      overlaps(ws, need, w, (size_t)s.n_total * dtype_size(dtype)))
+    return PFR_EINVAL;
+  return launch_result(launch_multinomial_iid(dtype == PFR_F64, w, s.n_total, make_key(rng),
+                                              rng.offset, rng.filter_base, ancestors, ws,
+                                              dev_flags, (hipStream_t)stream));
 }
 
 int resample_stratified(const void* w, pfr_dtype dtype, const pfr_segments* seg,
@@ -527,5 +551,7 @@ const char* pfr_status_string(int status) {
 }
 
 const char* pfr_version(void) { return "0.1.0"; }
+
+int pfr_philox_rounds(void) { return kPhiloxRounds; }
 
 }  // extern "C"

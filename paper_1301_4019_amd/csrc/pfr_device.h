@@ -19,6 +19,7 @@ constexpr uint32_t DOM_EXP = 1u;     // exponential spacings (multinomial)
 constexpr uint32_t DOM_TRIAL = 2u;   // Metropolis steps, rejection trials
 constexpr uint32_t DOM_NOISE = 3u;   // state-space propagation noise
 constexpr uint32_t DOM_INIT = 4u;    // state-space initial state
+constexpr uint32_t DOM_UNIFORM = 5u; // independent uniforms (multinomial, Code 5)
 
 // Result bits OR-ed into the caller's device flag word.
 constexpr uint32_t FLAG_ZERO_TOTAL = 1u;
@@ -39,7 +40,7 @@ __device__ __forceinline__ uint32_t counter_offset(const Key& key, uint32_t offs
   return key.offset_dev ? *key.offset_dev : offset;
 }
 
-// Philox4x32 with 10 rounds (Salmon, Moraes, Dror & Shaw, SC'11).  Each round
+// Philox4x32 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round
 // forms the 64-bit products of counter words 0 and 2 with two odd multipliers
 // and mixes their high halves with words 1 and 3 and the round key; the key
 // advances by two Weyl increments per round.  The key is uniform across the
@@ -50,11 +51,20 @@ __device__ __forceinline__ uint32_t xor3_key(uint32_t a, uint32_t b, uint32_t k)
   return __builtin_amdgcn_bitop3_b32(a, b, k, 0x96);
 }
 
+// The round count is 10 (Philox4x32-10); a study build may set another with
+// -DPFR_PHILOX_ROUNDS (Salmon et al. report 7 rounds as the least that passes
+// their statistical test batteries, 10 as the default with a safety margin).
+#ifndef PFR_PHILOX_ROUNDS
+#define PFR_PHILOX_ROUNDS 10
+#endif
+static_assert(PFR_PHILOX_ROUNDS >= 1 && PFR_PHILOX_ROUNDS <= 16, "Philox round count");
+constexpr int kPhiloxRounds = PFR_PHILOX_ROUNDS;
+
 __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, uint32_t c3,
                                         Key key) {
   uint32_t k0 = key.k0, k1 = key.k1;
 #pragma unroll
-  for (int r = 0; r < 10; ++r) {
+  for (int r = 0; r < kPhiloxRounds; ++r) {
     // one v_mad_u64_u32 per product (instead of separate mul_hi / mul_lo)
     const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
     const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;

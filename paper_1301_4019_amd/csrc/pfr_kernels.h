@@ -81,6 +81,12 @@ hipError_t launch_scan_batched(int scheme, bool f64, const void* w, int64_t n_to
                                uint32_t offset, uint32_t filter_base, int32_t* a, uint32_t* flags,
                                hipStream_t stream);
 
+// Code 5 with independent uniforms (single vectors, exact prefix).
+size_t multinomial_iid_workspace_bytes(int64_t n);
+hipError_t launch_multinomial_iid(bool f64, const void* w, int64_t n, Key key, uint32_t offset,
+                                  uint32_t filter, int32_t* a, void* ws, uint32_t* flags,
+                                  hipStream_t stream);
+
 // Floating-point prefix modes (pfr_precision values 1..3).
 enum Prec : int { PREC_F64 = 1, PREC_COMP_F32 = 2, PREC_NAIVE_F32 = 3 };
 hipError_t launch_fscan(int scheme, int prec, bool f64, const void* w, int64_t n, Key key,

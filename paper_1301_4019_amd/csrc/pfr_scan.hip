@@ -331,6 +331,82 @@ __global__ __launch_bounds__(kT) void k_scan_emit(const T* __restrict__ w, int64
                         &L, &s);
 }
 
+// ---------------------------------------------------------------- Code 5
+// Multinomial resampling with one independent uniform per particle, as Code 5
+// prints it: the scaled prefix r_k = n W_k / W_n of the exact sums is written
+// out (binary64, the same values the other schemes compare against), then
+// particle i draws u_i = m 2^-53 (m: 21 bits of word 0 and 32 of word 1 of its
+// uniform-domain Philox call), p_i = n u_i, and takes #{k < n-1 : r_k <= p_i}.
+// The search is two-level: every workgroup holds up to kSplit splitters
+// r_{(j+1) S - 1} (S a power of two) in LDS, which narrow each point to S
+// candidates, and a bisection over those in global memory finishes it.
+template <typename T>
+__global__ __launch_bounds__(kT) void k_scan_r(const T* __restrict__ w, int64_t n,
+                                               const ScanHeader* __restrict__ hdr,
+                                               const BlockRec* __restrict__ recs,
+                                               const u128* __restrict__ C,
+                                               double* __restrict__ r_out) {
+  __shared__ WgScratch s;
+  if (hdr->status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) return;
+  const uint32_t b = blockIdx.x;
+  const RMap rm = make_rmap(hdr->Q, n);
+  double r[kPer];
+  const int64_t P0 = (int64_t)b * kBlock;
+  block_r(w, n, P0, recs[b], C[b], hdr->gscale, rm, r, &s);
+#pragma unroll
+  for (int v = 0; v < kPer; ++v) {
+    const int64_t i = P0 + (int64_t)threadIdx.x * kPer + v;
+    if (i < n) r_out[i] = r[v];
+  }
+}
+
+constexpr int kSplit = 4096;
+
+__global__ __launch_bounds__(kT) void k_multinomial_iid(int64_t n,
+                                                        const ScanHeader* __restrict__ hdr,
+                                                        const double* __restrict__ r,
+                                                        int stride_log2, Key key,
+                                                        uint32_t offset, uint32_t filter,
+                                                        int32_t* __restrict__ a,
+                                                        uint32_t* __restrict__ flags) {
+  __shared__ double sp[kSplit];
+  offset = counter_offset(key, offset);
+  const uint32_t status = hdr->status;
+  if (flags && blockIdx.x == 0 && threadIdx.x == 0 && status) atomicOr(flags, status);
+  const bool identity = (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) != 0;
+  const int64_t m = n - 1;                  // candidates r_0 .. r_{m-1}
+  const int64_t S = (int64_t)1 << stride_log2;
+  const int J = (int)(m >> stride_log2);  // splitters inside [0, m), J <= kSplit
+  if (!identity)
+    for (int j = (int)threadIdx.x; j < J; j += kT) sp[j] = r[((int64_t)(j + 1) << stride_log2) - 1];
+  __syncthreads();
+  const int64_t stride = (int64_t)gridDim.x * kT;
+  for (int64_t i = (int64_t)blockIdx.x * kT + threadIdx.x; i < n; i += stride) {
+    if (identity) {
+      a[i] = (int32_t)i;
+      continue;
+    }
+    const uint4 x = draw(key, (uint32_t)i, DOM_UNIFORM, 0, filter, offset);
+    const uint64_t mb = ((uint64_t)(x.x >> 11) << 32) | (uint64_t)x.y;
+    const double p = (double)n * ((double)mb * 0x1p-53);
+    // splitters: every r_k with k < lo S is <= p; r_{(lo+1) S - 1} > p if lo < J
+    int lo = 0, hi = J;
+    while (lo < hi) {
+      const int mid = (lo + hi) >> 1;
+      if (sp[mid] <= p) lo = mid + 1;
+      else hi = mid;
+    }
+    int64_t L = (int64_t)lo << stride_log2;
+    int64_t H = lo < J ? L + S - 1 : m;  // the answer lies in [L, H]
+    while (L < H) {
+      const int64_t mid = (L + H) >> 1;
+      if (r[mid] <= p) L = mid + 1;
+      else H = mid;
+    }
+    a[i] = (int32_t)L;
+  }
+}
+
 // Ragged batch: one workgroup per filter runs the reduce, the carries and the
 // emission of its own segment, with the records and carries in LDS.
 constexpr int kBatchMaxBlocks = 256;  // segments up to 2^18 particles
@@ -715,6 +791,45 @@ hipError_t launch_scan(int scheme, bool f64, const void* w, int64_t n, Key key, 
                        hipStream_t stream) {
   return f64 ? launch_scan_scheme<double>(scheme, w, n, key, offset, filter, a, ws, flags, stream)
              : launch_scan_scheme<float>(scheme, w, n, key, offset, filter, a, ws, flags, stream);
+}
+
+size_t multinomial_iid_workspace_bytes(int64_t n) {
+  return scan_layout(n, false).total + align256((size_t)n * sizeof(double));
+}
+
+template <typename T>
+hipError_t launch_multinomial_iid_t(const T* w, int64_t n, Key key, uint32_t offset,
+                                    uint32_t filter, int32_t* a, void* ws, uint32_t* flags,
+                                    hipStream_t stream) {
+  const ScanLayout L = scan_layout(n, false);
+  char* base = (char*)ws;
+  ScanHeader* hdr = (ScanHeader*)base;
+  BlockRec* recs = (BlockRec*)(base + L.recs);
+  u128* C = (u128*)(base + L.carries);
+  double* r = (double*)(base + L.total);
+  const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((k_scan_records<T, false>), dim3(nb), dim3(kT), 0, stream, w, n, nb, key,
+                     offset, filter, recs, (uint64_t*)nullptr);
+  hipLaunchKernelGGL((k_scan_carries<false>), dim3(1), dim3(kT), 0, stream, nb, 0u, hdr, recs,
+                     (const uint64_t*)nullptr, C, (u128*)nullptr);
+  hipLaunchKernelGGL((k_scan_r<T>), dim3(nb), dim3(kT), 0, stream, w, n, hdr, recs, C, r);
+  // splitter stride: the smallest power of two leaving at most kSplit splitters
+  int sl = 0;
+  while (((n - 1) >> sl) > kSplit) ++sl;
+  int64_t grid = (n + kT - 1) / kT;
+  if (grid > 1024) grid = 1024;
+  hipLaunchKernelGGL(k_multinomial_iid, dim3((unsigned)grid), dim3(kT), 0, stream, n, hdr, r, sl,
+                     key, offset, filter, a, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_multinomial_iid(bool f64, const void* w, int64_t n, Key key, uint32_t offset,
+                                  uint32_t filter, int32_t* a, void* ws, uint32_t* flags,
+                                  hipStream_t stream) {
+  return f64 ? launch_multinomial_iid_t((const double*)w, n, key, offset, filter, a, ws, flags,
+                                        stream)
+             : launch_multinomial_iid_t((const float*)w, n, key, offset, filter, a, ws, flags,
+                                        stream);
 }
 
 hipError_t launch_scan_batched(int scheme, bool f64, const void* w, int64_t n_total,

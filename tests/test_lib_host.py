@@ -105,6 +105,15 @@ def test_auxiliary_arguments_rejected_on_host():
                                           out, None, 0, None, None) == _lib.PFR_EINVAL
     assert lib.resample_partial_rejection(fake, 0, ctypes.byref(seg(10)), 0.0, None, 16, rng, out,
                                           ws, None, 0, None, None) == _lib.PFR_EINVAL
+    # Code 5 with independent uniforms: single vectors only, workspace required
+    assert lib.resample_multinomial_iid(fake, 0, ctypes.byref(seg(100, 3, fake)), rng, out, ws,
+                                        1 << 20, None, None) == _lib.PFR_ENOTSUP
+    assert lib.resample_multinomial_iid(fake, 0, ctypes.byref(seg(100)), rng, out, None, 0, None,
+                                        None) == _lib.PFR_EWORKSPACE
+    small = lib.pfr_workspace_bytes(_lib.OP_MULTINOMIAL_IID, ctypes.byref(seg(1 << 20)), 0)
+    assert small >= 8 << 20
+    assert lib.resample_multinomial_iid(fake, 0, ctypes.byref(seg(1 << 20)), rng, out, ws,
+                                        small - 256, None, None) == _lib.PFR_EWORKSPACE
     # empty input is a no-op
     assert lib.copy_particles(None, ctypes.byref(seg(0)), None, 4, 3, I64(3), I64(1), None,
                               None) == _lib.PFR_OK
