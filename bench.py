@@ -5,8 +5,10 @@ x_i ~ N(0,1), for each y in {0, 1, 2, 3, 4}; each weight set is resampled by
 all five resamplers -- multinomial, stratified, systematic (exact prefix sums),
 Metropolis with B from the bias bound (eps = 1/100, beta = E[w]/w_max, giving
 B = 4, 6, 16, 60, 354), rejection with w_max = 1 -- and every ancestry is then
-permuted for in-place propagation.  That is 25 resamples of 2^20 particles
-per step; inputs are resident in HBM before the timed region.
+permuted for in-place propagation (for stratified and systematic the claim
+pass of the permutation is fused into the emission: resample_permuted).
+That is 25 resamples of 2^20 particles per step; inputs are resident in HBM
+before the timed region.
 
 Prints one JSON line: whole-step particles/s, the roofline of the dominant
 kernel measured with HIP events inside the timed steps, a per-scheme
@@ -32,6 +34,9 @@ if ROOT not in sys.path:
 N = 1 << 20
 YS = (0.0, 1.0, 2.0, 3.0, 4.0)
 SCHEMES = ("multinomial", "stratified", "systematic", "metropolis", "rejection")
+# schemes whose claim pass of the permutation is fused into the resampler
+# (resample_permuted); the others run resample_<scheme> then permute_ancestors
+FUSED = ("stratified", "systematic")
 HBM_PEAK_GBS = 8000.0
 # Philox4x32-10 per call: 20 32x32->64-bit products (one v_mad_u64_u32 each)
 # and 20 three-input xors (one v_bitop3_b32 each) = 40 VALU instructions per
@@ -754,6 +759,11 @@ def main():
     def step(record=False):
         for yi, y in enumerate(YS):
             for s in SCHEMES:
+                if s in FUSED:
+                    # the emission writes the claim vector and marks itself
+                    pfr.resample_permuted(s, ws_[yi], seed=1, out=out[(y, s)],
+                                          permuted=perm[(y, s)], flags=flags)
+                    continue
                 if record and (y, s) == dominant:
                     e0 = torch.cuda.Event(enable_timing=True)
                     e1 = torch.cuda.Event(enable_timing=True)
@@ -820,7 +830,18 @@ def main():
             torch.cuda.synchronize()
             t_res = e0.elapsed_time(e1) / reps
             t_perm = e1.elapsed_time(e2) / reps
-            rows.append({"y": y, "resample_us": 1e3 * t_res, "permute_us": 1e3 * t_perm,
+            fused = {}
+            if s in FUSED:
+                e3 = torch.cuda.Event(enable_timing=True)
+                e2.synchronize()
+                e2.record(stream)
+                for _ in range(reps):
+                    pfr.resample_permuted(s, ws_[yi], seed=1, out=out[(y, s)],
+                                          permuted=perm[(y, s)], flags=flags)
+                e3.record(stream)
+                e3.synchronize()
+                fused = {"fused_us": 1e3 * e2.elapsed_time(e3) / reps}
+            rows.append({"y": y, "resample_us": 1e3 * t_res, "permute_us": 1e3 * t_perm, **fused,
                          "particles_per_s": N / (t_res * 1e-3),
                          "hbm_frac_8B_per_particle": 8.0 * N / (t_res * 1e-3) / (HBM_PEAK_GBS * 1e9)})
         breakdown[s] = rows

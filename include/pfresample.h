@@ -229,6 +229,40 @@ PFR_API int resample_partial_rejection(const void* w, pfr_dtype dtype, const pfr
                                        void* weights_out, void* ws, size_t ws_bytes,
                                        uint32_t* dev_flags, void* stream);
 
+/* Scheme parameters of resample_permuted (the fields of other schemes are
+ * ignored). */
+typedef struct {
+    pfr_precision precision;  /* multinomial, stratified, systematic */
+    int32_t B;                /* Metropolis steps; B_dev (device int32[n_filters]) may override */
+    const int32_t* B_dev;
+    double w_max;             /* rejection bound; w_max_dev (device double[n_filters]) may override */
+    const double* w_max_dev;
+    uint32_t max_trials;      /* rejection trial cap (>= 1) */
+} pfr_scheme_params;
+
+/* Bytes of workspace for resample_permuted (256-byte aligned; zero it once
+ * with pfr_workspace_init). */
+PFR_API size_t pfr_resample_permuted_workspace_bytes(pfr_op scheme, const pfr_segments* seg,
+                                                     pfr_dtype dtype);
+
+/* Resampling and the ancestor permutation in one call (the paper times
+ * resampling until an ancestry satisfying eq. (predicate) is delivered,
+ * section 3.4, and appends Prepermute to every kernel that produces an
+ * ancestry, appendix E).  scheme is one of PFR_OP_MULTINOMIAL ..
+ * PFR_OP_REJECTION.  Writes the scheme's ancestry to `ancestors` and its
+ * Code 10 permutation to `permuted`, bit for bit what resample_<scheme>
+ * followed by permute_ancestors (sorted_hint set for the collective schemes)
+ * would write, with the same flags.  For a long single vector of the exact
+ * stratified or systematic scheme the emission writes the claim vector and
+ * the marked ancestry itself, so only the resolve pass follows; the other
+ * cases run the two steps one after the other (claiming inside Metropolis and
+ * rejection, with atomics beside their random weight loads, measured slower
+ * than the separate claim pass on MI355X). */
+PFR_API int resample_permuted(pfr_op scheme, const void* w, pfr_dtype dtype,
+                              const pfr_segments* seg, const pfr_scheme_params* params,
+                              pfr_rng rng, int32_t* ancestors, int32_t* permuted, void* ws,
+                              size_t ws_bytes, uint32_t* dev_flags, void* stream);
+
 /* ---------------------------------------------------------------- auxiliaries */
 
 /* Offspring counts to ancestors (appendix D, Code 11 after an inclusive prefix

@@ -275,6 +275,41 @@ def resample_partial_rejection(w, v_max, seed=0, offset=0, filter_base=0, max_tr
     return a, weights_out
 
 
+def resample_permuted(scheme, w, seed=0, offset=0, filter_base=0, precision=SCAN_EXACT, B=0,
+                      B_per_filter=None, w_max=1.0, w_max_per_filter=None, max_trials=1 << 20,
+                      offsets=None, max_len=None, out=None, permuted=None, flags=None,
+                      workspace=None):
+    """Resample and permute in one call (Prepermute fused into the resampler
+    for long single vectors).  scheme: "multinomial", "stratified",
+    "systematic", "metropolis" or "rejection".  Returns (ancestors, permuted),
+    the same bits as resample_<scheme> followed by permute_ancestors."""
+    _require_cuda(w, B_per_filter, w_max_per_filter, flags)
+    op = _SCHEME_OPS[scheme]
+    dt = _dtype_code(w)
+    seg = _segments(w.numel(), offsets, max_len)
+    _per_segment(B_per_filter, "int32", seg, "B_per_filter")
+    _per_segment(w_max_per_filter, "float64", seg, "w_max_per_filter")
+    a = _out_like(w.numel(), w.device, out)
+    c = _out_like(w.numel(), w.device, permuted)
+    lib = _lib.load()
+    need = int(lib.pfr_resample_permuted_workspace_bytes(op, ctypes.byref(seg), dt))
+    if workspace is None:
+        key = (str(w.device), "permuted", op, need)
+        workspace = _WS_CACHE.get(key)
+        if workspace is None:
+            workspace = new_workspace(need, w.device)
+            _WS_CACHE[key] = workspace
+    params = _lib.SchemeParams(int(precision), int(B), None if B_per_filter is None
+                               else B_per_filter.data_ptr(), float(w_max),
+                               None if w_max_per_filter is None else w_max_per_filter.data_ptr(),
+                               int(max_trials))
+    rc = lib.resample_permuted(op, _ptr(w), dt, ctypes.byref(seg), ctypes.byref(params),
+                               _rng(seed, offset, filter_base), _ptr(a), _ptr(c), _ptr(workspace),
+                               workspace.numel(), _ptr(flags), _stream())
+    _lib.check(rc, "resample_permuted")
+    return a, c
+
+
 def offspring_to_ancestors(o, offsets=None, max_len=None, out=None, flags=None, workspace=None):
     """Ancestors from int32 offspring counts (Code 11 after a prefix sum)."""
     torch = _torch()

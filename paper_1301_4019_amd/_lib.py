@@ -34,6 +34,7 @@ EXPORTS = (
     "resample_systematic", "resample_metropolis", "resample_rejection",
     "resample_partial_rejection", "offspring_to_ancestors",
     "permute_ancestors", "ancestors_to_offspring", "effective_sample_size", "copy_particles",
+    "pfr_resample_permuted_workspace_bytes", "resample_permuted",
     "lgssm_workspace_bytes", "lgssm_init", "lgssm_step",
     "pfr_tuning_defaults", "pfr_get_tuning", "pfr_set_tuning", "pfr_load_tuning",
     "pfr_status_string", "pfr_version", "pfr_philox_rounds",
@@ -42,6 +43,12 @@ EXPORTS = (
 TUNING_VERSION = 1
 # tuning chosen for this machine by autotune.py; PFR_TUNING overrides the path
 TUNING_PATH = os.environ.get("PFR_TUNING", os.path.join(HERE, "tuning.json"))
+
+
+class SchemeParams(ctypes.Structure):
+    _fields_ = [("precision", ctypes.c_int), ("B", ctypes.c_int32),
+                ("B_dev", ctypes.c_void_p), ("w_max", ctypes.c_double),
+                ("w_max_dev", ctypes.c_void_p), ("max_trials", ctypes.c_uint32)]
 
 
 class Segments(ctypes.Structure):
@@ -96,6 +103,9 @@ def open_library(path: str) -> ctypes.CDLL:
         "resample_partial_rejection": (I, [P, I, SEG, D, P, U32, Rng, P, P, P, SZ, P, P]),
         "offspring_to_ancestors": (I, [P, SEG, P, P, SZ, P, P]),
         "permute_ancestors": (I, [P, SEG, I32, P, P, SZ, P, P]),
+        "pfr_resample_permuted_workspace_bytes": (SZ, [I, SEG, I]),
+        "resample_permuted": (I, [I, P, I, SEG, ctypes.POINTER(SchemeParams), Rng, P, P, P, SZ,
+                                  P, P]),
         "ancestors_to_offspring": (I, [P, SEG, I32, P, P, P]),
         "effective_sample_size": (I, [P, I, SEG, P, P, SZ, P, P]),
         "copy_particles": (I, [P, SEG, P, SZ, I32, ctypes.c_int64, ctypes.c_int64, P, P]),

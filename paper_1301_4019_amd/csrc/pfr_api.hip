@@ -358,6 +358,76 @@ int copy_particles(const int32_t* permuted, const pfr_segments* seg, void* x, si
                                    (hipStream_t)stream));
 }
 
+size_t pfr_resample_permuted_workspace_bytes(pfr_op scheme, const pfr_segments* seg,
+                                             pfr_dtype dtype) {
+  SegInfo s;
+  if (check_segments(seg, &s)) return 0;
+  if (scheme < PFR_OP_MULTINOMIAL || scheme > PFR_OP_REJECTION) return 0;
+  const size_t perm = permute_workspace_bytes(s.n_total);
+  return perm + pfr_workspace_bytes(scheme, seg, dtype);
+}
+
+int resample_permuted(pfr_op scheme, const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                      const pfr_scheme_params* params, pfr_rng rng, int32_t* ancestors,
+                      int32_t* permuted, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                      void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (!params || scheme < PFR_OP_MULTINOMIAL || scheme > PFR_OP_REJECTION) return PFR_EINVAL;
+  if (dtype != PFR_F32 && dtype != PFR_F64) return PFR_EINVAL;
+  if (s.n_total == 0) return PFR_OK;
+  if (!w || !ancestors || !permuted) return PFR_EINVAL;
+  const size_t abytes = (size_t)s.n_total * 4;
+  if (overlaps(ancestors, abytes, permuted, abytes) ||
+      overlaps(w, (size_t)s.n_total * dtype_size(dtype), permuted, abytes))
+    return PFR_EINVAL;
+  const size_t perm = permute_workspace_bytes(s.n_total);
+  const size_t need = perm + pfr_workspace_bytes(scheme, seg, dtype);
+  if (!ws || ws_bytes < need || !aligned256(ws)) return PFR_EWORKSPACE;
+  if (overlaps(ws, need, ancestors, abytes) || overlaps(ws, need, permuted, abytes))
+    return PFR_EINVAL;
+  void* rws = (char*)ws + perm;  // the resampler's own workspace
+  const size_t rbytes = ws_bytes - perm;
+  const bool sorted_out = scheme <= PFR_OP_SYSTEMATIC;  // collective schemes
+  const hipStream_t st = (hipStream_t)stream;
+  // the claim fused into the emission: long single vectors of the exact
+  // stratified and systematic schemes (shorter ones are permuted in LDS)
+  if (s.n_filters == 1 && (scheme == PFR_OP_STRATIFIED || scheme == PFR_OP_SYSTEMATIC) &&
+      params->precision == PFR_SCAN_EXACT && uses_scan_workspace(s) && s.n_total > 1024) {
+    rc = launch_result(launch_scan_claimed(scheme == PFR_OP_STRATIFIED ? SCHEME_STRATIFIED
+                                                                       : SCHEME_SYSTEMATIC,
+                                           dtype == PFR_F64, w, s.n_total, make_key(rng),
+                                           rng.offset, rng.filter_base, ancestors, rws, dev_flags,
+                                           permute_claims(ws), permute_marks(ws, s.n_total), st));
+    if (rc) return rc;
+    return launch_result(launch_resolve(s.n_total, permuted, ws, dev_flags, st));
+  }
+  // the two steps one after the other
+  switch (scheme) {
+    case PFR_OP_MULTINOMIAL:
+    case PFR_OP_STRATIFIED:
+    case PFR_OP_SYSTEMATIC:
+      rc = collective(scheme == PFR_OP_MULTINOMIAL   ? SCHEME_MULTINOMIAL
+                      : scheme == PFR_OP_STRATIFIED ? SCHEME_STRATIFIED
+                                                    : SCHEME_SYSTEMATIC,
+                      w, dtype, seg, params->precision, rng, ancestors, rws, rbytes, dev_flags,
+                      stream);
+      break;
+    case PFR_OP_METROPOLIS:
+      rc = resample_metropolis(w, dtype, seg, params->B, params->B_dev, rng, ancestors, rws,
+                               rbytes, stream);
+      break;
+    default:
+      rc = resample_rejection(w, dtype, seg, params->w_max, params->w_max_dev, params->max_trials,
+                              rng, ancestors, rws, rbytes, dev_flags, stream);
+      break;
+  }
+  if (rc) return rc;
+  return permute_ancestors(ancestors, seg, sorted_out ? 1 : 0, permuted, ws, perm, dev_flags,
+                           stream);
+}
+
 size_t lgssm_workspace_bytes(int32_t n_filters, int32_t n) {
   if (n_filters < 1 || n < 1 || (int64_t)n_filters * n >= kMaxN) return 0;
   const int64_t total = (int64_t)n_filters * n;

@@ -622,6 +622,19 @@ hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offs
   return hipGetLastError();
 }
 
+int32_t* permute_claims(void* ws) { return (int32_t*)ws; }
+int32_t* permute_marks(void* ws, int64_t n_total) {
+  return (int32_t*)((char*)ws + align256((size_t)n_total * sizeof(int32_t)));
+}
+
+hipError_t launch_resolve(int64_t n_total, int32_t* c, void* ws, uint32_t* flags,
+                          hipStream_t stream) {
+  hipLaunchKernelGGL(k_resolve, dim3(grid_for(n_total)), dim3(256), 0, stream, n_total,
+                     (const int64_t*)nullptr, 1u, (int64_t)0, permute_claims(ws),
+                     permute_marks(ws, n_total), c, flags);
+  return hipGetLastError();
+}
+
 __global__ void k_zero_u32(uint32_t* __restrict__ p, size_t count) {
   const size_t stride = (size_t)gridDim.x * blockDim.x;
   for (size_t i = (size_t)blockIdx.x * blockDim.x + threadIdx.x; i < count; i += stride) p[i] = 0;

@@ -175,7 +175,9 @@ template <typename T, int SCHEME, typename CEPtr>
 __device__ void emit_block(const T* __restrict__ w, int64_t n, uint32_t b, const BlockRec rec,
                            u128 Cb, u128 Cb1, int32_t gscale, const RMap& rm, Key key,
                            uint32_t filter, uint32_t offset, CEPtr CE, uint32_t nbe,
-                           int32_t* __restrict__ a_out, EmitLds* L, WgScratch* s) {
+                           int32_t* __restrict__ a_out, EmitLds* L, WgScratch* s,
+                           int32_t* __restrict__ d_out = nullptr,
+                           int32_t* __restrict__ e_out = nullptr) {
   const int64_t P0 = (int64_t)b * kBlock;
   const int cnt = (int)min((int64_t)kBlock, n - P0);
   const double r_lo = rm(Cb);
@@ -192,7 +194,8 @@ __device__ void emit_block(const T* __restrict__ w, int64_t n, uint32_t b, const
     const uint32_t u_sys =
         SCHEME == SCHEME_SYSTEMATIC ? draw(key, 0, DOM_STRATA, 0, filter, offset).x : 0u;
     emit_strata<SCHEME == SCHEME_SYSTEMATIC, false>(r, cnt, r_lo, r_hi, n, P0, key, filter,
-                                                    offset, u_sys, a_out, &L->st, s);
+                                                    offset, u_sys, a_out, &L->st, s, d_out,
+                                                    e_out);
   }
 }
 
@@ -298,7 +301,9 @@ __global__ __launch_bounds__(kT) void k_scan_emit(const T* __restrict__ w, int64
                                                   const u128* __restrict__ C,
                                                   const u128* __restrict__ CE,
                                                   int32_t* __restrict__ a,
-                                                  uint32_t* __restrict__ flags) {
+                                                  uint32_t* __restrict__ flags,
+                                                  int32_t* __restrict__ d_out,
+                                                  int32_t* __restrict__ e_out) {
   offset = counter_offset(key, offset);
   __shared__ EmitLds L;
   __shared__ WgScratch s;
@@ -322,13 +327,20 @@ __global__ __launch_bounds__(kT) void k_scan_emit(const T* __restrict__ w, int64
   }
   if (flags && b == 0 && threadIdx.x == 0 && status) atomicOr(flags, status);
   if (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
+    // identity: every position claims its own slot
     const int64_t P0 = (int64_t)b * kBlock;
-    for (int64_t i = P0 + threadIdx.x; i < min(P0 + kBlock, n); i += kT) a[i] = (int32_t)i;
+    for (int64_t i = P0 + threadIdx.x; i < min(P0 + kBlock, n); i += kT) {
+      a[i] = (int32_t)i;
+      if (d_out) {
+        d_out[i] = (int32_t)i;
+        e_out[i] = (int32_t)i;
+      }
+    }
     return;
   }
   const RMap rm = make_rmap(Q, n);
   emit_block<T, SCHEME>(w, n, b, recs[b], Cb, Cb1, gscale, rm, key, filter, offset, CE, nbe, a,
-                        &L, &s);
+                        &L, &s, d_out, e_out);
 }
 
 // ---------------------------------------------------------------- Code 5
@@ -621,7 +633,8 @@ __global__ __launch_bounds__(kT) void k_seg_emit(
 
 template <typename T, int SCHEME>
 hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, uint32_t filter,
-                         int32_t* a, void* ws, uint32_t* flags, hipStream_t stream) {
+                         int32_t* a, void* ws, uint32_t* flags, hipStream_t stream,
+                         int32_t* d_out = nullptr, int32_t* e_out = nullptr) {
   const T* w = (const T*)wv;
   constexpr bool multi = SCHEME == SCHEME_MULTINOMIAL;
   const ScanLayout L = scan_layout(n, multi);
@@ -639,7 +652,7 @@ hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, ui
   if (e != hipSuccess) return e;
   if (!multi && nb <= (uint32_t)tuning().direct_max_blocks && nb <= kDirectMax) {
     hipLaunchKernelGGL((k_scan_emit<T, SCHEME, true>), dim3(nb), dim3(kT), 0, stream, w, n, nb,
-                       nbe, key, offset, filter, hdr, recs, C, CE, a, flags);
+                       nbe, key, offset, filter, hdr, recs, C, CE, a, flags, d_out, e_out);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_scan_carries<multi>), dim3(1), dim3(kT), 0, stream, nb, nbe, hdr, recs,
@@ -647,7 +660,7 @@ hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, ui
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_scan_emit<T, SCHEME, false>), dim3(nb), dim3(kT), 0, stream, w, n, nb,
-                     nbe, key, offset, filter, hdr, recs, C, CE, a, flags);
+                     nbe, key, offset, filter, hdr, recs, C, CE, a, flags, d_out, e_out);
   return hipGetLastError();
 }
 
@@ -830,6 +843,22 @@ hipError_t launch_multinomial_iid(bool f64, const void* w, int64_t n, Key key, u
                                         stream)
              : launch_multinomial_iid_t((const float*)w, n, key, offset, filter, a, ws, flags,
                                         stream);
+}
+
+hipError_t launch_scan_claimed(int scheme, bool f64, const void* w, int64_t n, Key key,
+                               uint32_t offset, uint32_t filter, int32_t* a, void* ws,
+                               uint32_t* flags, int32_t* d, int32_t* e, hipStream_t stream) {
+  if (scheme == SCHEME_STRATIFIED)
+    return f64 ? launch_scan_t<double, SCHEME_STRATIFIED>(w, n, key, offset, filter, a, ws, flags,
+                                                          stream, d, e)
+               : launch_scan_t<float, SCHEME_STRATIFIED>(w, n, key, offset, filter, a, ws, flags,
+                                                         stream, d, e);
+  if (scheme == SCHEME_SYSTEMATIC)
+    return f64 ? launch_scan_t<double, SCHEME_SYSTEMATIC>(w, n, key, offset, filter, a, ws, flags,
+                                                          stream, d, e)
+               : launch_scan_t<float, SCHEME_SYSTEMATIC>(w, n, key, offset, filter, a, ws, flags,
+                                                         stream, d, e);
+  return hipErrorInvalidValue;
 }
 
 hipError_t launch_scan_batched(int scheme, bool f64, const void* w, int64_t n_total,

@@ -223,10 +223,18 @@ __device__ void wg_max_scan(int32_t* M, int len, WgScratch* s) {
 // a_out[s] = P0 + i for every stratum s in [O(r_lo), O(r_hi)).  The r must be
 // non-decreasing and within [r_lo, r_hi]; u_sys is the raw offset word of the
 // systematic scheme.
+//
+// With d_out and e_out (both or neither), the Prepermute of Code 10 is fused
+// in: the output is sorted, so particle i's claim is the first position of its
+// run, d_out[i] = O_{i-1} (n when it has no offspring), and the marked
+// ancestry is e_out[s] = i at the first position of i's run, -1 - i at the
+// others -- what the claim pass of permute_ancestors would write.
 template <bool SYSTEMATIC, bool NAIVE>
 __device__ void emit_strata(const double (&r)[kPer], int cnt, double r_lo, double r_hi, int64_t n,
                             int64_t P0, Key key, uint32_t filter, uint32_t offset, uint32_t u_sys,
-                            int32_t* __restrict__ a_out, StrataLds* L, WgScratch* s) {
+                            int32_t* __restrict__ a_out, StrataLds* L, WgScratch* s,
+                            int32_t* __restrict__ d_out = nullptr,
+                            int32_t* __restrict__ e_out = nullptr) {
   const int tid = (int)threadIdx.x;
   // stratum offsets of the strata the block's r-range touches
   const int64_t m_lo = (int64_t)floor(r_lo);
@@ -255,6 +263,13 @@ __device__ void emit_strata(const double (&r)[kPer], int cnt, double r_lo, doubl
   const int64_t O_lo = cum_of<NAIVE>(r_lo, n, u_of(m_lo));
   const int64_t O_hi = cum_of<NAIVE>(r_hi, n, u_of((int64_t)floor(r_hi)));
   __syncthreads();
+  if (d_out) {
+    for (int e = tid; e < cnt; e += kT) {
+      const int64_t Oe = L->O[e];
+      const int64_t Op = e == 0 ? O_lo : (int64_t)L->O[e - 1];
+      d_out[P0 + e] = (int32_t)(Oe > Op ? Op : n);
+    }
+  }
   // expansion: a marker at the first output of every particle, then a max-scan
   for (int64_t cs = O_lo; cs < O_hi; cs += kChunk) {
     const int64_t ce = min(cs + (int64_t)kChunk, O_hi);
@@ -269,6 +284,13 @@ __device__ void emit_strata(const double (&r)[kPer], int cnt, double r_lo, doubl
     const int len = (int)(ce - cs);
     wg_max_scan(L->M, len, s);
     for (int k = tid; k < len; k += kT) a_out[cs + k] = (int32_t)(P0 + L->M[k]);
+    if (e_out) {
+      for (int k = tid; k < len; k += kT) {
+        const int e = L->M[k];
+        const int64_t Op = e == 0 ? O_lo : (int64_t)L->O[e - 1];
+        e_out[cs + k] = (cs + k == Op) ? (int32_t)(P0 + e) : (int32_t)(-1 - (P0 + e));
+      }
+    }
     __syncthreads();
   }
 }

@@ -1,0 +1,90 @@
+"""resample_permuted against the two separate calls and the oracle: the
+claim pass fused into the stratified / systematic emission (the claim vector
+and the marked ancestry written there) must give the ancestors and the
+permutation bit for bit, on one and several emission workgroups; the other
+schemes, short vectors and batches run the two steps in turn."""
+import numpy as np
+import pytest
+
+import oracle
+from paper_1301_4019_amd import inputs
+
+torch = pytest.importorskip("torch")
+pytestmark = pytest.mark.gpu
+
+SCHEMES = ["multinomial", "stratified", "systematic", "metropolis", "rejection"]
+
+
+def pfr():
+    import paper_1301_4019_amd as m
+    return m
+
+
+def host(t):
+    torch.cuda.synchronize()
+    return t.cpu().numpy()
+
+
+def separate(scheme, w, seed, **kw):
+    if scheme == "metropolis":
+        a = pfr().resample_metropolis(w, kw.get("B", 16), seed=seed)
+    elif scheme == "rejection":
+        a = pfr().resample_rejection(w, 1.0, seed=seed)
+    else:
+        a = getattr(pfr(), "resample_" + scheme)(w, seed=seed)
+    c = pfr().permute_ancestors(a, sorted_hint=scheme not in ("metropolis", "rejection"))
+    return host(a), host(c)
+
+
+@pytest.mark.parametrize("scheme", SCHEMES)
+@pytest.mark.parametrize("n", [1000, 5000, 20000, (1 << 16) + 7, 1 << 20])
+@pytest.mark.parametrize("y", [0.0, 3.0])
+def test_fused_equals_separate(scheme, n, y):
+    w = torch.from_numpy(inputs.weights(n, y, seed=n)).cuda()
+    B = 60 if y > 0 else 4
+    fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+    a, c = pfr().resample_permuted(scheme, w, seed=7, B=B, w_max=1.0, flags=fl)
+    a, c = host(a), host(c)
+    a_ref, c_ref = separate(scheme, w, 7, B=B)
+    assert int(host(fl)[0]) == 0
+    assert np.array_equal(a, a_ref)
+    assert np.array_equal(c, c_ref)
+    if n <= 20000:
+        assert np.array_equal(c, oracle.permute(a)[0])
+
+
+@pytest.mark.parametrize("dtype", [np.float32, np.float64])
+def test_fused_float64_and_table_path(dtype):
+    n = 1 << 18
+    w = torch.from_numpy(inputs.weights(n, 4.0, seed=1).astype(dtype)).cuda()
+    for scheme in ("metropolis", "rejection", "systematic"):
+        a, c = pfr().resample_permuted(scheme, w, seed=2, B=354)
+        a_ref, c_ref = separate(scheme, w, 2, B=354)
+        assert np.array_equal(host(a), a_ref), scheme
+        assert np.array_equal(host(c), c_ref), scheme
+
+
+def test_zero_weights_give_identity_and_flag():
+    n = 50000
+    w = torch.zeros(n, device="cuda")
+    for scheme in ("stratified", "systematic"):
+        fl = torch.zeros(1, dtype=torch.int32, device="cuda")
+        a, c = pfr().resample_permuted(scheme, w, seed=1, flags=fl)
+        assert int(host(fl)[0]) == pfr().FLAG_ZERO_TOTAL
+        assert np.array_equal(host(a), np.arange(n)) and np.array_equal(host(c), np.arange(n))
+
+
+def test_batch_runs_the_two_steps():
+    w, off, ys = inputs.ragged_batch(n_filters=32, seed=4)
+    wd, od = torch.from_numpy(w).cuda(), torch.from_numpy(off).cuda()
+    ml = int(np.diff(off).max())
+    for scheme in ("systematic", "rejection"):
+        a, c = pfr().resample_permuted(scheme, wd, seed=3, offsets=od, max_len=ml)
+        if scheme == "systematic":
+            a_ref = pfr().resample_systematic(wd, seed=3, offsets=od, max_len=ml)
+        else:
+            a_ref = pfr().resample_rejection(wd, 1.0, seed=3, offsets=od, max_len=ml)
+        c_ref = pfr().permute_ancestors(a_ref, sorted_hint=scheme == "systematic", offsets=od,
+                                        max_len=ml)
+        assert np.array_equal(host(a), host(a_ref)), scheme
+        assert np.array_equal(host(c), host(c_ref)), scheme

@@ -114,6 +114,24 @@ def test_auxiliary_arguments_rejected_on_host():
     assert small >= 8 << 20
     assert lib.resample_multinomial_iid(fake, 0, ctypes.byref(seg(1 << 20)), rng, out, ws,
                                         small - 256, None, None) == _lib.PFR_EWORKSPACE
+    # resample_permuted: no parameters, unknown scheme, no workspace, outputs aliasing
+    prm = _lib.SchemeParams(0, 4, None, 1.0, None, 16)
+    assert lib.resample_permuted(_lib.OP_SYSTEMATIC, fake, 0, ctypes.byref(seg(10)), None, rng,
+                                 out, ws, ws, 1 << 20, None, None) == _lib.PFR_EINVAL
+    assert lib.resample_permuted(_lib.OP_PERMUTE, fake, 0, ctypes.byref(seg(10)),
+                                 ctypes.byref(prm), rng, out, ws, ws, 1 << 20, None,
+                                 None) == _lib.PFR_EINVAL
+    perm_out = ctypes.c_void_p(0x10000 + (3 << 30))
+    assert lib.resample_permuted(_lib.OP_SYSTEMATIC, fake, 0, ctypes.byref(seg(1 << 20)),
+                                 ctypes.byref(prm), rng, out, perm_out, None, 0, None,
+                                 None) == _lib.PFR_EWORKSPACE
+    assert lib.resample_permuted(_lib.OP_METROPOLIS, fake, 0, ctypes.byref(seg(10)),
+                                 ctypes.byref(prm), rng, out, out, ws, 1 << 20, None,
+                                 None) == _lib.PFR_EINVAL
+    need = lib.pfr_resample_permuted_workspace_bytes(_lib.OP_SYSTEMATIC, ctypes.byref(seg(1 << 20)), 0)
+    assert need >= lib.pfr_workspace_bytes(_lib.OP_PERMUTE, ctypes.byref(seg(1 << 20)), 0) + \
+        lib.pfr_workspace_bytes(_lib.OP_SYSTEMATIC, ctypes.byref(seg(1 << 20)), 0)
+    assert ctypes.sizeof(_lib.SchemeParams) == 40
     # empty input is a no-op
     assert lib.copy_particles(None, ctypes.byref(seg(0)), None, 4, 3, I64(3), I64(1), None,
                               None) == _lib.PFR_OK
