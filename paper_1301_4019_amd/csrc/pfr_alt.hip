@@ -236,7 +236,7 @@ struct BoundTable {
   }
   // true when u * lb > ub(j), i.e. u * w_k > w_j for every w_k >= lb
   __device__ __forceinline__ bool rejects(double u, double lb, uint32_t j) const {
-    return usable && (u * lb) * (1.0 - 0x1p-50) > ub(j);
+    return usable & ((u * lb) * (1.0 - 0x1p-50) > ub(j));
   }
 };
 
@@ -430,17 +430,28 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
           cur = -1;
         }
       } else {
+        // the four trials' draws, then their table checks, then their weight
+        // loads issued together (a trial that needs no load re-reads the
+        // particle's own weight, a cache hit), then the decisions: one wait
+        // per pass instead of one per trial
         uint32_t jq[kRejBatch];
-        bool accq[kRejBatch];
+        double uq[kRejBatch];
 #pragma unroll
         for (int q = 0; q < kRejBatch; ++q) {
-          const uint32_t tt = t + (uint32_t)q;
-          const uint4 x = draw(key, i, DOM_TRIAL, tt, filt, offset);
+          const uint4 x = draw(key, i, DOM_TRIAL, t + (uint32_t)q, filt, offset);
           jq[q] = index_draw(x.x, x.y, n);
-          const double u = u_accept(x.z);
-          const bool live = tt < max_trials && !(TABLE && tab.rejects(u, wmax, jq[q]));
-          accq[q] = live && accept_exact(u, wmax, (double)ws[live ? jq[q] : i]);
+          uq[q] = u_accept(x.z);
         }
+        bool live[kRejBatch];
+#pragma unroll
+        for (int q = 0; q < kRejBatch; ++q)
+          live[q] = (t + (uint32_t)q < max_trials) & !(TABLE && tab.rejects(uq[q], wmax, jq[q]));
+        double vq[kRejBatch];
+#pragma unroll
+        for (int q = 0; q < kRejBatch; ++q) vq[q] = (double)ws[live[q] ? jq[q] : i];
+        bool accq[kRejBatch];
+#pragma unroll
+        for (int q = 0; q < kRejBatch; ++q) accq[q] = live[q] & accept_exact(uq[q], wmax, vq[q]);
         int first = -1;
 #pragma unroll
         for (int q = kRejBatch - 1; q >= 0; --q)
