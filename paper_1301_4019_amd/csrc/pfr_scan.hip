@@ -155,7 +155,10 @@ __device__ void block_r(const T* __restrict__ w, int64_t n, int64_t base, const 
                         WgScratch* s) {
   T x[kPer];
   load4(w, n, base, x);
-  const int e_ref = 52 + WTraits<T>::BIAS - rec.scale;
+  // the block's scale is the same in every lane: keep it scalar, so that the
+  // 128-bit shifts below branch on it once instead of selecting per lane
+  const int32_t scale = (int32_t)__builtin_amdgcn_readfirstlane(rec.scale);
+  const int e_ref = 52 + WTraits<T>::BIAS - scale;
   uint64_t q[kPer];
   uint64_t acc = 0;
 #pragma unroll
@@ -165,7 +168,7 @@ __device__ void block_r(const T* __restrict__ w, int64_t n, int64_t base, const 
   }
   uint64_t tot;
   const uint64_t off = wg_exclusive(acc, s->u, &tot);
-  const int sh = gscale - rec.scale;
+  const int sh = (int32_t)__builtin_amdgcn_readfirstlane(gscale) - scale;
 #pragma unroll
   for (int v = 0; v < kPer; ++v) r[v] = rm(Cb + shift_u128((u128)(off + q[v]), sh));
 }

@@ -150,7 +150,7 @@ __device__ __forceinline__ RMap make_rmap(u128 Q, int64_t n) {
 // m = floor(r) when frac(r) >= 1 - u_m (both sides exact in binary64).
 __device__ __forceinline__ int64_t cum_strata(double r, int64_t n, double u) {
   const double mf = floor(r);
-  const int64_t m = (int64_t)mf;
+  const int64_t m = (int32_t)mf;  // 0 <= r <= n < 2^31: the 32-bit conversion is exact
   if (m >= n) return n;
   return m + (((r - mf) >= (1.0 - u)) ? 1 : 0);
 }
