@@ -83,9 +83,11 @@ def test_ragged_batch_full_size_sampled(batch):
         assert np.array_equal(ar[sl], oracle.rejection(seg, 1.0, seed=1, filt=f)[0]), f
 
 
-@pytest.mark.parametrize("scheme", ["systematic", "stratified"])
-def test_collective_2p22(scheme):
-    n = 1 << 22
+@pytest.mark.parametrize("scheme", ["systematic", "stratified", "multinomial"])
+@pytest.mark.parametrize("n", [1 << 22, (1 << 23) + 999])
+def test_collective_long_vectors(scheme, n):
+    """Long enough for the persistent, pipelined emission (several blocks per
+    workgroup), with a ragged last block."""
     w = inputs.weights(n, 3.0, seed=0)
     a = host(getattr(pfr(), "resample_" + scheme)(torch.from_numpy(w).cuda(), seed=5))
     check_collective(scheme, w.astype(np.float64), a, seed=5, filt=0)

@@ -53,6 +53,16 @@ def test_fused_equals_separate(scheme, n, y):
         assert np.array_equal(c, oracle.permute(a)[0])
 
 
+@pytest.mark.parametrize("scheme", ["stratified", "systematic"])
+def test_fused_long_vector_pipelined_emission(scheme):
+    n = (1 << 23) + 5
+    w = torch.from_numpy(inputs.weights(n, 1.0, seed=3)).cuda()
+    a, c = pfr().resample_permuted(scheme, w, seed=4)
+    a_ref, c_ref = separate(scheme, w, 4)
+    assert np.array_equal(host(a), a_ref)
+    assert np.array_equal(host(c), c_ref)
+
+
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 def test_fused_float64_and_table_path(dtype):
     n = 1 << 18
