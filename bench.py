@@ -608,6 +608,53 @@ def philox_workload(args):
                       "speed": sp10 + sp7, "quality": q10 + q7}), flush=True)
 
 
+def scaling_workload(args):
+    """The collective resamplers on one long vector, n = 2^20 .. 2^26 float32
+    weights (uniform on [0.01, 1.01), seed 0): device time of one call (median
+    of 5, the Infinity Cache flushed before each), particles/s and the HBM
+    fraction of the 8 algorithmic bytes per particle (read w, write a)."""
+    import torch
+    import paper_1301_4019_amd as pfr
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    g = torch.Generator(device=dev)
+    rows = []
+    for lg in args.scaling_log2n:
+        n = 1 << lg
+        g.manual_seed(0)
+        w = torch.rand(n, device=dev, dtype=torch.float32, generator=g) + 0.01
+        a = torch.empty(n, dtype=torch.int32, device=dev)
+        for s in ("multinomial", "stratified", "systematic"):
+            fn = getattr(pfr, "resample_" + s)
+            fn(w, seed=1, out=a, flags=flags)
+            ts = []
+            for r in range(5):
+                flush.fill_(r)
+                e0 = torch.cuda.Event(enable_timing=True)
+                e1 = torch.cuda.Event(enable_timing=True)
+                e0.record(stream)
+                fn(w, seed=1, out=a, flags=flags)
+                e1.record(stream)
+                e1.synchronize()
+                ts.append(e0.elapsed_time(e1) * 1e-3)
+            t = sorted(ts)[2]
+            rows.append({"log2n": lg, "scheme": s, "us": t * 1e6, "particles_per_s": n / t,
+                         "hbm_frac_8B_per_particle": 8.0 * n / t / (HBM_PEAK_GBS * 1e9)})
+            log(f"  n=2^{lg} {s:12s} {t * 1e6:9.1f} us  {n / t:.3e} particles/s  "
+                f"{100 * 8.0 * n / t / (HBM_PEAK_GBS * 1e9):.1f} % HBM")
+    if int(flags.cpu()[0]) != 0:
+        raise RuntimeError(f"data flags raised: {int(flags.cpu()[0])}")
+    print(json.dumps({"metric": "collective resamplers on one long vector", "unit": "particles/s",
+                      "higher_is_better": True, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "single vector, float32 weights U[0.01, 1.01), "
+                                             "n = 2^" + ",".join(map(str, args.scaling_log2n))},
+                      "rows": rows}), flush=True)
+
+
 def filter_workload(args):
     """Bootstrap filter on x_t = 0.9 x_{t-1} + N(0,1), y_t = x_t + N(0, 0.5^2):
     1024 filters of 2^14 particles, T = 200 synthetic observations (seed 0); one
@@ -674,14 +721,14 @@ def main():
                          "known traffic for scaling hardware byte counters")
     ap.add_argument("--cpu-sample", type=int, default=1 << 18)
     ap.add_argument("--workload", choices=("step", "precision", "batch", "filter", "decision",
-                                              "aux", "philox"),
+                                              "aux", "philox", "scaling"),
                     default="step",
                     help="step: the timed resampling step (default); precision: the bias "
                          "sweep over prefix-sum precision modes; batch: ragged batch of "
                          "4096 filters; filter: full bootstrap filter, 1024 x 2^14 x 200; "
                          "decision: fastest scheme per (N, y) and the Metropolis B*/C "
                          "trade-off; aux: the auxiliary exports; philox: 10 vs 7 Philox "
-                         "rounds")
+                         "rounds; scaling: collective schemes at n = 2^20..2^26")
     ap.add_argument("--filters", type=int, default=4096)
     ap.add_argument("--filters-ssm", type=int, default=1024)
     ap.add_argument("--filter-reps", type=int, default=3)
@@ -691,6 +738,7 @@ def main():
     ap.add_argument("--decision-reps", type=int, default=20)
     ap.add_argument("--tradeoff-log2n", type=int, nargs="+", default=[12, 16, 20])
     ap.add_argument("--forms-log2n", type=int, nargs="+", default=[10, 14, 18, 20, 22, 24])
+    ap.add_argument("--scaling-log2n", type=int, nargs="+", default=[20, 22, 24, 26])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the resampling step here runs on a single MI355X "
@@ -713,6 +761,9 @@ def main():
         return
     if args.workload == "philox":
         philox_workload(args)
+        return
+    if args.workload == "scaling":
+        scaling_workload(args)
         return
 
     import torch
