@@ -11,8 +11,10 @@ That is 25 resamples of 2^20 particles per step; inputs are resident in HBM
 before the timed region.
 
 Prints one JSON line: whole-step particles/s, the roofline of the dominant
-kernel measured with HIP events inside the timed steps, a per-scheme
-breakdown, and the CPU oracle timed on a bounded sample of the same workload.
+kernel measured with HIP events inside the timed steps, the HBM fraction of
+each scheme at n = 2^20, batched filters/s on the ragged 4096-vector batch
+(the metric's second part), a per-scheme breakdown, and the CPU oracle timed
+on a bounded sample of the same workload.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
 """
@@ -165,6 +167,64 @@ def _time_ms(fn, reps, torch):
         fn()
     torch.cuda.synchronize()
     return 1e3 * (time.perf_counter() - t0) / reps
+
+
+def batched_summary(torch, pfr, inputs, dev, stream, reps=5):
+    """Filters/s of each resampler on the ragged batch (4096 float32 vectors,
+    N_f = 2^(8+8v), y_f ~ U[0,4], seed 0), one launch sequence per call, HIP
+    events around `reps` calls; plus the per-filter binary64 systematic form
+    replayed from a captured graph."""
+    F = 4096
+    w_np, off_np, ys = inputs.ragged_batch(n_filters=F, seed=0)
+    total = int(off_np[-1])
+    max_len = int(np.diff(off_np).max())
+    w = torch.from_numpy(w_np).to(dev)
+    offsets = torch.from_numpy(off_np).to(dev)
+    B = torch.tensor([b_star(float(y)) for y in ys], dtype=torch.int32, device=dev)
+    a = torch.empty(total, dtype=torch.int32, device=dev)
+    flags = torch.zeros(1, dtype=torch.int32, device=dev)
+
+    def timed(fn):
+        fn()
+        e0 = torch.cuda.Event(enable_timing=True)
+        e1 = torch.cuda.Event(enable_timing=True)
+        e0.record(stream)
+        for _ in range(reps):
+            fn()
+        e1.record(stream)
+        e1.synchronize()
+        return e0.elapsed_time(e1) / reps
+
+    out = {}
+    for s in ("multinomial", "stratified", "systematic"):
+        fn = getattr(pfr, "resample_" + s)
+        for mode, prec in (("exact", pfr.SCAN_EXACT), ("comp_f32", pfr.SCAN_COMP_F32)):
+            ms = timed(lambda: fn(w, seed=1, precision=prec, offsets=offsets, max_len=max_len,
+                                  out=a, flags=flags))
+            out[f"{s}_{mode}"] = F / (ms * 1e-3)
+    out["metropolis"] = F / (1e-3 * timed(lambda: pfr.resample_metropolis(
+        w, 0, seed=1, B_per_filter=B, offsets=offsets, max_len=max_len, out=a)))
+    out["rejection"] = F / (1e-3 * timed(lambda: pfr.resample_rejection(
+        w, 1.0, seed=1, offsets=offsets, max_len=max_len, out=a, flags=flags)))
+    w64 = w.double()
+    views = [(w64[off_np[f]:off_np[f + 1]], a[off_np[f]:off_np[f + 1]]) for f in range(F)]
+
+    def per_filter():
+        for f, (wf, af) in enumerate(views):
+            pfr.resample_systematic(wf, seed=1, filter_base=f, precision=pfr.SCAN_F64, out=af,
+                                    flags=flags)
+
+    per_filter()
+    g = torch.cuda.CUDAGraph()
+    with torch.cuda.graph(g):
+        per_filter()
+    out["systematic_f64_per_filter_graph"] = F / (1e-3 * timed(g.replay))
+    if int(flags.cpu()[0]) != 0:
+        raise RuntimeError(f"data flags raised in the batch: {int(flags.cpu()[0])}")
+    return {"unit": "filters/s", "filters": F, "particles": total, "max_len": max_len,
+            "workload": "ragged batch: 4096 float32 weight vectors, N_f = 2^(8+8v), v ~ U[0,1), "
+                        "y_f ~ U[0,4] (seed 0); one launch sequence per resampler",
+            "filters_per_s": out}
 
 
 def batch_workload(args):
@@ -716,6 +776,8 @@ def main():
     ap.add_argument("--steps", type=int, default=20)
     ap.add_argument("--warmup", type=int, default=3)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-batched", action="store_true",
+                    help="skip the batched filters/s summary of the default workload")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of "
                          "known traffic for scaling hardware byte counters")
@@ -898,6 +960,14 @@ def main():
         breakdown[s] = rows
     log("breakdown done")
 
+    # the metric's second part: batched filters/s on the ragged batch of
+    # 4096 vectors (one launch per resampler; per-filter binary64 form beside)
+    batched = None
+    if not args.no_batched:
+        batched = batched_summary(torch, pfr, inputs, dev, stream, reps=5)
+        log("batched summary done")
+    hbm_2p20 = {s: max(r["hbm_frac_8B_per_particle"] for r in rows) for s, rows in breakdown.items()}
+
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
@@ -922,6 +992,8 @@ def main():
                    "n": N, "y": list(YS), "B": Bs, "resamples_per_step": len(YS) * len(SCHEMES)},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "hbm_frac_8B_per_particle_at_2p20": hbm_2p20,
+        "batched": batched,
         "breakdown": breakdown,
     }
     print(json.dumps(result), flush=True)
