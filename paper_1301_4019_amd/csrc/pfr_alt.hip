@@ -172,10 +172,10 @@ __global__ __launch_bounds__(THREADS) void k_metropolis_staged(
 // The bound is a power of two, 2^(cM - 127 - c4): cM is the largest bucket
 // code of the vector and c4 = min(15, cM - c) the 4-bit distance of the
 // bucket's code c, where 2^(c - 127) >= the bucket maximum.  Two buckets per
-// LDS byte: 128 KB cover 2^18 buckets.  The skip test compares
-// u * (a lower bound of w_k) with ub after scaling the product down by
-// (1 - 2^-50), which exceeds the rounding of the few products involved, so a
-// skipped step is one that the exact test rejects; the output is the same.
+// LDS byte: 128 KB cover 2^18 buckets.  The skip test compares the rounded
+// product u * (a lower bound of w_k) with ub with a margin of 2^-20 relative,
+// far above the product's rounding, so a skipped step is one that the exact
+// test rejects; the output is the same.
 constexpr int kTableBuckets = 1 << 18;  // nibbles in LDS (128 KB)
 constexpr int kTableThreads = 1024;
 constexpr int kCodeThreads = 256;
@@ -227,16 +227,23 @@ __global__ __launch_bounds__(kCodeThreads) void k_bound_codes(const T* __restric
 struct BoundTable {
   const uint8_t* nib;  // LDS, two 4-bit codes per byte
   int shift;
-  int cM;
-  bool usable;
-  __device__ __forceinline__ double ub(uint32_t j) const {
+  // high word of the binary64 bound 2^(cM - 127) of the largest bucket, or
+  // 0xFFFFFFFF when the table is unusable (no product exceeds it)
+  uint32_t hi_top;
+  __device__ __forceinline__ uint32_t c4(uint32_t j) const {
     const uint32_t b = j >> shift;
-    const uint32_t c4 = (nib[b >> 1] >> ((b & 1u) * 4u)) & 15u;
-    return ldexp(1.0, cM - 127 - (int)c4);
+    return __builtin_amdgcn_ubfe((uint32_t)nib[b >> 1], (b << 2) & 4u, 4u);
   }
-  // true when u * lb > ub(j), i.e. u * w_k > w_j for every w_k >= lb
+  // true when u * lb > ub(j) = 2^(cM - 127 - c4), i.e. u * w_k > w_j for every
+  // w_k >= lb.  The test reads only the high word of p = fl(u * lb) (the same
+  // product the exact accept test forms): high(p) > high(ub) means
+  // p >= ub (1 + 2^-20), and since p exceeds u * lb by at most a factor
+  // 1 + 2^-53, u * lb > ub follows.  Adding c4 << 20 to high(p) instead of
+  // subtracting it from the exponent of ub keeps the test to two integer
+  // instructions; neither side wraps (high(p) < 2^31).
   __device__ __forceinline__ bool rejects(double u, double lb, uint32_t j) const {
-    return usable & ((u * lb) * (1.0 - 0x1p-50) > ub(j));
+    const uint32_t hp = (uint32_t)((uint64_t)__double_as_longlong(u * lb) >> 32);
+    return hp + (c4(j) << 20) > hi_top;
   }
 };
 
@@ -271,8 +278,8 @@ __device__ BoundTable load_bound_table(const uint8_t* __restrict__ codes,
   BoundTable t;
   t.nib = nib;
   t.shift = shift;
-  t.cM = (int)cM;
-  t.usable = cM < 255u;
+  // 2^(cM - 127) has binary64 exponent field cM - 127 + 1023 = cM + 896
+  t.hi_top = cM < 255u ? (cM + 896u) << 20 : 0xFFFFFFFFu;
   return t;
 }
 
@@ -291,6 +298,8 @@ __global__ __launch_bounds__(kTableThreads) void k_metropolis_table(
   __shared__ uint32_t slot[kTableThreads / kWave];
   offset = counter_offset(key, offset);
   const BoundTable tab = load_bound_table(codes, wg_max, n_wg, nb, shift, nib, slot);
+  // n * sizeof(T) < 2^31 (checked by the launcher)
+  const __amdgpu_buffer_rsrc_t wv = buffer_view(w, (uint32_t)(n * (int64_t)sizeof(T)));
   const int64_t p0 = (int64_t)blockIdx.x * chunk;
   const int64_t p1 = p0 + chunk < n ? p0 + chunk : n;
   for (int64_t gb = p0 + threadIdx.x; gb < p1; gb += (int64_t)K * kTableThreads) {
@@ -333,15 +342,20 @@ __global__ __launch_bounds__(kTableThreads) void k_metropolis_table(
           for (int c = 0; c < K; ++c) {
             j[c] = index_draw(x[c][3 * q], x[c][3 * q + 1], (uint32_t)n);
             u[c] = u_accept(x[c][3 * q + 2]);
-            need[c] = live[c] && !tab.rejects(u[c], wk[c], j[c]);
-            v[c] = need[c] ? (double)w[j[c]] : 0.0;
+            // a dead chain (past the chunk end) runs a copy of chain gb and is not stored
+            need[c] = !tab.rejects(u[c], wk[c], j[c]);
           }
+          // the K gathers go out together; lanes with nothing to load read zero
+#pragma unroll
+          for (int c = 0; c < K; ++c)
+            v[c] = (double)buffer_gather<T>(wv, need[c] ? j[c] * (uint32_t)sizeof(T) : kNoLoad);
 #pragma unroll
           for (int c = 0; c < K; ++c) {
-            if (need[c] && accept_exact(u[c], wk[c], v[c])) {
-              k[c] = j[c];
-              wk[c] = v[c];
-            }
+            // selects, not a branch: the gathered value is used on every lane,
+            // so the gathers cannot be sunk into per-chain branches
+            const bool acc = need[c] & accept_exact(u[c], wk[c], v[c]);
+            k[c] = acc ? j[c] : k[c];
+            wk[c] = acc ? v[c] : wk[c];
           }
         }
       }
@@ -395,6 +409,8 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
                                      Key key, uint32_t offset, int32_t* __restrict__ a,
                                      uint32_t& my_flags, const BoundTable& tab) {
   const uint32_t lane = lane_id();
+  // table kernels: ws is a global vector of n * sizeof(T) < 2^31 bytes
+  const __amdgpu_buffer_rsrc_t wv = buffer_view(ws, TABLE ? n * (uint32_t)sizeof(T) : 0u);
   int64_t next = r0;  // wave-uniform: next particle of the range to hand out
   int64_t cur = -1;   // particle (global index) this lane works on
   uint32_t t = 0;     // its next trial
@@ -431,9 +447,10 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
         }
       } else {
         // the four trials' draws, then their table checks, then their weight
-        // loads issued together (a trial that needs no load re-reads the
-        // particle's own weight, a cache hit), then the decisions: one wait
-        // per pass instead of one per trial
+        // loads issued together, then the decisions: one wait per pass
+        // instead of one per trial.  A trial that needs no load reads nothing
+        // (table kernel: an out-of-range buffer offset) or re-reads the
+        // particle's own weight (staged kernels: an LDS read)
         uint32_t jq[kRejBatch];
         double uq[kRejBatch];
 #pragma unroll
@@ -448,7 +465,12 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
           live[q] = (t + (uint32_t)q < max_trials) & !(TABLE && tab.rejects(uq[q], wmax, jq[q]));
         double vq[kRejBatch];
 #pragma unroll
-        for (int q = 0; q < kRejBatch; ++q) vq[q] = (double)ws[live[q] ? jq[q] : i];
+        for (int q = 0; q < kRejBatch; ++q) {
+          if constexpr (TABLE)
+            vq[q] = (double)buffer_gather<T>(wv, live[q] ? jq[q] * (uint32_t)sizeof(T) : kNoLoad);
+          else
+            vq[q] = (double)ws[live[q] ? jq[q] : i];
+        }
         bool accq[kRejBatch];
 #pragma unroll
         for (int q = 0; q < kRejBatch; ++q) accq[q] = live[q] & accept_exact(uq[q], wmax, vq[q]);
@@ -674,7 +696,10 @@ TableGeom table_geom(int64_t n) {
 // that the table prologue pays off.
 template <typename T>
 bool use_table(int64_t n_total, uint32_t n_filters, int64_t max_len) {
+  // the table kernels gather through a buffer resource, whose byte range
+  // must stay below 2^31
   return n_filters == 1 && n_total >= (1 << 16) &&
+         n_total * (int64_t)sizeof(T) < ((int64_t)1 << 31) &&
          staged_capacity<T>(max_len, n_total, n_filters) == 0;
 }
 

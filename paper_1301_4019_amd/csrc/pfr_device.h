@@ -93,15 +93,38 @@ __device__ __forceinline__ uint32_t index_draw(uint32_t x0, uint32_t x1, uint32_
   return (uint32_t)__umul64hi(r, (uint64_t)n);
 }
 
-// Exact u * wk <= wj.  The product p = fl(u wk) and its rounding error e
-// (recovered exactly by one fused multiply-add) give u wk = p + e exactly;
-// since |e| is at most half an ulp of p, the comparison is decided by p unless
-// p == wj, in which case the sign of e decides.  Valid while u wk stays in the
-// normal range (always for float32 weights).
+// Exact u * wk <= wj.  One fused multiply-add forms u wk - wj exactly and
+// rounds it once; rounding to nearest keeps the sign and maps only zero to
+// zero as long as a nonzero difference exceeds 2^-1075.  It does whenever wk
+// and wj lie on the 2^-1042 lattice (u wk then lies on the 2^-1074 lattice):
+// every float32 weight, and binary64 weights from 2^-990 up (zero included).
 __device__ __forceinline__ bool accept_exact(double u, double wk, double wj) {
-  const double p = u * wk;
-  const double e = __fma_rn(u, wk, -p);
-  return (p < wj) || (p == wj && e <= 0.0);
+  return __fma_rn(u, wk, -wj) <= 0.0;
+}
+
+// ------------------------------------------------------------------ buffer gathers
+// A raw buffer resource over [base, base + bytes) (bytes below 2^31).  A load
+// at a byte offset at or beyond `bytes` is dropped by the range check and
+// returns zero without touching memory, so a wave can issue one gather for
+// all lanes, without a branch, while only the lanes that need a value read
+// one: the others pass kNoLoad.  Several such gathers are then in flight at
+// once and a single wait covers them.
+constexpr uint32_t kNoLoad = 0x80000000u;
+__device__ __forceinline__ __amdgpu_buffer_rsrc_t buffer_view(const void* base, uint32_t bytes) {
+  // 0x00020000: 32-bit data format, the setting for untyped loads on gfx9
+  return __builtin_amdgcn_make_buffer_rsrc(const_cast<void*>(base), 0, (int)bytes, 0x00020000);
+}
+template <typename T>
+__device__ __forceinline__ T buffer_gather(__amdgpu_buffer_rsrc_t r, uint32_t byte_off);
+template <>
+__device__ __forceinline__ float buffer_gather<float>(__amdgpu_buffer_rsrc_t r, uint32_t byte_off) {
+  return __builtin_bit_cast(float, __builtin_amdgcn_raw_buffer_load_b32(r, (int)byte_off, 0, 0));
+}
+template <>
+__device__ __forceinline__ double buffer_gather<double>(__amdgpu_buffer_rsrc_t r,
+                                                        uint32_t byte_off) {
+  const auto v = __builtin_amdgcn_raw_buffer_load_b64(r, (int)byte_off, 0, 0);
+  return __builtin_bit_cast(double, ((uint64_t)v[1] << 32) | v[0]);
 }
 
 // ------------------------------------------------------------------ wave64
