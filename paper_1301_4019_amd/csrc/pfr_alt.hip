@@ -230,9 +230,11 @@ struct BoundTable {
   // high word of the binary64 bound 2^(cM - 127) of the largest bucket, or
   // 0xFFFFFFFF when the table is unusable (no product exceeds it)
   uint32_t hi_top;
+  // bucket b = j >> shift sits in byte b >> 1, low nibble for even b; the
+  // nibble's bit offset 4 (b & 1) is bit `shift` of j moved to bit 2
+  // (shift >= 2)
   __device__ __forceinline__ uint32_t c4(uint32_t j) const {
-    const uint32_t b = j >> shift;
-    return __builtin_amdgcn_ubfe((uint32_t)nib[b >> 1], (b << 2) & 4u, 4u);
+    return __builtin_amdgcn_ubfe((uint32_t)nib[j >> (shift + 1)], (j >> (shift - 2)) & 4u, 4u);
   }
   // true when u * lb > ub(j) = 2^(cM - 127 - c4), i.e. u * w_k > w_j for every
   // w_k >= lb.  The test reads only the high word of p = fl(u * lb) (the same
@@ -402,7 +404,7 @@ __device__ __forceinline__ int nth_set_bit(uint64_t mask, int q) {
 // segment (weights ws, length n, filter id filt).
 // With TABLE, a trial whose u * w_max exceeds the bucket bound of j is
 // rejected without loading w_j.
-constexpr int kRejBatch = 4;  // trials per lane and pass after trial 0
+constexpr int kRejBatch = 4;  // trials per lane and pass (past the first pass)
 template <bool TABLE, typename T>
 __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint32_t filt,
                                      double wmax, int64_t r0, int64_t r1, uint32_t max_trials,
@@ -415,8 +417,13 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
   int64_t cur = -1;   // particle (global index) this lane works on
   uint32_t t = 0;     // its next trial
 
-  // main phase: trial 0 (j = i) alone, then four trials per lane and pass,
-  // of which the lowest accepting one counts (as if they ran one by one)
+  // main phase: each pass tries trials t .. t + nq - 1 of every lane's
+  // particle, of which the lowest accepting one counts (as if they ran one by
+  // one).  nq is the same on every lane: 1 while every busy lane is at trial
+  // 0 (the first pass, where a likely acceptance makes speculation wasteful),
+  // 4 as soon as one busy lane is past it.  A lane that takes a new particle
+  // in a 4-trial pass starts it with trials 0..3, trial 0 proposing j = i, so
+  // the wave never runs two code paths in one pass.
   while (true) {
     const uint64_t freem = ballot(cur < 0);
     if (freem != 0 && next < r1) {
@@ -431,92 +438,116 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
       next += take;
     }
     if (next >= r1) break;
+    const int nq = ballot(cur >= 0 && t != 0) == 0 ? 1 : kRejBatch;
     if (cur >= 0) {
       const uint32_t i = (uint32_t)(cur - base);
-      if (t == 0) {
-        const uint4 x = draw(key, i, DOM_TRIAL, 0, filt, offset);
-        const double u = u_accept(x.z);
-        const bool skip = TABLE && tab.rejects(u, wmax, i);
-        if (!skip && accept_exact(u, wmax, (double)ws[i])) {
-          a[cur] = (int32_t)i;
-          cur = -1;
-        } else if (++t >= max_trials) {
+      // the trials' draws, then their table checks, then their weight loads
+      // issued together, then the decisions: one wait per pass instead of one
+      // per trial.  A trial that needs no load reads nothing (table kernel: an
+      // out-of-range buffer offset) or re-reads the particle's own weight
+      // (staged kernels: an LDS read)
+      uint32_t jq[kRejBatch];
+      double uq[kRejBatch];
+      bool live[kRejBatch];
+#pragma unroll
+      for (int q = 0; q < kRejBatch; ++q) {
+        live[q] = false;
+        jq[q] = i;
+        uq[q] = 1.0;
+        if (q < nq) {
+          const uint4 x = draw(key, i, DOM_TRIAL, t + (uint32_t)q, filt, offset);
+          jq[q] = (q == 0 && t == 0) ? i : index_draw(x.x, x.y, n);
+          uq[q] = u_accept(x.z);
+          live[q] = (t + (uint32_t)q < max_trials) & !(TABLE && tab.rejects(uq[q], wmax, jq[q]));
+        }
+      }
+      double vq[kRejBatch];
+#pragma unroll
+      for (int q = 0; q < kRejBatch; ++q) {
+        if constexpr (TABLE)
+          vq[q] = (double)buffer_gather<T>(wv, live[q] ? jq[q] * (uint32_t)sizeof(T) : kNoLoad);
+        else
+          vq[q] = (double)ws[live[q] ? jq[q] : i];
+      }
+      bool accq[kRejBatch];
+#pragma unroll
+      for (int q = 0; q < kRejBatch; ++q) accq[q] = live[q] & accept_exact(uq[q], wmax, vq[q]);
+      int first = -1;
+#pragma unroll
+      for (int q = kRejBatch - 1; q >= 0; --q)
+        if (accq[q]) first = q;
+      if (first >= 0) {
+        uint32_t jsel = jq[0];
+#pragma unroll
+        for (int q = 1; q < kRejBatch; ++q)
+          if (q == first) jsel = jq[q];
+        a[cur] = (int32_t)jsel;
+        cur = -1;
+      } else {
+        t += (uint32_t)nq;
+        if (t >= max_trials) {
           a[cur] = (int32_t)i;
           my_flags |= FLAG_TRIAL_CAP;
           cur = -1;
-        }
-      } else {
-        // the four trials' draws, then their table checks, then their weight
-        // loads issued together, then the decisions: one wait per pass
-        // instead of one per trial.  A trial that needs no load reads nothing
-        // (table kernel: an out-of-range buffer offset) or re-reads the
-        // particle's own weight (staged kernels: an LDS read)
-        uint32_t jq[kRejBatch];
-        double uq[kRejBatch];
-#pragma unroll
-        for (int q = 0; q < kRejBatch; ++q) {
-          const uint4 x = draw(key, i, DOM_TRIAL, t + (uint32_t)q, filt, offset);
-          jq[q] = index_draw(x.x, x.y, n);
-          uq[q] = u_accept(x.z);
-        }
-        bool live[kRejBatch];
-#pragma unroll
-        for (int q = 0; q < kRejBatch; ++q)
-          live[q] = (t + (uint32_t)q < max_trials) & !(TABLE && tab.rejects(uq[q], wmax, jq[q]));
-        double vq[kRejBatch];
-#pragma unroll
-        for (int q = 0; q < kRejBatch; ++q) {
-          if constexpr (TABLE)
-            vq[q] = (double)buffer_gather<T>(wv, live[q] ? jq[q] * (uint32_t)sizeof(T) : kNoLoad);
-          else
-            vq[q] = (double)ws[live[q] ? jq[q] : i];
-        }
-        bool accq[kRejBatch];
-#pragma unroll
-        for (int q = 0; q < kRejBatch; ++q) accq[q] = live[q] & accept_exact(uq[q], wmax, vq[q]);
-        int first = -1;
-#pragma unroll
-        for (int q = kRejBatch - 1; q >= 0; --q)
-          if (accq[q]) first = q;
-        if (first >= 0) {
-          uint32_t jsel = jq[0];
-#pragma unroll
-          for (int q = 1; q < kRejBatch; ++q)
-            if (q == first) jsel = jq[q];
-          a[cur] = (int32_t)jsel;
-          cur = -1;
-        } else {
-          t += kRejBatch;
-          if (t >= max_trials) {
-            a[cur] = (int32_t)i;
-            my_flags |= FLAG_TRIAL_CAP;
-            cur = -1;
-          }
         }
       }
     }
   }
 
-  // tail phase: the remaining particles share the wave's lanes
+  // tail phase: the remaining particles share the wave's lanes.  Each gets
+  // slot = 64 / m lanes (m = particles left); lane r of a particle's group
+  // tries its trials t + tb r .. t + tb r + tb - 1, so a pass covers trials
+  // t .. t + slot tb - 1 of every particle, and the lowest accepting one wins
+  // (the lowest lane of the group with an acceptance, and its lowest trial).
+  // tb is 4 once some particle is past its first four trials (acceptance is
+  // then unlikely, and four trials share one pass's overhead), else 1.
   while (true) {
     const uint64_t act = ballot(cur >= 0);
     if (act == 0) break;
+    const int tb = ballot(cur >= 0 && t >= (uint32_t)kRejBatch) != 0 ? kRejBatch : 1;
     const int m = __popcll(act);
     const int slot = kWave / m;  // lanes per particle
-    const int q = (int)lane / slot;
-    const bool helper = q < m;
-    const int owner = helper ? nth_set_bit(act, q) : (int)lane;
+    const int grp = (int)lane / slot;
+    const bool helper = grp < m;
+    const int owner = helper ? nth_set_bit(act, grp) : (int)lane;
     const int64_t o_cur = shfl(cur, owner);
     const uint32_t o_t = shfl(t, owner);
-    const uint32_t tt = o_t + (lane - (uint32_t)(q * slot));
+    const uint32_t t0 = o_t + (uint32_t)tb * (lane - (uint32_t)(grp * slot));
     bool acc = false;
     uint32_t jj = 0;
-    if (helper && tt < max_trials) {
+    if (helper) {
       const uint32_t i = (uint32_t)(o_cur - base);
-      const uint4 x = draw(key, i, DOM_TRIAL, tt, filt, offset);
-      jj = (tt == 0) ? i : index_draw(x.x, x.y, n);
-      const double u = u_accept(x.z);
-      acc = !(TABLE && tab.rejects(u, wmax, jj)) && accept_exact(u, wmax, (double)ws[jj]);
+      uint32_t jb[kRejBatch];
+      double ub[kRejBatch];
+      bool live[kRejBatch];
+#pragma unroll
+      for (int b = 0; b < kRejBatch; ++b) {
+        live[b] = false;
+        jb[b] = i;
+        ub[b] = 1.0;
+        if (b < tb) {
+          const uint32_t tt = t0 + (uint32_t)b;  // < 2^28 + 256: no wrap
+          const uint4 x = draw(key, i, DOM_TRIAL, tt, filt, offset);
+          jb[b] = (tt == 0) ? i : index_draw(x.x, x.y, n);
+          ub[b] = u_accept(x.z);
+          live[b] = (tt < max_trials) & !(TABLE && tab.rejects(ub[b], wmax, jb[b]));
+        }
+      }
+      double vb[kRejBatch];
+#pragma unroll
+      for (int b = 0; b < kRejBatch; ++b) {
+        if constexpr (TABLE)
+          vb[b] = (double)buffer_gather<T>(wv, live[b] ? jb[b] * (uint32_t)sizeof(T) : kNoLoad);
+        else
+          vb[b] = (double)ws[live[b] ? jb[b] : i];
+      }
+#pragma unroll
+      for (int b = kRejBatch - 1; b >= 0; --b) {
+        if (live[b] & accept_exact(ub[b], wmax, vb[b])) {
+          acc = true;
+          jj = jb[b];
+        }
+      }
     }
     const uint64_t accm = ballot(acc);
     int src = (int)lane;
@@ -533,7 +564,7 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
         a[cur] = (int32_t)jsel;
         cur = -1;
       } else {
-        t += (uint32_t)slot;
+        t += (uint32_t)(slot * tb);
         if (t >= max_trials) {
           a[cur] = (int32_t)(cur - base);
           my_flags |= FLAG_TRIAL_CAP;
@@ -682,7 +713,7 @@ struct TableGeom {
 
 TableGeom table_geom(int64_t n) {
   TableGeom g;
-  g.shift = 2;
+  g.shift = 2;  // at least 4 particles per bucket (BoundTable::c4 needs shift >= 2)
   while ((((n - 1) >> g.shift) + 1) > kTableBuckets) ++g.shift;
   g.nb = (uint32_t)(((n - 1) >> g.shift) + 1);
   g.n_wg = (g.nb + kCodeThreads - 1) / kCodeThreads;
