@@ -53,7 +53,12 @@ GATHER_CEILING_PER_S = 2.65e11
 # HBM bytes per launch of the dominant kernel (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from
 # two rocprofv3 --pmc passes, scaled by a 256 MiB copy; profiles/metropolis_table_n2p20_pmc.md).
 # Set to None when the kernel changes until the counters are taken again.
-DOMINANT_TRAFFIC_BYTES = (43.0 + 4.0) * (1 << 20)
+DOMINANT_TRAFFIC_BYTES = (43.5 + 4.0) * (1 << 20)
+# VALU instructions per lane and Metropolis step of the dominant kernel (SQ_INSTS_VALU x 64 /
+# steps, same profile; None when the kernel changes), against the lane-instruction rate of
+# 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz.
+DOMINANT_VALU_PER_STEP = 49.3
+LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
 
 
 def metropolis_calls_per_lane(B):
@@ -915,9 +920,15 @@ def main():
     roofline = {"bound": "alu", "kernel": f"Metropolis resample (y=4, B={B_dom})",
                 "achieved": achieved / 1e9, "peak": PHILOX_PEAK_PER_S / 1e9,
                 "unit": "G Philox4x32-10 calls/s", "frac": achieved / PHILOX_PEAK_PER_S,
-                "limiter": f"random weight loads: {gathers / 1e9:.0f} G/s of steps, "
-                           f"{gathers / GATHER_CEILING_PER_S:.2f} of the "
-                           f"{GATHER_CEILING_PER_S / 1e9:.0f} G/s a plain gather kernel reaches",
+                "limiter": (f"VALU instruction count: {gathers / 1e9:.0f} G steps/s x "
+                            f"{DOMINANT_VALU_PER_STEP} VALU per step = "
+                            f"{gathers * DOMINANT_VALU_PER_STEP / LANE_INSTR_PER_S:.2f} of the "
+                            f"lane-instruction rate at 2.4 GHz (30 of the {DOMINANT_VALU_PER_STEP} "
+                            f"are Philox); the steps run at "
+                            f"{gathers / GATHER_CEILING_PER_S:.2f} x the "
+                            f"{GATHER_CEILING_PER_S / 1e9:.0f} G/s of a plain gather kernel, "
+                            f"the bound table skipping two thirds of the weight loads")
+                           if DOMINANT_VALU_PER_STEP else None,
                 "traffic": DOMINANT_TRAFFIC_BYTES, "traffic_unit": "bytes per launch",
                 "algorithmic_bytes": 8.0 * N, "avg_launch_ms": dom_ms}
 

@@ -419,11 +419,12 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
 
   // main phase: each pass tries trials t .. t + nq - 1 of every lane's
   // particle, of which the lowest accepting one counts (as if they ran one by
-  // one).  nq is the same on every lane: 1 while every busy lane is at trial
-  // 0 (the first pass, where a likely acceptance makes speculation wasteful),
-  // 4 as soon as one busy lane is past it.  A lane that takes a new particle
-  // in a 4-trial pass starts it with trials 0..3, trial 0 proposing j = i, so
-  // the wave never runs two code paths in one pass.
+  // one).  nq is the same on every lane, so the wave never runs two code
+  // paths in one pass (a particle's trial 0 proposes j = i): 4 while the
+  // wave's acceptance rate so far is below 1/2 (long runs of rejections,
+  // where four trials share one pass's overhead), else 1 (acceptance is
+  // likely and further trials would be wasted draws and loads).
+  uint64_t tried = 0, accepted = 0;  // wave-uniform counts of this range
   while (true) {
     const uint64_t freem = ballot(cur < 0);
     if (freem != 0 && next < r1) {
@@ -438,7 +439,9 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
       next += take;
     }
     if (next >= r1) break;
-    const int nq = ballot(cur >= 0 && t != 0) == 0 ? 1 : kRejBatch;
+    const int nq = accepted * 2u < tried ? kRejBatch : 1;  // (results do not depend on nq)
+    const uint64_t busy = ballot(cur >= 0);
+    bool won = false;
     if (cur >= 0) {
       const uint32_t i = (uint32_t)(cur - base);
       // the trials' draws, then their table checks, then their weight loads
@@ -483,6 +486,7 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
           if (q == first) jsel = jq[q];
         a[cur] = (int32_t)jsel;
         cur = -1;
+        won = true;
       } else {
         t += (uint32_t)nq;
         if (t >= max_trials) {
@@ -492,6 +496,8 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
         }
       }
     }
+    tried += (uint64_t)nq * (uint64_t)__popcll(busy);
+    accepted += (uint64_t)__popcll(ballot(won));
   }
 
   // tail phase: the remaining particles share the wave's lanes.  Each gets
@@ -499,12 +505,12 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
   // tries its trials t + tb r .. t + tb r + tb - 1, so a pass covers trials
   // t .. t + slot tb - 1 of every particle, and the lowest accepting one wins
   // (the lowest lane of the group with an acceptance, and its lowest trial).
-  // tb is 4 once some particle is past its first four trials (acceptance is
-  // then unlikely, and four trials share one pass's overhead), else 1.
+  // tb follows the wave's acceptance rate as nq does (the counts go on in
+  // the tail, which is all there is when the range is shorter than a wave).
   while (true) {
     const uint64_t act = ballot(cur >= 0);
     if (act == 0) break;
-    const int tb = ballot(cur >= 0 && t >= (uint32_t)kRejBatch) != 0 ? kRejBatch : 1;
+    const int tb = accepted * 2u < tried ? kRejBatch : 1;
     const int m = __popcll(act);
     const int slot = kWave / m;  // lanes per particle
     const int grp = (int)lane / slot;
@@ -559,10 +565,12 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
       if (g) src = __ffsll((long long)g) - 1;
     }
     const uint32_t jsel = shfl(jj, src);
+    bool won = false;
     if (cur >= 0) {
       if (g) {
         a[cur] = (int32_t)jsel;
         cur = -1;
+        won = true;
       } else {
         t += (uint32_t)(slot * tb);
         if (t >= max_trials) {
@@ -572,6 +580,8 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
         }
       }
     }
+    tried += (uint64_t)(m * slot * tb);
+    accepted += (uint64_t)__popcll(ballot(won));
   }
 }
 
