@@ -56,15 +56,16 @@ struct ScanHeader {
 static_assert(sizeof(ScanHeader) == 256, "scan header is 256 bytes");
 
 struct ScanLayout {
-  size_t recs, carries, erecs, ecarries, total;
+  size_t recs, carries, erecs, ecarries, evals, total;
 };
 ScanLayout scan_layout(int64_t n, bool multinomial);
 
 // Workspace of a block-parallel batch (exact prefix): block prefixes per
-// segment, one record per weight block, one sum per exponential block.
+// segment, one record per weight block, one sum per exponential block and
+// (multinomial) the quantised spacings of every exponential block.
 struct SegLayout {
   uint32_t grid_b, grid_e;  // launch bounds on the block counts
-  size_t bstart, estart, recs, esums, carries, ecarries, hdr, total;
+  size_t bstart, estart, recs, esums, carries, ecarries, hdr, evals, total;
 };
 SegLayout seg_layout(int64_t n_total, uint32_t n_filters, bool multinomial);
 hipError_t launch_scan_segmented(int scheme, bool f64, const void* w, int64_t n_total,

@@ -180,7 +180,8 @@ __device__ void emit_block(const T* __restrict__ w, int64_t n, uint32_t b, const
                            uint32_t filter, uint32_t offset, CEPtr CE, uint32_t nbe,
                            int32_t* __restrict__ a_out, EmitLds* L, WgScratch* s,
                            int32_t* __restrict__ d_out = nullptr,
-                           int32_t* __restrict__ e_out = nullptr) {
+                           int32_t* __restrict__ e_out = nullptr,
+                           const uint64_t* __restrict__ evals = nullptr) {
   const int64_t P0 = (int64_t)b * kBlock;
   const int cnt = (int)min((int64_t)kBlock, n - P0);
   const double r_lo = rm(Cb);
@@ -192,7 +193,7 @@ __device__ void emit_block(const T* __restrict__ w, int64_t n, uint32_t b, const
     for (int v = 0; v < kPer; ++v) L->mu.r[threadIdx.x * kPer + v] = r[v];
     __syncthreads();
     emit_multinomial(L->mu.r, cnt, r_lo, r_hi, P0 + cnt == n, n, P0, key, filter, offset, CE, nbe,
-                     a_out, s);
+                     a_out, s, evals);
   } else {
     const uint32_t u_sys =
         SCHEME == SCHEME_SYSTEMATIC ? draw(key, 0, DOM_STRATA, 0, filter, offset).x : 0u;
@@ -204,14 +205,16 @@ __device__ void emit_block(const T* __restrict__ w, int64_t n, uint32_t b, const
 
 // ---------------------------------------------------------------- kernels
 // One record per weight block (and, for the multinomial scheme, one sum per
-// exponential block).  No cross-workgroup communication: the kernel boundary
-// makes the records visible to the next kernel.
+// exponential block, whose quantised spacings are kept in `evals` for the
+// emission).  No cross-workgroup communication: the kernel boundary makes the
+// records visible to the next kernel.
 template <typename T, bool MULTI>
 __global__ __launch_bounds__(kT) void k_scan_records(const T* __restrict__ w, int64_t n,
                                                      uint32_t nb, Key key, uint32_t offset,
                                                      uint32_t filter,
                                                      BlockRec* __restrict__ recs,
-                                                     uint64_t* __restrict__ esums) {
+                                                     uint64_t* __restrict__ esums,
+                                                     uint64_t* __restrict__ evals) {
   offset = counter_offset(key, offset);
   __shared__ WgScratch s;
   if (blockIdx.x < nb) {
@@ -221,6 +224,7 @@ __global__ __launch_bounds__(kT) void k_scan_records(const T* __restrict__ w, in
     const uint32_t b = blockIdx.x - nb;
     uint64_t q[kPer];
     exp_values(key, filter, offset, n, b, q);
+    store_exp_values(evals, b, q);
     const uint64_t sum = wg_reduce(q[0] + q[1] + q[2] + q[3], OpAdd(), s.u);
     if (threadIdx.x == 0) esums[b] = sum;
   }
@@ -306,7 +310,8 @@ __global__ __launch_bounds__(kT) void k_scan_emit(const T* __restrict__ w, int64
                                                   int32_t* __restrict__ a,
                                                   uint32_t* __restrict__ flags,
                                                   int32_t* __restrict__ d_out,
-                                                  int32_t* __restrict__ e_out) {
+                                                  int32_t* __restrict__ e_out,
+                                                  const uint64_t* __restrict__ evals) {
   offset = counter_offset(key, offset);
   __shared__ EmitLds L;
   __shared__ WgScratch s;
@@ -343,7 +348,7 @@ __global__ __launch_bounds__(kT) void k_scan_emit(const T* __restrict__ w, int64
   }
   const RMap rm = make_rmap(Q, n);
   emit_block<T, SCHEME>(w, n, b, recs[b], Cb, Cb1, gscale, rm, key, filter, offset, CE, nbe, a,
-                        &L, &s, d_out, e_out);
+                        &L, &s, d_out, e_out, evals);
 }
 
 // ---------------------------------------------------------------- Code 5
@@ -544,7 +549,7 @@ __global__ __launch_bounds__(kT) void k_seg_records(
     const T* __restrict__ w, const int64_t* __restrict__ offsets, uint32_t n_filters,
     uint32_t grid_b, Key key, uint32_t offset, uint32_t filter_base,
     const uint32_t* __restrict__ bstart, const uint32_t* __restrict__ estart,
-    BlockRec* __restrict__ recs, uint64_t* __restrict__ esums) {
+    BlockRec* __restrict__ recs, uint64_t* __restrict__ esums, uint64_t* __restrict__ evals) {
   __shared__ WgScratch s;
   offset = counter_offset(key, offset);
   if (blockIdx.x < grid_b) {
@@ -562,6 +567,7 @@ __global__ __launch_bounds__(kT) void k_seg_records(
     const int64_t n = offsets[f + 1] - offsets[f];
     uint64_t q[kPer];
     exp_values(key, filter_base + f, offset, n, g - estart[f], q);
+    store_exp_values(evals, g, q);  // global block g = segment block g - estart[f]
     const uint64_t sum = wg_reduce(q[0] + q[1] + q[2] + q[3], OpAdd(), s.u);
     if (threadIdx.x == 0) esums[g] = sum;
   }
@@ -608,7 +614,7 @@ __global__ __launch_bounds__(kT) void k_seg_emit(
     uint32_t offset, uint32_t filter_base, const uint32_t* __restrict__ bstart,
     const uint32_t* __restrict__ estart, const BlockRec* __restrict__ recs,
     const u128* __restrict__ C, const u128* __restrict__ CE, const SegHdr* __restrict__ hdr,
-    int32_t* __restrict__ a, uint32_t* __restrict__ flags) {
+    int32_t* __restrict__ a, uint32_t* __restrict__ flags, const uint64_t* __restrict__ evals) {
   __shared__ EmitLds L;
   __shared__ WgScratch s;
   offset = counter_offset(key, offset);
@@ -630,8 +636,10 @@ __global__ __launch_bounds__(kT) void k_seg_emit(
   const uint32_t nbe = SCHEME == SCHEME_MULTINOMIAL ? estart[f + 1] - estart[f] : 0u;
   const u128* CEs = SCHEME == SCHEME_MULTINOMIAL ? CE + estart[f] + f : CE;
   const RMap rm = make_rmap(hdr[f].Q, n);
+  const uint64_t* evs =
+      SCHEME == SCHEME_MULTINOMIAL ? evals + (size_t)estart[f] * kBlock : nullptr;
   emit_block<T, SCHEME>(w + base, n, b, recs[g], Cs[b], Cs[b + 1], hdr[f].gscale, rm, key,
-                        filter_base + f, offset, CEs, nbe, as, &L, &s);
+                        filter_base + f, offset, CEs, nbe, as, &L, &s, nullptr, nullptr, evs);
 }
 
 template <typename T, int SCHEME>
@@ -647,15 +655,17 @@ hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, ui
   u128* C = (u128*)(base + L.carries);
   uint64_t* esums = (uint64_t*)(base + L.erecs);
   u128* CE = (u128*)(base + L.ecarries);
+  uint64_t* evals = multi ? (uint64_t*)(base + L.evals) : nullptr;
   const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
   const uint32_t nbe = multi ? (uint32_t)((n + 1 + kBlock - 1) / kBlock) : 0u;
   hipLaunchKernelGGL((k_scan_records<T, multi>), dim3(nb + nbe), dim3(kT), 0, stream, w, n, nb,
-                     key, offset, filter, recs, esums);
+                     key, offset, filter, recs, esums, evals);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if (!multi && nb <= (uint32_t)tuning().direct_max_blocks && nb <= kDirectMax) {
     hipLaunchKernelGGL((k_scan_emit<T, SCHEME, true>), dim3(nb), dim3(kT), 0, stream, w, n, nb,
-                       nbe, key, offset, filter, hdr, recs, C, CE, a, flags, d_out, e_out);
+                       nbe, key, offset, filter, hdr, recs, C, CE, a, flags, d_out, e_out,
+                       (const uint64_t*)evals);
     return hipGetLastError();
   }
   hipLaunchKernelGGL((k_scan_carries<multi>), dim3(1), dim3(kT), 0, stream, nb, nbe, hdr, recs,
@@ -663,7 +673,8 @@ hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, ui
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_scan_emit<T, SCHEME, false>), dim3(nb), dim3(kT), 0, stream, w, n, nb,
-                     nbe, key, offset, filter, hdr, recs, C, CE, a, flags, d_out, e_out);
+                     nbe, key, offset, filter, hdr, recs, C, CE, a, flags, d_out, e_out,
+                     (const uint64_t*)evals);
   return hipGetLastError();
 }
 
@@ -718,13 +729,14 @@ hipError_t launch_segmented_t(const T* w, int64_t n_total, const int64_t* offset
   uint32_t* estart = multi ? (uint32_t*)(base + L.estart) : nullptr;
   BlockRec* recs = (BlockRec*)(base + L.recs);
   uint64_t* esums = (uint64_t*)(base + L.esums);
+  uint64_t* evals = multi ? (uint64_t*)(base + L.evals) : nullptr;
   hipLaunchKernelGGL(k_seg_prefix, dim3(1), dim3(kT), 0, stream, offsets, n_filters, bstart,
                      estart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_seg_records<T, multi>), dim3(L.grid_b + (multi ? L.grid_e : 0u)),
                      dim3(kT), 0, stream, w, offsets, n_filters, L.grid_b, key, offset,
-                     filter_base, bstart, estart, recs, esums);
+                     filter_base, bstart, estart, recs, esums, evals);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   u128* C = (u128*)(base + L.carries);
@@ -736,7 +748,7 @@ hipError_t launch_segmented_t(const T* w, int64_t n_total, const int64_t* offset
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL((k_seg_emit<T, SCHEME>), dim3(L.grid_b), dim3(kT), 0, stream, w, offsets,
                      n_filters, key, offset, filter_base, bstart, estart, recs, C, CE, hdr, a,
-                     flags);
+                     flags, (const uint64_t*)evals);
   return hipGetLastError();
 }
 
@@ -774,7 +786,8 @@ SegLayout seg_layout(int64_t n_total, uint32_t n_filters, bool multinomial) {
   L.ecarries = L.carries + align256(((size_t)L.grid_b + n_filters) * sizeof(u128));
   L.hdr = L.ecarries +
           (multinomial ? align256(((size_t)L.grid_e + n_filters) * sizeof(u128)) : 0);
-  L.total = L.hdr + align256((size_t)n_filters * sizeof(SegHdr));
+  L.evals = L.hdr + align256((size_t)n_filters * sizeof(SegHdr));
+  L.total = L.evals + (multinomial ? align256((size_t)L.grid_e * kBlock * sizeof(uint64_t)) : 0);
   return L;
 }
 
@@ -796,7 +809,8 @@ ScanLayout scan_layout(int64_t n, bool multinomial) {
   L.carries = L.recs + align256(nb * sizeof(BlockRec));
   L.erecs = L.carries + align256((nb + 1) * sizeof(u128));
   L.ecarries = L.erecs + align256(nbe * sizeof(uint64_t));
-  L.total = L.ecarries + align256((nbe + 1) * sizeof(u128));
+  L.evals = L.ecarries + align256((nbe + 1) * sizeof(u128));
+  L.total = L.evals + align256(nbe * kBlock * sizeof(uint64_t));
   return L;
 }
 
@@ -825,7 +839,7 @@ hipError_t launch_multinomial_iid_t(const T* w, int64_t n, Key key, uint32_t off
   double* r = (double*)(base + L.total);
   const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
   hipLaunchKernelGGL((k_scan_records<T, false>), dim3(nb), dim3(kT), 0, stream, w, n, nb, key,
-                     offset, filter, recs, (uint64_t*)nullptr);
+                     offset, filter, recs, (uint64_t*)nullptr, (uint64_t*)nullptr);
   hipLaunchKernelGGL((k_scan_carries<false>), dim3(1), dim3(kT), 0, stream, nb, 0u, hdr, recs,
                      (const uint64_t*)nullptr, C, (u128*)nullptr);
   hipLaunchKernelGGL((k_scan_r<T>), dim3(nb), dim3(kT), 0, stream, w, n, hdr, recs, C, r);

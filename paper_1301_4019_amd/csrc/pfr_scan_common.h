@@ -93,6 +93,25 @@ __device__ __forceinline__ void exp_values(Key key, uint32_t filter, uint32_t of
   }
 }
 
+// The four quantised spacings of thread t in block b, stored by the records
+// pass at evals[b kBlock + 4 t ..] (32-byte aligned).
+__device__ __forceinline__ void store_exp_values(uint64_t* __restrict__ evals, uint32_t blk,
+                                                 const uint64_t (&q)[kPer]) {
+  ulonglong2* p = reinterpret_cast<ulonglong2*>(evals + (size_t)blk * kBlock + threadIdx.x * kPer);
+  p[0] = make_ulonglong2(q[0], q[1]);
+  p[1] = make_ulonglong2(q[2], q[3]);
+}
+__device__ __forceinline__ void load_exp_values(const uint64_t* __restrict__ evals, uint32_t blk,
+                                                uint64_t (&q)[kPer]) {
+  const ulonglong2* p =
+      reinterpret_cast<const ulonglong2*>(evals + (size_t)blk * kBlock + threadIdx.x * kPer);
+  const ulonglong2 v0 = p[0], v1 = p[1];
+  q[0] = v0.x;
+  q[1] = v0.y;
+  q[2] = v1.x;
+  q[3] = v1.y;
+}
+
 __device__ __forceinline__ int ceil_log2(uint32_t x) {
   return x <= 1 ? 0 : 32 - __clz(x - 1);
 }
@@ -320,13 +339,16 @@ __device__ __forceinline__ void count_le4(const double* __restrict__ r, int cnt,
 
 // Multinomial points for a block with r-range [r_lo, r_hi) (the vector's last
 // block: [r_lo, inf)).  The points p_k = n S_k / S_n of every exponential
-// block whose points can fall in the range are rebuilt from their Philox calls
-// and exact carries CE[b].
+// block whose points can fall in the range are rebuilt from the exact carries
+// CE[b] and the quantised spacings of the block: read from `evals` (kBlock
+// per block, stored by the records pass) when given, else recomputed from
+// their Philox calls.
 template <typename CEPtr>
 __device__ void emit_multinomial(const double* __restrict__ r_lds, int cnt, double r_lo,
                                  double r_hi, bool last, int64_t n, int64_t P0, Key key,
                                  uint32_t filter, uint32_t offset, CEPtr CE, uint32_t nbe,
-                                 int32_t* __restrict__ a_out, WgScratch* s) {
+                                 int32_t* __restrict__ a_out, WgScratch* s,
+                                 const uint64_t* __restrict__ evals = nullptr) {
   if (cnt <= 0 || !(last || r_hi > r_lo)) return;
   const RMap em = make_rmap(CE[nbe], n);
   // P(b) = value of the last point of exponential block b-1, b = 1..nbe-1
@@ -364,7 +386,8 @@ __device__ void emit_multinomial(const double* __restrict__ r_lds, int cnt, doub
   }
   for (uint32_t b = b_first; b <= b_last; ++b) {
     uint64_t q[kPer];
-    exp_values(key, filter, offset, n, b, q);
+    if (evals) load_exp_values(evals, b, q);
+    else exp_values(key, filter, offset, n, b, q);
     uint64_t acc = 0;
 #pragma unroll
     for (int v = 0; v < kPer; ++v) {
