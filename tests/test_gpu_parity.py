@@ -323,6 +323,34 @@ def test_alternatives_bound_table(dtype, n, y, B):
         assert np.array_equal(ar, oracle.rejection(w, 1.0, seed=6, offset=2)[0])
 
 
+@pytest.mark.parametrize("n", [5000, 1 << 17])
+def test_alternatives_tiny_binary64_weights(n):
+    """Binary64 weights scaled by 2^-900 (inside the range where the single
+    fused multiply-add accept test is exact) give the oracle's ancestors for
+    Metropolis and rejection, on the LDS-staged (n = 5000) and the bound-table
+    (n = 2^17) paths."""
+    w = inputs.weights(n, 2.0, seed=n + 21).astype(np.float64) * 2.0**-900
+    wmax = float(w.max())
+    a = host(pfr().resample_metropolis(dev(w), 24, seed=4))
+    assert np.array_equal(a, oracle.metropolis(w, 24, seed=4))
+    a = host(pfr().resample_rejection(dev(w), wmax, seed=4))
+    assert np.array_equal(a, oracle.rejection(w, wmax, seed=4)[0])
+
+
+@pytest.mark.parametrize("max_trials", [1, 3, 7, 13])
+def test_rejection_table_trial_cap(max_trials):
+    """A bound far above the weights on the bound-table path: passes of four
+    trials and four-trial tail slots must not use a trial at or beyond the
+    cap (odd caps end inside a pass)."""
+    n = 1 << 17
+    w = inputs.weights(n, 3.0, seed=max_trials)
+    fl = new_flags()
+    a = host(pfr().resample_rejection(dev(w), 64.0, seed=5, max_trials=max_trials, flags=fl))
+    ref, rfl = oracle.rejection(w, 64.0, seed=5, max_trials=max_trials)
+    assert np.array_equal(a, ref)
+    assert int(host(fl)[0]) == rfl
+
+
 def test_bound_table_with_zero_and_huge_weights():
     n = 1 << 17
     w = inputs.weights(n, 3.0, seed=1).astype(np.float64)
