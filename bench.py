@@ -13,10 +13,13 @@ before the timed region.
 Prints one JSON line: whole-step particles/s, the roofline of the dominant
 kernel measured with HIP events inside the timed steps, the HBM fraction of
 each scheme at n = 2^20, batched filters/s on the ragged 4096-vector batch
-(the metric's second part), a per-scheme breakdown, and the CPU oracle timed
-on a bounded sample of the same workload.
+(the metric's second part), a per-scheme breakdown, the CPU oracle timed on
+a bounded sample of the same workload, and ('concurrent') the same steps with
+the five weight sets spread over three HIP streams.  The timed steps run on
+one stream (--streams) so that the dominant kernel's events time it alone.
 
     python bench.py [--steps K] [--warmup W] [--gpus 1] [--no-cpu-baseline]
+                    [--streams S] [--concurrent-streams C]
 """
 from __future__ import annotations
 
@@ -783,6 +786,12 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-batched", action="store_true",
                     help="skip the batched filters/s summary of the default workload")
+    ap.add_argument("--streams", type=int, default=1,
+                    help="HIP streams the independent resamples of a step are spread over "
+                         "(weight set y on stream y mod S)")
+    ap.add_argument("--concurrent-streams", type=int, default=3,
+                    help="also time the step with the weight sets on this many streams "
+                         "(reported as 'concurrent'; 1 = off)")
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of "
                          "known traffic for scaling hardware byte counters")
@@ -853,15 +862,25 @@ def main():
     Bs = [b_star(y) for y in YS]
     out = {(y, s): torch.empty(N, dtype=torch.int32, device=dev) for y in YS for s in SCHEMES}
     perm = {(y, s): torch.empty(N, dtype=torch.int32, device=dev) for y in YS for s in SCHEMES}
-    wsp = {op: pfr.new_workspace(max(256, pfr.workspace_bytes(op, N)), dev)
-           for op in (_lib.OP_MULTINOMIAL, _lib.OP_STRATIFIED, _lib.OP_SYSTEMATIC,
-                      _lib.OP_PERMUTE)}
+    # one stream per group of weight sets (the resamples of different weight
+    # sets are independent); workspaces are per stream.  Stream 0 is the
+    # current stream; the others exist for --streams / --concurrent-streams.
+    n_streams = max(1, min(args.streams, len(YS)))
+    n_conc = max(1, min(args.concurrent_streams, len(YS)))
+    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(device=dev)
+                                               for _ in range(max(n_streams, n_conc) - 1)]
+    wsp = {}
+    for k, st in enumerate(streams):
+        with torch.cuda.stream(st):
+            for op in (_lib.OP_MULTINOMIAL, _lib.OP_STRATIFIED, _lib.OP_SYSTEMATIC,
+                       _lib.OP_PERMUTE):
+                wsp[(k, op)] = pfr.new_workspace(max(256, pfr.workspace_bytes(op, N)), dev)
+    torch.cuda.synchronize()
     flags = torch.zeros(1, dtype=torch.int32, device=dev)
-    stream = torch.cuda.current_stream()
     dominant = (4.0, "metropolis")
     ev = []
 
-    def resample(yi, y, s):
+    def resample(yi, y, s, k):
         w = ws_[yi]
         a = out[(y, s)]
         if s == "metropolis":
@@ -871,29 +890,32 @@ def main():
         else:
             op = {"multinomial": _lib.OP_MULTINOMIAL, "stratified": _lib.OP_STRATIFIED,
                   "systematic": _lib.OP_SYSTEMATIC}[s]
-            getattr(pfr, "resample_" + s)(w, seed=1, out=a, flags=flags, workspace=wsp[op])
+            getattr(pfr, "resample_" + s)(w, seed=1, out=a, flags=flags, workspace=wsp[(k, op)])
         return a
 
-    def step(record=False):
+    def step(record=False, n_st=n_streams):
         for yi, y in enumerate(YS):
-            for s in SCHEMES:
-                if s in FUSED:
-                    # the emission writes the claim vector and marks itself
-                    pfr.resample_permuted(s, ws_[yi], seed=1, out=out[(y, s)],
-                                          permuted=perm[(y, s)], flags=flags)
-                    continue
-                if record and (y, s) == dominant:
-                    e0 = torch.cuda.Event(enable_timing=True)
-                    e1 = torch.cuda.Event(enable_timing=True)
-                    e0.record(stream)
-                    a = resample(yi, y, s)
-                    e1.record(stream)
-                    ev.append((e0, e1))
-                else:
-                    a = resample(yi, y, s)
-                pfr.permute_ancestors(a, sorted_hint=s not in ("metropolis", "rejection"),
-                                      out=perm[(y, s)], flags=flags,
-                                      workspace=wsp[_lib.OP_PERMUTE])
+            k = yi % n_st
+            stream = streams[k]
+            with torch.cuda.stream(stream):
+                for s in SCHEMES:
+                    if s in FUSED:
+                        # the emission writes the claim vector and marks itself
+                        pfr.resample_permuted(s, ws_[yi], seed=1, out=out[(y, s)],
+                                              permuted=perm[(y, s)], flags=flags)
+                        continue
+                    if record and (y, s) == dominant:
+                        e0 = torch.cuda.Event(enable_timing=True)
+                        e1 = torch.cuda.Event(enable_timing=True)
+                        e0.record(stream)
+                        a = resample(yi, y, s, k)
+                        e1.record(stream)
+                        ev.append((e0, e1))
+                    else:
+                        a = resample(yi, y, s, k)
+                    pfr.permute_ancestors(a, sorted_hint=s not in ("metropolis", "rejection"),
+                                          out=perm[(y, s)], flags=flags,
+                                          workspace=wsp[(k, _lib.OP_PERMUTE)])
 
     for _ in range(args.warmup):
         step()
@@ -907,6 +929,25 @@ def main():
     log(f"timed {args.steps} steps in {elapsed:.3f} s")
     if int(flags.cpu()[0]) != 0:
         raise RuntimeError(f"data flags raised during the benchmark: {int(flags.cpu()[0])}")
+
+    # the same steps with the weight sets spread over several streams, so that
+    # the short launches of one set overlap the long kernels of another
+    concurrent = None
+    if n_conc > 1 and n_conc != n_streams:
+        for _ in range(args.warmup):
+            step(n_st=n_conc)
+        torch.cuda.synchronize()
+        tc0 = time.perf_counter()
+        for _ in range(args.steps):
+            step(n_st=n_conc)
+        torch.cuda.synchronize()
+        tc = time.perf_counter() - tc0
+        concurrent = {"streams": n_conc, "ms_per_step": 1e3 * tc / args.steps,
+                      "value": len(YS) * len(SCHEMES) * N * args.steps / tc,
+                      "unit": "particles/s"}
+        log(f"timed {args.steps} steps on {n_conc} streams in {tc:.3f} s")
+        if int(flags.cpu()[0]) != 0:
+            raise RuntimeError(f"data flags raised during the benchmark: {int(flags.cpu()[0])}")
 
     ms_step = 1e3 * elapsed / args.steps
     particles = len(YS) * len(SCHEMES) * N
@@ -932,7 +973,9 @@ def main():
                 "traffic": DOMINANT_TRAFFIC_BYTES, "traffic_unit": "bytes per launch",
                 "algorithmic_bytes": 8.0 * N, "avg_launch_ms": dom_ms}
 
-    # per-scheme breakdown (untimed pass, events around each call)
+    # per-scheme breakdown (untimed pass, events around each call, one stream;
+    # the timed steps have been synchronised, so stream 0's workspaces are free)
+    stream = torch.cuda.current_stream()
     breakdown = {}
     for s in SCHEMES:
         rows = []
@@ -943,13 +986,13 @@ def main():
             e2 = torch.cuda.Event(enable_timing=True)
             e0.record(stream)
             for _ in range(reps):
-                resample(yi, y, s)
+                resample(yi, y, s, 0)
             e1.record(stream)
             for _ in range(reps):
                 pfr.permute_ancestors(out[(y, s)],
                                       sorted_hint=s not in ("metropolis", "rejection"),
                                       out=perm[(y, s)], flags=flags,
-                                      workspace=wsp[_lib.OP_PERMUTE])
+                                      workspace=wsp[(0, _lib.OP_PERMUTE)])
             e2.record(stream)
             torch.cuda.synchronize()
             t_res = e0.elapsed_time(e1) / reps
@@ -1000,9 +1043,11 @@ def main():
         "config": {"workload": "single resample, n=2^20 float32 weights, y in {0,1,2,3,4}, "
                                "five resamplers (Metropolis B from the bias bound, rejection "
                                "w_max=1) + permute_ancestors on each output",
-                   "n": N, "y": list(YS), "B": Bs, "resamples_per_step": len(YS) * len(SCHEMES)},
+                   "n": N, "y": list(YS), "B": Bs, "resamples_per_step": len(YS) * len(SCHEMES),
+                   "streams": n_streams},
         "roofline": roofline,
         "cpu_baseline": cpu,
+        "concurrent": concurrent,
         "hbm_frac_8B_per_particle_at_2p20": hbm_2p20,
         "batched": batched,
         "breakdown": breakdown,

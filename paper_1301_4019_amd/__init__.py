@@ -117,9 +117,14 @@ def _rng(seed, offset, filter_base, offset_dev=None):
                     None if offset_dev is None else offset_dev.data_ptr())
 
 
-# workspaces are zeroed once and reused; calls sharing one must be ordered on
-# one stream (the default here: torch's current stream)
+# workspaces are zeroed once and reused; calls sharing one must be ordered, so
+# the cache keeps one per (device, stream, op, size): calls on different
+# streams never share a cached workspace
 _WS_CACHE: dict = {}
+
+
+def _stream_key():
+    return _torch().cuda.current_stream().cuda_stream
 
 
 def workspace_bytes(op: int, n_total: int, offsets=None, max_len=None, dtype_code=0) -> int:
@@ -142,7 +147,7 @@ def _workspace(op, seg, dtype_code, device, ws):
         return ws, need
     if need == 0:
         return None, 0
-    key = (str(device), op, need)
+    key = (str(device), _stream_key(), op, need)
     cached = _WS_CACHE.get(key)
     if cached is None:
         cached = new_workspace(need, device)
@@ -294,7 +299,7 @@ def resample_permuted(scheme, w, seed=0, offset=0, filter_base=0, precision=SCAN
     lib = _lib.load()
     need = int(lib.pfr_resample_permuted_workspace_bytes(op, ctypes.byref(seg), dt))
     if workspace is None:
-        key = (str(w.device), "permuted", op, need)
+        key = (str(w.device), _stream_key(), "permuted", op, need)
         workspace = _WS_CACHE.get(key)
         if workspace is None:
             workspace = new_workspace(need, w.device)
