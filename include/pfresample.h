@@ -186,15 +186,17 @@ PFR_API int resample_systematic(const void* w, pfr_dtype dtype, const pfr_segmen
  * Lane i's words come from Philox calls (i, 2<<28 | c), word m being word
  * m&3 of call m>>2; step s takes words x0, x1, x2 = 3s, 3s+1, 3s+2 (four steps
  * per three calls), proposes j = floor(((x1<<32)|x0) n / 2^64) with
- * u = (x2 + 1) 2^-32, and moves to j when u w_k <= w_j (decided exactly).
- * B_dev (device int32[n_filters], may be NULL) overrides B per segment.
+ * u = (x2 + 1) 2^-32, and moves to j when u w_k <= w_j, decided exactly (one
+ * fused multiply-add, rounded once, keeps the sign of u w_k - w_j) for every
+ * float32 weight, and for binary64 weights as long as w_k is zero or at least
+ * 2^-990.  B_dev (device int32[n_filters], may be NULL) overrides B per segment.
  * No collective operation: the chains are independent, so the output does
  * not depend on the launch shape.  Segments of up to 16K (float32) or 8K
  * (float64) weights, and with pfr_segments.max_len set up to 32K / 16K, are
  * staged in LDS.  The workspace (may be NULL, ws_bytes 0) holds, for a single
- * long vector, a table of power-of-two weight bounds per bucket of particles
- * that lets most rejected proposals skip the load of w_j; it changes the
- * speed, never the result. */
+ * long vector of less than 2^31 bytes of weights, a table of power-of-two
+ * weight bounds per bucket of particles that lets most rejected proposals
+ * skip the load of w_j; it changes the speed, never the result. */
 PFR_API int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segments* seg, int32_t B,
                         const int32_t* B_dev, pfr_rng rng, int32_t* ancestors, void* ws,
                         size_t ws_bytes, void* stream);
@@ -202,7 +204,8 @@ PFR_API int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segmen
 /* Rejection resampling (Code 3): particle i first proposes j = i, then draws
  * j as above from Philox call (i, 2<<28 | t) for trial t >= 1 (every trial
  * takes u from its own call), and keeps the first j with u w_max <= w_j
- * (decided exactly).  w_max must bound the weights (else the output is
+ * (decided exactly as for resample_metropolis, here for w_max of at least
+ * 2^-990).  w_max must bound the weights (else the output is
  * biased); w_max_dev (device double[n_filters], may be NULL) overrides it per
  * segment.  After max_trials trials (>= 1) a particle keeps a_i = i and
  * PFR_FLAG_TRIAL_CAP is raised.  No collective operation; LDS staging and
