@@ -308,6 +308,7 @@ __global__ __launch_bounds__(kTableThreads) void k_metropolis_table(
     uint32_t idx[K], k[K];
     double wk[K];
     bool live[K];
+    PhiloxLane pl[K];
 #pragma unroll
     for (int c = 0; c < K; ++c) {
       const int64_t g = gb + (int64_t)c * kTableThreads;
@@ -315,6 +316,7 @@ __global__ __launch_bounds__(kTableThreads) void k_metropolis_table(
       idx[c] = (uint32_t)(live[c] ? g : gb);
       k[c] = idx[c];
       wk[c] = (double)w[idx[c]];
+      pl[c] = philox_lane(key, idx[c], filter, offset);
     }
     for (int32_t m = 0; 4 * m < B; ++m) {
       const int32_t left = B - 4 * m;
@@ -326,7 +328,9 @@ __global__ __launch_bounds__(kTableThreads) void k_metropolis_table(
 #pragma unroll
         for (int c3 = 0; c3 < 3; ++c3) {
           if (c3 < ncall) {
-            const uint4 v = draw(key, idx[c], DOM_TRIAL, (uint32_t)(3 * m + c3), filter, offset);
+            // step, filter and offset are the same on every lane (one vector)
+            const uint4 v =
+                philox_lane_call(pl[c], key, DOM_TRIAL, (uint32_t)(3 * m + c3), filter, offset);
             x[c][4 * c3 + 0] = v.x;
             x[c][4 * c3 + 1] = v.y;
             x[c][4 * c3 + 2] = v.z;

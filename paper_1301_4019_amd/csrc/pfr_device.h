@@ -83,6 +83,7 @@ __device__ __forceinline__ uint4 draw(Key key, uint32_t index, uint32_t domain, 
   return philox(index, (domain << 28) | (step & 0x0FFFFFFFu), filter, offset, key);
 }
 
+
 // u in (0, 1] on the 2^-32 lattice (accept tests).
 __device__ __forceinline__ double u_accept(uint32_t x) { return ((double)x + 1.0) * 0x1p-32; }
 // u in [0, 1) on the 2^-32 lattice (stratum offsets).
@@ -144,6 +145,67 @@ __device__ __forceinline__ uint32_t uniform_u32(uint32_t v) {
 }
 __device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int lane) {
   return (uint32_t)__builtin_amdgcn_readlane((int)v, lane);
+}
+
+// Philox calls of one lane whose counter words 1..3 are the same on every lane
+// of the wave (word 1 changing from call to call) and whose word 0 is the
+// lane's particle index.  Everything that depends only on (word 0, word 2,
+// word 3) -- the first round's product of word 0 and the second round's
+// product of word 2 -- is formed once per lane (PhiloxLane); what depends on
+// word 1 alone -- the first round's product of word 2 and the second round's
+// product of word 0 -- runs on the scalar unit.  Each call then costs one
+// VALU instruction for rounds 1-2 instead of eight, with the same bits as
+// draw(); callers must guarantee the uniformity (the arguments other than
+// the PhiloxLane must be kernel arguments or loop counters).
+struct PhiloxLane {
+  uint32_t index, e0, e1, d3;
+};
+__device__ __forceinline__ PhiloxLane philox_lane(Key key, uint32_t index, uint32_t filter,
+                                                  uint32_t offset) {
+  const uint64_t p0 = (uint64_t)0xD2511F53u * index;             // round 1, word 0
+  const uint32_t d2 = (uint32_t)(p0 >> 32) ^ offset ^ key.k1;
+  const uint32_t d1 = 0xCD9E8D57u * filter;                       // round 1, word 2 (low)
+  const uint64_t q1 = (uint64_t)0xCD9E8D57u * d2;                 // round 2, word 2
+  PhiloxLane L;
+  L.index = index;
+  L.e0 = (uint32_t)(q1 >> 32) ^ d1 ^ (key.k0 + 0x9E3779B9u);
+  L.e1 = (uint32_t)q1;
+  L.d3 = (uint32_t)p0;
+  return L;
+}
+__device__ __forceinline__ uint4 philox_lane_call(const PhiloxLane& L, Key key, uint32_t domain,
+                                                  uint32_t step, uint32_t filter,
+                                                  uint32_t offset) {
+  if (kPhiloxRounds < 3) return draw(key, L.index, domain, step, filter, offset);
+  // (the arguments other than L are kernel arguments and loop counters, which
+  // the compiler keeps in scalar registers; so are the values below)
+  const uint32_t c1 = (domain << 28) | (step & 0x0FFFFFFFu);
+  const uint32_t k0 = key.k0, k1 = key.k1;
+  // round 1, word 2 (high): scalar
+  const uint32_t d0 = __umulhi(0xCD9E8D57u, filter) ^ c1 ^ k0;
+  // round 2, word 0: scalar product; its high word meets the lane's d3
+  const uint32_t q0hi = __umulhi(0xD2511F53u, d0), q0lo = 0xD2511F53u * d0;
+  const uint32_t e2 = L.d3 ^ (q0hi ^ (k1 + 0xBB67AE85u));
+  // round 3: word 3 (q0lo) is still uniform
+  uint32_t kk0 = k0 + 2u * 0x9E3779B9u, kk1 = k1 + 2u * 0xBB67AE85u;
+  const uint64_t a0 = (uint64_t)0xD2511F53u * L.e0;
+  const uint64_t a1 = (uint64_t)0xCD9E8D57u * e2;
+  uint32_t c[4] = {xor3_key((uint32_t)(a1 >> 32), L.e1, kk0), (uint32_t)a1,
+                   (uint32_t)(a0 >> 32) ^ (q0lo ^ kk1), (uint32_t)a0};
+  kk0 += 0x9E3779B9u;
+  kk1 += 0xBB67AE85u;
+#pragma unroll
+  for (int r = 3; r < kPhiloxRounds; ++r) {
+    const uint64_t b0 = (uint64_t)0xD2511F53u * c[0];
+    const uint64_t b1 = (uint64_t)0xCD9E8D57u * c[2];
+    c[0] = xor3_key((uint32_t)(b1 >> 32), c[1], kk0);
+    c[1] = (uint32_t)b1;
+    c[2] = xor3_key((uint32_t)(b0 >> 32), c[3], kk1);
+    c[3] = (uint32_t)b0;
+    kk0 += 0x9E3779B9u;
+    kk1 += 0xBB67AE85u;
+  }
+  return make_uint4(c[0], c[1], c[2], c[3]);
 }
 
 template <typename T>
