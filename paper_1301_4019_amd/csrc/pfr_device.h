@@ -154,9 +154,9 @@ __device__ __forceinline__ uint32_t readlane_u32(uint32_t v, int lane) {
 // product of word 2 -- is formed once per lane (PhiloxLane); what depends on
 // word 1 alone -- the first round's product of word 2 and the second round's
 // product of word 0 -- runs on the scalar unit.  Each call then costs one
-// VALU instruction for rounds 1-2 instead of eight, with the same bits as
-// draw(); callers must guarantee the uniformity (the arguments other than
-// the PhiloxLane must be kernel arguments or loop counters).
+// VALU instruction for rounds 1-2 instead of eight.  The bits are those of
+// draw() for any arguments; only the cost depends on the uniformity (word 1
+// from a loop counter, filter and offset from kernel arguments).
 struct PhiloxLane {
   uint32_t index, e0, e1, d3;
 };
@@ -184,7 +184,8 @@ __device__ __forceinline__ uint4 philox_lane_call(const PhiloxLane& L, Key key, 
   // round 1, word 2 (high): scalar
   const uint32_t d0 = __umulhi(0xCD9E8D57u, filter) ^ c1 ^ k0;
   // round 2, word 0: scalar product; its high word meets the lane's d3
-  const uint32_t q0hi = __umulhi(0xD2511F53u, d0), q0lo = 0xD2511F53u * d0;
+  const uint64_t q0 = (uint64_t)0xD2511F53u * d0;
+  const uint32_t q0hi = (uint32_t)(q0 >> 32), q0lo = (uint32_t)q0;
   const uint32_t e2 = L.d3 ^ (q0hi ^ (k1 + 0xBB67AE85u));
   // round 3: word 3 (q0lo) is still uniform
   uint32_t kk0 = k0 + 2u * 0x9E3779B9u, kk1 = k1 + 2u * 0xBB67AE85u;
