@@ -48,17 +48,20 @@ struct MGroup {
   int nq;
 };
 
+// pl: the lane's Philox parts for particle i (philox_lane); the step number,
+// filter and offset are the same on every lane of the wave.
 template <typename T>
 __device__ __forceinline__ void metropolis_fetch(const T* __restrict__ ws, Key key, uint32_t i,
-                                                 uint32_t filt, uint32_t offset, uint32_t n,
-                                                 int32_t steps, int32_t m, MGroup& g) {
+                                                 const PhiloxLane& pl, uint32_t filt,
+                                                 uint32_t offset, uint32_t n, int32_t steps,
+                                                 int32_t m, MGroup& g) {
   uint32_t x[12];
   const int32_t left = steps - 4 * m;
   const int ncall = left >= 4 ? 3 : (3 * left + 3) / 4;
 #pragma unroll
   for (int c3 = 0; c3 < 3; ++c3) {
     if (c3 < ncall) {
-      const uint4 v = draw(key, i, DOM_TRIAL, (uint32_t)(3 * m + c3), filt, offset);
+      const uint4 v = philox_lane_call(pl, key, DOM_TRIAL, (uint32_t)(3 * m + c3), filt, offset);
       x[4 * c3 + 0] = v.x;
       x[4 * c3 + 1] = v.y;
       x[4 * c3 + 2] = v.z;
@@ -101,10 +104,11 @@ __device__ __forceinline__ uint32_t metropolis_chain(const T* ws, Key key, uint3
                                                      int32_t steps) {
   uint32_t k = i;
   double wk = (double)ws[i];
+  const PhiloxLane pl = philox_lane(key, i, filt, offset);
   const int32_t groups = (steps + 3) / 4;
   for (int32_t m = 0; m < groups; ++m) {
     MGroup g;
-    metropolis_fetch(ws, key, i, filt, offset, n, steps, m, g);
+    metropolis_fetch(ws, key, i, pl, filt, offset, n, steps, m, g);
     metropolis_accept(g, k, wk);
   }
   return k;
@@ -150,12 +154,15 @@ __global__ __launch_bounds__(THREADS) void k_metropolis_staged(
         uint32_t k = i;
         double wk = (double)ws[i];
         const int32_t groups = (steps + 3) / 4;
+        const PhiloxLane pl = philox_lane(key, i, filt, offset);
         MGroup ga, gb;
-        if (groups > 0) metropolis_fetch(ws, key, i, filt, offset, n, steps, 0, ga);
+        if (groups > 0) metropolis_fetch(ws, key, i, pl, filt, offset, n, steps, 0, ga);
         for (int32_t m = 0; m < groups; m += 2) {
-          if (m + 1 < groups) metropolis_fetch(ws, key, i, filt, offset, n, steps, m + 1, gb);
+          if (m + 1 < groups)
+            metropolis_fetch(ws, key, i, pl, filt, offset, n, steps, m + 1, gb);
           metropolis_accept(ga, k, wk);
-          if (m + 2 < groups) metropolis_fetch(ws, key, i, filt, offset, n, steps, m + 2, ga);
+          if (m + 2 < groups)
+            metropolis_fetch(ws, key, i, pl, filt, offset, n, steps, m + 2, ga);
           if (m + 1 < groups) metropolis_accept(gb, k, wk);
         }
         a[g] = (int32_t)k;
