@@ -84,7 +84,10 @@ __global__ __launch_bounds__(kFT) void k_lg_init(int32_t n_filters, int32_t n, d
 // One workgroup per filter: copy, propagate, weight, log Z and the Metropolis
 // step count for the next resampling, B = ceil(log eps / log(1 - beta)) with
 // beta = mean(w) (the shifted weights have maximum 1).
-__global__ __launch_bounds__(kFT) void k_lg_move(int32_t n, double phi, double q, double r,
+// inv_r = 1 / r in binary64: the scaled residual is (y - x) * inv_r, one
+// multiply where a division would cost a dozen VALU instructions (it may
+// differ from (y - x) / r in the last bit).
+__global__ __launch_bounds__(kFT) void k_lg_move(int32_t n, double phi, double q, double inv_r,
                                                  double log_norm, double log_eps,
                                                  const double* __restrict__ y, int32_t T,
                                                  const uint32_t* __restrict__ t_dev, Key key,
@@ -115,14 +118,14 @@ __global__ __launch_bounds__(kFT) void k_lg_move(int32_t n, double phi, double q
     const uint4 u = draw(key, (uint32_t)i, DOM_NOISE, t, filter_base + f, offset);
     const float xn = (float)(phi * (double)x[base + i] + q * normal_bm(u.x, u.y));
     x[base + i] = xn;
-    const double d = (yt - (double)xn) / r;
+    const double d = (yt - (double)xn) * inv_r;
     const double lw = -0.5 * d * d + log_norm;
     mx = lw > mx ? lw : mx;
   }
   mx = block_max(mx, slot);
   double sum = 0.0;
   for (int32_t i = tid; i < n; i += kFT) {
-    const double d = (yt - (double)x[base + i]) / r;
+    const double d = (yt - (double)x[base + i]) * inv_r;
     const double e = exp((-0.5 * d * d + log_norm) - mx);
     w[base + i] = (float)e;
     sum += e;
@@ -162,9 +165,9 @@ hipError_t launch_lgssm_move(int32_t n_filters, int32_t n, double phi, double q,
                              float* x, float* w, double* logz, int32_t* B_dev, uint32_t* flags,
                              hipStream_t stream) {
   const double log_norm = -log(r) - 0.5 * log(6.283185307179586);
-  hipLaunchKernelGGL(k_lg_move, dim3((uint32_t)n_filters), dim3(kFT), 0, stream, n, phi, q, r,
-                     log_norm, log_eps, y, T, t_dev, key, offset, filter_base, c, x, w, logz,
-                     B_dev, flags);
+  hipLaunchKernelGGL(k_lg_move, dim3((uint32_t)n_filters), dim3(kFT), 0, stream, n, phi, q,
+                     1.0 / r, log_norm, log_eps, y, T, t_dev, key, offset, filter_base, c, x, w,
+                     logz, B_dev, flags);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   hipLaunchKernelGGL(k_lg_tick, dim3(1), dim3(64), 0, stream, t_dev);
