@@ -374,22 +374,50 @@ __global__ __launch_bounds__(256) void k_fill_unclaimed(int32_t* __restrict__ d,
   }
 }
 
+// Claims of one workgroup are first merged in LDS: a 256-entry table keyed
+// by the slot's low bits keeps the smallest (slot, position) pair per entry,
+// and a position whose entry holds the same slot with a smaller position
+// cannot win, so it issues no global atomic.  Equal ancestors inside a
+// workgroup (degenerate weights: every particle descends from one) then cost
+// one atomic per workgroup instead of one per particle, all on one address.
+// Positions whose entry holds another slot still claim, so the result is the
+// same minimum as without the table.  Slots are global indices (< 2^31).
 __global__ __launch_bounds__(256) void k_claim_min(const int32_t* __restrict__ a, int64_t n_total,
                                                    const int64_t* __restrict__ offsets,
                                                    uint32_t n_filters, int64_t min_len,
                                                    int32_t* __restrict__ d,
                                                    uint32_t* __restrict__ flags) {
+  __shared__ unsigned long long tab[256];
   bool bad = false;
   const int64_t stride = (int64_t)gridDim.x * blockDim.x;
-  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
-    const SegIdx s = seg_index(offsets, n_filters, n_total, g);
-    if (s.n < min_len) continue;
-    const int64_t ai = anc_at(a, s, s.i, bad);
-    int32_t* slot = &d[s.base + ai];
-    // d only decreases, so a stale (cached) value that is already <= i proves
-    // the claim lost; only a larger one needs the atomic
-    if (__hip_atomic_load(slot, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > (int32_t)s.i)
-      atomicMin(slot, (int32_t)s.i);
+  for (int64_t g0 = (int64_t)blockIdx.x * blockDim.x; g0 < n_total; g0 += stride) {
+    const int64_t g = g0 + threadIdx.x;
+    bool valid = false;
+    uint32_t slot = 0, pos = 0;
+    if (g < n_total) {
+      const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+      if (s.n >= min_len) {
+        valid = true;
+        slot = (uint32_t)(s.base + anc_at(a, s, s.i, bad));
+        pos = (uint32_t)s.i;
+      }
+    }
+    const unsigned long long key = ((unsigned long long)slot << 32) | pos;
+    tab[threadIdx.x] = ~0ull;
+    __syncthreads();
+    if (valid) atomicMin(&tab[slot & 255u], key);
+    __syncthreads();
+    if (valid) {
+      const unsigned long long best = tab[slot & 255u];
+      const bool beaten = (uint32_t)(best >> 32) == slot && (uint32_t)best < pos;
+      int32_t* dst = &d[slot];
+      // d only decreases, so a stale (cached) value that is already <= pos
+      // proves the claim lost; only a larger one needs the atomic
+      if (!beaten &&
+          __hip_atomic_load(dst, __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_WORKGROUP) > (int32_t)pos)
+        atomicMin(dst, (int32_t)pos);
+    }
+    __syncthreads();  // the table is reset by the next iteration
   }
   if (flags) {
     const uint32_t b = (uint32_t)wave_reduce((uint32_t)bad, OpOr());

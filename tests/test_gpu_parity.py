@@ -476,6 +476,32 @@ def test_permute_bad_ancestors_and_batched():
             assert np.array_equal(c[off[f]:off[f + 1]], ref)
 
 
+def test_permute_degenerate_ancestries():
+    # many equal claims inside one workgroup, and distinct slots that share a
+    # low-bits entry of the per-workgroup claim table (multiples of 256)
+    n = 1 << 20
+    g = np.random.default_rng(11)
+    cases = {
+        "one parent": np.full(n, 12345, np.int32),
+        "sixteen parents": g.integers(0, 16, n).astype(np.int32) * 4099,
+        "colliding slots": g.integers(0, 16, n).astype(np.int32) * 256,
+        "two blocks": np.repeat(np.array([n - 1, 0], np.int32), n // 2),
+    }
+    for name, a in cases.items():
+        ref, _ = oracle.permute(a)
+        c = host(pfr().permute_ancestors(dev(a), sorted_hint=False))
+        assert np.array_equal(c, ref), name
+    # the same through the batched global kernels (segments longer than 16384)
+    sizes = [100000, 3, 70000, 40000]
+    off = np.concatenate([[0], np.cumsum(sizes)]).astype(np.int64)
+    a = np.concatenate([np.full(sizes[0], 7), g.integers(0, 3, 3), g.integers(0, 4, sizes[2]) * 256,
+                        np.full(sizes[3], sizes[3] - 1)]).astype(np.int32)
+    c = host(pfr().permute_ancestors(dev(a), sorted_hint=False, offsets=dev(off)))
+    for f in range(len(sizes)):
+        ref, _ = oracle.permute(a[off[f]:off[f + 1]])
+        assert np.array_equal(c[off[f]:off[f + 1]], ref), f
+
+
 def test_permute_long_chain():
     # a = [0, 0, 1, 2, ..., n-2]: one chain runs through every slot
     n = 3000
