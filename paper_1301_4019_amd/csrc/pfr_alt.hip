@@ -702,11 +702,39 @@ hipError_t launch_metropolis_t(const void* wv, int64_t n_total, const int64_t* o
                        filter_base, a, chunk, min_len, kAll);
     return hipGetLastError();
   };
-  if (cap == 0) return global_launch(0);
+  if (cap == 0) {
+    // one vector of up to 128 KB of weights: staged as below (one workgroup
+    // per CU for the LDS), otherwise chains gather from global memory
+    if ((!offsets || n_filters <= 1) && n_total <= 128 * per_kb) {
+      const int64_t chunk1 = 256;
+      hipLaunchKernelGGL((k_metropolis_staged<T, 128 * per_kb, 256>),
+                         dim3((unsigned)((n_total + chunk1 - 1) / chunk1)), dim3(256), 0, stream,
+                         w, n_total, offsets, n_filters, B, B_dev, key, offset, filter_base, a,
+                         chunk1, (int64_t)0, kAll);
+      return hipGetLastError();
+    }
+    return global_launch(0);
+  }
   // segments longer than the LDS tier run in the same launch, from global
   // memory (a second, pipelined launch for them measured slower on ragged
   // batches: its chunks hold several long chains per lane)
   const int64_t hi = kAll;
+  if (!offsets || n_filters <= 1) {
+    // one short vector: every workgroup stages all of it and runs 256 of its
+    // chains, one per lane, so that long chains (large B) spread over many CUs
+    // instead of running four to a lane on one to four of them
+    const int64_t chunk1 = 256;
+    const dim3 grid1((unsigned)((n_total + chunk1 - 1) / chunk1));
+    if (cap == 16 * per_kb)
+      hipLaunchKernelGGL((k_metropolis_staged<T, 16 * per_kb, 256>), grid1, dim3(256), 0, stream,
+                         w, n_total, offsets, n_filters, B, B_dev, key, offset, filter_base, a,
+                         chunk1, (int64_t)0, hi);
+    else
+      hipLaunchKernelGGL((k_metropolis_staged<T, 64 * per_kb, 256>), grid1, dim3(256), 0, stream,
+                         w, n_total, offsets, n_filters, B, B_dev, key, offset, filter_base, a,
+                         chunk1, (int64_t)0, hi);
+    return hipGetLastError();
+  }
   const int64_t chunk = 4096;
   const dim3 grid((unsigned)((n_total + chunk - 1) / chunk));
   if (cap == 16 * per_kb)
@@ -781,10 +809,20 @@ hipError_t launch_metropolis_table(const T* w, int64_t n, int32_t B, Key key, ui
   if (e != hipSuccess) return e;
   const int64_t chunk = (n + kTableGrid - 1) / kTableGrid;
   char* base = (char*)ws;
-  hipLaunchKernelGGL((k_metropolis_table<T, 4>), dim3((unsigned)((n + chunk - 1) / chunk)),
-                     dim3(kTableThreads), 0, stream, w, n, B, key, offset, filter, a, chunk,
-                     (const uint8_t*)(base + g.codes_off), (const uint32_t*)(base + g.wg_off),
-                     g.n_wg, g.nb, g.shift);
+  const dim3 grid((unsigned)((n + chunk - 1) / chunk));
+  const uint8_t* codes = (const uint8_t*)(base + g.codes_off);
+  const uint32_t* wg_max = (const uint32_t*)(base + g.wg_off);
+  // chains per lane: as many as the chunk fills (four from 2^20 particles up);
+  // more than that would run copies of dead chains on every lane
+  if (chunk <= kTableThreads)
+    hipLaunchKernelGGL((k_metropolis_table<T, 1>), grid, dim3(kTableThreads), 0, stream, w, n, B,
+                       key, offset, filter, a, chunk, codes, wg_max, g.n_wg, g.nb, g.shift);
+  else if (chunk <= 2 * kTableThreads)
+    hipLaunchKernelGGL((k_metropolis_table<T, 2>), grid, dim3(kTableThreads), 0, stream, w, n, B,
+                       key, offset, filter, a, chunk, codes, wg_max, g.n_wg, g.nb, g.shift);
+  else
+    hipLaunchKernelGGL((k_metropolis_table<T, 4>), grid, dim3(kTableThreads), 0, stream, w, n, B,
+                       key, offset, filter, a, chunk, codes, wg_max, g.n_wg, g.nb, g.shift);
   return hipGetLastError();
 }
 

@@ -37,7 +37,8 @@ def new_flags():
 # ----------------------------------------------------------------- alternatives
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
 @pytest.mark.parametrize("n,y,B", [(1024, 2.0, 64), (1, 2.0, 5), (3, 0.0, 7), (4097, 3.0, 11),
-                                   (100003, 4.0, 9)])
+                                   (100003, 4.0, 9), (16385, 4.0, 300), (20000, 3.0, 61),
+                                   (32768, 4.0, 357), (32769, 1.0, 8), (12000, 3.0, 60)])
 def test_metropolis_bit_exact(dtype, n, y, B):
     w = inputs.weights(n, y, seed=n, dtype=dtype)
     a = host(pfr().resample_metropolis(dev(w), B, seed=12345, offset=3, filter_base=7))
@@ -306,7 +307,8 @@ def test_alternatives_single_vector_each_tier(n):
 
 @pytest.mark.parametrize("dtype", [np.float32, np.float64])
 @pytest.mark.parametrize("n,y,B", [(65536, 4.0, 354), (100003, 3.0, 60), (1 << 20, 4.0, 41),
-                                   (1 << 20, 0.5, 9), (3 << 20, 2.0, 16)])
+                                   (1 << 20, 0.5, 9), (3 << 20, 2.0, 16), (1 << 19, 4.0, 100),
+                                   (300007, 3.0, 60), ((1 << 20) + 5, 4.0, 70)])
 def test_alternatives_bound_table(dtype, n, y, B):
     """Long single vectors use the bound table when given a workspace; the
     result is the same as without one, and bit-exact against the oracle."""
