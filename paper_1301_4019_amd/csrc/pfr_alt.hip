@@ -856,11 +856,30 @@ hipError_t launch_rejection_t(const void* wv, int64_t n_total, const int64_t* of
   const T* w = (const T*)wv;
   constexpr int per_kb = 1024 / (int)sizeof(T);
   const int cap = staged_capacity<T>(max_len, n_total, n_filters);
+  const bool single = !offsets || n_filters <= 1;
   if (cap == 0) {
-    const int64_t chunk = (int64_t)tuning().rejection_per_wave * 4;
+    // a short single vector: 256 particles per workgroup, so that its long
+    // trial sequences spread over more CUs
+    const int64_t chunk = single && n_total < (1 << 17) ? 256
+                                                          : (int64_t)tuning().rejection_per_wave * 4;
     hipLaunchKernelGGL((k_rejection<T, 0, 256>), dim3((unsigned)((n_total + chunk - 1) / chunk)),
                        dim3(256), 0, stream, w, n_total, offsets, n_filters, w_max, w_max_dev,
                        max_trials, key, offset, filter_base, a, flags, chunk);
+    return hipGetLastError();
+  }
+  if (single) {
+    // one vector in LDS: every 256-thread workgroup stages all of it and takes
+    // 256 of its particles (one per lane on average)
+    const int64_t chunk1 = 256;
+    const dim3 grid1((unsigned)((n_total + chunk1 - 1) / chunk1));
+    if (cap == 16 * per_kb)
+      hipLaunchKernelGGL((k_rejection<T, 16 * per_kb, 256>), grid1, dim3(256), 0, stream, w,
+                         n_total, offsets, n_filters, w_max, w_max_dev, max_trials, key, offset,
+                         filter_base, a, flags, chunk1);
+    else
+      hipLaunchKernelGGL((k_rejection<T, 64 * per_kb, 256>), grid1, dim3(256), 0, stream, w,
+                         n_total, offsets, n_filters, w_max, w_max_dev, max_trials, key, offset,
+                         filter_base, a, flags, chunk1);
     return hipGetLastError();
   }
   const int64_t chunk = (int64_t)tuning().rejection_per_wave * 16;

@@ -56,7 +56,9 @@ def test_metropolis_full_size_config():
 
 
 @pytest.mark.parametrize("dtype", [np.float64, np.float32])
-@pytest.mark.parametrize("n,y", [(1024, 2.0), (1, 0.0), (2, 4.0), (5000, 3.0), (65537, 1.0)])
+@pytest.mark.parametrize("n,y", [(1024, 2.0), (1, 0.0), (2, 4.0), (5000, 3.0), (65537, 1.0),
+                                 (4096, 4.0), (16384, 4.0), (16385, 4.0), (40000, 2.0),
+                                 (131071, 4.0)])
 def test_rejection_bit_exact(dtype, n, y):
     w = inputs.weights(n, y, seed=n + 1, dtype=dtype)
     fl = new_flags()
