@@ -860,7 +860,7 @@ hipError_t launch_rejection_t(const void* wv, int64_t n_total, const int64_t* of
   if (cap == 0) {
     // a short single vector: 256 particles per workgroup, so that its long
     // trial sequences spread over more CUs
-    const int64_t chunk = single && n_total < (1 << 17) ? 256
+    const int64_t chunk = single && n_total < (1 << 19) ? 256
                                                           : (int64_t)tuning().rejection_per_wave * 4;
     hipLaunchKernelGGL((k_rejection<T, 0, 256>), dim3((unsigned)((n_total + chunk - 1) / chunk)),
                        dim3(256), 0, stream, w, n_total, offsets, n_filters, w_max, w_max_dev,
@@ -921,7 +921,8 @@ hipError_t launch_rejection(bool f64, const void* w, int64_t n_total, const int6
                             const double* w_max_dev, uint32_t max_trials, Key key,
                             uint32_t offset, uint32_t filter_base, int32_t* a, uint32_t* flags,
                             void* ws, size_t ws_bytes, hipStream_t stream) {
-  if (ws && !w_max_dev && tuning().rejection_table &&
+  // below 2^20 particles the plain kernel was faster at every y measured (0..4)
+  if (ws && !w_max_dev && tuning().rejection_table && n_total >= (1 << 20) &&
       ws_bytes >= alt_workspace_bytes(f64, n_total, n_filters, max_len) &&
       (f64 ? use_table<double>(n_total, n_filters, max_len)
            : use_table<float>(n_total, n_filters, max_len)))

@@ -346,7 +346,7 @@ def test_rejection_table_trial_cap(max_trials):
     """A bound far above the weights on the bound-table path: passes of four
     trials and four-trial tail slots must not use a trial at or beyond the
     cap (odd caps end inside a pass)."""
-    n = 1 << 17
+    n = 1 << 20
     w = inputs.weights(n, 3.0, seed=max_trials)
     fl = new_flags()
     a = host(pfr().resample_rejection(dev(w), 64.0, seed=5, max_trials=max_trials, flags=fl))
@@ -356,7 +356,7 @@ def test_rejection_table_trial_cap(max_trials):
 
 
 def test_bound_table_with_zero_and_huge_weights():
-    n = 1 << 17
+    n = 1 << 20
     w = inputs.weights(n, 3.0, seed=1).astype(np.float64)
     w[::7] = 0.0
     w[5] = 1e300  # beyond binary32 codes: the table is switched off for this vector
