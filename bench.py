@@ -177,6 +177,100 @@ def _time_ms(fn, reps, torch):
     return 1e3 * (time.perf_counter() - t0) / reps
 
 
+class StepWorkload:
+    """The benchmark step: its inputs, outputs, workspaces and calls.
+
+    Weight set y (n = 2^20 float32, data seed 100 + y) is resampled by every
+    scheme with Philox seed 1 and every ancestry is permuted, exactly as timed;
+    the GPU parity tests run this same object."""
+
+    DOMINANT = (4.0, "metropolis")
+
+    def __init__(self, torch, pfr, dev, n_streams=1):
+        from paper_1301_4019_amd import inputs, _lib
+        self.torch, self.pfr, self._lib = torch, pfr, _lib
+        self.w = [torch.from_numpy(inputs.weights(N, y, seed=100 + int(y))).to(dev) for y in YS]
+        self.Bs = [b_star(y) for y in YS]
+        self.out = {(y, s): torch.empty(N, dtype=torch.int32, device=dev)
+                    for y in YS for s in SCHEMES}
+        self.perm = {(y, s): torch.empty(N, dtype=torch.int32, device=dev)
+                     for y in YS for s in SCHEMES}
+        # one stream per group of weight sets (the resamples of different
+        # weight sets are independent); workspaces are per stream.  Stream 0
+        # is the current stream.
+        self.streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(device=dev)
+                                                        for _ in range(n_streams - 1)]
+        self.wsp = {}
+        for k, st in enumerate(self.streams):
+            with torch.cuda.stream(st):
+                for op in (_lib.OP_MULTINOMIAL, _lib.OP_STRATIFIED, _lib.OP_SYSTEMATIC,
+                           _lib.OP_PERMUTE):
+                    self.wsp[(k, op)] = pfr.new_workspace(max(256, pfr.workspace_bytes(op, N)),
+                                                          dev)
+        torch.cuda.synchronize()
+        self.flags = torch.zeros(1, dtype=torch.int32, device=dev)
+        self.ev = []
+
+    def resample(self, yi, y, s, k):
+        pfr, _lib = self.pfr, self._lib
+        w = self.w[yi]
+        a = self.out[(y, s)]
+        if s == "metropolis":
+            pfr.resample_metropolis(w, self.Bs[yi], seed=1, out=a)
+        elif s == "rejection":
+            pfr.resample_rejection(w, 1.0, seed=1, out=a, flags=self.flags)
+        else:
+            op = {"multinomial": _lib.OP_MULTINOMIAL, "stratified": _lib.OP_STRATIFIED,
+                  "systematic": _lib.OP_SYSTEMATIC}[s]
+            getattr(pfr, "resample_" + s)(w, seed=1, out=a, flags=self.flags,
+                                          workspace=self.wsp[(k, op)])
+        return a
+
+    def permute(self, y, s, k):
+        self.pfr.permute_ancestors(self.out[(y, s)],
+                                   sorted_hint=s not in ("metropolis", "rejection"),
+                                   out=self.perm[(y, s)], flags=self.flags,
+                                   workspace=self.wsp[(k, self._lib.OP_PERMUTE)])
+
+    def step(self, record=False, n_st=1):
+        torch, pfr = self.torch, self.pfr
+        for yi, y in enumerate(YS):
+            k = yi % n_st
+            stream = self.streams[k]
+            with torch.cuda.stream(stream):
+                for s in SCHEMES:
+                    if s in FUSED:
+                        # the emission writes the claim vector and marks itself
+                        pfr.resample_permuted(s, self.w[yi], seed=1, out=self.out[(y, s)],
+                                              permuted=self.perm[(y, s)], flags=self.flags)
+                        continue
+                    if record and (y, s) == self.DOMINANT:
+                        e0 = torch.cuda.Event(enable_timing=True)
+                        e1 = torch.cuda.Event(enable_timing=True)
+                        e0.record(stream)
+                        self.resample(yi, y, s, k)
+                        e1.record(stream)
+                        self.ev.append((e0, e1))
+                    else:
+                        self.resample(yi, y, s, k)
+                    self.permute(y, s, k)
+
+
+def batch_calls(pfr, w, offsets, max_len, B, a, flags):
+    """The ragged-batch calls the benchmark times, one per (scheme, mode)."""
+    calls = {}
+    for s in ("multinomial", "stratified", "systematic"):
+        fn = getattr(pfr, "resample_" + s)
+        for mode, prec in (("exact", pfr.SCAN_EXACT), ("comp_f32", pfr.SCAN_COMP_F32)):
+            calls[f"{s}_{mode}"] = (lambda fn=fn, prec=prec: fn(
+                w, seed=1, precision=prec, offsets=offsets, max_len=max_len, out=a, flags=flags))
+    calls["metropolis"] = lambda: pfr.resample_metropolis(
+        w, 0, seed=1, B_per_filter=B, offsets=offsets, max_len=max_len, out=a)
+    calls["rejection"] = lambda: pfr.resample_rejection(
+        w, 1.0, seed=1, offsets=offsets, max_len=max_len, out=a, flags=flags)
+    return calls
+
+
 def batched_summary(torch, pfr, inputs, dev, stream, reps=5):
     """Filters/s of each resampler on the ragged batch (4096 float32 vectors,
     N_f = 2^(8+8v), y_f ~ U[0,4], seed 0), one launch sequence per call, HIP
@@ -203,17 +297,8 @@ def batched_summary(torch, pfr, inputs, dev, stream, reps=5):
         e1.synchronize()
         return e0.elapsed_time(e1) / reps
 
-    out = {}
-    for s in ("multinomial", "stratified", "systematic"):
-        fn = getattr(pfr, "resample_" + s)
-        for mode, prec in (("exact", pfr.SCAN_EXACT), ("comp_f32", pfr.SCAN_COMP_F32)):
-            ms = timed(lambda: fn(w, seed=1, precision=prec, offsets=offsets, max_len=max_len,
-                                  out=a, flags=flags))
-            out[f"{s}_{mode}"] = F / (ms * 1e-3)
-    out["metropolis"] = F / (1e-3 * timed(lambda: pfr.resample_metropolis(
-        w, 0, seed=1, B_per_filter=B, offsets=offsets, max_len=max_len, out=a)))
-    out["rejection"] = F / (1e-3 * timed(lambda: pfr.resample_rejection(
-        w, 1.0, seed=1, offsets=offsets, max_len=max_len, out=a, flags=flags)))
+    out = {name: F / (1e-3 * timed(fn))
+           for name, fn in batch_calls(pfr, w, offsets, max_len, B, a, flags).items()}
     w64 = w.double()
     views = [(w64[off_np[f]:off_np[f + 1]], a[off_np[f]:off_np[f + 1]]) for f in range(F)]
 
@@ -858,64 +943,15 @@ def main():
         torch.cuda.synchronize()
         log(f"calibration copy: {nbytes} bytes read, {nbytes} bytes written")
         del src, dst
-    ws_ = [torch.from_numpy(inputs.weights(N, y, seed=100 + int(y))).to(dev) for y in YS]
-    Bs = [b_star(y) for y in YS]
-    out = {(y, s): torch.empty(N, dtype=torch.int32, device=dev) for y in YS for s in SCHEMES}
-    perm = {(y, s): torch.empty(N, dtype=torch.int32, device=dev) for y in YS for s in SCHEMES}
-    # one stream per group of weight sets (the resamples of different weight
-    # sets are independent); workspaces are per stream.  Stream 0 is the
-    # current stream; the others exist for --streams / --concurrent-streams.
     n_streams = max(1, min(args.streams, len(YS)))
     n_conc = max(1, min(args.concurrent_streams, len(YS)))
-    streams = [torch.cuda.current_stream()] + [torch.cuda.Stream(device=dev)
-                                               for _ in range(max(n_streams, n_conc) - 1)]
-    wsp = {}
-    for k, st in enumerate(streams):
-        with torch.cuda.stream(st):
-            for op in (_lib.OP_MULTINOMIAL, _lib.OP_STRATIFIED, _lib.OP_SYSTEMATIC,
-                       _lib.OP_PERMUTE):
-                wsp[(k, op)] = pfr.new_workspace(max(256, pfr.workspace_bytes(op, N)), dev)
-    torch.cuda.synchronize()
-    flags = torch.zeros(1, dtype=torch.int32, device=dev)
-    dominant = (4.0, "metropolis")
-    ev = []
-
-    def resample(yi, y, s, k):
-        w = ws_[yi]
-        a = out[(y, s)]
-        if s == "metropolis":
-            pfr.resample_metropolis(w, Bs[yi], seed=1, out=a)
-        elif s == "rejection":
-            pfr.resample_rejection(w, 1.0, seed=1, out=a, flags=flags)
-        else:
-            op = {"multinomial": _lib.OP_MULTINOMIAL, "stratified": _lib.OP_STRATIFIED,
-                  "systematic": _lib.OP_SYSTEMATIC}[s]
-            getattr(pfr, "resample_" + s)(w, seed=1, out=a, flags=flags, workspace=wsp[(k, op)])
-        return a
+    wl = StepWorkload(torch, pfr, dev, max(n_streams, n_conc))
+    Bs, flags, ev, dominant = wl.Bs, wl.flags, wl.ev, wl.DOMINANT
+    out, perm, wsp, ws_ = wl.out, wl.perm, wl.wsp, wl.w
+    resample = wl.resample
 
     def step(record=False, n_st=n_streams):
-        for yi, y in enumerate(YS):
-            k = yi % n_st
-            stream = streams[k]
-            with torch.cuda.stream(stream):
-                for s in SCHEMES:
-                    if s in FUSED:
-                        # the emission writes the claim vector and marks itself
-                        pfr.resample_permuted(s, ws_[yi], seed=1, out=out[(y, s)],
-                                              permuted=perm[(y, s)], flags=flags)
-                        continue
-                    if record and (y, s) == dominant:
-                        e0 = torch.cuda.Event(enable_timing=True)
-                        e1 = torch.cuda.Event(enable_timing=True)
-                        e0.record(stream)
-                        a = resample(yi, y, s, k)
-                        e1.record(stream)
-                        ev.append((e0, e1))
-                    else:
-                        a = resample(yi, y, s, k)
-                    pfr.permute_ancestors(a, sorted_hint=s not in ("metropolis", "rejection"),
-                                          out=perm[(y, s)], flags=flags,
-                                          workspace=wsp[(k, _lib.OP_PERMUTE)])
+        wl.step(record, n_st)
 
     for _ in range(args.warmup):
         step()

@@ -35,7 +35,7 @@ def build(force: bool = True) -> str:
     if not force and os.path.exists(_LIB_PATH):
         return _LIB_PATH
     tmp = _LIB_PATH + ".tmp"
-    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fPIC", "-shared",
+    cmd = ["gcc", "-O2", "-std=c11", "-ffp-contract=off", "-fopenmp", "-fPIC", "-shared",
            "-Wall", "-Wextra", "-o", tmp, _SRC, "-lm"]
     subprocess.run(cmd, check=True)
     os.replace(tmp, _LIB_PATH)
@@ -85,6 +85,13 @@ def _load():
         "orc_lgssm_move": (None, [i32, i32, dbl, dbl, dbl, u32, dbl, u64, u32, u32, P, P, P, P,
                                   P]),
         "orc_kalman_loglik": (dbl, [P, i64, dbl, dbl, dbl, dbl]),
+        "orc_threads": (ctypes.c_int, [ctypes.c_int]),
+        "orc_resample_metropolis_mt": (ctypes.c_int, [P, i64, i32, u64, u32, u32, P,
+                                                      ctypes.c_int]),
+        "orc_resample_rejection_mt": (ctypes.c_int, [P, i64, dbl, u32, u64, u32, u32, P, P, P,
+                                                     ctypes.c_int]),
+        "orc_batch_mt": (ctypes.c_int, [ctypes.c_int, P, P, P, i32, P, dbl, u64, u32, u32, P, P,
+                                        P, P, ctypes.c_int]),
     }
     for name, (res, args) in sig.items():
         fn = getattr(lib, name)
@@ -277,6 +284,64 @@ def multinomial_points(w, p):
     _check(_load().orc_multinomial_points(_ptr(w), w.size, _ptr(p), _ptr(a), _ptr(fl)),
            "multinomial_points")
     return a, int(fl[0])
+
+
+# ------------------------------------------------------------------ all-cores legs
+def default_threads():
+    """Host threads for the all-cores legs: every core, at most 16."""
+    return max(1, min(16, os.cpu_count() or 1))
+
+
+def threads(requested=0):
+    """The number of host threads a call with `requested` threads uses."""
+    return int(_load().orc_threads(int(requested)))
+
+
+def metropolis_mt(w, B, seed=0, filt=0, offset=0, nthreads=None):
+    """metropolis() over disjoint lane ranges on several host threads (same bits)."""
+    w = _w(w)
+    a = np.empty(w.size, dtype=np.int32)
+    nt = default_threads() if nthreads is None else int(nthreads)
+    _check(_load().orc_resample_metropolis_mt(_ptr(w), w.size, int(B), seed, filt, offset,
+                                              _ptr(a), nt), "metropolis_mt")
+    return a
+
+
+def rejection_mt(w, w_max, seed=0, filt=0, offset=0, max_trials=1 << 20, nthreads=None):
+    """rejection() over disjoint lane ranges on several host threads (same bits)."""
+    w = _w(w)
+    a = np.empty(w.size, dtype=np.int32)
+    fl = np.zeros(1, dtype=np.uint32)
+    nt = default_threads() if nthreads is None else int(nthreads)
+    _check(_load().orc_resample_rejection_mt(_ptr(w), w.size, float(w_max), int(max_trials),
+                                             seed, filt, offset, _ptr(a), None, _ptr(fl), nt),
+           "rejection_mt")
+    return a, int(fl[0])
+
+
+BATCH_OPS = {"multinomial": 0, "stratified": 1, "systematic": 2, "metropolis": 3, "rejection": 4}
+
+
+def batch_mt(scheme, w, offsets, segs=None, B=None, w_max=1.0, seed=0, filter_base=0, offset=0,
+             return_rp=False, nthreads=None):
+    """One call per listed vector of a ragged batch, vectors spread over host
+    threads.  Returns (a, flags) or, with return_rp, (a, flags, r, p); entries
+    outside the listed vectors are left unset."""
+    w = _w(w)
+    off = np.ascontiguousarray(offsets, dtype=np.int64)
+    F = off.size - 1
+    segs = np.arange(F, dtype=np.int32) if segs is None else np.ascontiguousarray(segs,
+                                                                               dtype=np.int32)
+    Bv = None if B is None else np.ascontiguousarray(B, dtype=np.int32)
+    a = np.full(w.size, -1, dtype=np.int32)
+    r = np.full(w.size, np.nan) if return_rp else None
+    p = np.full(w.size, np.nan) if (return_rp and scheme == "multinomial") else None
+    fl = np.zeros(1, dtype=np.uint32)
+    nt = default_threads() if nthreads is None else int(nthreads)
+    _check(_load().orc_batch_mt(BATCH_OPS[scheme], _ptr(w), _ptr(off), _ptr(segs), segs.size,
+                                _ptr(Bv), float(w_max), int(seed) & (2**64 - 1), filter_base,
+                                offset, _ptr(a), _ptr(r), _ptr(p), _ptr(fl), nt), "batch_mt")
+    return (a, int(fl[0]), r, p) if return_rp else (a, int(fl[0]))
 
 
 # ------------------------------------------------------------------ auxiliaries

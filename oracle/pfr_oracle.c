@@ -144,12 +144,12 @@ static uint32_t ws_word(word_stream* s, int64_t k)
 /* j) and 3n+2 (for u) of lane i's stream in the trial domain, so four steps */
 /* use three Philox calls.                                                   */
 /* ------------------------------------------------------------------------ */
-int orc_resample_metropolis(const double* w, int64_t n, int32_t B, uint64_t seed,
-                            uint32_t filter, uint32_t offset, int32_t* a)
+/* Lanes [i0, i1) of Code 2 on the n weights (every lane reads all of w). */
+static void metropolis_lanes(const double* w, int64_t n, int32_t B, uint64_t seed,
+                             uint32_t filter, uint32_t offset, int64_t i0, int64_t i1, int32_t* a)
 {
     int64_t i;
-    if (n < 0 || B < 0 || (n > 0 && (!w || !a))) return -1;
-    for (i = 0; i < n; ++i) {
+    for (i = i0; i < i1; ++i) {
         int64_t k = i;
         int32_t step;
         word_stream s;
@@ -164,6 +164,13 @@ int orc_resample_metropolis(const double* w, int64_t n, int32_t B, uint64_t seed
         }
         a[i] = (int32_t)k;
     }
+}
+
+int orc_resample_metropolis(const double* w, int64_t n, int32_t B, uint64_t seed,
+                            uint32_t filter, uint32_t offset, int32_t* a)
+{
+    if (n < 0 || B < 0 || (n > 0 && (!w || !a))) return -1;
+    metropolis_lanes(w, n, B, seed, filter, offset, 0, n, a);
     return 0;
 }
 
@@ -174,14 +181,14 @@ int orc_resample_metropolis(const double* w, int64_t n, int32_t B, uint64_t seed
 /* 0 uses only that call's u.  A lane that rejects max_trials proposals ends */
 /* with a_i = i and raises ORC_FLAG_TRIAL_CAP (the paper's loop has no cap). */
 /* ------------------------------------------------------------------------ */
-int orc_resample_rejection(const double* w, int64_t n, double w_max, uint32_t max_trials,
-                           uint64_t seed, uint32_t filter, uint32_t offset, int32_t* a,
-                           uint32_t* trials, uint32_t* flags)
+/* Lanes [i0, i1) of Code 3; returns the flags they raise. */
+static uint32_t rejection_lanes(const double* w, int64_t n, double w_max, uint32_t max_trials,
+                                uint64_t seed, uint32_t filter, uint32_t offset, int64_t i0,
+                                int64_t i1, int32_t* a, uint32_t* trials)
 {
     int64_t i;
     uint32_t fl = 0;
-    if (n < 0 || max_trials == 0 || (n > 0 && (!w || !a))) return -1;
-    for (i = 0; i < n; ++i) {
+    for (i = i0; i < i1; ++i) {
         uint32_t x[4], t = 0;
         int64_t j = i;
         double u;
@@ -205,6 +212,16 @@ int orc_resample_rejection(const double* w, int64_t n, double w_max, uint32_t ma
         a[i] = (int32_t)j;
         if (trials) trials[i] = t + 1;
     }
+    return fl;
+}
+
+int orc_resample_rejection(const double* w, int64_t n, double w_max, uint32_t max_trials,
+                           uint64_t seed, uint32_t filter, uint32_t offset, int32_t* a,
+                           uint32_t* trials, uint32_t* flags)
+{
+    uint32_t fl;
+    if (n < 0 || max_trials == 0 || (n > 0 && (!w || !a))) return -1;
+    fl = rejection_lanes(w, n, w_max, max_trials, seed, filter, offset, 0, n, a, trials);
     if (flags) *flags |= fl;
     return 0;
 }
@@ -766,4 +783,112 @@ double orc_kalman_loglik(const double* y, int64_t T, double phi, double q, doubl
         P = (1.0 - K) * P;
     }
     return ll;
+}
+
+/* ------------------------------------------------------------------------ */
+/* All-cores legs.  The lanes of Codes 2 and 3 and the vectors of a batch    */
+/* are independent and every random number is keyed on (lane, filter), so    */
+/* running the serial functions above over disjoint ranges on several host    */
+/* threads gives the serial result bit for bit.  Used to time the oracle on  */
+/* every host core and to check large cases; the arithmetic is the serial    */
+/* code's.                                                                   */
+/* ------------------------------------------------------------------------ */
+#ifdef _OPENMP
+#include <omp.h>
+#endif
+
+#define ORC_MT_CHUNK 2048
+
+int orc_threads(int requested)
+{
+#ifdef _OPENMP
+    return requested > 0 ? requested : omp_get_max_threads();
+#else
+    (void)requested;
+    return 1;
+#endif
+}
+
+int orc_resample_metropolis_mt(const double* w, int64_t n, int32_t B, uint64_t seed,
+                               uint32_t filter, uint32_t offset, int32_t* a, int nthreads)
+{
+    int64_t c, nc;
+    if (n < 0 || B < 0 || (n > 0 && (!w || !a))) return -1;
+    nc = (n + ORC_MT_CHUNK - 1) / ORC_MT_CHUNK;
+#pragma omp parallel for schedule(dynamic, 1) num_threads(orc_threads(nthreads))
+    for (c = 0; c < nc; ++c) {
+        const int64_t i0 = c * ORC_MT_CHUNK;
+        const int64_t i1 = (i0 + ORC_MT_CHUNK < n) ? i0 + ORC_MT_CHUNK : n;
+        metropolis_lanes(w, n, B, seed, filter, offset, i0, i1, a);
+    }
+    return 0;
+}
+
+int orc_resample_rejection_mt(const double* w, int64_t n, double w_max, uint32_t max_trials,
+                              uint64_t seed, uint32_t filter, uint32_t offset, int32_t* a,
+                              uint32_t* trials, uint32_t* flags, int nthreads)
+{
+    int64_t c, nc;
+    uint32_t fl = 0;
+    if (n < 0 || max_trials == 0 || (n > 0 && (!w || !a))) return -1;
+    nc = (n + ORC_MT_CHUNK - 1) / ORC_MT_CHUNK;
+#pragma omp parallel for schedule(dynamic, 1) reduction(|:fl) num_threads(orc_threads(nthreads))
+    for (c = 0; c < nc; ++c) {
+        const int64_t i0 = c * ORC_MT_CHUNK;
+        const int64_t i1 = (i0 + ORC_MT_CHUNK < n) ? i0 + ORC_MT_CHUNK : n;
+        fl |= rejection_lanes(w, n, w_max, max_trials, seed, filter, offset, i0, i1, a, trials);
+    }
+    if (flags) *flags |= fl;
+    return 0;
+}
+
+/* One resampler per vector of a ragged batch: vector f holds positions
+ * [off[f], off[f+1]) and is resampled as a call on it alone with filter id
+ * filter_base + f, ancestors local to the vector.  Only the vectors listed
+ * in segs[0..n_segs) are computed (their outputs a, and r_out / p_out when
+ * not NULL, at the vector's positions).  op: 0 multinomial, 1 stratified,
+ * 2 systematic, 3 Metropolis (B[f] steps), 4 rejection (bound w_max). */
+int orc_batch_mt(int op, const double* w, const int64_t* off, const int32_t* segs, int32_t n_segs,
+                 const int32_t* B, double w_max, uint64_t seed, uint32_t filter_base,
+                 uint32_t offset, int32_t* a, double* r_out, double* p_out, uint32_t* flags,
+                 int nthreads)
+{
+    int32_t k;
+    int bad = 0;
+    uint32_t fl = 0;
+    if (op < 0 || op > 4 || !w || !off || !segs || n_segs < 0 || !a) return -1;
+    if (op == 3 && !B) return -1;
+#pragma omp parallel for schedule(dynamic, 1) reduction(|:fl) reduction(|:bad) \
+    num_threads(orc_threads(nthreads))
+    for (k = 0; k < n_segs; ++k) {
+        const int32_t f = segs[k];
+        const int64_t o = off[f], m = off[f + 1] - off[f];
+        const uint32_t filt = filter_base + (uint32_t)f;
+        uint32_t sfl = 0;
+        int rc = 0;
+        double* r = r_out ? r_out + o : NULL;
+        switch (op) {
+        case 0:
+            rc = orc_resample_multinomial(w + o, m, seed, filt, offset, a + o, r,
+                                          p_out ? p_out + o : NULL, &sfl);
+            break;
+        case 1:
+            rc = orc_resample_stratified(w + o, m, seed, filt, offset, a + o, r, &sfl);
+            break;
+        case 2:
+            rc = orc_resample_systematic(w + o, m, seed, filt, offset, a + o, r, &sfl);
+            break;
+        case 3:
+            rc = orc_resample_metropolis(w + o, m, B[f], seed, filt, offset, a + o);
+            break;
+        default:
+            rc = orc_resample_rejection(w + o, m, w_max, 1u << 20, seed, filt, offset, a + o,
+                                        NULL, &sfl);
+            break;
+        }
+        fl |= sfl;
+        bad |= (rc != 0);
+    }
+    if (flags) *flags |= fl;
+    return bad ? -1 : 0;
 }

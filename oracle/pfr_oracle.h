@@ -130,6 +130,25 @@ int orc_ess(const double* w, int64_t n, double* ess, uint32_t* flags);
 int orc_copy_rows(const int32_t* c, int64_t n, int64_t dim, const double* x_in, double* x_out,
                   uint32_t* flags);
 
+/* All-cores legs: the serial functions above run over disjoint lane ranges
+ * (or vectors) on `nthreads` host threads (<= 0: every core OpenMP sees),
+ * with the serial result bit for bit.  For timing the oracle on the host's
+ * cores and for large test cases. */
+int orc_threads(int requested);
+int orc_resample_metropolis_mt(const double* w, int64_t n, int32_t B, uint64_t seed,
+                               uint32_t filter, uint32_t offset, int32_t* a, int nthreads);
+int orc_resample_rejection_mt(const double* w, int64_t n, double w_max, uint32_t max_trials,
+                              uint64_t seed, uint32_t filter, uint32_t offset, int32_t* a,
+                              uint32_t* trials, uint32_t* flags, int nthreads);
+/* One resampler per listed vector of a ragged batch (vector f = positions
+ * [off[f], off[f+1]), filter id filter_base + f, local ancestors); op 0..4 =
+ * multinomial, stratified, systematic, Metropolis (B[f]), rejection (w_max,
+ * trial cap 2^20).  r_out / p_out (may be NULL) as for the single calls. */
+int orc_batch_mt(int op, const double* w, const int64_t* off, const int32_t* segs, int32_t n_segs,
+                 const int32_t* B, double w_max, uint64_t seed, uint32_t filter_base,
+                 uint32_t offset, int32_t* a, double* r_out, double* p_out, uint32_t* flags,
+                 int nthreads);
+
 /* Code 10 (Prepermute + Permute); c receives the permuted ancestry, d (may be
  * NULL) the final claim vector (n = unclaimed). */
 int orc_permute(const int32_t* a, int64_t n, int32_t* c, int32_t* d, uint32_t* flags);
