@@ -61,7 +61,12 @@ typedef enum {
 typedef enum { PFR_F32 = 0, PFR_F64 = 1 } pfr_dtype;
 
 /* Arithmetic of the prefix sum of the collective resamplers.
- *   PFR_SCAN_EXACT      exact fixed-point sums (default; see below)
+ *   PFR_SCAN_EXACT      fixed-point sums, exact for the quantised weights
+ *                       (default; see below): every float32 weight within
+ *                       2^29 of its block maximum, and every binary64 weight
+ *                       whose bits lie within 53 bits of the block maximum's
+ *                       exponent, is summed without error; smaller ones are
+ *                       truncated to that grid (error below max(w) 2^-52)
  *   PFR_SCAN_F64        binary64 sums and scaling
  *   PFR_SCAN_COMP_F32   compensated (two-sum) binary32 sums, binary64 scaling
  *   PFR_SCAN_NAIVE_F32  binary32 sums and the literal binary32 floor(r + u) of
@@ -186,10 +191,11 @@ PFR_API int resample_systematic(const void* w, pfr_dtype dtype, const pfr_segmen
  * Lane i's words come from Philox calls (i, 2<<28 | c), word m being word
  * m&3 of call m>>2; step s takes words x0, x1, x2 = 3s, 3s+1, 3s+2 (four steps
  * per three calls), proposes j = floor(((x1<<32)|x0) n / 2^64) with
- * u = (x2 + 1) 2^-32, and moves to j when u w_k <= w_j, decided exactly (one
- * fused multiply-add, rounded once, keeps the sign of u w_k - w_j) for every
- * float32 weight, and for binary64 weights as long as w_k is zero or at least
- * 2^-990.  B_dev (device int32[n_filters], may be NULL) overrides B per segment.
+ * u = (x2 + 1) 2^-32, and moves to j when u w_k <= w_j, decided exactly for
+ * every weight, subnormal binary64 weights included (one fused multiply-add,
+ * rounded once, keeps the sign of u w_k - w_j whenever the weights lie on the
+ * 2^-1042 lattice; a zero result with w_k below 2^-900 is re-decided on both
+ * weights scaled by 2^200).  B_dev (device int32[n_filters], may be NULL) overrides B per segment.
  * No collective operation: the chains are independent, so the output does
  * not depend on the launch shape.  Segments of up to 16K (float32) or 8K
  * (float64) weights, and with pfr_segments.max_len set up to 32K / 16K, are
@@ -204,8 +210,7 @@ PFR_API int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segmen
 /* Rejection resampling (Code 3): particle i first proposes j = i, then draws
  * j as above from Philox call (i, 2<<28 | t) for trial t >= 1 (every trial
  * takes u from its own call), and keeps the first j with u w_max <= w_j
- * (decided exactly as for resample_metropolis, here for w_max of at least
- * 2^-990).  w_max must bound the weights (else the output is
+ * (decided exactly as for resample_metropolis, for any w_max).  w_max must bound the weights (else the output is
  * biased); w_max_dev (device double[n_filters], may be NULL) overrides it per
  * segment.  After max_trials trials (>= 1) a particle keeps a_i = i and
  * PFR_FLAG_TRIAL_CAP is raised.  No collective operation; LDS staging and

@@ -13,7 +13,9 @@ provides memory and streams.  Nothing here computes on the CPU.
 """
 from __future__ import annotations
 
+import collections
 import ctypes
+import os
 
 from . import _lib
 from ._lib import (FLAG_BAD_ANCESTOR, FLAG_BAD_COUNTS, FLAG_BAD_STEP, FLAG_BAD_WEIGHTS,
@@ -117,10 +119,39 @@ def _rng(seed, offset, filter_base, offset_dev=None):
                     None if offset_dev is None else offset_dev.data_ptr())
 
 
-# workspaces are zeroed once and reused; calls sharing one must be ordered, so
-# the cache keeps one per (device, stream, op, size): calls on different
-# streams never share a cached workspace
-_WS_CACHE: dict = {}
+class _WorkspaceCache:
+    """Workspaces are zeroed once and reused; calls sharing one must be
+    ordered, so there is one per (device, stream, op, size): calls on
+    different streams never share a cached workspace.  The least recently
+    used ones are dropped once the cached bytes exceed the budget
+    ($PFR_WS_CACHE_BYTES, default 4 GiB); a dropped workspace goes back to
+    torch's stream-ordered allocator, so work already enqueued on its stream
+    still finds it intact."""
+
+    def __init__(self, budget):
+        self.budget = int(budget)
+        self.items = collections.OrderedDict()
+        self.bytes = 0
+
+    def get(self, key):
+        ws = self.items.get(key)
+        if ws is not None:
+            self.items.move_to_end(key)
+        return ws
+
+    def put(self, key, ws):
+        self.items[key] = ws
+        self.bytes += ws.numel()
+        while self.bytes > self.budget and len(self.items) > 1:
+            _, old = self.items.popitem(last=False)
+            self.bytes -= old.numel()
+
+    def clear(self):
+        self.items.clear()
+        self.bytes = 0
+
+
+_WS_CACHE = _WorkspaceCache(int(os.environ.get("PFR_WS_CACHE_BYTES", 4 << 30)))
 
 
 def _stream_key():
@@ -151,7 +182,7 @@ def _workspace(op, seg, dtype_code, device, ws):
     cached = _WS_CACHE.get(key)
     if cached is None:
         cached = new_workspace(need, device)
-        _WS_CACHE[key] = cached
+        _WS_CACHE.put(key, cached)
     return cached, need
 
 
@@ -303,7 +334,7 @@ def resample_permuted(scheme, w, seed=0, offset=0, filter_base=0, precision=SCAN
         workspace = _WS_CACHE.get(key)
         if workspace is None:
             workspace = new_workspace(need, w.device)
-            _WS_CACHE[key] = workspace
+            _WS_CACHE.put(key, workspace)
     params = _lib.SchemeParams(int(precision), int(B), None if B_per_filter is None
                                else B_per_filter.data_ptr(), float(w_max),
                                None if w_max_per_filter is None else w_max_per_filter.data_ptr(),

@@ -77,10 +77,11 @@ __device__ __forceinline__ void metropolis_fetch(const T* __restrict__ ws, Key k
   }
 }
 
+template <typename T>
 __device__ __forceinline__ void metropolis_accept(const MGroup& g, uint32_t& k, double& wk) {
 #pragma unroll
   for (int q = 0; q < 4; ++q) {
-    if (q < g.nq && accept_exact(u_accept(g.u[q]), wk, g.wj[q])) {
+    if (q < g.nq && accept_exact<T>(u_accept(g.u[q]), wk, g.wj[q])) {
       k = g.j[q];
       wk = g.wj[q];
     }
@@ -109,7 +110,7 @@ __device__ __forceinline__ uint32_t metropolis_chain(const T* ws, Key key, uint3
   for (int32_t m = 0; m < groups; ++m) {
     MGroup g;
     metropolis_fetch(ws, key, i, pl, filt, offset, n, steps, m, g);
-    metropolis_accept(g, k, wk);
+    metropolis_accept<T>(g, k, wk);
   }
   return k;
 }
@@ -160,10 +161,10 @@ __global__ __launch_bounds__(THREADS) void k_metropolis_staged(
         for (int32_t m = 0; m < groups; m += 2) {
           if (m + 1 < groups)
             metropolis_fetch(ws, key, i, pl, filt, offset, n, steps, m + 1, gb);
-          metropolis_accept(ga, k, wk);
+          metropolis_accept<T>(ga, k, wk);
           if (m + 2 < groups)
             metropolis_fetch(ws, key, i, pl, filt, offset, n, steps, m + 2, ga);
-          if (m + 1 < groups) metropolis_accept(gb, k, wk);
+          if (m + 1 < groups) metropolis_accept<T>(gb, k, wk);
         }
         a[g] = (int32_t)k;
       }
@@ -366,7 +367,7 @@ __global__ __launch_bounds__(kTableThreads) void k_metropolis_table(
           for (int c = 0; c < K; ++c) {
             // selects, not a branch: the gathered value is used on every lane,
             // so the gathers cannot be sunk into per-chain branches
-            const bool acc = need[c] & accept_exact(u[c], wk[c], v[c]);
+            const bool acc = need[c] & accept_exact<T>(u[c], wk[c], v[c]);
             k[c] = acc ? j[c] : k[c];
             wk[c] = acc ? v[c] : wk[c];
           }
@@ -485,7 +486,7 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
       }
       bool accq[kRejBatch];
 #pragma unroll
-      for (int q = 0; q < kRejBatch; ++q) accq[q] = live[q] & accept_exact(uq[q], wmax, vq[q]);
+      for (int q = 0; q < kRejBatch; ++q) accq[q] = live[q] & accept_exact<double>(uq[q], wmax, vq[q]);
       int first = -1;
 #pragma unroll
       for (int q = kRejBatch - 1; q >= 0; --q)
@@ -560,7 +561,7 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
       }
 #pragma unroll
       for (int b = kRejBatch - 1; b >= 0; --b) {
-        if (live[b] & accept_exact(ub[b], wmax, vb[b])) {
+        if (live[b] & accept_exact<double>(ub[b], wmax, vb[b])) {
           acc = true;
           jj = jb[b];
         }

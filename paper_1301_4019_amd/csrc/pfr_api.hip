@@ -5,16 +5,24 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <mutex>
+
 #include "pfresample.h"
 #include "pfr_kernels.h"
 
 namespace pfr {
 
 namespace {
+// Set by pfr_set_tuning, read by the launchers of any host thread: every
+// access holds the lock, and readers get a copy.
+std::mutex g_tuning_mu;
 Tuning g_tuning = {4096, 2048, 32, 1, 256, 256};
 }  // namespace
 
-const Tuning& tuning() { return g_tuning; }
+Tuning tuning() {
+  std::lock_guard<std::mutex> lock(g_tuning_mu);
+  return g_tuning;
+}
 
 }  // namespace pfr
 
@@ -521,7 +529,7 @@ void pfr_tuning_defaults(pfr_tuning* t) {
 
 int pfr_get_tuning(pfr_tuning* t) {
   if (!t) return PFR_EINVAL;
-  const Tuning& g = tuning();
+  const Tuning g = tuning();
   t->version = PFR_TUNING_VERSION;
   t->single_wg_max = g.single_wg_max;
   t->direct_max_blocks = g.direct_max_blocks;
@@ -541,6 +549,7 @@ int pfr_set_tuning(const pfr_tuning* t) {
   if (t->rejection_per_wave < 64 || t->rejection_per_wave > 4096) return PFR_EINVAL;
   if (t->metropolis_chunk < 256 || t->metropolis_chunk > 8192 || t->metropolis_chunk % 256)
     return PFR_EINVAL;
+  std::lock_guard<std::mutex> lock(g_tuning_mu);
   g_tuning.single_wg_max = t->single_wg_max;
   g_tuning.direct_max_blocks = t->direct_max_blocks;
   g_tuning.metropolis_table_min_B = t->metropolis_table_min_B;

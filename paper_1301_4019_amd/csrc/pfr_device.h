@@ -94,13 +94,22 @@ __device__ __forceinline__ uint32_t index_draw(uint32_t x0, uint32_t x1, uint32_
   return (uint32_t)__umul64hi(r, (uint64_t)n);
 }
 
-// Exact u * wk <= wj.  One fused multiply-add forms u wk - wj exactly and
-// rounds it once; rounding to nearest keeps the sign and maps only zero to
-// zero as long as a nonzero difference exceeds 2^-1075.  It does whenever wk
-// and wj lie on the 2^-1042 lattice (u wk then lies on the 2^-1074 lattice):
-// every float32 weight, and binary64 weights from 2^-990 up (zero included).
+// Exact u * wk <= wj for weights of type T (u on the 2^-32 lattice).  One
+// fused multiply-add forms u wk - wj exactly and rounds it once; rounding to
+// nearest keeps the sign and maps only zero to zero as long as a nonzero
+// difference exceeds 2^-1075.  It does whenever wk and wj lie on the 2^-1042
+// lattice (u wk then lies on the 2^-1074 lattice): every float32 weight, and
+// binary64 weights from 2^-990 up (zero included).  Below that a nonzero
+// difference of binary64 weights can round to zero; then both weights are
+// below 2^-900 (they differ by less than 2^-1075), so the test is repeated on
+// both scaled by 2^200, which is exact and puts them back on the lattice.
+template <typename T>
 __device__ __forceinline__ bool accept_exact(double u, double wk, double wj) {
-  return __fma_rn(u, wk, -wj) <= 0.0;
+  double d = __fma_rn(u, wk, -wj);
+  if constexpr (sizeof(T) == 8) {
+    if (d == 0.0 && wk < 0x1p-900) d = __fma_rn(u, wk * 0x1p200, -(wj * 0x1p200));
+  }
+  return d <= 0.0;
 }
 
 // ------------------------------------------------------------------ buffer gathers

@@ -21,13 +21,13 @@ struct Tuning {
   int32_t rejection_per_wave;      // particles per wave of the rejection schedule
   int32_t metropolis_chunk;        // particles per workgroup of the global-memory Metropolis kernel
 };
-const Tuning& tuning();
+Tuning tuning();  // a copy of the current settings (thread-safe)
 
 // Collective schemes handled by the scan kernels.
 enum Scheme : int { SCHEME_MULTINOMIAL = 0, SCHEME_STRATIFIED = 1, SCHEME_SYSTEMATIC = 2 };
 
-// Canonical quantisation block of the exact prefix sums: 1024 weights, one
-// wave (64 lanes x 16 values).  A reduce workgroup covers kBlocksPerWG blocks.
+// Canonical quantisation block of the exact prefix sums: 1024 weights, held
+// by one workgroup of kWGThreads = 256 threads, 4 consecutive weights each.
 constexpr int kBlock = 1024;
 constexpr int kBlocksPerWG = 4;
 constexpr int kWGThreads = kWave * kBlocksPerWG;

@@ -104,9 +104,23 @@ def test_steps_match_oracle(scheme):
         assert ulp_close(host(flt.x), xo, 2)
         assert ulp_close(host(flt.w), wo, 4)
         np.testing.assert_allclose(host(flt.log_z), lzo, rtol=1e-12, atol=1e-12)
-        assert np.array_equal(host(flt.B), Bo)
+        check_B(host(flt.B), Bo, wo, F, n)
         assert int(host(flt.t)[0]) == t + 1
     assert int(host(flt.flags)[0]) == 0
+
+
+def check_B(B_gpu, B_or, w_or, F, n):
+    """B of eq. (B) per filter.  The GPU and the oracle form the weights with
+    different libm calls (a few ulps apart), so their beta differ in the last
+    bits and B = ceil(log eps / log(1 - beta)) may differ by one, but only
+    where log eps / log(1 - beta) lies next to an integer; the resampled
+    ancestors are checked with the GPU's own B."""
+    diff = np.nonzero(B_gpu != B_or)[0]
+    for f in diff:
+        beta = float(np.mean(w_or[f * n:(f + 1) * n].astype(np.float64)))
+        bstar = np.log(0.01) / np.log1p(-beta)
+        assert abs(int(B_gpu[f]) - int(B_or[f])) == 1, f
+        assert abs(bstar - round(bstar)) < 1e-5 * bstar, (f, bstar)
 
 
 @pytest.mark.parametrize("scheme", ["systematic", "metropolis"])

@@ -86,8 +86,8 @@ def test_ragged_batch_full_size_sampled(batch):
 @pytest.mark.parametrize("scheme", ["systematic", "stratified", "multinomial"])
 @pytest.mark.parametrize("n", [1 << 22, (1 << 23) + 999])
 def test_collective_long_vectors(scheme, n):
-    """Long enough for the persistent, pipelined emission (several blocks per
-    workgroup), with a ragged last block."""
+    """Long vectors (4096 and 8193 weight blocks, hence the separate carries
+    pass), with a ragged last block."""
     w = inputs.weights(n, 3.0, seed=0)
     a = host(getattr(pfr(), "resample_" + scheme)(torch.from_numpy(w).cuda(), seed=5))
     check_collective(scheme, w.astype(np.float64), a, seed=5, filt=0)

@@ -341,6 +341,25 @@ def test_alternatives_tiny_binary64_weights(n):
     assert np.array_equal(a, oracle.rejection(w, wmax, seed=4)[0])
 
 
+@pytest.mark.parametrize("n", [5000, 1 << 17, 1 << 20])
+def test_alternatives_subnormal_binary64_weights(n):
+    """Binary64 weights k 2^-1074, k = 0..7 (subnormal): a rounded fused
+    multiply-add maps many nonzero differences u w_k - w_j to zero here (for
+    w_k = 3 2^-1074, w_j = 2^-1074 every u in (1/3, 1/2) does), so the exact
+    accept test must decide them on rescaled weights.  Metropolis (staged, global
+    and bound-table paths) and rejection must give the oracle's ancestors (Code 2
+    and Code 3 with the exact test)."""
+    rng = np.random.default_rng(n + 3)
+    w = rng.integers(0, 8, size=n).astype(np.float64) * 2.0**-1074
+    w[0] = 7 * 2.0**-1074
+    assert np.all((w == 0) | (w < 2.0**-1070))
+    a = host(pfr().resample_metropolis(dev(w), 24, seed=6))
+    assert np.array_equal(a, oracle.metropolis(w, 24, seed=6))
+    wmax = float(w.max())
+    a = host(pfr().resample_rejection(dev(w), wmax, seed=6))
+    assert np.array_equal(a, oracle.rejection(w, wmax, seed=6)[0])
+
+
 @pytest.mark.parametrize("max_trials", [1, 3, 7, 13])
 def test_rejection_table_trial_cap(max_trials):
     """A bound far above the weights on the bound-table path: passes of four
@@ -441,9 +460,11 @@ def test_permute_batched_lds_and_global_segments(hint, max_len):
         a = g.choice(s, size=s, p=p / p.sum()).astype(np.int32) if s else np.zeros(0, np.int32)
         parts.append(np.sort(a) if hint else a)
     a = np.concatenate(parts).astype(np.int32)
-    a[3] = 99  # out of range: treated as its own index, flagged
+    # out of range: treated as its own index and flagged; at the end of the
+    # first segment it keeps a sorted ancestry sorted
+    a[4 if hint else 3] = 99
     fl = new_flags()
-    c = host(pfr().permute_ancestors(dev(a), sorted_hint=hint and False, offsets=dev(off),
+    c = host(pfr().permute_ancestors(dev(a), sorted_hint=hint, offsets=dev(off),
                                      max_len=max(sizes) if max_len else None, flags=fl))
     for f, s in enumerate(sizes):
         if s == 0:
