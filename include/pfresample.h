@@ -55,7 +55,8 @@ typedef enum {
     PFR_EINVAL = 1,     /* invalid argument (null pointer, size, alias, ...) */
     PFR_EWORKSPACE = 2, /* workspace missing, too small or misaligned */
     PFR_ELAUNCH = 3,    /* a kernel launch failed */
-    PFR_ENOTSUP = 4     /* combination not supported */
+    PFR_ENOTSUP = 4,    /* combination not supported */
+    PFR_ETOOBIG = 5     /* input beyond the fixed scratch of a no-allocation entry point */
 } pfr_status;
 
 typedef enum { PFR_F32 = 0, PFR_F64 = 1 } pfr_dtype;
@@ -294,6 +295,24 @@ PFR_API int offspring_to_ancestors(const int32_t* offspring, const pfr_segments*
 PFR_API int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t sorted_hint,
                       int32_t* permuted, void* ws, size_t ws_bytes, uint32_t* dev_flags,
                       void* stream);
+
+/* permute_ancestors without a workspace argument, for callers that cannot
+ * allocate device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc).  Same arguments, result and flags as
+ * permute_ancestors with the workspace removed; the claim vector and the
+ * marked ancestry live in a static device array of
+ * PFR_NOALLOC_SCRATCH_BYTES inside the library (one per GPU, held until the
+ * process ends), so n_total is limited to PFR_NOALLOC_MAX_N: a longer input
+ * returns PFR_ETOOBIG and enqueues nothing.  Every call on one GPU uses that
+ * GPU's one array: calls that overlap in time on the same GPU (different
+ * streams, or host threads without ordering) race and give undefined
+ * results; order them.  The call allocates nothing (no hipMalloc, no library
+ * allocation); its first call on a device looks up the array's address. */
+#define PFR_NOALLOC_MAX_N (1 << 22)
+#define PFR_NOALLOC_SCRATCH_BYTES ((size_t)32 << 20)
+PFR_API int permute_ancestors_noalloc(const int32_t* ancestors, const pfr_segments* seg,
+                                      int32_t sorted_hint, int32_t* permuted,
+                                      uint32_t* dev_flags, void* stream);
 
 /* Ancestors to offspring counts (appendix D, Code 12): o_j = #{i : a_i = j}.
  * With sorted_hint != 0 the ancestry must be non-decreasing (as produced by

@@ -379,6 +379,24 @@ def permute_ancestors(a, sorted_hint=False, offsets=None, max_len=None, out=None
     return c
 
 
+def permute_ancestors_noalloc(a, sorted_hint=False, offsets=None, max_len=None, out=None,
+                              flags=None):
+    """permute_ancestors with the library's static device scratch instead of a
+    workspace (at most NOALLOC_MAX_N particles).  The call itself allocates
+    nothing on the device when `out` is given."""
+    torch = _torch()
+    _require_cuda(a, flags)
+    if a.dtype != torch.int32:
+        raise TypeError("ancestors must be int32")
+    seg = _segments(a.numel(), offsets, max_len)
+    c = _out_like(a.numel(), a.device, out)
+    rc = _lib.load().permute_ancestors_noalloc(_ptr(a), ctypes.byref(seg),
+                                               1 if sorted_hint else 0, _ptr(c), _ptr(flags),
+                                               _stream())
+    _lib.check(rc, "permute_ancestors_noalloc")
+    return c
+
+
 def ancestors_to_offspring(a, sorted_hint=False, offsets=None, max_len=None, out=None,
                            flags=None):
     """Offspring counts o_j = #{i : a_i = j} (Code 12); atomic-free when

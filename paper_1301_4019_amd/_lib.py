@@ -13,7 +13,7 @@ import os
 HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(HERE, "libpfresample.so")
 
-PFR_OK, PFR_EINVAL, PFR_EWORKSPACE, PFR_ELAUNCH, PFR_ENOTSUP = range(5)
+PFR_OK, PFR_EINVAL, PFR_EWORKSPACE, PFR_ELAUNCH, PFR_ENOTSUP, PFR_ETOOBIG = range(6)
 PFR_F32, PFR_F64 = 0, 1
 SCAN_EXACT, SCAN_F64, SCAN_COMP_F32, SCAN_NAIVE_F32 = 0, 1, 2, 3
 (OP_MULTINOMIAL, OP_STRATIFIED, OP_SYSTEMATIC, OP_METROPOLIS, OP_REJECTION,
@@ -27,13 +27,14 @@ FLAG_BAD_WEIGHTS = 8
 FLAG_BAD_ANCESTOR = 16
 FLAG_BAD_STEP = 32
 MAX_BATCH_SEGMENT = 256 * 1024 - 1
+NOALLOC_MAX_N = 1 << 22
 
 EXPORTS = (
     "pfr_workspace_bytes", "pfr_workspace_init", "resample_multinomial",
     "resample_multinomial_iid", "resample_stratified",
     "resample_systematic", "resample_metropolis", "resample_rejection",
     "resample_partial_rejection", "offspring_to_ancestors",
-    "permute_ancestors", "ancestors_to_offspring", "effective_sample_size", "copy_particles",
+    "permute_ancestors", "permute_ancestors_noalloc", "ancestors_to_offspring", "effective_sample_size", "copy_particles",
     "pfr_resample_permuted_workspace_bytes", "resample_permuted",
     "lgssm_workspace_bytes", "lgssm_init", "lgssm_step",
     "pfr_tuning_defaults", "pfr_get_tuning", "pfr_set_tuning", "pfr_load_tuning",
@@ -103,6 +104,7 @@ def open_library(path: str) -> ctypes.CDLL:
         "resample_partial_rejection": (I, [P, I, SEG, D, P, U32, Rng, P, P, P, SZ, P, P]),
         "offspring_to_ancestors": (I, [P, SEG, P, P, SZ, P, P]),
         "permute_ancestors": (I, [P, SEG, I32, P, P, SZ, P, P]),
+        "permute_ancestors_noalloc": (I, [P, SEG, I32, P, P, P]),
         "pfr_resample_permuted_workspace_bytes": (SZ, [I, SEG, I]),
         "resample_permuted": (I, [I, P, I, SEG, ctypes.POINTER(SchemeParams), Rng, P, P, P, SZ,
                                   P, P]),

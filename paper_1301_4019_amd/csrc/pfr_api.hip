@@ -308,6 +308,63 @@ int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t
                                       (hipStream_t)stream));
 }
 
+}  // extern "C"
+
+namespace {
+
+// Scratch of permute_ancestors_noalloc: the claim vector and the marked
+// ancestry (4 + 4 bytes per particle, each part 256-byte aligned) of up to
+// PFR_NOALLOC_MAX_N particles.  One copy per GPU, at that GPU's own address,
+// held until the process ends.  Host code never uses the name `scratch` as an
+// address: the device address comes from hipGetSymbolAddress, once per device.
+static __device__ __align__(256) uint8_t scratch[PFR_NOALLOC_SCRATCH_BYTES];
+
+constexpr int kMaxDevices = 64;
+std::mutex g_scratch_mu;
+void* g_scratch_dev[kMaxDevices];  // device address of `scratch` on each device (or null)
+
+// The current device's scratch address, looked up on the first call on that
+// device.  The permutation writes every claim and mark before reading it, so
+// the scratch needs no clearing.
+int noalloc_scratch(void** out) {
+  int dev = -1;
+  if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PFR_ELAUNCH;
+  std::lock_guard<std::mutex> lock(g_scratch_mu);
+  if (!g_scratch_dev[dev]) {
+    void* p = nullptr;
+    if (hipGetSymbolAddress(&p, HIP_SYMBOL(scratch)) != hipSuccess || !p) return PFR_ELAUNCH;
+    g_scratch_dev[dev] = p;
+  }
+  *out = g_scratch_dev[dev];
+  return PFR_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+int permute_ancestors_noalloc(const int32_t* ancestors, const pfr_segments* seg,
+                              int32_t sorted_hint, int32_t* permuted, uint32_t* dev_flags,
+                              void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (s.n_total == 0) return PFR_OK;
+  if (s.n_total > PFR_NOALLOC_MAX_N) return PFR_ETOOBIG;
+  if (!ancestors || !permuted) return PFR_EINVAL;
+  if (overlaps(ancestors, (size_t)s.n_total * 4, permuted, (size_t)s.n_total * 4))
+    return PFR_EINVAL;
+  static_assert(PFR_NOALLOC_SCRATCH_BYTES >= 2 * (size_t)PFR_NOALLOC_MAX_N * sizeof(int32_t),
+                "the scratch holds the claim vector and the marks of PFR_NOALLOC_MAX_N particles");
+  if (permute_workspace_bytes(s.n_total) > PFR_NOALLOC_SCRATCH_BYTES) return PFR_ETOOBIG;
+  void* ws = nullptr;
+  rc = noalloc_scratch(&ws);
+  if (rc) return rc;
+  return launch_result(launch_permute(ancestors, s.n_total, s.offsets, s.n_filters, s.max_len,
+                                      sorted_hint != 0, permuted, ws, dev_flags,
+                                      (hipStream_t)stream));
+}
+
 int ancestors_to_offspring(const int32_t* ancestors, const pfr_segments* seg, int32_t sorted_hint,
                            int32_t* offspring, uint32_t* dev_flags, void* stream) {
   SegInfo s;
@@ -625,6 +682,8 @@ const char* pfr_status_string(int status) {
     case PFR_EWORKSPACE: return "workspace missing, too small or misaligned";
     case PFR_ELAUNCH: return "kernel launch failed";
     case PFR_ENOTSUP: return "not supported";
+    case PFR_ETOOBIG:
+      return "input longer than the static scratch of the no-allocation entry point allows";
   }
   return "unknown status";
 }

@@ -132,6 +132,17 @@ def test_auxiliary_arguments_rejected_on_host():
     assert need >= lib.pfr_workspace_bytes(_lib.OP_PERMUTE, ctypes.byref(seg(1 << 20)), 0) + \
         lib.pfr_workspace_bytes(_lib.OP_SYSTEMATIC, ctypes.byref(seg(1 << 20)), 0)
     assert ctypes.sizeof(_lib.SchemeParams) == 40
+    # the no-allocation permutation: aliasing, null output, input beyond its
+    # static scratch (rejected before any GPU call)
+    assert lib.permute_ancestors_noalloc(fake, ctypes.byref(seg(10)), 1, fake, None,
+                                         None) == _lib.PFR_EINVAL
+    assert lib.permute_ancestors_noalloc(fake, ctypes.byref(seg(10)), 0, None, None,
+                                         None) == _lib.PFR_EINVAL
+    assert lib.permute_ancestors_noalloc(fake, ctypes.byref(seg(_lib.NOALLOC_MAX_N + 1)), 0, out,
+                                         None, None) == _lib.PFR_ETOOBIG
+    assert lib.permute_ancestors_noalloc(None, ctypes.byref(seg(0)), 0, None, None,
+                                         None) == _lib.PFR_OK
+    assert b"static scratch" in lib.pfr_status_string(_lib.PFR_ETOOBIG)
     # empty input is a no-op
     assert lib.copy_particles(None, ctypes.byref(seg(0)), None, 4, 3, I64(3), I64(1), None,
                               None) == _lib.PFR_OK
