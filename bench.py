@@ -78,27 +78,109 @@ def b_star(y, eps=0.01):
     return math.ceil(math.log(eps) / math.log(1.0 - expected_weight(y)))
 
 
-def cpu_baseline(n_sample: int):
-    """The oracle (single-threaded C, binary128 sums) on the same step at n_sample."""
+def cpu_model():
+    """Host CPU model name and logical core count (from /proc/cpuinfo)."""
+    name, count = "unknown", 0
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    count += 1
+                    name = line.split(":", 1)[1].strip()
+    except OSError:
+        pass
+    return name, count or (os.cpu_count() or 0)
+
+
+def cpu_baseline(n_sample: int, budget_s: float = 30.0, max_runs: int = 5):
+    """The oracle on the benchmark step: every (weight set, resampler) cell at
+    n_sample particles plus its permutation (Code 10), Metropolis and
+    rejection on every host core (their lanes are independent; the all-cores
+    legs give the serial oracle's bits), the collective schemes and the
+    permutation single-threaded (binary128 sums in order).  Each cell's time
+    is the median of up to max_runs runs: every cell runs once, then the
+    cheapest cells run again while the time budget lasts."""
     import oracle
     from paper_1301_4019_amd import inputs
-    t0 = time.perf_counter()
-    done = 0
-    for y in YS:
-        w = inputs.weights(n_sample, y, seed=100 + int(y))
-        for s in SCHEMES:
-            if s == "metropolis":
-                a = oracle.metropolis(w, b_star(y), seed=1)
-            elif s == "rejection":
-                a = oracle.rejection(w, 1.0, seed=1)[0]
-            else:
-                a = getattr(oracle, s)(w, seed=1)[0]
-            oracle.permute(a)
-            done += n_sample
-    dt = time.perf_counter() - t0
-    return {"value": done / dt, "unit": "particles/s", "cores": 1, "kind": "oracle",
-            "sample": f"the full step (5 weight sets x 5 resamplers + permutation) at n = "
-                      f"{n_sample} instead of 2^20; {dt:.1f} s on one host core"}
+    threads = oracle.default_threads()
+
+    def run(w, y, s):
+        if s == "metropolis":
+            a = oracle.metropolis_mt(w, b_star(y), seed=1, nthreads=threads)
+        elif s == "rejection":
+            a = oracle.rejection_mt(w, 1.0, seed=1, nthreads=threads)[0]
+        else:
+            a = getattr(oracle, s)(w, seed=1)[0]
+        oracle.permute(a)
+
+    ws = {y: inputs.weights(n_sample, y, seed=100 + int(y)) for y in YS}
+    times = {(y, s): [] for y in YS for s in SCHEMES}
+    t_start = time.perf_counter()
+    for _ in range(max_runs):
+        order = sorted(times, key=lambda c: float(np.median(times[c])) if times[c] else 0.0)
+        for c in order:
+            if times[c] and len(times[c]) >= max_runs:
+                continue
+            if times[c] and time.perf_counter() - t_start > budget_s:
+                break
+            t0 = time.perf_counter()
+            run(ws[c[0]], c[0], c[1])
+            times[c].append(time.perf_counter() - t0)
+    step_s = sum(float(np.median(v)) for v in times.values())
+    runs = [len(v) for v in times.values()]
+    name, logical = cpu_model()
+    return {"value": len(YS) * len(SCHEMES) * n_sample / step_s, "unit": "particles/s",
+            "cores": threads, "kind": "oracle",
+            "cpu": {"model": name, "logical_cores": logical},
+            "step_s": step_s,
+            "sample": (f"the full step (5 weight sets x 5 resamplers + permutation) at n = "
+                       f"{n_sample}; Metropolis and rejection on {threads} threads, the "
+                       f"collective schemes and the permutation on one; per cell the median of "
+                       f"{min(runs)}-{max(runs)} runs; "
+                       f"{time.perf_counter() - t_start:.1f} s of host time")}
+
+
+def implied_bias(torch, pfr, w, precision, e=None, workspace=None):
+    """Deterministic bias of a precision mode for one weight vector: with r the
+    scaled prefix the mode computes (pfr_scaled_prefix), the stratified and
+    systematic schemes give particle i r_i - r_{i-1} offspring in expectation
+    (the multinomial scheme too, up to its cap), against n w_i / W exactly.
+    Returns sum_i (dr_i - n w_i / W)^2 and max_i |dr_i - n w_i / W|; the
+    reference uses the binary64 weights and a binary64 total."""
+    n = w.numel()
+    if e is None:
+        wd = w.double()
+        e = n * wd / wd.sum()
+    r = pfr.scaled_prefix(w, precision=precision, workspace=workspace)
+    dr = torch.diff(r, prepend=torch.zeros(1, dtype=torch.float64, device=r.device))
+    d = dr - e
+    return float((d * d).sum()), float(d.abs().max())
+
+
+def batch_implied_bias(torch, pfr, w32, off_np):
+    """Deterministic bias (as implied_bias) over the vectors of a ragged batch,
+    for the batched compensated-binary32 form (float32 weights) and the plain
+    per-filter binary64 form (float64 weights): the sum over the vectors and
+    the largest single-vector value."""
+    out = {}
+    w64 = w32.double()
+    # one workspace of the largest vector's size serves every call
+    from paper_1301_4019_amd import _lib
+    max_len = int(np.diff(off_np).max())
+    ws = pfr.new_workspace(pfr.workspace_bytes(_lib.OP_SCALED_PREFIX, max_len), w32.device)
+    for name, ww, prec in (("comp_f32_batched", w32, pfr.SCAN_COMP_F32),
+                           ("f64_per_filter", w64, pfr.SCAN_F64)):
+        tot, worst, dmax = 0.0, 0.0, 0.0
+        for f in range(off_np.size - 1):
+            seg = ww[int(off_np[f]):int(off_np[f + 1])]
+            if seg.numel() == 0:
+                continue
+            b2, mx = implied_bias(torch, pfr, seg, prec, workspace=ws)
+            tot += b2
+            worst = max(worst, b2)
+            dmax = max(dmax, mx)
+        out[name] = {"sum_bias2": tot, "max_bias2_per_vector": worst, "max_abs_dev": dmax}
+    return out
 
 
 def precision_sweep(args):
@@ -110,7 +192,12 @@ def precision_sweep(args):
     are counted on the GPU and accumulated in binary64.  Reported, as in the
     paper's section 3: ||Bias||^2 = sum_i (mean o_i - n w_i / W)^2, the MSE,
     their ratio (about 1 / (K + 1) for an unbiased scheme) and MSE / n, plus
-    the noise-corrected excess ||Bias||^2 - tr(Var) / K.
+    the noise-corrected excess ||Bias||^2 - tr(Var) / K with an approximate
+    standard error (particles treated as independent), and per mode the
+    deterministic bias implied by the scaled prefix the mode computes
+    (implied_bias).  The ragged batch of 4096 vectors adds the deterministic
+    bias of its batched compensated-binary32 form and of the per-filter
+    binary64 form.
     """
     import torch
     import paper_1301_4019_amd as pfr
@@ -123,13 +210,16 @@ def precision_sweep(args):
     modes = {"exact": pfr.SCAN_EXACT, "f64": pfr.SCAN_F64, "comp_f32": pfr.SCAN_COMP_F32,
              "naive_f32": pfr.SCAN_NAIVE_F32}
     flags = torch.zeros(1, dtype=torch.int32, device=dev)
-    rows = []
+    rows, implied = [], []
     t_start = time.perf_counter()
     for lg in args.sweep_log2n:
         n = 1 << lg
         w = torch.from_numpy(inputs.weights(n, y, seed=0)).to(dev)
         wd = w.double()
         e = n * wd / wd.sum()
+        for mode, prec in modes.items():
+            b2, mx = implied_bias(torch, pfr, w, prec, e)
+            implied.append({"n": n, "precision": mode, "bias2": b2, "max_abs_dev": mx})
         a = torch.empty(n, dtype=torch.int32, device=dev)
         cases = [(s, m) for s in ("multinomial", "stratified", "systematic") for m in modes]
         cases += [("metropolis", "-"), ("rejection", "-")]
@@ -148,22 +238,27 @@ def precision_sweep(args):
                 S1 += o
                 S2 += o * o
             mean = S1 / K
-            bias2 = float(((mean - e) ** 2).sum())
+            d = mean - e
+            bias2 = float((d * d).sum())
             mse = float((S2 / K - 2.0 * e * mean + e * e).sum())
-            var_tr = float(((S2 - K * mean * mean) / (K - 1)).sum())
+            v = (S2 - K * mean * mean) / (K - 1)
+            var_tr = float(v.sum())
+            se = math.sqrt(float((4.0 * d * d * v / K + 2.0 * v * v / (K * K)).sum()))
             rows.append({"n": n, "scheme": scheme, "precision": mode, "bias2": bias2, "mse": mse,
                          "bias2_over_mse": bias2 / mse, "mse_over_n": mse / n,
-                         "bias2_excess": bias2 - var_tr / K})
+                         "bias2_excess": bias2 - var_tr / K, "bias2_excess_se": se})
         log(f"n = 2^{lg} done ({time.perf_counter() - t_start:.0f} s)")
     if int(flags.cpu()[0]) != 0:
         raise RuntimeError(f"data flags raised during the sweep: {int(flags.cpu()[0])}")
+    w_np, off_np, _ = inputs.ragged_batch(n_filters=4096, seed=0)
+    batch = batch_implied_bias(torch, pfr, torch.from_numpy(w_np).to(dev), off_np)
     result = {"metric": "bias contribution to the MSE per prefix-sum precision",
               "unit": "ratio", "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
               "config": {"workload": "precision sweep: y = 3 weights (data seed 0), "
                                      f"{K} Philox seeds per case, n = 2^" +
                                      ",".join(str(v) for v in args.sweep_log2n),
                          "replicates": K, "y": y, "unbiased_ratio": 1.0 / (K + 1)},
-              "rows": rows}
+              "rows": rows, "implied": implied, "batch_implied": batch}
     print(json.dumps(result), flush=True)
 
 
@@ -314,7 +409,9 @@ def batched_summary(torch, pfr, inputs, dev, stream, reps=5):
     out["systematic_f64_per_filter_graph"] = F / (1e-3 * timed(g.replay))
     if int(flags.cpu()[0]) != 0:
         raise RuntimeError(f"data flags raised in the batch: {int(flags.cpu()[0])}")
+    stated_bias = batch_implied_bias(torch, pfr, w, off_np)
     return {"unit": "filters/s", "filters": F, "particles": total, "max_len": max_len,
+            "stated_bias": stated_bias,
             "workload": "ragged batch: 4096 float32 weight vectors, N_f = 2^(8+8v), v ~ U[0,1), "
                         "y_f ~ U[0,4] (seed 0); one launch sequence per resampler",
             "filters_per_s": out}
@@ -880,7 +977,11 @@ def main():
     ap.add_argument("--copy-calibration-mb", type=int, default=0,
                     help="first run one device-to-device copy of this many MiB, a kernel of "
                          "known traffic for scaling hardware byte counters")
-    ap.add_argument("--cpu-sample", type=int, default=1 << 18)
+    ap.add_argument("--cpu-sample", type=int, default=N)
+    ap.add_argument("--cpu-budget", type=float, default=30.0,
+                    help="host seconds for repeated oracle runs (each cell runs at least once)")
+    ap.add_argument("--no-cold", action="store_true",
+                    help="skip the cold-cache variant of the step")
     ap.add_argument("--workload", choices=("step", "precision", "batch", "filter", "decision",
                                               "aux", "philox", "scaling"),
                     default="step",
@@ -893,7 +994,7 @@ def main():
     ap.add_argument("--filters", type=int, default=4096)
     ap.add_argument("--filters-ssm", type=int, default=1024)
     ap.add_argument("--filter-reps", type=int, default=3)
-    ap.add_argument("--replicates", type=int, default=256)
+    ap.add_argument("--replicates", type=int, default=1000)
     ap.add_argument("--sweep-log2n", type=int, nargs="+", default=[16, 18, 20, 22, 24])
     ap.add_argument("--decision-log2n", type=int, nargs=2, default=[4, 22])
     ap.add_argument("--decision-reps", type=int, default=20)
@@ -989,6 +1090,32 @@ def main():
     particles = len(YS) * len(SCHEMES) * N
     value = particles * args.steps / elapsed
 
+    # the same step with cold caches: a 512 MiB write (twice the Infinity
+    # Cache) before each step, HIP events around the step alone
+    cold = None
+    if not args.no_cold:
+        flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+        cur = torch.cuda.current_stream()
+        t_cold = []
+        for r in range(args.steps):
+            flush.fill_(r & 0xFF)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(cur)
+            step()
+            e1.record(cur)
+            e1.synchronize()
+            t_cold.append(e0.elapsed_time(e1))
+        del flush
+        ms_cold = float(np.median(t_cold))
+        cold = {"ms_per_step": ms_cold, "value": particles / (1e-3 * ms_cold),
+                "unit": "particles/s", "flush_bytes": 512 << 20,
+                "timing": f"HIP events around each step, a 512 MiB write before it, median of "
+                          f"{args.steps}"}
+        log(f"cold-cache step: {ms_cold:.3f} ms")
+        if int(flags.cpu()[0]) != 0:
+            raise RuntimeError(f"data flags raised during the benchmark: {int(flags.cpu()[0])}")
+
     dom_ms = float(np.mean([a.elapsed_time(b) for a, b in ev]))
     B_dom = Bs[YS.index(dominant[0])]
     dom_calls = N * metropolis_calls_per_lane(B_dom)
@@ -1061,7 +1188,7 @@ def main():
     cpu = None
     if not args.no_cpu_baseline:
         log("timing the CPU oracle ...")
-        cpu = cpu_baseline(args.cpu_sample)
+        cpu = cpu_baseline(args.cpu_sample, args.cpu_budget)
 
     result = {
         "metric": "resampled particles/sec and % HBM roofline at N=2^20 FP32; batched filters/sec",
@@ -1084,6 +1211,7 @@ def main():
         "roofline": roofline,
         "cpu_baseline": cpu,
         "concurrent": concurrent,
+        "cold": cold,
         "hbm_frac_8B_per_particle_at_2p20": hbm_2p20,
         "batched": batched,
         "breakdown": breakdown,

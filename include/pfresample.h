@@ -128,7 +128,8 @@ typedef enum {
     PFR_OP_PERMUTE = 6,
     PFR_OP_ANCESTORS_TO_OFFSPRING = 7,
     PFR_OP_ESS = 8,
-    PFR_OP_MULTINOMIAL_IID = 9
+    PFR_OP_MULTINOMIAL_IID = 9,
+    PFR_OP_SCALED_PREFIX = 10
 } pfr_op;
 
 /* Bytes of workspace the operation needs for these segments (0 if none). */
@@ -151,6 +152,20 @@ PFR_API int pfr_workspace_init(void* ws, size_t ws_bytes, void* stream);
  * workspace), with identical results.  The floating-point precision modes
  * ignore a batch workspace.
  */
+
+/* The scaled prefix r_i = n W_i / W_n (binary64, r_{n-1} = n) that the
+ * collective resamplers of a single vector compare their points against in
+ * the given precision mode (sections 3.1 and 3.2: it carries the whole effect
+ * of the prefix sum's arithmetic).  Given r, the stratified and systematic
+ * schemes give particle i r_i - r_{i-1} offspring in expectation (also the
+ * multinomial scheme, up to its cap at n - 1), so
+ * sum_i (r_i - r_{i-1} - n w_i / W)^2 is the deterministic bias of the mode.
+ * For analysis and tests; single vectors (n_filters = 1) only.  Workspace:
+ * pfr_workspace_bytes(PFR_OP_SCALED_PREFIX, ...).  Zero or invalid weights
+ * leave r_out unwritten and raise the flags of the resamplers. */
+PFR_API int pfr_scaled_prefix(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                              pfr_precision precision, double* r_out, void* ws, size_t ws_bytes,
+                              uint32_t* dev_flags, void* stream);
 
 /* Multinomial resampling (Code 5): draws the order statistics of n uniforms
  * from exponential spacings E_k = -log((x + 1/2) 2^-32), k = 0..n, taken from

@@ -397,6 +397,25 @@ def permute_ancestors_noalloc(a, sorted_hint=False, offsets=None, max_len=None, 
     return c
 
 
+def scaled_prefix(w, precision=SCAN_EXACT, out=None, flags=None, workspace=None):
+    """The scaled prefix r_i = n W_i / W_n (float64) a collective resampler
+    of this single vector compares against in the given precision mode."""
+    torch = _torch()
+    _require_cuda(w, flags)
+    dt = _dtype_code(w)
+    seg = _segments(w.numel())
+    r = out if out is not None else torch.empty(w.numel(), dtype=torch.float64, device=w.device)
+    if r.dtype != torch.float64 or r.numel() != w.numel():
+        raise ValueError("out must be a float64 tensor with one entry per particle")
+    _require_cuda(r)
+    ws, _ = _workspace(_lib.OP_SCALED_PREFIX, seg, dt, w.device, workspace)
+    rc = _lib.load().pfr_scaled_prefix(_ptr(w), dt, ctypes.byref(seg), int(precision), _ptr(r),
+                                       _ptr(ws), 0 if ws is None else ws.numel(), _ptr(flags),
+                                       _stream())
+    _lib.check(rc, "pfr_scaled_prefix")
+    return r
+
+
 def ancestors_to_offspring(a, sorted_hint=False, offsets=None, max_len=None, out=None,
                            flags=None):
     """Offspring counts o_j = #{i : a_i = j} (Code 12); atomic-free when

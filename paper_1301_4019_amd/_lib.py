@@ -18,7 +18,7 @@ PFR_F32, PFR_F64 = 0, 1
 SCAN_EXACT, SCAN_F64, SCAN_COMP_F32, SCAN_NAIVE_F32 = 0, 1, 2, 3
 (OP_MULTINOMIAL, OP_STRATIFIED, OP_SYSTEMATIC, OP_METROPOLIS, OP_REJECTION,
  OP_OFFSPRING_TO_ANCESTORS, OP_PERMUTE, OP_ANCESTORS_TO_OFFSPRING, OP_ESS,
- OP_MULTINOMIAL_IID) = range(10)
+ OP_MULTINOMIAL_IID, OP_SCALED_PREFIX) = range(11)
 
 FLAG_ZERO_TOTAL = 1
 FLAG_TRIAL_CAP = 2
@@ -30,7 +30,7 @@ MAX_BATCH_SEGMENT = 256 * 1024 - 1
 NOALLOC_MAX_N = 1 << 22
 
 EXPORTS = (
-    "pfr_workspace_bytes", "pfr_workspace_init", "resample_multinomial",
+    "pfr_workspace_bytes", "pfr_workspace_init", "pfr_scaled_prefix", "resample_multinomial",
     "resample_multinomial_iid", "resample_stratified",
     "resample_systematic", "resample_metropolis", "resample_rejection",
     "resample_partial_rejection", "offspring_to_ancestors",
@@ -95,6 +95,7 @@ def open_library(path: str) -> ctypes.CDLL:
     sigs = {
         "pfr_workspace_bytes": (SZ, [I, SEG, I]),
         "pfr_workspace_init": (I, [P, SZ, P]),
+        "pfr_scaled_prefix": (I, [P, I, SEG, I, P, P, SZ, P, P]),
         "resample_multinomial": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),
         "resample_multinomial_iid": (I, [P, I, SEG, Rng, P, P, SZ, P, P]),
         "resample_stratified": (I, [P, I, SEG, I, Rng, P, P, SZ, P, P]),

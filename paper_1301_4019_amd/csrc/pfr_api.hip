@@ -155,8 +155,33 @@ size_t pfr_workspace_bytes(pfr_op op, const pfr_segments* seg, pfr_dtype dtype) 
       return ess_workspace_bytes(s.n_total, s.n_filters);
     case PFR_OP_MULTINOMIAL_IID:
       return multinomial_iid_workspace_bytes(s.n_total);
+    case PFR_OP_SCALED_PREFIX:
+      return s.n_filters == 1 && s.n_total > 0 ? scan_layout(s.n_total, false).total : 0;
   }
   return 0;
+}
+
+int pfr_scaled_prefix(const void* w, pfr_dtype dtype, const pfr_segments* seg,
+                      pfr_precision precision, double* r_out, void* ws, size_t ws_bytes,
+                      uint32_t* dev_flags, void* stream) {
+  SegInfo s;
+  int rc = check_segments(seg, &s);
+  if (rc) return rc;
+  if (dtype != PFR_F32 && dtype != PFR_F64) return PFR_EINVAL;
+  if (precision < PFR_SCAN_EXACT || precision > PFR_SCAN_NAIVE_F32) return PFR_EINVAL;
+  if (s.n_filters > 1) return PFR_ENOTSUP;
+  if (s.n_total == 0) return PFR_OK;
+  if (!w || !r_out) return PFR_EINVAL;
+  const size_t need = scan_layout(s.n_total, false).total;
+  if (!ws || ws_bytes < need || !aligned256(ws)) return PFR_EWORKSPACE;
+  const size_t rb = (size_t)s.n_total * sizeof(double);
+  if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), r_out, rb) || overlaps(ws, need, r_out, rb))
+    return PFR_EINVAL;
+  const hipStream_t st = (hipStream_t)stream;
+  if (precision == PFR_SCAN_EXACT)
+    return launch_result(launch_scan_r(dtype == PFR_F64, w, s.n_total, r_out, ws, dev_flags, st));
+  return launch_result(launch_fscan_r((int)precision, dtype == PFR_F64, w, s.n_total, r_out, ws,
+                                      dev_flags, st));
 }
 
 int pfr_workspace_init(void* ws, size_t ws_bytes, void* stream) {

@@ -37,7 +37,9 @@ struct Key {
 };
 
 __device__ __forceinline__ uint32_t counter_offset(const Key& key, uint32_t offset) {
-  return key.offset_dev ? *key.offset_dev : offset;
+  // the same value on every lane: kept in a scalar register, so that the
+  // uniform parts of the Philox calls that use it stay on the scalar unit
+  return key.offset_dev ? (uint32_t)__builtin_amdgcn_readfirstlane(*key.offset_dev) : offset;
 }
 
 // Philox4x32 (Salmon, Moraes, Dror & Shaw, SC'11).  Each round
@@ -81,6 +83,27 @@ __device__ __forceinline__ uint4 philox(uint32_t c0, uint32_t c1, uint32_t c2, u
 __device__ __forceinline__ uint4 draw(Key key, uint32_t index, uint32_t domain, uint32_t step,
                                       uint32_t filter, uint32_t offset) {
   return philox(index, (domain << 28) | (step & 0x0FFFFFFFu), filter, offset, key);
+}
+
+// The same call for arguments that are the same on every lane of the wave:
+// plain two-input xors, which the compiler keeps on the scalar unit (the
+// three-input form above exists only as a vector instruction).  Same bits.
+__device__ __forceinline__ uint4 draw_uniform(Key key, uint32_t index, uint32_t domain,
+                                              uint32_t step, uint32_t filter, uint32_t offset) {
+  uint32_t c0 = index, c1 = (domain << 28) | (step & 0x0FFFFFFFu), c2 = filter, c3 = offset;
+  uint32_t k0 = key.k0, k1 = key.k1;
+#pragma unroll
+  for (int r = 0; r < kPhiloxRounds; ++r) {
+    const uint64_t p0 = (uint64_t)0xD2511F53u * c0;
+    const uint64_t p1 = (uint64_t)0xCD9E8D57u * c2;
+    c0 = (uint32_t)(p1 >> 32) ^ c1 ^ k0;
+    c1 = (uint32_t)p1;
+    c2 = (uint32_t)(p0 >> 32) ^ c3 ^ k1;
+    c3 = (uint32_t)p0;
+    k0 += 0x9E3779B9u;
+    k1 += 0xBB67AE85u;
+  }
+  return make_uint4(c0, c1, c2, c3);
 }
 
 
@@ -259,6 +282,57 @@ __device__ __forceinline__ T wave_reduce(T v, Op op) {
 #pragma unroll
   for (int d = 1; d < kWave; d <<= 1) v = op(v, shfl(v, l ^ d));
   return v;
+}
+
+// ------------------------------------------------------------------ DPP scans
+// Cross-lane moves of the GFX9 data-parallel primitives: shifts by 1, 2, 4, 8
+// inside rows of 16 lanes, broadcasts of lane 15 (to the next row) and lane 31
+// (to rows 2 and 3), and a shift of the whole wave by one lane.  A lane whose
+// source lies outside its row, or whose row ROW_MASK leaves out, gets `old`.
+constexpr int kDppShr1 = 0x111, kDppShr2 = 0x112, kDppShr4 = 0x114, kDppShr8 = 0x118;
+constexpr int kDppBcast15 = 0x142, kDppBcast31 = 0x143, kDppWaveShr1 = 0x138;
+
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint32_t dpp_u32(uint32_t old, uint32_t v) {
+  return (uint32_t)__builtin_amdgcn_update_dpp((int)old, (int)v, CTRL, ROW_MASK, 0xF, false);
+}
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ uint64_t dpp_u64(uint64_t old, uint64_t v) {
+  const uint32_t lo = dpp_u32<CTRL, ROW_MASK>((uint32_t)old, (uint32_t)v);
+  const uint32_t hi = dpp_u32<CTRL, ROW_MASK>((uint32_t)(old >> 32), (uint32_t)(v >> 32));
+  return ((uint64_t)hi << 32) | lo;
+}
+
+// Inclusive scans over the 64 lanes in six DPP steps: within rows, then row 0
+// into row 1 and row 2 into row 3, then rows 0-1 into rows 2-3.
+__device__ __forceinline__ uint64_t wave_incl_add_u64(uint64_t x) {
+  x += dpp_u64<kDppShr1>(0ull, x);
+  x += dpp_u64<kDppShr2>(0ull, x);
+  x += dpp_u64<kDppShr4>(0ull, x);
+  x += dpp_u64<kDppShr8>(0ull, x);
+  x += dpp_u64<kDppBcast15, 0xA>(0ull, x);
+  x += dpp_u64<kDppBcast31, 0xC>(0ull, x);
+  return x;
+}
+// Inclusive max-scan of values >= -1.
+__device__ __forceinline__ int32_t wave_incl_max_i32(int32_t x) {
+  const uint32_t m1 = 0xFFFFFFFFu;
+  x = max(x, (int32_t)dpp_u32<kDppShr1>(m1, (uint32_t)x));
+  x = max(x, (int32_t)dpp_u32<kDppShr2>(m1, (uint32_t)x));
+  x = max(x, (int32_t)dpp_u32<kDppShr4>(m1, (uint32_t)x));
+  x = max(x, (int32_t)dpp_u32<kDppShr8>(m1, (uint32_t)x));
+  x = max(x, (int32_t)dpp_u32<kDppBcast15, 0xA>(m1, (uint32_t)x));
+  x = max(x, (int32_t)dpp_u32<kDppBcast31, 0xC>(m1, (uint32_t)x));
+  return x;
+}
+// The value of the previous lane (lane 0 gets `first`).
+__device__ __forceinline__ uint32_t wave_shift_up_u32(uint32_t v, uint32_t first) {
+  return dpp_u32<kDppWaveShr1>(first, v);
+}
+// Orders the LDS accesses of the lanes of one wave (no workgroup barrier).
+__device__ __forceinline__ void wave_lds_sync() {
+  __builtin_amdgcn_fence(__ATOMIC_ACQ_REL, "wavefront");
+  __builtin_amdgcn_wave_barrier();
 }
 
 struct OpAdd {

@@ -238,17 +238,17 @@ __device__ uint32_t fcarries(uint32_t nb, SumPtr sums, CPtr C, WgScratch* s) {
 }
 
 // ---------------------------------------------------------------- emit
-template <typename T, int P, int SCHEME, typename CEPtr>
-__device__ void femit_block(const T* __restrict__ w, int64_t n, uint32_t b, double Cb, double Cb1,
-                            const FRMap<P>& rm, Key key, uint32_t filter, uint32_t offset,
-                            CEPtr CE, uint32_t nbe, int32_t* __restrict__ a_out, EmitLds* L,
-                            WgScratch* s) {
+// r of the thread's 4 particles of block b in the mode's arithmetic: local
+// prefix plus C_b, mapped, clamped into [r(C_b), r(C_{b+1})], made
+// non-decreasing, and r(C_{b+1}) for the block's last particle.
+template <typename T, int P>
+__device__ void fblock_r(const T* __restrict__ w, int64_t n, uint32_t b, double Cb, double Cb1,
+                         const FRMap<P>& rm, double r_lo, double r_hi, double (&r)[kPer],
+                         WgScratch* s) {
   typedef typename FA<P>::V V;
   const int tid = (int)threadIdx.x;
   const int64_t P0 = (int64_t)b * kBlock;
   const int cnt = (int)min((int64_t)kBlock, n - P0);
-  const double r_lo = rm(FA<P>::from_value(Cb));
-  const double r_hi = rm(FA<P>::from_value(Cb1));
   T x[kPer];
   load4(w, n, P0, x);
   V acc[kPer];
@@ -261,7 +261,6 @@ __device__ void femit_block(const T* __restrict__ w, int64_t n, uint32_t b, doub
   V tot;
   const V off = wg_exclusive_op(run, FAdd<P>(), FA<P>::zero(), (V*)s->v, &tot);
   const V base = FA<P>::add(FA<P>::from_value(Cb), off);
-  double r[kPer];
 #pragma unroll
   for (int v = 0; v < kPer; ++v) {
     double t = rm(FA<P>::add(base, acc[v]));
@@ -274,6 +273,21 @@ __device__ void femit_block(const T* __restrict__ w, int64_t n, uint32_t b, doub
     r[v] = r[v] > ex ? r[v] : ex;
     if (tid * kPer + v >= cnt - 1) r[v] = r_hi;  // block end and past the vector's end
   }
+}
+
+template <typename T, int P, int SCHEME, typename CEPtr>
+__device__ void femit_block(const T* __restrict__ w, int64_t n, uint32_t b, double Cb, double Cb1,
+                            const FRMap<P>& rm, Key key, uint32_t filter, uint32_t offset,
+                            CEPtr CE, uint32_t nbe, int32_t* __restrict__ a_out, EmitLds* L,
+                            WgScratch* s) {
+  typedef typename FA<P>::V V;
+  const int tid = (int)threadIdx.x;
+  const int64_t P0 = (int64_t)b * kBlock;
+  const int cnt = (int)min((int64_t)kBlock, n - P0);
+  const double r_lo = rm(FA<P>::from_value(Cb));
+  const double r_hi = rm(FA<P>::from_value(Cb1));
+  double r[kPer];
+  fblock_r<T, P>(w, n, b, Cb, Cb1, rm, r_lo, r_hi, r, s);
   if (SCHEME == SCHEME_MULTINOMIAL) {
 #pragma unroll
     for (int v = 0; v < kPer; ++v) L->mu.r[tid * kPer + v] = r[v];
@@ -347,6 +361,32 @@ __global__ __launch_bounds__(kT) void k_fscan_emit(const T* __restrict__ w, int6
   const FRMap<P> rm = make_frmap<P>(hdr->W, n);
   femit_block<T, P, SCHEME>(w, n, b, C[b], C[b + 1], rm, key, filter, offset, CE, nbe, a, &L,
                             &s);
+}
+
+__global__ void k_fscan_status(const ScanHeader* __restrict__ hdr, uint32_t* __restrict__ flags) {
+  if (hdr->status) atomicOr(flags, hdr->status);
+}
+
+// The scaled prefix r of the mode, written out (binary64) instead of
+// resampling: what the emission compares its points against.
+template <typename T, int P>
+__global__ __launch_bounds__(kT) void k_fscan_r(const T* __restrict__ w, int64_t n,
+                                                const ScanHeader* __restrict__ hdr,
+                                                const double* __restrict__ C,
+                                                double* __restrict__ r_out) {
+  __shared__ WgScratch s;
+  if (hdr->status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) return;
+  const uint32_t b = blockIdx.x;
+  const FRMap<P> rm = make_frmap<P>(hdr->W, n);
+  const double r_lo = rm(FA<P>::from_value(C[b]));
+  const double r_hi = rm(FA<P>::from_value(C[b + 1]));
+  double r[kPer];
+  fblock_r<T, P>(w, n, b, C[b], C[b + 1], rm, r_lo, r_hi, r, &s);
+#pragma unroll
+  for (int v = 0; v < kPer; ++v) {
+    const int64_t i = (int64_t)b * kBlock + threadIdx.x * kPer + v;
+    if (i < n) r_out[i] = r[v];
+  }
 }
 
 constexpr int kFBatchMaxBlocks = 256;  // segments up to 2^18 particles
@@ -516,7 +556,41 @@ hipError_t fbatched_prec(int scheme, int prec, const void* w, int64_t n_total,
   }
 }
 
+template <typename T, int P>
+hipError_t launch_fscan_r_t(const T* w, int64_t n, double* r, void* ws, uint32_t* flags,
+                            hipStream_t stream) {
+  const ScanLayout L = scan_layout(n, false);
+  char* base = (char*)ws;
+  ScanHeader* hdr = (ScanHeader*)base;
+  double* sums = (double*)(base + L.recs);
+  double* C = (double*)(base + L.carries);
+  const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
+  hipLaunchKernelGGL((k_fscan_records<T, P, false>), dim3(nb), dim3(kT), 0, stream, w, n, nb,
+                     Key{0, 0, nullptr}, 0u, 0u, sums, (uint64_t*)nullptr);
+  hipLaunchKernelGGL((k_fscan_carries<P, false>), dim3(1), dim3(kT), 0, stream, nb, 0u, hdr, sums,
+                     (const uint64_t*)nullptr, C, (u128*)nullptr);
+  hipLaunchKernelGGL((k_fscan_r<T, P>), dim3(nb), dim3(kT), 0, stream, w, n, hdr, C, r);
+  if (flags) hipLaunchKernelGGL(k_fscan_status, dim3(1), dim3(1), 0, stream, hdr, flags);
+  return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_fscan_r_p(int prec, const T* w, int64_t n, double* r, void* ws, uint32_t* flags,
+                            hipStream_t stream) {
+  switch (prec) {
+    case PREC_F64: return launch_fscan_r_t<T, PREC_F64>(w, n, r, ws, flags, stream);
+    case PREC_COMP_F32: return launch_fscan_r_t<T, PREC_COMP_F32>(w, n, r, ws, flags, stream);
+    default: return launch_fscan_r_t<T, PREC_NAIVE_F32>(w, n, r, ws, flags, stream);
+  }
+}
+
 }  // namespace
+
+hipError_t launch_fscan_r(int prec, bool f64, const void* w, int64_t n, double* r, void* ws,
+                          uint32_t* flags, hipStream_t stream) {
+  return f64 ? launch_fscan_r_p<double>(prec, (const double*)w, n, r, ws, flags, stream)
+             : launch_fscan_r_p<float>(prec, (const float*)w, n, r, ws, flags, stream);
+}
 
 hipError_t launch_fscan(int scheme, int prec, bool f64, const void* w, int64_t n, Key key,
                         uint32_t offset, uint32_t filter, int32_t* a, void* ws, uint32_t* flags,

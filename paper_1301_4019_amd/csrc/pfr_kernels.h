@@ -88,11 +88,18 @@ hipError_t launch_multinomial_iid(bool f64, const void* w, int64_t n, Key key, u
                                   uint32_t filter, int32_t* a, void* ws, uint32_t* flags,
                                   hipStream_t stream);
 
+// The scaled prefix r = n W_i / W (binary64) of a single vector, exact mode /
+// floating-point modes; workspace as scan_layout(n, false).
+hipError_t launch_scan_r(bool f64, const void* w, int64_t n, double* r, void* ws, uint32_t* flags,
+                         hipStream_t stream);
+
 // Floating-point prefix modes (pfr_precision values 1..3).
 enum Prec : int { PREC_F64 = 1, PREC_COMP_F32 = 2, PREC_NAIVE_F32 = 3 };
 hipError_t launch_fscan(int scheme, int prec, bool f64, const void* w, int64_t n, Key key,
                         uint32_t offset, uint32_t filter, int32_t* a, void* ws, uint32_t* flags,
                         hipStream_t stream);
+hipError_t launch_fscan_r(int prec, bool f64, const void* w, int64_t n, double* r, void* ws,
+                          uint32_t* flags, hipStream_t stream);
 hipError_t launch_fscan_batched(int scheme, int prec, bool f64, const void* w, int64_t n_total,
                                 const int64_t* offsets, uint32_t n_filters, Key key,
                                 uint32_t offset, uint32_t filter_base, int32_t* a,

@@ -351,6 +351,647 @@ __global__ __launch_bounds__(kT) void k_scan_emit(const T* __restrict__ w, int64
                         &L, &s, d_out, e_out, evals);
 }
 
+// ---------------------------------------------------------------- one block per wave
+// The stratified and systematic emission and the records pass run one
+// 1024-weight block per wave, lane l holding particles 16 l .. 16 l + 15 of
+// the block, four waves (four consecutive blocks) per workgroup.  A block's
+// prefix then needs no workgroup barrier: the lane sums its 16 quantised
+// weights and one DPP scan over the wave gives the lane's offset.  r is formed
+// from the exact block carry by an affine map in binary64,
+//   r_i = min(fl(L_i c + r(C_b)), r(C_{b+1})),  c = n 2^(gscale - scale_b) / Q,
+// with L_i the block's exact integer prefix (below 2^63) rounded once: the map
+// is monotone in L_i, flat over zero weights and clamped to the block's range,
+// so O_i is monotone across blocks as well; it adds at most five roundings of
+// n 2^-53 to the error of r against the exact value.
+constexpr int kWPer = kBlock / kWave;  // particles per lane (16)
+constexpr int kWavesPerWG = kT / kWave;
+constexpr int kUTabW = 2048;           // stratum offset words cached per wave
+
+template <typename T>
+__device__ __forceinline__ void wave_load(const T* __restrict__ w, int64_t n, int64_t base,
+                                          T (&x)[kWPer]) {
+  const int64_t idx = base + (int64_t)lane_id() * kWPer;
+  const bool aligned = ((reinterpret_cast<uintptr_t>(w + idx) & 15u) == 0);
+  if (aligned && idx + kWPer <= n) {
+    if constexpr (sizeof(T) == 4) {
+      const float4* p = reinterpret_cast<const float4*>(w + idx);
+#pragma unroll
+      for (int k = 0; k < kWPer / 4; ++k) {
+        const float4 t = p[k];
+        x[4 * k] = t.x; x[4 * k + 1] = t.y; x[4 * k + 2] = t.z; x[4 * k + 3] = t.w;
+      }
+    } else {
+      const double2* p = reinterpret_cast<const double2*>(w + idx);
+#pragma unroll
+      for (int k = 0; k < kWPer / 2; ++k) {
+        const double2 t = p[k];
+        x[2 * k] = t.x; x[2 * k + 1] = t.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int v = 0; v < kWPer; ++v) x[v] = (idx + v < n) ? w[idx + v] : (T)0;
+  }
+}
+
+// quantize() without branches: q = floor(v 2^scale) for every finite v >= 0
+// of a block whose scale keeps q below 2^53.  binary32: scaling by a power of
+// two is exact (a result below 2^-126 may round, but it floors to zero
+// anyway), the floor is exact, and q splits exactly into two 32-bit halves
+// (t - hi 2^32 keeps at most t's 24 significant bits).  binary64: the
+// significand shifted by scale + exponent - 1075, truncated.
+template <typename T>
+__device__ __forceinline__ uint64_t quantize_nb(T v, int scale) {
+  if constexpr (sizeof(T) == 4) {
+    const float t = floorf(ldexpf(v, scale));
+    const float hi = floorf(t * 0x1p-32f);
+    const float lo = __builtin_fmaf(hi, -0x1p32f, t);
+    return ((uint64_t)(uint32_t)hi << 32) | (uint32_t)lo;
+  } else {
+    typedef WTraits<T> Tr;
+    const uint64_t b = Tr::bits(v);
+    const uint32_t ef = (uint32_t)((b >> 52) & 0x7FFu);
+    const uint64_t m = (b & 0xFFFFFFFFFFFFFull) | (ef ? (1ull << 52) : 0ull);
+    const int sh = (int)(ef < 1u ? 1u : ef) - 1075 + scale;
+    const uint64_t up = m << (sh & 63);
+    const uint64_t dn = m >> (uint32_t)min(-sh, 63);
+    return sh >= 0 ? up : dn;
+  }
+}
+
+// u64 -> binary64, rounded once (the high half converts exactly).
+__device__ __forceinline__ double u64_to_f64(uint64_t x) { return (double)x; }
+
+// Record of the block at base (one wave): validity, reference exponent, sum.
+template <typename T>
+__device__ __forceinline__ BlockRec wave_block_record(const T* __restrict__ w, int64_t n, int64_t base) {
+  T x[kWPer];
+  wave_load(w, n, base, x);
+  uint32_t bad = 0, emax = 1;
+#pragma unroll
+  for (int v = 0; v < kWPer; ++v) {
+    if (!weight_ok(x[v])) bad = FLAG_BAD_WEIGHTS;
+    else emax = max(emax, (uint32_t)exp_field(x[v]));
+  }
+  const uint32_t key = wave_reduce((bad << 16) | emax, OpMax());
+  BlockRec r;
+  r.bad = key >> 16;
+  const int e_ref = (int)(key & 0xFFFFu);
+  r.scale = scale_of<T>(e_ref);
+  uint64_t sum = 0;
+  if (!r.bad) {
+#pragma unroll
+    for (int v = 0; v < kWPer; ++v) sum += quantize_nb(x[v], r.scale);
+  }
+  r.sum = readlane(wave_incl_add_u64(sum), kWave - 1);
+  return r;
+}
+
+// r of the wave's block: lane l gets r_i of particles P0 + 16 l + v (values
+// past the vector's end repeat the last one), and the block's range
+// [r(C_b), r(C_{b+1})].
+struct BlockR {
+  double r[kWPer];
+  double lo, hi;
+};
+
+template <typename T>
+__device__ __forceinline__ void block_r_wave(const T* __restrict__ w, int64_t n, int64_t P0,
+                                             const BlockRec rec, u128 Cb, u128 Cb1,
+                                             int32_t gscale, u128 Q, BlockR& R) {
+  const RMap rm = make_rmap(Q, n);
+  R.lo = rm(Cb);
+  R.hi = rm(Cb1);
+  const int32_t scale = (int32_t)__builtin_amdgcn_readfirstlane(rec.scale);
+  const int sh = (int32_t)__builtin_amdgcn_readfirstlane(gscale) - scale;
+  const double c = ldexp(rm.Nd * rm.invQ, sh);
+  T x[kWPer];
+  wave_load(w, n, P0, x);
+  uint64_t q[kWPer];
+  uint64_t acc = 0;
+#pragma unroll
+  for (int v = 0; v < kWPer; ++v) {
+    acc += quantize_nb(x[v], scale);
+    q[v] = acc;
+  }
+  const uint64_t incl = wave_incl_add_u64(acc);
+  const uint64_t off = incl - acc;
+  const uint64_t total = readlane(incl, kWave - 1);
+  // every particle from the block's last positive weight on has the whole
+  // block sum, i.e. r = r(C_{b+1}) exactly: that particle then ends the
+  // block's range, as in exact arithmetic
+#pragma unroll
+  for (int v = 0; v < kWPer; ++v) {
+    const uint64_t Lv = off + q[v];
+    const double rv = __fma_rn(u64_to_f64(Lv), c, R.lo);
+    R.r[v] = (Lv == total || rv > R.hi) ? R.hi : rv;
+  }
+}
+
+// Expansion of cumulative offspring into ancestors, 1024 outputs at a time:
+// the block's outputs are [O_lo, O_hi) and particle P0 + 16 lane + v takes
+// [Op[v], O[v]).  A marker at the first output of every run, a max-scan (16
+// values per lane in registers, then over the wave), the result written back
+// to LDS and stored row by row (coalesced).  With e_out also the marked
+// ancestry of Code 10's Prepermute (run starts keep i, the others -1 - i).
+__device__ __forceinline__ void expand_wave(const uint32_t (&O)[kWPer], const uint32_t (&Op)[kWPer],
+                                            uint32_t O_lo, uint32_t O_hi, int64_t P0, int64_t n,
+                                            int32_t* __restrict__ a_out, int32_t* M,
+                                            int32_t* __restrict__ e_out) {
+  const int lane = (int)lane_id();
+  O_hi = min(O_hi, (uint32_t)n);  // (never binds: every O is at most n)
+  int32_t carry = -1;  // particle covering the first output of the chunk
+  int4* M4 = reinterpret_cast<int4*>(M) + lane * (kWPer / 4);
+  const int32_t P0_32 = (int32_t)P0;
+  for (uint32_t cs = O_lo; cs < O_hi; cs += kBlock) {
+    const uint32_t len = min((uint32_t)kBlock, O_hi - cs);
+#pragma unroll
+    for (int k = 0; k < kWPer / 4; ++k) M4[k] = make_int4(-1, -1, -1, -1);
+    wave_lds_sync();
+    // (a particle that starts no run in this chunk writes the spare slot)
+#pragma unroll
+    for (int v = 0; v < kWPer; ++v) {
+      const uint32_t pos = Op[v] - cs;
+      M[(O[v] > Op[v] && pos < len) ? pos : (uint32_t)kBlock] = lane * kWPer + v;
+    }
+    wave_lds_sync();
+    int32_t m[kWPer];
+    uint32_t marked = 0;  // bit k: position 16 lane + k starts a run
+#pragma unroll
+    for (int k = 0; k < kWPer / 4; ++k) {
+      const int4 t = M4[k];
+      m[4 * k] = t.x; m[4 * k + 1] = t.y; m[4 * k + 2] = t.z; m[4 * k + 3] = t.w;
+    }
+#pragma unroll
+    for (int k = 0; k < kWPer; ++k) {
+      marked |= (m[k] >= 0 ? 1u : 0u) << k;
+      if (k > 0) m[k] = max(m[k], m[k - 1]);
+    }
+    const int32_t incl = wave_incl_max_i32(m[kWPer - 1]);
+    const int32_t before = max(carry, (int32_t)wave_shift_up_u32((uint32_t)incl, 0xFFFFFFFFu));
+#pragma unroll
+    for (int k = 0; k < kWPer; ++k) m[k] = max(m[k], before);
+    carry = (int32_t)__builtin_amdgcn_readlane(m[kWPer - 1], kWave - 1);
+    wave_lds_sync();
+#pragma unroll
+    for (int k = 0; k < kWPer / 4; ++k) {
+      int4 t;
+      if (e_out) {
+        t = make_int4(2 * m[4 * k] + (int)((marked >> (4 * k)) & 1u),
+                      2 * m[4 * k + 1] + (int)((marked >> (4 * k + 1)) & 1u),
+                      2 * m[4 * k + 2] + (int)((marked >> (4 * k + 2)) & 1u),
+                      2 * m[4 * k + 3] + (int)((marked >> (4 * k + 3)) & 1u));
+      } else {
+        t = make_int4(m[4 * k], m[4 * k + 1], m[4 * k + 2], m[4 * k + 3]);
+      }
+      M4[k] = t;
+    }
+    wave_lds_sync();
+    int32_t* __restrict__ a_chunk = a_out + cs;  // the same on every lane
+#pragma unroll
+    for (int j = 0; j < kWPer; ++j) {
+      const uint32_t p = (uint32_t)lane + (uint32_t)j * kWave;
+      if (p < len) {
+        const int32_t v = M[p];
+        if (e_out) {
+          const int32_t i = P0_32 + (v >> 1);
+          a_chunk[p] = i;
+          e_out[cs + p] = (v & 1) ? i : -1 - i;
+        } else {
+          a_chunk[p] = P0_32 + v;
+        }
+      }
+    }
+    wave_lds_sync();
+  }
+}
+
+template <bool SYSTEMATIC>
+struct StrataWaveLds {
+  int32_t M[kBlock + 4];                   // expansion markers, then the expanded chunk; M[kBlock] spare
+  uint32_t u[SYSTEMATIC ? 1 : kUTabW];     // raw offset words of strata [m_lo, m_lo + kUTabW)
+};
+
+// Stratified / systematic emission of one block by one wave: the block's
+// particles are P0 .. P0 + cnt - 1 of a vector of n, with exclusive exact
+// carry Cb and inclusive Cb1 at global scale gscale, total Q.  Writes a_out[s]
+// = P0 + i for every s in [O_{i-1}, O_i); with d_out and e_out also the claim
+// vector and the marked ancestry of Code 10's Prepermute (as emit_strata).
+template <typename T, bool SYSTEMATIC>
+__device__ __forceinline__ void emit_block_wave(const T* __restrict__ w, int64_t n, int64_t P0,
+                                                const BlockRec rec, u128 Cb, u128 Cb1,
+                                                int32_t gscale, u128 Q, Key key, uint32_t filter,
+                                                uint32_t offset, int32_t* __restrict__ a_out,
+                                                StrataWaveLds<SYSTEMATIC>* L,
+                                                int32_t* __restrict__ d_out,
+                                                int32_t* __restrict__ e_out) {
+  const int lane = (int)lane_id();
+  const int cnt = (int)min((int64_t)kBlock, n - P0);
+  BlockR R;
+  block_r_wave(w, n, P0, rec, Cb, Cb1, gscale, Q, R);
+  if (!(R.hi > R.lo) && !d_out) return;  // an empty range has no outputs
+
+  // stratum offsets of the strata the block's range touches
+  const int64_t m_lo = (int64_t)floor(R.lo);
+  const int64_t m_hi = min(n - 1, (int64_t)floor(R.hi));
+  const bool table = !SYSTEMATIC && (m_hi - m_lo + 1 <= kUTabW);
+  const double t_sys =
+      SYSTEMATIC ? 1.0 - u_offset(draw_uniform(key, 0, DOM_STRATA, 0, filter, offset).x) : 0.0;
+  if (table && m_hi >= m_lo) {
+    for (int64_t cc = (m_lo >> 2) + lane; cc <= (m_hi >> 2); cc += kWave) {
+      const uint4 xw = draw(key, (uint32_t)cc, DOM_STRATA, 0, filter, offset);
+      const uint32_t xs[4] = {xw.x, xw.y, xw.z, xw.w};
+#pragma unroll
+      for (int v = 0; v < 4; ++v) {
+        const int64_t m = cc * 4 + v;
+        if (m >= m_lo && m <= m_hi) L->u[m - m_lo] = xs[v];
+      }
+    }
+    wave_lds_sync();
+  }
+  // O(r) = #{s : s + 1 - u_s <= r}, exactly: m = floor(r), frac(r) >= 1 - u_m
+  // (0 <= r <= n < 2^31, so m converts exactly to 32 bits)
+  const int32_t n32 = (int32_t)n, mlo32 = (int32_t)m_lo;
+  auto cum_sys = [&](double rv) -> uint32_t {
+    const double mf = floor(rv);
+    const int32_t m = (int32_t)mf;
+    return m >= n32 ? (uint32_t)n32 : (uint32_t)m + ((rv - mf) >= t_sys ? 1u : 0u);
+  };
+  auto cum_tab = [&](double rv) -> uint32_t {
+    const double mf = floor(rv);
+    const int32_t m = (int32_t)mf;
+    const double t = 1.0 - u_offset(L->u[m >= n32 ? 0 : m - mlo32]);
+    return m >= n32 ? (uint32_t)n32 : (uint32_t)m + ((rv - mf) >= t ? 1u : 0u);
+  };
+  auto cum_draw = [&](double rv) -> uint32_t {
+    const double mf = floor(rv);
+    const int32_t m = (int32_t)mf;
+    if (m >= n32) return (uint32_t)n32;
+    const double t = 1.0 - u_offset(stratum_word(key, filter, offset, m));
+    return (uint32_t)m + ((rv - mf) >= t ? 1u : 0u);
+  };
+  uint32_t O[kWPer];
+  uint32_t O_lo, O_hi;
+  if (SYSTEMATIC) {
+#pragma unroll
+    for (int v = 0; v < kWPer; ++v) O[v] = cum_sys(R.r[v]);
+    O_lo = cum_sys(R.lo);
+    O_hi = cum_sys(R.hi);
+  } else if (table) {
+#pragma unroll
+    for (int v = 0; v < kWPer; ++v) O[v] = cum_tab(R.r[v]);
+    O_lo = cum_tab(R.lo);
+    O_hi = cum_tab(R.hi);
+  } else {
+#pragma unroll
+    for (int v = 0; v < kWPer; ++v) O[v] = cum_draw(R.r[v]);
+    O_lo = cum_draw(R.lo);
+    O_hi = cum_draw(R.hi);
+  }
+  O_lo = (uint32_t)__builtin_amdgcn_readfirstlane(O_lo);
+  O_hi = (uint32_t)__builtin_amdgcn_readfirstlane(O_hi);
+  uint32_t Op[kWPer];
+  Op[0] = wave_shift_up_u32(O[kWPer - 1], O_lo);
+#pragma unroll
+  for (int v = 1; v < kWPer; ++v) Op[v] = O[v - 1];
+
+  if (d_out) {
+#pragma unroll
+    for (int v = 0; v < kWPer; ++v) {
+      const int i = lane * kWPer + v;
+      if (i < cnt) d_out[P0 + i] = O[v] > Op[v] ? (int32_t)Op[v] : (int32_t)n;
+    }
+  }
+  expand_wave(O, Op, O_lo, O_hi, P0, n, a_out, L->M, e_out);
+}
+
+// ---------------------------------------------------------------- multinomial, one block per wave
+// The points p_k = n S_k / S_n of the exponential spacings are formed per
+// exponential block as r is per weight block: the block's exact carry CE[e]
+// plus the lane's quantised spacings, by the affine map (p of the block's
+// last spacing pinned to r(CE[e+1]), so blocks meet exactly).  A weight
+// block's particles need O_i = #{k : p_k < r_i}, the cumulative offspring:
+// particle i is then the ancestor of outputs [O_{i-1}, O_i), which is
+// a_k = #{i : r_i <= p_k}, the upper-bound search of Code 5 (below n - 1, as
+// i < cnt).  O_i comes from a binary search over the 1024 points of the one
+// exponential block whose range holds r_i, in LDS; the wave walks the
+// exponential blocks from the one holding the first point at or above
+// r(C_b) to the one holding the first at or above r(C_{b+1}) (usually one or
+// two), and the expansion is the one of the stratified scheme.
+struct MultiWaveLds {
+  double P[kBlock];      // the points of one exponential block
+  int32_t M[kBlock + 4]; // expansion markers; M[kBlock] spare
+};
+
+// The lane's 16 quantised spacings of exponential block e (indices
+// 1024 e + 16 lane + v): stored by the records pass, or drawn again.
+__device__ __forceinline__ void exp_values_wave(Key key, uint32_t filter, uint32_t offset,
+                                                int64_t n, uint32_t e,
+                                                const uint64_t* __restrict__ evals,
+                                                uint64_t (&q)[kWPer]) {
+  const int lane = (int)lane_id();
+  if (evals) {
+    const ulonglong2* p =
+        reinterpret_cast<const ulonglong2*>(evals + (size_t)e * kBlock + lane * kWPer);
+#pragma unroll
+    for (int k = 0; k < kWPer / 2; ++k) {
+      const ulonglong2 t = p[k];
+      q[2 * k] = t.x;
+      q[2 * k + 1] = t.y;
+    }
+    return;
+  }
+#pragma unroll
+  for (int c = 0; c < kWPer / 4; ++c) {
+    const uint32_t call = e * (uint32_t)(kBlock / 4) + (uint32_t)lane * (kWPer / 4) + c;
+    const uint4 x = draw(key, call, DOM_EXP, 0, filter, offset);
+    const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+#pragma unroll
+    for (int v = 0; v < 4; ++v) {
+      const int64_t k = (int64_t)call * 4 + v;
+      const double ev = -log(((double)xs[v] + 0.5) * 0x1p-32);
+      q[4 * c + v] = (k <= n) ? (uint64_t)(ev * 0x1p48) : 0ull;
+    }
+  }
+}
+
+// Exponential block holding the first point at or above x: the number of
+// blocks whose last point P(b + 1) = em(CE[b + 1]) lies below x.  The last
+// points sit within a few blocks of (b + 1) 1024 n / (n + 1), so one probe of
+// 256 consecutive boundaries (four per lane) around the guess settles it; a
+// bisection is the fallback.
+template <typename CEPtr>
+__device__ __forceinline__ uint32_t exp_block_of(double x, int64_t n, CEPtr CE, uint32_t nbe,
+                                                 const RMap& em) {
+  const double per_block = (double)kBlock * (double)n / (double)(n + 1);
+  int64_t w0 = (int64_t)(x / per_block) - 128;  // first probed boundary index b + 1
+  if (w0 < 1) w0 = 1;
+  const int64_t last = (int64_t)nbe - 1;  // boundaries 1 .. nbe - 1
+  const int lane = (int)lane_id();
+  uint32_t below = 0;
+#pragma unroll
+  for (int k = 0; k < 4; ++k) {
+    const int64_t b = w0 + lane * 4 + k;
+    below += (b <= last && em(CE[b]) < x) ? 1u : 0u;
+  }
+  below = wave_reduce(below, OpAdd());
+  const int64_t w1 = min(w0 + 255, last);
+  const int64_t span = w1 - w0 + 1;
+  const bool ok = w0 > last || ((w0 == 1 || below > 0) && (w1 == last || (int64_t)below < span));
+  if (ok) return (uint32_t)(w0 > last ? last : w0 - 1 + below);
+  uint32_t lo = 1, hi = nbe;  // #{b in [1, nbe - 1] : P(b) < x}
+  while (lo < hi) {
+    const uint32_t mid = (lo + hi) >> 1;
+    if (em(CE[mid]) < x) lo = mid + 1;
+    else hi = mid;
+  }
+  return lo - 1;
+}
+
+template <typename T, typename CEPtr>
+__device__ __forceinline__ void emit_multi_wave(const T* __restrict__ w, int64_t n, int64_t P0,
+                                                const BlockRec rec, u128 Cb, u128 Cb1,
+                                                int32_t gscale, u128 Q, Key key, uint32_t filter,
+                                                uint32_t offset, CEPtr CE, uint32_t nbe,
+                                                const uint64_t* __restrict__ evals,
+                                                int32_t* __restrict__ a_out, MultiWaveLds* L) {
+  const int lane = (int)lane_id();
+  BlockR R;
+  block_r_wave(w, n, P0, rec, Cb, Cb1, gscale, Q, R);
+  if (!(R.hi > R.lo)) return;  // an empty range has no outputs
+  const RMap em = make_rmap(CE[nbe], n);
+  const double ce = em.Nd * em.invQ;
+  const uint32_t e_first = (uint32_t)__builtin_amdgcn_readfirstlane(exp_block_of(R.lo, n, CE, nbe, em));
+  const uint32_t e_last = (uint32_t)__builtin_amdgcn_readfirstlane(exp_block_of(R.hi, n, CE, nbe, em));
+  uint32_t O[kWPer];
+#pragma unroll
+  for (int v = 0; v < kWPer; ++v) O[v] = 0;
+  uint32_t det = 0;  // bit v: O[v] is known
+  uint32_t O_lo = 0, O_hi = 0;
+  bool lo_det = false, hi_det = false;
+  double2* P2 = reinterpret_cast<double2*>(L->P) + lane * (kWPer / 2);
+  // lower bound in the block's points (x at most its last point)
+  auto lb = [&](double x) -> uint32_t {
+    uint32_t pos = (L->P[kBlock / 2 - 1] < x) ? (uint32_t)(kBlock / 2) : 0u;
+#pragma unroll
+    for (uint32_t st = kBlock / 4; st > 0; st >>= 1) pos += (L->P[pos + st - 1] < x) ? st : 0u;
+    return pos;
+  };
+  for (uint32_t e = e_first; e <= e_last; ++e) {
+    uint64_t q[kWPer];
+    exp_values_wave(key, filter, offset, n, e, evals, q);
+    uint64_t acc = 0;
+#pragma unroll
+    for (int v = 0; v < kWPer; ++v) {
+      acc += q[v];
+      q[v] = acc;
+    }
+    const uint64_t incl = wave_incl_add_u64(acc);
+    const uint64_t off = incl - acc;
+    const uint64_t total = readlane(incl, kWave - 1);
+    const double p_base = em(CE[e]), p_top = em(CE[e + 1]);
+#pragma unroll
+    for (int k = 0; k < kWPer / 2; ++k) {
+      double pv[2];
+#pragma unroll
+      for (int h = 0; h < 2; ++h) {
+        const uint64_t Lv = off + q[2 * k + h];
+        const double v = __fma_rn(u64_to_f64(Lv), ce, p_base);
+        pv[h] = (Lv == total || v > p_top) ? p_top : v;
+      }
+      P2[k] = make_double2(pv[0], pv[1]);
+    }
+    wave_lds_sync();
+    const uint32_t base = e * (uint32_t)kBlock;
+#pragma unroll
+    for (int v = 0; v < kWPer; ++v) {
+      const bool need = !((det >> v) & 1u) && R.r[v] <= p_top;
+      if (ballot(need)) {
+        const uint32_t pos = lb(R.r[v]);
+        if (need) {
+          O[v] = base + pos;
+          det |= 1u << v;
+        }
+      }
+    }
+    if (!lo_det && R.lo <= p_top) {
+      O_lo = base + lb(R.lo);
+      lo_det = true;
+    }
+    if (!hi_det && R.hi <= p_top) {
+      O_hi = base + lb(R.hi);
+      hi_det = true;
+    }
+    wave_lds_sync();
+  }
+  O_lo = (uint32_t)__builtin_amdgcn_readfirstlane(O_lo);
+  O_hi = (uint32_t)__builtin_amdgcn_readfirstlane(O_hi);
+  uint32_t Op[kWPer];
+  Op[0] = wave_shift_up_u32(O[kWPer - 1], O_lo);
+#pragma unroll
+  for (int v = 1; v < kWPer; ++v) Op[v] = O[v - 1];
+  expand_wave(O, Op, O_lo, O_hi, P0, n, a_out, L->M, nullptr);
+}
+
+// Weight records, one block per wave (blockIdx.x < wgs_b), and for the
+// multinomial scheme the exponential blocks (one per workgroup beyond them).
+template <typename T, bool MULTI>
+__global__ __launch_bounds__(kT) void k_scan_records_w(const T* __restrict__ w, int64_t n,
+                                                       uint32_t nb, uint32_t wgs_b, Key key,
+                                                       uint32_t offset, uint32_t filter,
+                                                       BlockRec* __restrict__ recs,
+                                                       uint64_t* __restrict__ esums,
+                                                       uint64_t* __restrict__ evals) {
+  offset = counter_offset(key, offset);
+  if (blockIdx.x < wgs_b) {
+    const uint32_t b = blockIdx.x * kWavesPerWG +
+                       (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+    if (b >= nb) return;
+    const BlockRec r = wave_block_record(w, n, (int64_t)b * kBlock);
+    if (lane_id() == 0) recs[b] = r;
+  } else if (MULTI) {
+    __shared__ WgScratch s;
+    const uint32_t b = blockIdx.x - wgs_b;
+    uint64_t q[kPer];
+    exp_values(key, filter, offset, n, b, q);
+    store_exp_values(evals, b, q);
+    const uint64_t sum = wg_reduce(q[0] + q[1] + q[2] + q[3], OpAdd(), s.u);
+    if (threadIdx.x == 0) esums[b] = sum;
+  }
+}
+
+// Direct carries for the four blocks b0 .. b0 + 3 of a workgroup: every
+// workgroup reduces all records itself (at most kDirectMax), which saves the
+// carries launch for short vectors.
+struct Direct4 {
+  u128 C[kWavesPerWG + 1], Q;
+  int32_t gscale;
+  uint32_t status;
+};
+
+__device__ Direct4 direct_carries4(uint32_t nb, uint32_t b0, const BlockRec* __restrict__ recs,
+                                   WgScratch* s) {
+  const int tid = (int)threadIdx.x;
+  BlockRec r[8];
+  uint32_t bad = 0, smin_key = 0xFFFFFFFFu;
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t j = (uint32_t)tid + (uint32_t)k * kT;
+    if (j < nb) r[k] = recs[j];
+    else r[k].sum = 0, r[k].scale = 0, r[k].bad = 0;
+  }
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    bad |= r[k].bad;
+    if (r[k].sum) smin_key = min(smin_key, (uint32_t)r[k].scale ^ 0x80000000u);
+  }
+  bad = wg_reduce(bad, OpOr(), (uint32_t*)s->i);
+  smin_key = wg_reduce(smin_key, OpMin(), (uint32_t*)s->i);
+  Direct4 d;
+  d.gscale = (smin_key == 0xFFFFFFFFu)
+                 ? 0
+                 : (int32_t)(smin_key ^ 0x80000000u) + (kCarryBits - 63) - ceil_log2(nb);
+  u128 before = 0, all = 0, own[kWavesPerWG] = {0, 0, 0, 0};
+#pragma unroll
+  for (int k = 0; k < 8; ++k) {
+    const uint32_t j = (uint32_t)tid + (uint32_t)k * kT;
+    const u128 v = (j < nb) ? conv_rec(r[k], d.gscale) : (u128)0;
+    all += v;
+    if (j < b0) before += v;
+#pragma unroll
+    for (int q = 0; q < kWavesPerWG; ++q)
+      if (j == b0 + (uint32_t)q) own[q] = v;
+  }
+  d.C[0] = wg_reduce(before, OpAdd(), s->v);
+  d.Q = wg_reduce(all, OpAdd(), s->v);
+#pragma unroll
+  for (int q = 0; q < kWavesPerWG; ++q) d.C[q + 1] = d.C[q] + wg_reduce(own[q], OpAdd(), s->v);
+  d.status = bad;
+  if (!bad && d.Q == 0) d.status |= FLAG_ZERO_TOTAL;
+  return d;
+}
+
+template <typename T, int SCHEME, bool DIRECT>
+__global__ __launch_bounds__(kT) void k_scan_emit_w(const T* __restrict__ w, int64_t n,
+                                                    uint32_t nb, Key key, uint32_t offset,
+                                                    uint32_t filter,
+                                                    const ScanHeader* __restrict__ hdr,
+                                                    const BlockRec* __restrict__ recs,
+                                                    const u128* __restrict__ C,
+                                                    int32_t* __restrict__ a,
+                                                    uint32_t* __restrict__ flags,
+                                                    int32_t* __restrict__ d_out,
+                                                    int32_t* __restrict__ e_out) {
+  static_assert(SCHEME != SCHEME_MULTINOMIAL, "strata schemes only");
+  offset = counter_offset(key, offset);
+  __shared__ StrataWaveLds<SCHEME == SCHEME_SYSTEMATIC> L[kWavesPerWG];
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint32_t b = blockIdx.x * kWavesPerWG + wave;
+  uint32_t status;
+  u128 Cb, Cb1, Q;
+  int32_t gscale;
+  if (DIRECT) {
+    __shared__ WgScratch s;
+    const Direct4 d = direct_carries4(nb, blockIdx.x * kWavesPerWG, recs, &s);
+    status = d.status;
+    Cb = d.C[wave];
+    Cb1 = d.C[wave + 1];
+    Q = d.Q;
+    gscale = d.gscale;
+  } else {
+    if (b >= nb) return;
+    status = hdr->status;
+    Cb = C[b];
+    Cb1 = C[b + 1];
+    Q = hdr->Q;
+    gscale = hdr->gscale;
+  }
+  if (b >= nb) return;
+  if (flags && b == 0 && threadIdx.x == 0 && status) atomicOr(flags, status);
+  const int64_t P0 = (int64_t)b * kBlock;
+  if (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
+    // identity: every position claims its own slot
+    for (int64_t i = P0 + lane_id(); i < min(P0 + kBlock, n); i += kWave) {
+      a[i] = (int32_t)i;
+      if (d_out) {
+        d_out[i] = (int32_t)i;
+        e_out[i] = (int32_t)i;
+      }
+    }
+    return;
+  }
+  emit_block_wave<T, SCHEME == SCHEME_SYSTEMATIC>(w, n, P0, recs[b], Cb, Cb1, gscale, Q, key,
+                                                   filter, offset, a, &L[wave], d_out, e_out);
+}
+
+// Multinomial emission, one weight block per wave (after k_scan_carries).
+template <typename T>
+__global__ __launch_bounds__(kT) void k_scan_emit_mw(const T* __restrict__ w, int64_t n,
+                                                     uint32_t nb, uint32_t nbe, Key key,
+                                                     uint32_t offset, uint32_t filter,
+                                                     const ScanHeader* __restrict__ hdr,
+                                                     const BlockRec* __restrict__ recs,
+                                                     const u128* __restrict__ C,
+                                                     const u128* __restrict__ CE,
+                                                     const uint64_t* __restrict__ evals,
+                                                     int32_t* __restrict__ a,
+                                                     uint32_t* __restrict__ flags) {
+  offset = counter_offset(key, offset);
+  __shared__ MultiWaveLds L[kWavesPerWG];
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint32_t b = blockIdx.x * kWavesPerWG + wave;
+  if (b >= nb) return;
+  const uint32_t status = hdr->status;
+  if (flags && b == 0 && threadIdx.x == 0 && status) atomicOr(flags, status);
+  const int64_t P0 = (int64_t)b * kBlock;
+  if (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
+    for (int64_t i = P0 + lane_id(); i < min(P0 + kBlock, n); i += kWave) a[i] = (int32_t)i;
+    return;
+  }
+  emit_multi_wave<T>(w, n, P0, recs[b], C[b], C[b + 1], hdr->gscale, hdr->Q, key, filter, offset,
+                     CE, nbe, evals, a, &L[wave]);
+}
+
 // ---------------------------------------------------------------- Code 5
 // Multinomial resampling with one independent uniform per particle, as Code 5
 // prints it: the scaled prefix r_k = n W_k / W_n of the exact sums is written
@@ -361,23 +1002,26 @@ __global__ __launch_bounds__(kT) void k_scan_emit(const T* __restrict__ w, int64
 // r_{(j+1) S - 1} (S a power of two) in LDS, which narrow each point to S
 // candidates, and a bisection over those in global memory finishes it.
 template <typename T>
-__global__ __launch_bounds__(kT) void k_scan_r(const T* __restrict__ w, int64_t n,
+__global__ __launch_bounds__(kT) void k_scan_r(const T* __restrict__ w, int64_t n, uint32_t nb,
                                                const ScanHeader* __restrict__ hdr,
                                                const BlockRec* __restrict__ recs,
                                                const u128* __restrict__ C,
                                                double* __restrict__ r_out) {
-  __shared__ WgScratch s;
   if (hdr->status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) return;
-  const uint32_t b = blockIdx.x;
-  const RMap rm = make_rmap(hdr->Q, n);
-  double r[kPer];
+  const uint32_t b = blockIdx.x * kWavesPerWG +
+                     (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (b >= nb) return;
   const int64_t P0 = (int64_t)b * kBlock;
-  block_r(w, n, P0, recs[b], C[b], hdr->gscale, rm, r, &s);
+  BlockR R;
+  block_r_wave(w, n, P0, recs[b], C[b], C[b + 1], hdr->gscale, hdr->Q, R);
+  const int64_t i0 = P0 + (int64_t)lane_id() * kWPer;
 #pragma unroll
-  for (int v = 0; v < kPer; ++v) {
-    const int64_t i = P0 + (int64_t)threadIdx.x * kPer + v;
-    if (i < n) r_out[i] = r[v];
-  }
+  for (int v = 0; v < kWPer; ++v)
+    if (i0 + v < n) r_out[i0 + v] = R.r[v];
+}
+
+__global__ void k_scan_status(const ScanHeader* __restrict__ hdr, uint32_t* __restrict__ flags) {
+  if (hdr->status) atomicOr(flags, hdr->status);
 }
 
 constexpr int kSplit = 4096;
@@ -446,7 +1090,6 @@ __global__ __launch_bounds__(kT) void k_scan_batched(const T* __restrict__ w, in
                                                      uint32_t* __restrict__ flags) {
   offset = counter_offset(key, offset);
   __shared__ BatchLds B;
-  __shared__ EmitLds L;
   __shared__ WgScratch s;
   const uint32_t f = blockIdx.x;
   if (f >= n_filters) return;
@@ -464,9 +1107,10 @@ __global__ __launch_bounds__(kT) void k_scan_batched(const T* __restrict__ w, in
     if (tid == 0 && flags) atomicOr(flags, FLAG_BAD_COUNTS);
     return;
   }
-  for (uint32_t b = 0; b < nb; ++b) {
-    const BlockRec r = block_record(ws, n, (int64_t)b * kBlock, &s);
-    if (tid == 0) B.recs[b] = r;
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  for (uint32_t b = wave; b < nb; b += kWavesPerWG) {
+    const BlockRec r = wave_block_record(ws, n, (int64_t)b * kBlock);
+    if (lane_id() == 0) B.recs[b] = r;
   }
   if (SCHEME == SCHEME_MULTINOMIAL) {
     for (uint32_t b = 0; b < nbe; ++b) {
@@ -484,11 +1128,19 @@ __global__ __launch_bounds__(kT) void k_scan_batched(const T* __restrict__ w, in
     for (int64_t i = tid; i < n; i += kT) as[i] = (int32_t)i;
     return;
   }
-  const RMap rm = make_rmap(t.Q, n);
-  for (uint32_t b = 0; b < nb; ++b) {
-    emit_block<T, SCHEME>(ws, n, b, B.recs[b], B.C[b], B.C[b + 1], t.gscale, rm, key, filt,
-                          offset, (const u128*)B.CE, nbe, as, &L, &s);
-    __syncthreads();
+  if constexpr (SCHEME == SCHEME_MULTINOMIAL) {
+    __shared__ MultiWaveLds L[kWavesPerWG];
+    for (uint32_t b = wave; b < nb; b += kWavesPerWG)
+      emit_multi_wave<T>(ws, n, (int64_t)b * kBlock, B.recs[b], B.C[b], B.C[b + 1], t.gscale,
+                         t.Q, key, filt, offset, (const u128*)B.CE, nbe, (const uint64_t*)nullptr,
+                         as, &L[wave]);
+  } else {
+    __shared__ StrataWaveLds<SCHEME == SCHEME_SYSTEMATIC> L[kWavesPerWG];
+    for (uint32_t b = wave; b < nb; b += kWavesPerWG)
+      emit_block_wave<T, SCHEME == SCHEME_SYSTEMATIC>(ws, n, (int64_t)b * kBlock, B.recs[b],
+                                                       B.C[b], B.C[b + 1], t.gscale, t.Q, key,
+                                                       filt, offset, as, &L[wave], nullptr,
+                                                       nullptr);
   }
 }
 
@@ -573,6 +1225,24 @@ __global__ __launch_bounds__(kT) void k_seg_records(
   }
 }
 
+// Weight records of the segmented batch, one block per wave (strata schemes;
+// the multinomial scheme keeps k_seg_records for its exponential blocks).
+template <typename T>
+__global__ __launch_bounds__(kT) void k_seg_records_w(const T* __restrict__ w,
+                                                      const int64_t* __restrict__ offsets,
+                                                      uint32_t n_filters,
+                                                      const uint32_t* __restrict__ bstart,
+                                                      BlockRec* __restrict__ recs) {
+  const uint32_t g = blockIdx.x * kWavesPerWG +
+                     (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  if (g >= bstart[n_filters]) return;
+  const uint32_t f = seg_of_block(bstart, n_filters, g);
+  const int64_t base = offsets[f];
+  const int64_t n = offsets[f + 1] - base;
+  const BlockRec r = wave_block_record(w + base, n, (int64_t)(g - bstart[f]) * kBlock);
+  if (lane_id() == 0) recs[g] = r;
+}
+
 // Per segment (one workgroup each): global scale, exact carries C (nb + 1 per
 // segment, at cstart = bstart[f] + f), total and status, and the
 // exponential-block carries of the multinomial scheme (at estart[f] + f).
@@ -642,6 +1312,69 @@ __global__ __launch_bounds__(kT) void k_seg_emit(
                         filter_base + f, offset, CEs, nbe, as, &L, &s, nullptr, nullptr, evs);
 }
 
+// Emission of the segmented batch, one block per wave (strata schemes).
+template <typename T, int SCHEME>
+__global__ __launch_bounds__(kT) void k_seg_emit_w(
+    const T* __restrict__ w, const int64_t* __restrict__ offsets, uint32_t n_filters, Key key,
+    uint32_t offset, uint32_t filter_base, const uint32_t* __restrict__ bstart,
+    const BlockRec* __restrict__ recs, const u128* __restrict__ C,
+    const SegHdr* __restrict__ hdr, int32_t* __restrict__ a, uint32_t* __restrict__ flags) {
+  static_assert(SCHEME != SCHEME_MULTINOMIAL, "strata schemes only");
+  __shared__ StrataWaveLds<SCHEME == SCHEME_SYSTEMATIC> L[kWavesPerWG];
+  offset = counter_offset(key, offset);
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint32_t g = blockIdx.x * kWavesPerWG + wave;
+  if (g >= bstart[n_filters]) return;
+  const uint32_t f = seg_of_block(bstart, n_filters, g);
+  const int64_t base = offsets[f];
+  const int64_t n = offsets[f + 1] - base;
+  const uint32_t b = g - bstart[f];
+  int32_t* __restrict__ as = a + base;
+  const uint32_t status = hdr[f].status;
+  if (flags && b == 0 && lane_id() == 0 && status) atomicOr(flags, status);
+  const int64_t P0 = (int64_t)b * kBlock;
+  if (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
+    for (int64_t i = P0 + lane_id(); i < min(P0 + kBlock, n); i += kWave) as[i] = (int32_t)i;
+    return;
+  }
+  const u128* Cs = C + bstart[f] + f;
+  emit_block_wave<T, SCHEME == SCHEME_SYSTEMATIC>(w + base, n, P0, recs[g], Cs[b], Cs[b + 1],
+                                                   hdr[f].gscale, hdr[f].Q, key, filter_base + f,
+                                                   offset, as, &L[wave], nullptr, nullptr);
+}
+
+// Multinomial emission of the segmented batch, one block per wave.
+template <typename T>
+__global__ __launch_bounds__(kT) void k_seg_emit_mw(
+    const T* __restrict__ w, const int64_t* __restrict__ offsets, uint32_t n_filters, Key key,
+    uint32_t offset, uint32_t filter_base, const uint32_t* __restrict__ bstart,
+    const uint32_t* __restrict__ estart, const BlockRec* __restrict__ recs,
+    const u128* __restrict__ C, const u128* __restrict__ CE, const SegHdr* __restrict__ hdr,
+    int32_t* __restrict__ a, uint32_t* __restrict__ flags, const uint64_t* __restrict__ evals) {
+  __shared__ MultiWaveLds L[kWavesPerWG];
+  offset = counter_offset(key, offset);
+  const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
+  const uint32_t g = blockIdx.x * kWavesPerWG + wave;
+  if (g >= bstart[n_filters]) return;
+  const uint32_t f = seg_of_block(bstart, n_filters, g);
+  const int64_t base = offsets[f];
+  const int64_t n = offsets[f + 1] - base;
+  const uint32_t b = g - bstart[f];
+  int32_t* __restrict__ as = a + base;
+  const uint32_t status = hdr[f].status;
+  if (flags && b == 0 && lane_id() == 0 && status) atomicOr(flags, status);
+  const int64_t P0 = (int64_t)b * kBlock;
+  if (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
+    for (int64_t i = P0 + lane_id(); i < min(P0 + kBlock, n); i += kWave) as[i] = (int32_t)i;
+    return;
+  }
+  const u128* Cs = C + bstart[f] + f;
+  const uint32_t nbe = estart[f + 1] - estart[f];
+  emit_multi_wave<T>(w + base, n, P0, recs[g], Cs[b], Cs[b + 1], hdr[f].gscale, hdr[f].Q, key,
+                     filter_base + f, offset, CE + estart[f] + f, nbe,
+                     evals + (size_t)estart[f] * kBlock, as, &L[wave]);
+}
+
 template <typename T, int SCHEME>
 hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, uint32_t filter,
                          int32_t* a, void* ws, uint32_t* flags, hipStream_t stream,
@@ -658,23 +1391,29 @@ hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, ui
   uint64_t* evals = multi ? (uint64_t*)(base + L.evals) : nullptr;
   const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
   const uint32_t nbe = multi ? (uint32_t)((n + 1 + kBlock - 1) / kBlock) : 0u;
-  hipLaunchKernelGGL((k_scan_records<T, multi>), dim3(nb + nbe), dim3(kT), 0, stream, w, n, nb,
-                     key, offset, filter, recs, esums, evals);
+  const uint32_t wgs_b = (nb + kWavesPerWG - 1) / kWavesPerWG;
+  hipLaunchKernelGGL((k_scan_records_w<T, multi>), dim3(wgs_b + nbe), dim3(kT), 0, stream, w, n,
+                     nb, wgs_b, key, offset, filter, recs, esums, evals);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  if (!multi && nb <= (uint32_t)tuning().direct_max_blocks && nb <= kDirectMax) {
-    hipLaunchKernelGGL((k_scan_emit<T, SCHEME, true>), dim3(nb), dim3(kT), 0, stream, w, n, nb,
-                       nbe, key, offset, filter, hdr, recs, C, CE, a, flags, d_out, e_out,
-                       (const uint64_t*)evals);
-    return hipGetLastError();
+  if constexpr (!multi) {
+    if (nb <= (uint32_t)tuning().direct_max_blocks && nb <= kDirectMax) {
+      hipLaunchKernelGGL((k_scan_emit_w<T, SCHEME, true>), dim3(wgs_b), dim3(kT), 0, stream, w,
+                         n, nb, key, offset, filter, hdr, recs, C, a, flags, d_out, e_out);
+      return hipGetLastError();
+    }
   }
   hipLaunchKernelGGL((k_scan_carries<multi>), dim3(1), dim3(kT), 0, stream, nb, nbe, hdr, recs,
                      esums, C, CE);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_scan_emit<T, SCHEME, false>), dim3(nb), dim3(kT), 0, stream, w, n, nb,
-                     nbe, key, offset, filter, hdr, recs, C, CE, a, flags, d_out, e_out,
-                     (const uint64_t*)evals);
+  if constexpr (multi) {
+    hipLaunchKernelGGL((k_scan_emit_mw<T>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb, nbe, key,
+                       offset, filter, hdr, recs, C, CE, (const uint64_t*)evals, a, flags);
+  } else {
+    hipLaunchKernelGGL((k_scan_emit_w<T, SCHEME, false>), dim3(wgs_b), dim3(kT), 0, stream, w,
+                       n, nb, key, offset, filter, hdr, recs, C, a, flags, d_out, e_out);
+  }
   return hipGetLastError();
 }
 
@@ -734,9 +1473,14 @@ hipError_t launch_segmented_t(const T* w, int64_t n_total, const int64_t* offset
                      estart);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_seg_records<T, multi>), dim3(L.grid_b + (multi ? L.grid_e : 0u)),
-                     dim3(kT), 0, stream, w, offsets, n_filters, L.grid_b, key, offset,
-                     filter_base, bstart, estart, recs, esums, evals);
+  const uint32_t wgs_b = (L.grid_b + kWavesPerWG - 1) / kWavesPerWG;
+  if constexpr (multi)
+    hipLaunchKernelGGL((k_seg_records<T, multi>), dim3(L.grid_b + L.grid_e), dim3(kT), 0, stream,
+                       w, offsets, n_filters, L.grid_b, key, offset, filter_base, bstart, estart,
+                       recs, esums, evals);
+  else
+    hipLaunchKernelGGL((k_seg_records_w<T>), dim3(wgs_b), dim3(kT), 0, stream, w, offsets,
+                       n_filters, bstart, recs);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
   u128* C = (u128*)(base + L.carries);
@@ -746,9 +1490,13 @@ hipError_t launch_segmented_t(const T* w, int64_t n_total, const int64_t* offset
                      bstart, estart, recs, esums, C, CE, hdr);
   e = hipGetLastError();
   if (e != hipSuccess) return e;
-  hipLaunchKernelGGL((k_seg_emit<T, SCHEME>), dim3(L.grid_b), dim3(kT), 0, stream, w, offsets,
-                     n_filters, key, offset, filter_base, bstart, estart, recs, C, CE, hdr, a,
-                     flags, (const uint64_t*)evals);
+  if constexpr (multi)
+    hipLaunchKernelGGL((k_seg_emit_mw<T>), dim3(wgs_b), dim3(kT), 0, stream, w, offsets,
+                       n_filters, key, offset, filter_base, bstart, estart, recs, C, CE, hdr, a,
+                       flags, (const uint64_t*)evals);
+  else
+    hipLaunchKernelGGL((k_seg_emit_w<T, SCHEME>), dim3(wgs_b), dim3(kT), 0, stream, w, offsets,
+                       n_filters, key, offset, filter_base, bstart, recs, C, hdr, a, flags);
   return hipGetLastError();
 }
 
@@ -838,11 +1586,12 @@ hipError_t launch_multinomial_iid_t(const T* w, int64_t n, Key key, uint32_t off
   u128* C = (u128*)(base + L.carries);
   double* r = (double*)(base + L.total);
   const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
-  hipLaunchKernelGGL((k_scan_records<T, false>), dim3(nb), dim3(kT), 0, stream, w, n, nb, key,
-                     offset, filter, recs, (uint64_t*)nullptr, (uint64_t*)nullptr);
+  const uint32_t wgs_b = (nb + kWavesPerWG - 1) / kWavesPerWG;
+  hipLaunchKernelGGL((k_scan_records_w<T, false>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb,
+                     wgs_b, key, offset, filter, recs, (uint64_t*)nullptr, (uint64_t*)nullptr);
   hipLaunchKernelGGL((k_scan_carries<false>), dim3(1), dim3(kT), 0, stream, nb, 0u, hdr, recs,
                      (const uint64_t*)nullptr, C, (u128*)nullptr);
-  hipLaunchKernelGGL((k_scan_r<T>), dim3(nb), dim3(kT), 0, stream, w, n, hdr, recs, C, r);
+  hipLaunchKernelGGL((k_scan_r<T>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb, hdr, recs, C, r);
   // splitter stride: the smallest power of two leaving at most kSplit splitters
   int sl = 0;
   while (((n - 1) >> sl) > kSplit) ++sl;
@@ -851,6 +1600,32 @@ hipError_t launch_multinomial_iid_t(const T* w, int64_t n, Key key, uint32_t off
   hipLaunchKernelGGL(k_multinomial_iid, dim3((unsigned)grid), dim3(kT), 0, stream, n, hdr, r, sl,
                      key, offset, filter, a, flags);
   return hipGetLastError();
+}
+
+template <typename T>
+hipError_t launch_scan_r_t(const T* w, int64_t n, double* r, void* ws, uint32_t* flags,
+                           hipStream_t stream) {
+  const ScanLayout L = scan_layout(n, false);
+  char* base = (char*)ws;
+  ScanHeader* hdr = (ScanHeader*)base;
+  BlockRec* recs = (BlockRec*)(base + L.recs);
+  u128* C = (u128*)(base + L.carries);
+  const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
+  const uint32_t wgs_b = (nb + kWavesPerWG - 1) / kWavesPerWG;
+  hipLaunchKernelGGL((k_scan_records_w<T, false>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb,
+                     wgs_b, Key{0, 0, nullptr}, 0u, 0u, recs, (uint64_t*)nullptr,
+                     (uint64_t*)nullptr);
+  hipLaunchKernelGGL((k_scan_carries<false>), dim3(1), dim3(kT), 0, stream, nb, 0u, hdr, recs,
+                     (const uint64_t*)nullptr, C, (u128*)nullptr);
+  hipLaunchKernelGGL((k_scan_r<T>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb, hdr, recs, C, r);
+  if (flags) hipLaunchKernelGGL(k_scan_status, dim3(1), dim3(1), 0, stream, hdr, flags);
+  return hipGetLastError();
+}
+
+hipError_t launch_scan_r(bool f64, const void* w, int64_t n, double* r, void* ws, uint32_t* flags,
+                         hipStream_t stream) {
+  return f64 ? launch_scan_r_t((const double*)w, n, r, ws, flags, stream)
+             : launch_scan_r_t((const float*)w, n, r, ws, flags, stream);
 }
 
 hipError_t launch_multinomial_iid(bool f64, const void* w, int64_t n, Key key, uint32_t offset,

@@ -16,13 +16,17 @@ def gpu_r_error_bound(w, n):
     Each weight is quantised with absolute error below max(w) 2^-52 (it is
     truncated at 2^-s of its block, s set by the block maximum), so a prefix of
     i weights is off by at most i max(w) 2^-52, i.e. n^2 max(w) 2^-52 / W in r
-    units; the conversion to binary64 and the scaling add four roundings.
+    units.  The block's first value r(C_b) = n (C_b / Q) costs at most seven
+    roundings relative to r <= n (the two 128-bit conversions, the reciprocal
+    and the two products); inside a block r = fl(L c + r(C_b)) adds the
+    rounding of L, four in c = n 2^k / Q and the final one, at most six more:
+    13 n 2^-53 in all, taken as 16 n 2^-53.
     """
     w = np.asarray(w, dtype=np.float64)
     W = w.sum()
     if n == 0 or W == 0:
         return 0.0
-    return n * n * w.max() * 2.0**-52 / W + 6.0 * n * 2.0**-53
+    return n * n * w.max() * 2.0**-52 / W + 16.0 * n * 2.0**-53
 
 
 def check_ties(a_gpu, a_or, r, points, delta, max_ties):
