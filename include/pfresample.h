@@ -418,7 +418,7 @@ PFR_API int lgssm_step(const pfr_lgssm* model, pfr_op scheme, pfr_precision prec
  * changes a result: random numbers are drawn per particle and the exact
  * prefix sums do not depend on how they are split, so every setting gives the
  * same bits.  Process-wide; set them before launching work. */
-#define PFR_TUNING_VERSION 1
+#define PFR_TUNING_VERSION 2
 typedef struct {
     int32_t version;                /* PFR_TUNING_VERSION */
     int32_t single_wg_max;          /* collective: single vectors up to this length run in one
@@ -431,6 +431,20 @@ typedef struct {
     int32_t rejection_per_wave;     /* particles per wave of the rejection schedule [64, 4096] */
     int32_t metropolis_chunk;       /* particles per workgroup of the global-memory Metropolis
                                        kernel, a multiple of 256 in [256, 8192] */
+    /* ragged batches (n_filters > 1) */
+    int32_t batch_scan_wg_max_len;  /* collective, exact prefix: a batch whose longest segment is
+                                       at most this runs one workgroup per segment even with a
+                                       workspace, longer ones block-parallel
+                                       [0, PFR_MAX_BATCH_SEGMENT] */
+    int32_t batch_stage_max_kb;     /* Metropolis / rejection: largest LDS tier for staging a
+                                       segment's weights (16, 64 or 128 KB); longer segments
+                                       gather from global memory in the same launch */
+    int32_t batch_metropolis_chunk; /* particles per 1024-thread workgroup of the batched
+                                       Metropolis kernel, a multiple of 1024 in [1024, 65536] */
+    int32_t batch_rejection_per_wave; /* particles per wave of the batched rejection kernel
+                                       [64, 4096] */
+    int32_t batch_permute_lds_max;  /* segments up to this length are permuted in LDS, one
+                                       workgroup each (4096, 8192 or 16384) */
 } pfr_tuning;
 
 PFR_API void pfr_tuning_defaults(pfr_tuning* t);

@@ -41,7 +41,7 @@ EXPORTS = (
     "pfr_status_string", "pfr_version", "pfr_philox_rounds",
 )
 
-TUNING_VERSION = 1
+TUNING_VERSION = 2
 # tuning chosen for this machine by autotune.py; PFR_TUNING overrides the path
 TUNING_PATH = os.environ.get("PFR_TUNING", os.path.join(HERE, "tuning.json"))
 
@@ -72,7 +72,11 @@ class Tuning(ctypes.Structure):
                 ("direct_max_blocks", ctypes.c_int32),
                 ("metropolis_table_min_B", ctypes.c_int32),
                 ("rejection_table", ctypes.c_int32), ("rejection_per_wave", ctypes.c_int32),
-                ("metropolis_chunk", ctypes.c_int32)]
+                ("metropolis_chunk", ctypes.c_int32),
+                ("batch_scan_wg_max_len", ctypes.c_int32), ("batch_stage_max_kb", ctypes.c_int32),
+                ("batch_metropolis_chunk", ctypes.c_int32),
+                ("batch_rejection_per_wave", ctypes.c_int32),
+                ("batch_permute_lds_max", ctypes.c_int32)]
 
 
 class PfrError(RuntimeError):
@@ -128,11 +132,46 @@ def open_library(path: str) -> ctypes.CDLL:
         fn = getattr(lib, name)
         fn.restype = res
         fn.argtypes = args
-    if os.path.exists(TUNING_PATH):
-        rc = lib.pfr_load_tuning(TUNING_PATH.encode())
-        if rc != PFR_OK:
-            raise PfrError(f"invalid tuning file {TUNING_PATH} (status {rc})")
+    load_tuning_file(lib, TUNING_PATH)
     return lib
+
+
+def _device_arch():
+    """ISA name of GPU 0 (e.g. gfx950), or None without a GPU."""
+    try:
+        import torch
+        if not torch.cuda.is_available():
+            return None
+        return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
+    except Exception:
+        return None
+
+
+def load_tuning_file(lib, path):
+    """Apply the tuning file written by autotune.py if it was tuned for this
+    GPU's architecture and this library's tuning version; otherwise keep the
+    library's defaults (a file for another GPU would only mislead)."""
+    import json
+    import sys
+    if not os.path.exists(path):
+        return False
+    with open(path) as f:
+        doc = json.load(f)
+    arch = _device_arch()
+    if doc.get("version") != TUNING_VERSION or (arch and doc.get("arch") not in (None, arch)):
+        print(f"libpfresample: {path} was tuned for {doc.get('arch')} (version "
+              f"{doc.get('version')}); keeping the defaults", file=sys.stderr)
+        return False
+    t = Tuning()
+    lib.pfr_get_tuning(ctypes.byref(t))
+    for name, _ in Tuning._fields_:
+        if name in doc and name != "version":
+            setattr(t, name, int(doc[name]))
+    t.version = TUNING_VERSION
+    rc = lib.pfr_set_tuning(ctypes.byref(t))
+    if rc != PFR_OK:
+        raise PfrError(f"invalid tuning file {path} (status {rc})")
+    return True
 
 
 def load(path: str = LIB_PATH) -> ctypes.CDLL:

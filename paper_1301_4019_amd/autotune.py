@@ -190,8 +190,104 @@ def tune(reps=15, log=print):
     chosen["rejection_per_wave"] = int(best.split(",")[1].split("=")[1])
     meas["rejection"] = rows
 
+    # ---- ragged batches (config 4): 4096 float32 vectors, N_f = 2^(8+8v)
+    batch_tune(torch, pfr, inputs, timer, chosen, meas, with_tuning, same, log)
+
     pfr.set_tuning(**chosen)
     return chosen, meas
+
+
+def batch_tune(torch, pfr, inputs, timer, chosen, meas, with_tuning, same, log):
+    """Launch shapes of the ragged-batch kernels, each checked bit for bit
+    against the first candidate.  The collective threshold is measured per
+    bucket of the longest segment (batches of 4096 vectors with lengths
+    log-uniform up to 2^10 .. 2^16), the others on the full config-4 batch."""
+    from . import _lib
+
+    def batch(hi_log2, seed=0):
+        w_np, off_np, ys = inputs.ragged_batch(n_filters=4096, seed=seed)
+        if hi_log2 < 16:  # the same vectors, cut to at most 2^hi_log2 particles
+            lens = np.minimum(np.diff(off_np), 1 << hi_log2)
+            parts = [w_np[off_np[f]:off_np[f] + lens[f]] for f in range(lens.size)]
+            w_np = np.concatenate(parts)
+            off_np = np.concatenate([[0], np.cumsum(lens)]).astype(np.int64)
+        B = np.array([_b_star(float(y)) for y in ys], dtype=np.int32)
+        return (torch.from_numpy(w_np).cuda(), torch.from_numpy(off_np).cuda(),
+                int(np.diff(off_np).max()), torch.from_numpy(B).cuda())
+
+    # batch_scan_wg_max_len: one workgroup per segment up to this longest segment
+    rows = {}
+    thr = 0
+    for lg in (10, 12, 14, 16):
+        w, off, max_len, B = batch(lg)
+        out = torch.empty(w.numel(), dtype=torch.int32, device="cuda")
+        ws = pfr.new_workspace(pfr.workspace_bytes(_lib.OP_MULTINOMIAL, w.numel(), off, max_len))
+
+        def run():
+            for s in ("stratified", "systematic", "multinomial"):
+                getattr(pfr, "resample_" + s)(w, seed=1, offsets=off, max_len=max_len, out=out,
+                                              workspace=ws)
+
+        t_wg = with_tuning({"batch_scan_wg_max_len": _lib.MAX_BATCH_SEGMENT}, lambda: timer(run))
+        ref = out.clone()
+        t_blk = with_tuning({"batch_scan_wg_max_len": 0}, lambda: timer(run))
+        same(out, ref, "batch_scan_wg_max_len")
+        rows[f"max_len<=2^{lg}"] = {"one_workgroup_per_segment_ms": t_wg,
+                                    "block_parallel_ms": t_blk}
+        log(f"batch collective max_len 2^{lg}: one workgroup per segment {t_wg:.4f} ms, "
+            f"block-parallel {t_blk:.4f} ms")
+    # the largest bucket up to which one workgroup per segment wins at every bucket
+    for lg in (10, 12, 14, 16):
+        r = rows[f"max_len<=2^{lg}"]
+        if r["one_workgroup_per_segment_ms"] < r["block_parallel_ms"]:
+            thr = 1 << lg
+        else:
+            break
+    chosen["batch_scan_wg_max_len"] = min(thr, _lib.MAX_BATCH_SEGMENT)
+    meas["batch_scan_wg_max_len"] = rows
+
+    w, off, max_len, B = batch(16)
+    both = torch.empty(2 * w.numel(), dtype=torch.int32, device="cuda")
+    out_m, out = both[:w.numel()], both[w.numel():]
+    perm = torch.empty_like(out)
+
+    def pick(name, cands, fn, result):
+        rows, ref = {}, None
+        for c in cands:
+            t = with_tuning({name: c}, lambda: timer(fn))
+            if ref is None:
+                ref = result.clone()
+            same(result, ref, name)
+            rows[c] = t
+            log(f"{name} {c}: {t:.4f} ms")
+        chosen[name] = min(rows, key=rows.get)
+        meas[name] = rows
+
+    def metro():
+        pfr.resample_metropolis(w, 0, seed=1, B_per_filter=B, offsets=off, max_len=max_len,
+                                out=out_m)
+
+    def rej():
+        pfr.resample_rejection(w, 1.0, seed=1, offsets=off, max_len=max_len, out=out)
+
+    def alt_both():
+        metro()
+        rej()
+
+    pick("batch_stage_max_kb", (128, 64, 16), alt_both, both)
+    pick("batch_metropolis_chunk", (1024, 2048, 4096, 8192, 16384), metro, out_m)
+    pick("batch_rejection_per_wave", (64, 128, 256, 512, 1024), rej, out)
+
+    a_unsorted = torch.empty_like(out)
+    pfr.resample_metropolis(w, 0, seed=1, B_per_filter=B, offsets=off, max_len=max_len,
+                            out=a_unsorted)
+    a_sorted = pfr.resample_systematic(w, seed=1, offsets=off, max_len=max_len)
+
+    def permute_both():
+        pfr.permute_ancestors(a_unsorted, offsets=off, max_len=max_len, out=perm)
+        pfr.permute_ancestors(a_sorted, sorted_hint=True, offsets=off, max_len=max_len, out=perm)
+
+    pick("batch_permute_lds_max", (16384, 8192, 4096), permute_both, perm)
 
 
 def main():
@@ -203,13 +299,21 @@ def main():
     import torch
     t0 = time.time()
     chosen, meas = tune(args.reps, log=lambda m: print(m, file=sys.stderr, flush=True))
-    doc = {"version": 1, **chosen,
+    from . import _lib
+    doc = {"version": _lib.TUNING_VERSION, **chosen,
+           "arch": device_arch(),
            "device": torch.cuda.get_device_name(0),
            "tuned_seconds": round(time.time() - t0, 1),
            "measured_ms": meas}
     with open(args.out, "w") as f:
         json.dump(doc, f, indent=1)
-    print(json.dumps({"version": 1, **chosen}), flush=True)
+    print(json.dumps({"version": _lib.TUNING_VERSION, "arch": doc["arch"], **chosen}), flush=True)
+
+
+def device_arch():
+    """The GPU's ISA name (gfx950 on MI355X), which keys the tuning file."""
+    import torch
+    return torch.cuda.get_device_properties(0).gcnArchName.split(":")[0]
 
 
 if __name__ == "__main__":

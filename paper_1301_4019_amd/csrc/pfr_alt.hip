@@ -678,13 +678,18 @@ __global__ __launch_bounds__(kTableThreads) void k_rejection_table(
 template <typename T>
 int staged_capacity(int64_t max_len, int64_t n_total, uint32_t n_filters) {
   constexpr int64_t per_kb = 1024 / (int64_t)sizeof(T);
-  if (n_filters == 1) max_len = n_total;
+  if (n_filters == 1) {
+    if (n_total <= 16 * per_kb) return (int)(16 * per_kb);
+    if (n_total <= 64 * per_kb) return (int)(64 * per_kb);
+    return 0;
+  }
+  // batches: up to the tuned largest tier; longer segments run in the same
+  // launch from global memory
   if (max_len <= 0) max_len = (int64_t)128 * per_kb;
-  if (max_len <= 16 * per_kb) return (int)(16 * per_kb);
-  if (max_len <= 64 * per_kb) return (int)(64 * per_kb);
-  // batches: longer segments run in the same launch from global memory
-  if (n_filters > 1) return (int)(128 * per_kb);
-  return 0;
+  const int64_t top = (int64_t)tuning().batch_stage_max_kb;
+  if (max_len <= 16 * per_kb || top == 16) return (int)(16 * per_kb);
+  if (max_len <= 64 * per_kb || top == 64) return (int)(64 * per_kb);
+  return (int)(128 * per_kb);
 }
 
 template <typename T>
@@ -736,7 +741,7 @@ hipError_t launch_metropolis_t(const void* wv, int64_t n_total, const int64_t* o
                          chunk1, (int64_t)0, hi);
     return hipGetLastError();
   }
-  const int64_t chunk = 4096;
+  const int64_t chunk = tuning().batch_metropolis_chunk;
   const dim3 grid((unsigned)((n_total + chunk - 1) / chunk));
   if (cap == 16 * per_kb)
     hipLaunchKernelGGL((k_metropolis_staged<T, 16 * per_kb, 1024>), grid, dim3(1024), 0, stream, w,
@@ -883,7 +888,7 @@ hipError_t launch_rejection_t(const void* wv, int64_t n_total, const int64_t* of
                          filter_base, a, flags, chunk1);
     return hipGetLastError();
   }
-  const int64_t chunk = (int64_t)tuning().rejection_per_wave * 16;
+  const int64_t chunk = (int64_t)tuning().batch_rejection_per_wave * 16;
   const dim3 grid((unsigned)((n_total + chunk - 1) / chunk));
   if (cap == 16 * per_kb)
     hipLaunchKernelGGL((k_rejection<T, 16 * per_kb, 1024>), grid, dim3(1024), 0, stream, w,

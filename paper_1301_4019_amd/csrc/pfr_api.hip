@@ -16,7 +16,7 @@ namespace {
 // Set by pfr_set_tuning, read by the launchers of any host thread: every
 // access holds the lock, and readers get a copy.
 std::mutex g_tuning_mu;
-Tuning g_tuning = {4096, 2048, 32, 1, 256, 256};
+Tuning g_tuning = {4096, 2048, 32, 1, 256, 256, 0, 128, 4096, 256, 16384};
 }  // namespace
 
 Tuning tuning() {
@@ -103,9 +103,11 @@ int collective(int scheme, const void* w, pfr_dtype dtype, const pfr_segments* s
       return launch_result(launch_fscan_batched(scheme, (int)precision, dtype == PFR_F64, w,
                                                 s.n_total, s.offsets, s.n_filters, key,
                                                 rng.offset, rng.filter_base, a, dev_flags, st));
-    // a batch with a workspace runs block-parallel, without one in one
-    // workgroup per segment; the results are the same
-    if (s.n_filters > 1 && ws) {
+    // a batch with a workspace runs block-parallel, without one (or when
+    // its longest segment is short) in one workgroup per segment; the
+    // results are the same
+    if (s.n_filters > 1 && ws &&
+        !(s.max_len > 0 && s.max_len <= tuning().batch_scan_wg_max_len)) {
       const SegLayout SL = seg_layout(s.n_total, s.n_filters, scheme == SCHEME_MULTINOMIAL);
       if (ws_bytes < SL.total || !aligned256(ws)) return PFR_EWORKSPACE;
       if (overlaps(ws, SL.total, a, (size_t)s.n_total * 4)) return PFR_EINVAL;
@@ -607,6 +609,11 @@ void pfr_tuning_defaults(pfr_tuning* t) {
   t->rejection_table = 1;
   t->rejection_per_wave = 256;
   t->metropolis_chunk = 256;
+  t->batch_scan_wg_max_len = 0;
+  t->batch_stage_max_kb = 128;
+  t->batch_metropolis_chunk = 4096;
+  t->batch_rejection_per_wave = 256;
+  t->batch_permute_lds_max = 16384;
 }
 
 int pfr_get_tuning(pfr_tuning* t) {
@@ -619,6 +626,11 @@ int pfr_get_tuning(pfr_tuning* t) {
   t->rejection_table = g.rejection_table;
   t->rejection_per_wave = g.rejection_per_wave;
   t->metropolis_chunk = g.metropolis_chunk;
+  t->batch_scan_wg_max_len = g.batch_scan_wg_max_len;
+  t->batch_stage_max_kb = g.batch_stage_max_kb;
+  t->batch_metropolis_chunk = g.batch_metropolis_chunk;
+  t->batch_rejection_per_wave = g.batch_rejection_per_wave;
+  t->batch_permute_lds_max = g.batch_permute_lds_max;
   return PFR_OK;
 }
 
@@ -631,6 +643,17 @@ int pfr_set_tuning(const pfr_tuning* t) {
   if (t->rejection_per_wave < 64 || t->rejection_per_wave > 4096) return PFR_EINVAL;
   if (t->metropolis_chunk < 256 || t->metropolis_chunk > 8192 || t->metropolis_chunk % 256)
     return PFR_EINVAL;
+  if (t->batch_scan_wg_max_len < 0 || t->batch_scan_wg_max_len > PFR_MAX_BATCH_SEGMENT)
+    return PFR_EINVAL;
+  if (t->batch_stage_max_kb != 16 && t->batch_stage_max_kb != 64 && t->batch_stage_max_kb != 128)
+    return PFR_EINVAL;
+  if (t->batch_metropolis_chunk < 1024 || t->batch_metropolis_chunk > 65536 ||
+      t->batch_metropolis_chunk % 1024)
+    return PFR_EINVAL;
+  if (t->batch_rejection_per_wave < 64 || t->batch_rejection_per_wave > 4096) return PFR_EINVAL;
+  if (t->batch_permute_lds_max != 4096 && t->batch_permute_lds_max != 8192 &&
+      t->batch_permute_lds_max != 16384)
+    return PFR_EINVAL;
   std::lock_guard<std::mutex> lock(g_tuning_mu);
   g_tuning.single_wg_max = t->single_wg_max;
   g_tuning.direct_max_blocks = t->direct_max_blocks;
@@ -638,6 +661,11 @@ int pfr_set_tuning(const pfr_tuning* t) {
   g_tuning.rejection_table = t->rejection_table;
   g_tuning.rejection_per_wave = t->rejection_per_wave;
   g_tuning.metropolis_chunk = t->metropolis_chunk;
+  g_tuning.batch_scan_wg_max_len = t->batch_scan_wg_max_len;
+  g_tuning.batch_stage_max_kb = t->batch_stage_max_kb;
+  g_tuning.batch_metropolis_chunk = t->batch_metropolis_chunk;
+  g_tuning.batch_rejection_per_wave = t->batch_rejection_per_wave;
+  g_tuning.batch_permute_lds_max = t->batch_permute_lds_max;
   return PFR_OK;
 }
 
@@ -663,7 +691,12 @@ int pfr_load_tuning(const char* path) {
                 {"metropolis_table_min_B", &t.metropolis_table_min_B},
                 {"rejection_table", &t.rejection_table},
                 {"rejection_per_wave", &t.rejection_per_wave},
-                {"metropolis_chunk", &t.metropolis_chunk}};
+                {"metropolis_chunk", &t.metropolis_chunk},
+                {"batch_scan_wg_max_len", &t.batch_scan_wg_max_len},
+                {"batch_stage_max_kb", &t.batch_stage_max_kb},
+                {"batch_metropolis_chunk", &t.batch_metropolis_chunk},
+                {"batch_rejection_per_wave", &t.batch_rejection_per_wave},
+                {"batch_permute_lds_max", &t.batch_permute_lds_max}};
   int depth = 0;
   const char* key = nullptr;  // last string seen at depth 1
   size_t key_len = 0;

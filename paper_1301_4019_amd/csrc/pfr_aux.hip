@@ -441,6 +441,53 @@ __global__ __launch_bounds__(256) void k_mark(const int32_t* __restrict__ a, int
   }
 }
 
+// Backward walk on the ancestry itself (unsorted input, no marked ancestry):
+// from an unclaimed slot j, y = j; while position y won its claim
+// (d[a_y] == y) step to y = a_y; then c_j = a_y.  The same walk as k_resolve
+// on e = marks(a, d), with the mark of each visited position formed on the
+// way (two dependent loads per step instead of one), which saves the pass
+// that writes e.  d[j] and a[j] are loaded together.
+__global__ __launch_bounds__(256) void k_resolve_ad(const int32_t* __restrict__ a,
+                                                    int64_t n_total,
+                                                    const int64_t* __restrict__ offsets,
+                                                    uint32_t n_filters, int64_t min_len,
+                                                    const int32_t* __restrict__ d,
+                                                    int32_t* __restrict__ c,
+                                                    uint32_t* __restrict__ flags) {
+  bool broken = false, bad = false;
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  for (int64_t g = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; g < n_total; g += stride) {
+    const SegIdx s = seg_index(offsets, n_filters, n_total, g);
+    if (s.n < min_len) continue;
+    const int64_t j = s.i;
+    const int64_t dj = d[g];
+    int64_t ay = anc_at(a, s, j, bad);
+    if (dj >= 0 && dj < s.n) {  // claimed: its winner's ancestor is j
+      c[g] = (int32_t)j;
+      continue;
+    }
+    // unclaimed: retrace the chain that ends here back to its failed claimer
+    const int32_t* ds = d + s.base;
+    int64_t y = j;
+    int64_t steps = 0;
+    bool br = false;
+    while (ds[ay] == y) {  // position y won slot a_y: the chain came through it
+      y = ay;
+      ay = anc_at(a, s, y, bad);
+      if (++steps > s.n) {  // a chain visits distinct slots; only bad input gets here
+        br = true;
+        break;
+      }
+    }
+    broken |= br;
+    c[g] = br ? (int32_t)j : (int32_t)ay;
+  }
+  if (flags) {
+    const uint32_t b = (uint32_t)wave_reduce((uint32_t)(broken ? FLAG_BAD_ANCESTOR : 0u), OpOr());
+    if (b && lane_id() == 0) atomicOr(flags, b);
+  }
+}
+
 // Backward walk on e: one dependent load per chain step.
 __global__ __launch_bounds__(256) void k_resolve(int64_t n_total,
                                                  const int64_t* __restrict__ offsets,
@@ -456,13 +503,13 @@ __global__ __launch_bounds__(256) void k_resolve(int64_t n_total,
     if (s.n < min_len) continue;
     const int64_t j = s.i;
     const int64_t dj = d[g];
+    const int32_t* es = e + s.base;
+    int64_t ey = es[j];  // loaded with d[g]: the two loads are in flight together
     if (dj >= 0 && dj < s.n) {  // claimed: its winner's ancestor is j
       c[g] = (int32_t)j;
       continue;
     }
     // unclaimed: retrace the chain that ends here back to its failed claimer
-    const int32_t* es = e + s.base;
-    int64_t ey = es[j];
     int64_t steps = 0;
     while (ey >= 0) {
       ey = es[ey];
@@ -627,26 +674,35 @@ hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offs
     return hipGetLastError();
   }
   if (offsets && n_filters > 1) {
-    hipLaunchKernelGGL(k_permute_staged<16384>, dim3(n_filters), dim3(kPermThreads), 0, stream, a,
-                       n_total, offsets, n_filters, c, flags);
+    // segments up to the tuned length in LDS, the longer ones below
+    const int cap = tuning().batch_permute_lds_max;
+    if (cap == 4096)
+      hipLaunchKernelGGL(k_permute_staged<4096>, dim3(n_filters), dim3(kPermThreads), 0, stream,
+                         a, n_total, offsets, n_filters, c, flags);
+    else if (cap == 8192)
+      hipLaunchKernelGGL(k_permute_staged<8192>, dim3(n_filters), dim3(kPermThreads), 0, stream,
+                         a, n_total, offsets, n_filters, c, flags);
+    else
+      hipLaunchKernelGGL(k_permute_staged<16384>, dim3(n_filters), dim3(kPermThreads), 0, stream,
+                         a, n_total, offsets, n_filters, c, flags);
     hipError_t e0 = hipGetLastError();
     if (e0 != hipSuccess) return e0;
-    if (max_len > 0 && max_len <= 16384) return hipSuccess;
-    min_len = 16385;
+    if (max_len > 0 && max_len <= cap) return hipSuccess;
+    min_len = cap + 1;
   }
   if (sorted) {
     hipLaunchKernelGGL(k_claim_sorted, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
                        n_filters, min_len, d, e, flags);
-  } else {
-    hipLaunchKernelGGL(k_fill_unclaimed, dim3(grid), dim3(256), 0, stream, d, n_total, offsets,
-                       n_filters, min_len);
-    hipLaunchKernelGGL(k_claim_min, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
-                       n_filters, min_len, d, flags);
-    hipLaunchKernelGGL(k_mark, dim3(grid), dim3(256), 0, stream, a, n_total, offsets, n_filters,
-                       min_len, d, e);
+    hipLaunchKernelGGL(k_resolve, dim3(grid), dim3(256), 0, stream, n_total, offsets, n_filters,
+                       min_len, d, e, c, flags);
+    return hipGetLastError();
   }
-  hipLaunchKernelGGL(k_resolve, dim3(grid), dim3(256), 0, stream, n_total, offsets, n_filters,
-                     min_len, d, e, c, flags);
+  hipLaunchKernelGGL(k_fill_unclaimed, dim3(grid), dim3(256), 0, stream, d, n_total, offsets,
+                     n_filters, min_len);
+  hipLaunchKernelGGL(k_claim_min, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
+                     n_filters, min_len, d, flags);
+  hipLaunchKernelGGL(k_resolve_ad, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
+                     n_filters, min_len, d, c, flags);
   return hipGetLastError();
 }
 

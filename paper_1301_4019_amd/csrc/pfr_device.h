@@ -369,6 +369,23 @@ __device__ __forceinline__ double u128_to_double(u128 x) {
   return (double)hi * 0x1p64 + (double)lo;
 }
 
+// Inclusive wave scan of a 128-bit sum (six DPP steps on the four words).
+template <int CTRL, int ROW_MASK = 0xF>
+__device__ __forceinline__ u128 dpp_u128(u128 v) {
+  const uint64_t lo = dpp_u64<CTRL, ROW_MASK>(0ull, (uint64_t)v);
+  const uint64_t hi = dpp_u64<CTRL, ROW_MASK>(0ull, (uint64_t)(v >> 64));
+  return ((u128)hi << 64) | (u128)lo;
+}
+__device__ __forceinline__ u128 wave_incl_add_u128(u128 x) {
+  x += dpp_u128<kDppShr1>(x);
+  x += dpp_u128<kDppShr2>(x);
+  x += dpp_u128<kDppShr4>(x);
+  x += dpp_u128<kDppShr8>(x);
+  x += dpp_u128<kDppBcast15, 0xA>(x);
+  x += dpp_u128<kDppBcast31, 0xC>(x);
+  return x;
+}
+
 // ------------------------------------------------------------------ segments
 // Segment f holds global indices [offsets[f], offsets[f+1]); returns the f
 // with offsets[f] <= g < offsets[f+1] (offsets non-decreasing, g < offsets[F]).

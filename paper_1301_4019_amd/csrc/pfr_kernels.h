@@ -20,6 +20,11 @@ struct Tuning {
   int32_t rejection_table;         // long vectors: rejection with the bound table (0 / 1)
   int32_t rejection_per_wave;      // particles per wave of the rejection schedule
   int32_t metropolis_chunk;        // particles per workgroup of the global-memory Metropolis kernel
+  int32_t batch_scan_wg_max_len;   // batches: one workgroup per segment up to this longest segment
+  int32_t batch_stage_max_kb;      // batches: largest LDS staging tier of Metropolis / rejection
+  int32_t batch_metropolis_chunk;  // batches: particles per workgroup of staged Metropolis
+  int32_t batch_rejection_per_wave;  // batches: particles per wave of staged rejection
+  int32_t batch_permute_lds_max;   // batches: segments permuted in LDS up to this length
 };
 Tuning tuning();  // a copy of the current settings (thread-safe)
 
@@ -41,22 +46,20 @@ struct BlockRec {
 
 // Header at the start of a collective-scheme workspace.
 struct ScanHeader {
-  uint32_t ticket;   // unused (kept zero)
-  uint32_t status;   // FLAG_* bits of this call
-  int32_t gscale;    // global fixed-point scale of the carries
+  uint32_t status;       // FLAG_* bits of this call
+  int32_t gscale;        // global fixed-point scale of the carries
+  uint32_t groups_done;  // carry groups finished (zeroed by the records pass)
   uint32_t pad0;
-  uint64_t epoch;    // unused (kept zero)
-  uint64_t pad1;
   union {
     u128 Q;          // exact total at the global scale
     double W;        // floating-point total (precision modes other than exact)
   };
-  uint32_t pad[52];  // header padded to 256 bytes
+  uint32_t pad[56];  // header padded to 256 bytes
 };
 static_assert(sizeof(ScanHeader) == 256, "scan header is 256 bytes");
 
 struct ScanLayout {
-  size_t recs, carries, erecs, ecarries, evals, total;
+  size_t recs, carries, erecs, ecarries, groups, egroups, evals, total;
 };
 ScanLayout scan_layout(int64_t n, bool multinomial);
 

@@ -20,24 +20,27 @@
 // rounding is the final map r = n * I / I_total to binary64, itself monotone
 // with r = n at the end.
 //
-// One workgroup of 256 threads handles one block, 4 consecutive weights per
-// thread (one 16-byte load each for float32), so that a 2^20 vector runs
-// 1024 workgroups, 16 waves per CU.  Passes for one vector:
+// One vector: one wave handles one block, 16 consecutive weights per lane
+// (four 16-byte loads for float32), four waves per workgroup.  Passes:
 //   records one record per block (validity, block scale, quantised sum), and
-//           one sum per exponential-spacing block of the multinomial scheme.
-//   carries one workgroup turns the records into the global scale, the exact
-//           carries C_b and the total, and scans the exponential-block sums.
-//           With at most 2048 blocks and no exponential blocks this step is
-//           folded into the emit kernel: every emit workgroup reduces all
-//           records itself, which costs less than one more launch.
+//           one sum per exponential-spacing block of the multinomial scheme
+//           (whose points are kept for the emission).
+//   carries one workgroup of 1024 threads turns the records into the global
+//           scale, the exact carries C_b and the total, and scans the
+//           exponential-block sums.  With at most direct_max_blocks blocks
+//           and no exponential blocks this step is folded into the emission:
+//           every emit workgroup reduces all records itself, which costs less
+//           than one more launch.
 //   emit    each block rebuilds its exact prefix, I = C_b + local prefix, and
-//           r = n I / Q.  Stratified / systematic: every particle computes its
-//           cumulative offspring O_i = #{s : q_s <= r_i} in O(1) with the
-//           stratum offsets from an LDS table, and the block's output range
-//           [O(C_b), O(C_b+1)) is filled through LDS markers and a max-scan,
-//           then written coalesced.  Multinomial: the workgroup rebuilds the
-//           exponential blocks whose points fall in its r-range and locates
-//           each point with interleaved binary searches in r (LDS).
+//           r = n I / Q (a wave scan through DPP).  Stratified / systematic:
+//           every particle computes its cumulative offspring
+//           O_i = #{s : q_s <= r_i} in O(1), and the block's output range
+//           [O(C_b), O(C_b+1)) is filled through LDS markers and a wave
+//           max-scan, then written coalesced.  Multinomial: each block reads
+//           the exponential blocks whose points fall in its r-range and
+//           settles its particles with interleaved binary searches in LDS.
+// The workgroup-per-block variants (256 threads, 4 weights per thread) serve
+// the single-workgroup path of short vectors and the batch kernels.
 // Ragged batches run the same steps inside one workgroup per filter.
 #include "pfr_kernels.h"
 
@@ -147,209 +150,257 @@ __device__ Totals carries_from_records(uint32_t nb, RecPtr recs, CPtr C, WgScrat
   return t;
 }
 
-// r of the thread's 4 particles of the block at base, given the block's
-// exclusive carry Cb and record.
-template <typename T>
-__device__ void block_r(const T* __restrict__ w, int64_t n, int64_t base, const BlockRec rec,
-                        u128 Cb, int32_t gscale, const RMap& rm, double (&r)[kPer],
-                        WgScratch* s) {
-  T x[kPer];
-  load4(w, n, base, x);
-  // the block's scale is the same in every lane: keep it scalar, so that the
-  // 128-bit shifts below branch on it once instead of selecting per lane
-  const int32_t scale = (int32_t)__builtin_amdgcn_readfirstlane(rec.scale);
-  const int e_ref = 52 + WTraits<T>::BIAS - scale;
-  uint64_t q[kPer];
-  uint64_t acc = 0;
-#pragma unroll
-  for (int v = 0; v < kPer; ++v) {
-    acc += quantize(x[v], e_ref);
-    q[v] = acc;
-  }
-  uint64_t tot;
-  const uint64_t off = wg_exclusive(acc, s->u, &tot);
-  const int sh = (int32_t)__builtin_amdgcn_readfirstlane(gscale) - scale;
-#pragma unroll
-  for (int v = 0; v < kPer; ++v) r[v] = rm(Cb + shift_u128((u128)(off + q[v]), sh));
-}
-
-// Emission of block b of a vector (n weights at w, outputs at a_out).
-template <typename T, int SCHEME, typename CEPtr>
-__device__ void emit_block(const T* __restrict__ w, int64_t n, uint32_t b, const BlockRec rec,
-                           u128 Cb, u128 Cb1, int32_t gscale, const RMap& rm, Key key,
-                           uint32_t filter, uint32_t offset, CEPtr CE, uint32_t nbe,
-                           int32_t* __restrict__ a_out, EmitLds* L, WgScratch* s,
-                           int32_t* __restrict__ d_out = nullptr,
-                           int32_t* __restrict__ e_out = nullptr,
-                           const uint64_t* __restrict__ evals = nullptr) {
-  const int64_t P0 = (int64_t)b * kBlock;
-  const int cnt = (int)min((int64_t)kBlock, n - P0);
-  const double r_lo = rm(Cb);
-  const double r_hi = rm(Cb1);
-  double r[kPer];
-  block_r(w, n, P0, rec, Cb, gscale, rm, r, s);
-  if (SCHEME == SCHEME_MULTINOMIAL) {
-#pragma unroll
-    for (int v = 0; v < kPer; ++v) L->mu.r[threadIdx.x * kPer + v] = r[v];
-    __syncthreads();
-    emit_multinomial(L->mu.r, cnt, r_lo, r_hi, P0 + cnt == n, n, P0, key, filter, offset, CE, nbe,
-                     a_out, s, evals);
-  } else {
-    const uint32_t u_sys =
-        SCHEME == SCHEME_SYSTEMATIC ? draw(key, 0, DOM_STRATA, 0, filter, offset).x : 0u;
-    emit_strata<SCHEME == SCHEME_SYSTEMATIC, false>(r, cnt, r_lo, r_hi, n, P0, key, filter,
-                                                    offset, u_sys, a_out, &L->st, s, d_out,
-                                                    e_out);
-  }
-}
-
 // ---------------------------------------------------------------- kernels
-// One record per weight block (and, for the multinomial scheme, one sum per
-// exponential block, whose quantised spacings are kept in `evals` for the
-// emission).  No cross-workgroup communication: the kernel boundary makes the
-// records visible to the next kernel.
-template <typename T, bool MULTI>
-__global__ __launch_bounds__(kT) void k_scan_records(const T* __restrict__ w, int64_t n,
-                                                     uint32_t nb, Key key, uint32_t offset,
-                                                     uint32_t filter,
-                                                     BlockRec* __restrict__ recs,
-                                                     uint64_t* __restrict__ esums,
-                                                     uint64_t* __restrict__ evals) {
-  offset = counter_offset(key, offset);
-  __shared__ WgScratch s;
-  if (blockIdx.x < nb) {
-    const BlockRec r = block_record(w, n, (int64_t)blockIdx.x * kBlock, &s);
-    if (threadIdx.x == 0) recs[blockIdx.x] = r;
-  } else if (MULTI) {
-    const uint32_t b = blockIdx.x - nb;
-    uint64_t q[kPer];
-    exp_values(key, filter, offset, n, b, q);
-    store_exp_values(evals, b, q);
-    const uint64_t sum = wg_reduce(q[0] + q[1] + q[2] + q[3], OpAdd(), s.u);
-    if (threadIdx.x == 0) esums[b] = sum;
-  }
-}
+// ---------------------------------------------------------------- carries
+// Two levels.  The records fall into groups of kGrp = 1024 consecutive
+// blocks.  k_carry_groups (one 256-thread workgroup per group, all in
+// parallel) fixes the group's own scale gs_g from its largest block, exactly
+// as the global scale is fixed from the largest block overall (with the
+// group's 2^10 blocks in place of nb, so group sums stay below 2^100), and
+// writes every block's exclusive prefix P_b inside the group at that scale
+// and the group total T_g.  The group workgroup that finishes last (a count
+// in the header, zeroed by the records pass) takes the global scale from the
+// group keys, converts each T_g to it (a shift: truncation when gs_g is
+// finer) and scans them into Tx_g; the total Q is Tx_G.  The
+// carry of block b in group g is then
+//   C_b = Tx_g + floor(P_b 2^(gscale - gs_g)),  C_nb = Q,
+// an integer function of the records alone, monotone in b and continuous at
+// group ends (P at a group's end is T_g).  It differs from converting every
+// block to the global scale by truncation only (one unit of the global scale
+// per group), within the bound of the per-block quantisation.  The
+// exponential-block sums of the multinomial scheme are plain integers and
+// take the same two levels without scales.
+constexpr int kGrpLog = 10;
+constexpr uint32_t kGrp = 1u << kGrpLog;
+constexpr int kGPer = (int)kGrp / kT;  // blocks per thread of a group workgroup (4)
 
-// One workgroup: global scale, exact carries C[0..nb], total and status, and
-// the exponential-block carries CE[0..nbe] of the multinomial scheme.
-template <bool MULTI>
-__global__ __launch_bounds__(kT) void k_scan_carries(uint32_t nb, uint32_t nbe,
-                                                     ScanHeader* __restrict__ hdr,
-                                                     const BlockRec* __restrict__ recs,
-                                                     const uint64_t* __restrict__ esums,
-                                                     u128* __restrict__ C, u128* __restrict__ CE) {
-  __shared__ WgScratch s;
-  const Totals t = carries_from_records(nb, recs, C, &s);
-  if (MULTI) exp_carries(nbe, esums, CE, &s);
-  if (threadIdx.x == 0) {
-    hdr->status = t.status;
-    hdr->gscale = t.gscale;
-    hdr->Q = t.Q;
-  }
-}
-
-// Direct carries: with few blocks every emit workgroup derives the global
-// scale, its own exact carry and the total from all records itself (at most
-// kDirectMax records, held in registers), which saves the carry kernel.
-constexpr uint32_t kDirectMax = kT * 8;
-
-struct Direct {
-  u128 Cb, Cb1, Q;
-  int32_t gscale;
-  uint32_t status;
+struct CarryGroup {
+  u128 T;        // group total at the group's scale (exponential groups: plain sum)
+  int32_t gs;    // the group's scale
+  uint32_t key;  // min over non-empty blocks of scale ^ 2^31, ~0u if none
+  uint32_t bad;
+  uint32_t pad;
 };
 
-__device__ Direct direct_carries(uint32_t nb, uint32_t b, const BlockRec* __restrict__ recs,
-                                 WgScratch* s) {
-  const int tid = (int)threadIdx.x;
-  BlockRec r[8];
-  uint32_t bad = 0, smin_key = 0xFFFFFFFFu;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint32_t j = (uint32_t)tid + (uint32_t)k * kT;
-    if (j < nb) r[k] = recs[j];
-    else r[k].sum = 0, r[k].scale = 0, r[k].bad = 0;
-  }
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    bad |= r[k].bad;
-    if (r[k].sum) smin_key = min(smin_key, (uint32_t)r[k].scale ^ 0x80000000u);
-  }
-  bad = wg_reduce(bad, OpOr(), (uint32_t*)s->i);
-  smin_key = wg_reduce(smin_key, OpMin(), (uint32_t*)s->i);
-  Direct d;
-  d.gscale = (smin_key == 0xFFFFFFFFu)
-                 ? 0
-                 : (int32_t)(smin_key ^ 0x80000000u) + (kCarryBits - 63) - ceil_log2(nb);
-  u128 before = 0, all = 0, own = 0;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint32_t j = (uint32_t)tid + (uint32_t)k * kT;
-    const u128 v = (j < nb) ? conv_rec(r[k], d.gscale) : (u128)0;
-    all += v;
-    if (j < b) before += v;
-    if (j == b) own = v;
-  }
-  d.Cb = wg_reduce(before, OpAdd(), s->v);
-  d.Q = wg_reduce(all, OpAdd(), s->v);
-  own = wg_reduce(own, OpAdd(), s->v);
-  d.Cb1 = d.Cb + own;
-  d.status = bad;
-  if (!bad && d.Q == 0) d.status |= FLAG_ZERO_TOTAL;
-  return d;
+// conv_rec with 64-bit shifts only.  A non-empty block's shift is at most
+// kCarryBits - 63 (a group's or the global scale exceeds no non-empty block's
+// scale by more), and an empty block converts to zero under any shift, so
+// clamping the left shift to 63 changes nothing.
+static_assert(kCarryBits - 63 < 64, "left shifts of block sums stay below 64");
+__device__ __forceinline__ u128 conv_rec_fast(const BlockRec& r, int32_t scale) {
+  const int sh = scale - r.scale;
+  const uint64_t s = r.sum;
+  const uint32_t l = (uint32_t)min(max(sh, 0), 63), d = (uint32_t)min(-sh, 64);
+  const uint64_t lo = sh >= 0 ? s << l : (d >= 64 ? 0ull : s >> d);
+  const uint64_t hi = l > 0 ? s >> (64 - l) : 0ull;
+  return ((u128)hi << 64) | lo;
 }
 
-template <typename T, int SCHEME, bool DIRECT>
-__global__ __launch_bounds__(kT) void k_scan_emit(const T* __restrict__ w, int64_t n,
-                                                  uint32_t nb, uint32_t nbe, Key key,
-                                                  uint32_t offset, uint32_t filter,
-                                                  const ScanHeader* __restrict__ hdr,
-                                                  const BlockRec* __restrict__ recs,
-                                                  const u128* __restrict__ C,
-                                                  const u128* __restrict__ CE,
-                                                  int32_t* __restrict__ a,
-                                                  uint32_t* __restrict__ flags,
-                                                  int32_t* __restrict__ d_out,
-                                                  int32_t* __restrict__ e_out,
-                                                  const uint64_t* __restrict__ evals) {
-  offset = counter_offset(key, offset);
-  __shared__ EmitLds L;
-  __shared__ WgScratch s;
-  const uint32_t b = blockIdx.x;
-  uint32_t status;
-  u128 Cb, Cb1, Q;
-  int32_t gscale;
-  if (DIRECT) {
-    const Direct d = direct_carries(nb, b, recs, &s);
-    status = d.status;
-    Cb = d.Cb;
-    Cb1 = d.Cb1;
-    Q = d.Q;
-    gscale = d.gscale;
-  } else {
-    status = hdr->status;
-    Cb = C[b];
-    Cb1 = C[b + 1];
-    Q = hdr->Q;
-    gscale = hdr->gscale;
+// Exclusive scan of the kGrp values x (kGPer consecutive per thread) of one
+// workgroup; returns the thread's exclusive base and the workgroup total.
+__device__ __forceinline__ u128 group_scan(u128 (&x)[kGPer], u128* s_w, u128* total) {
+  const int wave = (int)threadIdx.x / kWave, lane = (int)threadIdx.x % kWave;
+  u128 run = 0;
+#pragma unroll
+  for (int k = 0; k < kGPer; ++k) {
+    const u128 v = x[k];
+    x[k] = run;
+    run += v;
   }
-  if (flags && b == 0 && threadIdx.x == 0 && status) atomicOr(flags, status);
-  if (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
-    // identity: every position claims its own slot
-    const int64_t P0 = (int64_t)b * kBlock;
-    for (int64_t i = P0 + threadIdx.x; i < min(P0 + kBlock, n); i += kT) {
-      a[i] = (int32_t)i;
-      if (d_out) {
-        d_out[i] = (int32_t)i;
-        e_out[i] = (int32_t)i;
-      }
-    }
-    return;
+  const u128 inc = wave_incl_add_u128(run);
+  if (lane == kWave - 1) s_w[wave] = inc;
+  __syncthreads();
+  u128 before = inc - run, tot = 0;
+#pragma unroll
+  for (int w2 = 0; w2 < kNW; ++w2) {
+    const u128 t = s_w[w2];
+    before += w2 < wave ? t : (u128)0;
+    tot += t;
   }
-  const RMap rm = make_rmap(Q, n);
-  emit_block<T, SCHEME>(w, n, b, recs[b], Cb, Cb1, gscale, rm, key, filter, offset, CE, nbe, a,
-                        &L, &s, d_out, e_out, evals);
+  *total = tot;
+  return before;
 }
+
+// Exclusive scan, in index order, of val(j) for j < m by a workgroup of NT
+// threads (CK consecutive values per thread per chunk); put(j, prefix) gets
+// each result.  Returns the total; s_w holds NT / 64 values.
+template <int NT, int CK, typename Val, typename Put>
+__device__ u128 wg_scan_blocked(uint32_t m, Val val, Put put, u128* s_w) {
+  constexpr int NW = NT / kWave;
+  constexpr uint32_t chunk = (uint32_t)NT * CK;
+  const int tid = (int)threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  u128 carry = 0;
+  for (uint32_t c0 = 0; c0 < m; c0 += chunk) {
+    const uint32_t j0 = c0 + (uint32_t)tid * CK;
+    u128 x[CK];
+#pragma unroll
+    for (int k = 0; k < CK; ++k) x[k] = j0 + (uint32_t)k < m ? val(j0 + (uint32_t)k) : (u128)0;
+    u128 run = 0;
+#pragma unroll
+    for (int k = 0; k < CK; ++k) {
+      const u128 v = x[k];
+      x[k] = run;
+      run += v;
+    }
+    const u128 inc = wave_incl_add_u128(run);
+    if (lane == kWave - 1) s_w[wave] = inc;
+    __syncthreads();
+    u128 before = carry + (inc - run), tot = 0;
+#pragma unroll 2
+    for (int w2 = 0; w2 < NW; ++w2) {
+      const u128 t = s_w[w2];
+      before += w2 < wave ? t : (u128)0;
+      tot += t;
+    }
+#pragma unroll
+    for (int k = 0; k < CK; ++k)
+      if (j0 + (uint32_t)k < m) put(j0 + (uint32_t)k, before + x[k]);
+    carry += tot;
+    __syncthreads();
+  }
+  return carry;
+}
+
+// The top level over the G group records (and the Ge exponential ones): global
+// scale, status, Tx[0..G] and TEx[0..Ge].  Run by the group workgroup that
+// finishes last (kT threads; G <= 2048 for n < 2^31, one chunk).
+template <bool MULTI>
+__device__ void carry_top(uint32_t nb, uint32_t G, uint32_t Ge,
+                          const CarryGroup* __restrict__ groups,
+                          const CarryGroup* __restrict__ egroups, u128* __restrict__ Tx,
+                          u128* __restrict__ TEx, ScanHeader* __restrict__ hdr, uint32_t* s_u,
+                          u128* s_w) {
+  const int tid = (int)threadIdx.x;
+  uint32_t bad = 0, key = 0xFFFFFFFFu;
+  for (uint32_t g = (uint32_t)tid; g < G; g += kT) {
+    bad |= groups[g].bad;
+    key = min(key, groups[g].key);
+  }
+  key = wg_reduce(key, OpMin(), s_u);
+  bad = wg_reduce(bad, OpOr(), s_u + kNW);
+  const int32_t gscale =
+      key == 0xFFFFFFFFu ? 0 : (int32_t)(key ^ 0x80000000u) + (kCarryBits - 63) - ceil_log2(nb);
+  const u128 Q = wg_scan_blocked<kT, 8>(
+      G, [&](uint32_t g) { return shift_u128(groups[g].T, gscale - groups[g].gs); },
+      [&](uint32_t g, u128 c) { Tx[g] = c; }, s_w);
+  if (MULTI) {
+    const u128 S = wg_scan_blocked<kT, 8>(
+        Ge, [&](uint32_t g) { return egroups[g].T; }, [&](uint32_t g, u128 c) { TEx[g] = c; },
+        s_w);
+    if (tid == 0) TEx[Ge] = S;
+  }
+  if (tid == 0) {
+    Tx[G] = Q;
+    uint32_t status = bad;
+    if (!bad && Q == 0) status |= FLAG_ZERO_TOTAL;
+    hdr->status = status;
+    hdr->gscale = gscale;
+    hdr->Q = Q;
+  }
+}
+
+template <bool MULTI>
+__global__ __launch_bounds__(kT) void k_carry_groups(uint32_t nb, uint32_t nbe, uint32_t G,
+                                                     const BlockRec* __restrict__ recs,
+                                                     const uint64_t* __restrict__ esums,
+                                                     u128* __restrict__ P, u128* __restrict__ PE,
+                                                     CarryGroup* __restrict__ groups,
+                                                     CarryGroup* __restrict__ egroups,
+                                                     uint32_t Ge, u128* __restrict__ Tx,
+                                                     u128* __restrict__ TEx,
+                                                     ScanHeader* __restrict__ hdr) {
+  __shared__ u128 s_w[kNW];
+  __shared__ uint32_t s_u[2 * kNW];
+  __shared__ uint32_t s_last;
+  const int tid = (int)threadIdx.x;
+  const bool weights = blockIdx.x < G;
+  if (!MULTI && !weights) return;  // (never: the grid has G workgroups then)
+  const uint32_t g = weights ? blockIdx.x : blockIdx.x - G;
+  const uint32_t m = weights ? nb : nbe;
+  const uint32_t j0 = g * kGrp + (uint32_t)tid * kGPer;
+  u128 x[kGPer];
+  uint32_t key = 0xFFFFFFFFu, bad = 0;
+  int32_t gs = 0;
+  if (weights) {
+    BlockRec r[kGPer];
+#pragma unroll
+    for (int k = 0; k < kGPer; ++k) {
+      if (j0 + k < m) r[k] = recs[j0 + k];
+      else r[k].sum = 0, r[k].scale = 0, r[k].bad = 0;
+    }
+#pragma unroll
+    for (int k = 0; k < kGPer; ++k) {
+      bad |= r[k].bad;
+      if (r[k].sum) key = min(key, (uint32_t)r[k].scale ^ 0x80000000u);
+    }
+    key = wg_reduce(key, OpMin(), s_u);
+    bad = wg_reduce(bad, OpOr(), s_u + kNW);
+    gs = key == 0xFFFFFFFFu ? 0 : (int32_t)(key ^ 0x80000000u) + (kCarryBits - 63) - kGrpLog;
+#pragma unroll
+    for (int k = 0; k < kGPer; ++k) x[k] = conv_rec_fast(r[k], gs);
+  } else {
+#pragma unroll
+    for (int k = 0; k < kGPer; ++k) x[k] = j0 + k < m ? (u128)esums[j0 + k] : (u128)0;
+  }
+  u128 total;
+  const u128 before = group_scan(x, s_w, &total);
+  u128* out = weights ? P : PE;
+#pragma unroll
+  for (int k = 0; k < kGPer; ++k)
+    if (j0 + k < m) out[j0 + k] = before + x[k];
+  if (tid == 0) {
+    CarryGroup c;
+    c.T = total;
+    c.gs = gs;
+    c.key = key;
+    c.bad = bad;
+    c.pad = 0;
+    (weights ? groups : egroups)[g] = c;
+    // the last group to finish (the records pass zeroed the count) runs the
+    // top level: release this group's record, count it, acquire the others
+    __threadfence();
+    s_last = atomicAdd(&hdr->groups_done, 1u) == G + (MULTI ? Ge : 0u) - 1u ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  carry_top<MULTI>(nb, G, Ge, groups, egroups, Tx, TEx, hdr, s_u, s_w);
+}
+
+
+// The exact carry C_b of block b (0 <= b <= nb) from the two levels.
+struct Carries {
+  const u128* __restrict__ P;
+  const u128* __restrict__ Tx;
+  const CarryGroup* __restrict__ grp;
+  uint32_t nb, G;
+  int32_t gscale;
+  __device__ __forceinline__ u128 operator[](uint32_t b) const {
+    if (b >= nb) return Tx[G];
+    const uint32_t g = b >> kGrpLog;
+    return Tx[g] + shift_u128(P[b], gscale - grp[g].gs);
+  }
+};
+
+// The exponential-block carries CE[e] (0 <= e <= nbe) from the two levels.
+struct ECarries {
+  const u128* __restrict__ PE;
+  const u128* __restrict__ TEx;
+  uint32_t nbe, Ge;
+  __device__ __forceinline__ u128 operator[](uint32_t e) const {
+    if (e >= nbe) return TEx[Ge];
+    return TEx[e >> kGrpLog] + PE[e];
+  }
+};
+
+__host__ __device__ constexpr uint32_t carry_groups(uint32_t nblocks) {
+  return (nblocks + kGrp - 1) / kGrp;
+}
+
+// Direct carries: with at most kDirectMax blocks every emit workgroup derives
+// the global scale, its own exact carry and the total from all records itself,
+// which saves the carry kernel.
+constexpr uint32_t kDirectMax = kT * 8;
 
 // ---------------------------------------------------------------- one block per wave
 // The stratified and systematic emission and the records pass run one
@@ -394,6 +445,75 @@ __device__ __forceinline__ void wave_load(const T* __restrict__ w, int64_t n, in
   }
 }
 
+// The block's weights in an order in which every load instruction is
+// coalesced (lane l takes the 16-byte pieces l, l + 64, ... of the block), for
+// the record, whose maximum and sum do not depend on the order.  Values past
+// the vector's end are zero.
+template <typename T>
+__device__ __forceinline__ void wave_load_unordered(const T* __restrict__ w, int64_t n,
+                                                    int64_t base, T (&x)[kWPer]) {
+  constexpr int kV = 16 / (int)sizeof(T);  // values per 16-byte piece
+  const int lane = (int)lane_id();
+  const bool aligned = ((reinterpret_cast<uintptr_t>(w + base) & 15u) == 0);
+  if (aligned && base + kBlock <= n) {
+#pragma unroll
+    for (int k = 0; k < kWPer / kV; ++k) {
+      const int64_t idx = base + (int64_t)(k * kWave + lane) * kV;
+      if constexpr (sizeof(T) == 4) {
+        const float4 t = *reinterpret_cast<const float4*>(w + idx);
+        x[4 * k] = t.x; x[4 * k + 1] = t.y; x[4 * k + 2] = t.z; x[4 * k + 3] = t.w;
+      } else {
+        const double2 t = *reinterpret_cast<const double2*>(w + idx);
+        x[2 * k] = t.x; x[2 * k + 1] = t.y;
+      }
+    }
+  } else {
+#pragma unroll
+    for (int k = 0; k < kWPer / kV; ++k)
+#pragma unroll
+      for (int v = 0; v < kV; ++v) {
+        const int64_t idx = base + (int64_t)(k * kWave + lane) * kV + v;
+        x[kV * k + v] = idx < n ? w[idx] : (T)0;
+      }
+  }
+}
+
+// wave_load of a whole, 16-byte aligned float32 block through 4 KB of the
+// wave's LDS: the global loads are coalesced (lane l takes the 16-byte pieces
+// l, l + 64, ...) and the lanes read their 16 consecutive weights back.  Piece
+// u sits at u ^ ((u >> 4) & 3), so that 16 lanes reading pieces 4l + k touch
+// 16 different bank groups.  Other blocks and binary64 load directly.
+template <typename T>
+__device__ __forceinline__ void wave_load_staged(const T* __restrict__ w, int64_t n, int64_t base,
+                                                 T (&x)[kWPer], int32_t* stage) {
+  if constexpr (sizeof(T) == 4) {
+    const bool aligned = ((reinterpret_cast<uintptr_t>(w + base) & 15u) == 0);
+    if (stage && aligned && base + kBlock <= n) {
+      const int lane = (int)lane_id();
+      const float4* g = reinterpret_cast<const float4*>(w + base);
+      float4* S = reinterpret_cast<float4*>(stage);
+      float4 t[kWPer / 4];
+#pragma unroll
+      for (int k = 0; k < kWPer / 4; ++k) t[k] = g[k * kWave + lane];
+#pragma unroll
+      for (int k = 0; k < kWPer / 4; ++k) {
+        const int u = k * kWave + lane;
+        S[u ^ ((u >> 4) & 3)] = t[k];
+      }
+      wave_lds_sync();
+#pragma unroll
+      for (int k = 0; k < kWPer / 4; ++k) {
+        const int u = lane * (kWPer / 4) + k;
+        const float4 v = S[u ^ ((u >> 4) & 3)];
+        x[4 * k] = v.x; x[4 * k + 1] = v.y; x[4 * k + 2] = v.z; x[4 * k + 3] = v.w;
+      }
+      wave_lds_sync();
+      return;
+    }
+  }
+  wave_load(w, n, base, x);
+}
+
 // quantize() without branches: q = floor(v 2^scale) for every finite v >= 0
 // of a block whose scale keeps q below 2^53.  binary32: scaling by a power of
 // two is exact (a result below 2^-126 may round, but it floors to zero
@@ -426,7 +546,7 @@ __device__ __forceinline__ double u64_to_f64(uint64_t x) { return (double)x; }
 template <typename T>
 __device__ __forceinline__ BlockRec wave_block_record(const T* __restrict__ w, int64_t n, int64_t base) {
   T x[kWPer];
-  wave_load(w, n, base, x);
+  wave_load_unordered(w, n, base, x);
   uint32_t bad = 0, emax = 1;
 #pragma unroll
   for (int v = 0; v < kWPer; ++v) {
@@ -458,7 +578,8 @@ struct BlockR {
 template <typename T>
 __device__ __forceinline__ void block_r_wave(const T* __restrict__ w, int64_t n, int64_t P0,
                                              const BlockRec rec, u128 Cb, u128 Cb1,
-                                             int32_t gscale, u128 Q, BlockR& R) {
+                                             int32_t gscale, u128 Q, BlockR& R,
+                                             int32_t* stage = nullptr) {
   const RMap rm = make_rmap(Q, n);
   R.lo = rm(Cb);
   R.hi = rm(Cb1);
@@ -466,7 +587,7 @@ __device__ __forceinline__ void block_r_wave(const T* __restrict__ w, int64_t n,
   const int sh = (int32_t)__builtin_amdgcn_readfirstlane(gscale) - scale;
   const double c = ldexp(rm.Nd * rm.invQ, sh);
   T x[kWPer];
-  wave_load(w, n, P0, x);
+  wave_load_staged(w, n, P0, x, stage);
   uint64_t q[kWPer];
   uint64_t acc = 0;
 #pragma unroll
@@ -568,7 +689,7 @@ __device__ __forceinline__ void expand_wave(const uint32_t (&O)[kWPer], const ui
 
 template <bool SYSTEMATIC>
 struct StrataWaveLds {
-  int32_t M[kBlock + 4];                   // expansion markers, then the expanded chunk; M[kBlock] spare
+  alignas(16) int32_t M[kBlock + 4];                   // expansion markers, then the expanded chunk; M[kBlock] spare
   uint32_t u[SYSTEMATIC ? 1 : kUTabW];     // raw offset words of strata [m_lo, m_lo + kUTabW)
 };
 
@@ -588,7 +709,7 @@ __device__ __forceinline__ void emit_block_wave(const T* __restrict__ w, int64_t
   const int lane = (int)lane_id();
   const int cnt = (int)min((int64_t)kBlock, n - P0);
   BlockR R;
-  block_r_wave(w, n, P0, rec, Cb, Cb1, gscale, Q, R);
+  block_r_wave(w, n, P0, rec, Cb, Cb1, gscale, Q, R, L->M);
   if (!(R.hi > R.lo) && !d_out) return;  // an empty range has no outputs
 
   // stratum offsets of the strata the block's range touches
@@ -679,18 +800,20 @@ __device__ __forceinline__ void emit_block_wave(const T* __restrict__ w, int64_t
 // r(C_b) to the one holding the first at or above r(C_{b+1}) (usually one or
 // two), and the expansion is the one of the stratified scheme.
 struct MultiWaveLds {
-  double P[kBlock];      // the points of one exponential block
-  int32_t M[kBlock + 4]; // expansion markers; M[kBlock] spare
+  double P[kBlock];                   // the points of one exponential block
+  alignas(16) int32_t M[kBlock + 4];  // expansion markers; M[kBlock] spare
 };
 
 // The lane's 16 quantised spacings of exponential block e (indices
-// 1024 e + 16 lane + v): stored by the records pass, or drawn again.
+// 1024 e + 16 lane + v): as the records pass stored them (STORED), or drawn
+// again (the one-workgroup batch path, which keeps no spacings).
+template <bool STORED>
 __device__ __forceinline__ void exp_values_wave(Key key, uint32_t filter, uint32_t offset,
                                                 int64_t n, uint32_t e,
                                                 const uint64_t* __restrict__ evals,
                                                 uint64_t (&q)[kWPer]) {
   const int lane = (int)lane_id();
-  if (evals) {
+  if constexpr (STORED) {
     const ulonglong2* p =
         reinterpret_cast<const ulonglong2*>(evals + (size_t)e * kBlock + lane * kWPer);
 #pragma unroll
@@ -699,18 +822,18 @@ __device__ __forceinline__ void exp_values_wave(Key key, uint32_t filter, uint32
       q[2 * k] = t.x;
       q[2 * k + 1] = t.y;
     }
-    return;
-  }
+  } else {
 #pragma unroll
-  for (int c = 0; c < kWPer / 4; ++c) {
-    const uint32_t call = e * (uint32_t)(kBlock / 4) + (uint32_t)lane * (kWPer / 4) + c;
-    const uint4 x = draw(key, call, DOM_EXP, 0, filter, offset);
-    const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
+    for (int c = 0; c < kWPer / 4; ++c) {
+      const uint32_t call = e * (uint32_t)(kBlock / 4) + (uint32_t)lane * (kWPer / 4) + c;
+      const uint4 x = draw(key, call, DOM_EXP, 0, filter, offset);
+      const uint32_t xs[4] = {x.x, x.y, x.z, x.w};
 #pragma unroll
-    for (int v = 0; v < 4; ++v) {
-      const int64_t k = (int64_t)call * 4 + v;
-      const double ev = -log(((double)xs[v] + 0.5) * 0x1p-32);
-      q[4 * c + v] = (k <= n) ? (uint64_t)(ev * 0x1p48) : 0ull;
+      for (int v = 0; v < 4; ++v) {
+        const int64_t k = (int64_t)call * 4 + v;
+        const double ev = neg_log_spacing(xs[v]);
+        q[4 * c + v] = (k <= n) ? (uint64_t)(ev * 0x1p48) : 0ull;
+      }
     }
   }
 }
@@ -748,7 +871,7 @@ __device__ __forceinline__ uint32_t exp_block_of(double x, int64_t n, CEPtr CE, 
   return lo - 1;
 }
 
-template <typename T, typename CEPtr>
+template <typename T, bool STORED, typename CEPtr>
 __device__ __forceinline__ void emit_multi_wave(const T* __restrict__ w, int64_t n, int64_t P0,
                                                 const BlockRec rec, u128 Cb, u128 Cb1,
                                                 int32_t gscale, u128 Q, Key key, uint32_t filter,
@@ -757,7 +880,7 @@ __device__ __forceinline__ void emit_multi_wave(const T* __restrict__ w, int64_t
                                                 int32_t* __restrict__ a_out, MultiWaveLds* L) {
   const int lane = (int)lane_id();
   BlockR R;
-  block_r_wave(w, n, P0, rec, Cb, Cb1, gscale, Q, R);
+  block_r_wave(w, n, P0, rec, Cb, Cb1, gscale, Q, R, L->M);
   if (!(R.hi > R.lo)) return;  // an empty range has no outputs
   const RMap em = make_rmap(CE[nbe], n);
   const double ce = em.Nd * em.invQ;
@@ -779,7 +902,7 @@ __device__ __forceinline__ void emit_multi_wave(const T* __restrict__ w, int64_t
   };
   for (uint32_t e = e_first; e <= e_last; ++e) {
     uint64_t q[kWPer];
-    exp_values_wave(key, filter, offset, n, e, evals, q);
+    exp_values_wave<STORED>(key, filter, offset, n, e, evals, q);
     uint64_t acc = 0;
 #pragma unroll
     for (int v = 0; v < kWPer; ++v) {
@@ -803,17 +926,34 @@ __device__ __forceinline__ void emit_multi_wave(const T* __restrict__ w, int64_t
     }
     wave_lds_sync();
     const uint32_t base = e * (uint32_t)kBlock;
+    // the particles this block settles: not settled yet and r <= its last
+    // point; eight of the lane's searches run step by step together, so that
+    // their LDS reads are in flight at the same time (eight, not sixteen,
+    // bounds the registers the reads hold: three waves per SIMD instead of one)
+    uint32_t need = 0;
 #pragma unroll
-    for (int v = 0; v < kWPer; ++v) {
-      const bool need = !((det >> v) & 1u) && R.r[v] <= p_top;
-      if (ballot(need)) {
-        const uint32_t pos = lb(R.r[v]);
-        if (need) {
-          O[v] = base + pos;
-          det |= 1u << v;
+    for (int v = 0; v < kWPer; ++v)
+      need |= (!((det >> v) & 1u) && R.r[v] <= p_top) ? (1u << v) : 0u;
+#pragma unroll
+    for (int h = 0; h < kWPer; h += kWPer / 2) {
+      const uint32_t need_h = need & (((1u << (kWPer / 2)) - 1u) << h);
+      if (ballot(need_h != 0)) {
+        uint32_t pos[kWPer / 2];
+#pragma unroll
+        for (int v = 0; v < kWPer / 2; ++v)
+          pos[v] = (L->P[kBlock / 2 - 1] < R.r[h + v]) ? (uint32_t)(kBlock / 2) : 0u;
+#pragma unroll
+        for (uint32_t st = kBlock / 4; st > 0; st >>= 1) {
+#pragma unroll
+          for (int v = 0; v < kWPer / 2; ++v)
+            pos[v] += (L->P[pos[v] + st - 1] < R.r[h + v]) ? st : 0u;
         }
+#pragma unroll
+        for (int v = 0; v < kWPer / 2; ++v)
+          if ((need_h >> (h + v)) & 1u) O[h + v] = base + pos[v];
       }
     }
+    det |= need;
     if (!lo_det && R.lo <= p_top) {
       O_lo = base + lb(R.lo);
       lo_det = true;
@@ -841,8 +981,10 @@ __global__ __launch_bounds__(kT) void k_scan_records_w(const T* __restrict__ w, 
                                                        uint32_t offset, uint32_t filter,
                                                        BlockRec* __restrict__ recs,
                                                        uint64_t* __restrict__ esums,
-                                                       uint64_t* __restrict__ evals) {
+                                                       uint64_t* __restrict__ evals,
+                                                       ScanHeader* __restrict__ hdr) {
   offset = counter_offset(key, offset);
+  if (blockIdx.x == 0 && threadIdx.x == 0) hdr->groups_done = 0;  // for the carries pass
   if (blockIdx.x < wgs_b) {
     const uint32_t b = blockIdx.x * kWavesPerWG +
                        (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -917,8 +1059,7 @@ __global__ __launch_bounds__(kT) void k_scan_emit_w(const T* __restrict__ w, int
                                                     uint32_t filter,
                                                     const ScanHeader* __restrict__ hdr,
                                                     const BlockRec* __restrict__ recs,
-                                                    const u128* __restrict__ C,
-                                                    int32_t* __restrict__ a,
+                                                    Carries C, int32_t* __restrict__ a,
                                                     uint32_t* __restrict__ flags,
                                                     int32_t* __restrict__ d_out,
                                                     int32_t* __restrict__ e_out) {
@@ -941,10 +1082,11 @@ __global__ __launch_bounds__(kT) void k_scan_emit_w(const T* __restrict__ w, int
   } else {
     if (b >= nb) return;
     status = hdr->status;
+    gscale = hdr->gscale;
+    C.gscale = gscale;
     Cb = C[b];
     Cb1 = C[b + 1];
     Q = hdr->Q;
-    gscale = hdr->gscale;
   }
   if (b >= nb) return;
   if (flags && b == 0 && threadIdx.x == 0 && status) atomicOr(flags, status);
@@ -964,15 +1106,14 @@ __global__ __launch_bounds__(kT) void k_scan_emit_w(const T* __restrict__ w, int
                                                    filter, offset, a, &L[wave], d_out, e_out);
 }
 
-// Multinomial emission, one weight block per wave (after k_scan_carries).
+// Multinomial emission, one weight block per wave (after the carries).
 template <typename T>
 __global__ __launch_bounds__(kT) void k_scan_emit_mw(const T* __restrict__ w, int64_t n,
                                                      uint32_t nb, uint32_t nbe, Key key,
                                                      uint32_t offset, uint32_t filter,
                                                      const ScanHeader* __restrict__ hdr,
                                                      const BlockRec* __restrict__ recs,
-                                                     const u128* __restrict__ C,
-                                                     const u128* __restrict__ CE,
+                                                     Carries C, ECarries CE,
                                                      const uint64_t* __restrict__ evals,
                                                      int32_t* __restrict__ a,
                                                      uint32_t* __restrict__ flags) {
@@ -988,8 +1129,9 @@ __global__ __launch_bounds__(kT) void k_scan_emit_mw(const T* __restrict__ w, in
     for (int64_t i = P0 + lane_id(); i < min(P0 + kBlock, n); i += kWave) a[i] = (int32_t)i;
     return;
   }
-  emit_multi_wave<T>(w, n, P0, recs[b], C[b], C[b + 1], hdr->gscale, hdr->Q, key, filter, offset,
-                     CE, nbe, evals, a, &L[wave]);
+  C.gscale = hdr->gscale;
+  emit_multi_wave<T, true>(w, n, P0, recs[b], C[b], C[b + 1], C.gscale, hdr->Q, key, filter,
+                           offset, CE, nbe, evals, a, &L[wave]);
 }
 
 // ---------------------------------------------------------------- Code 5
@@ -1004,8 +1146,7 @@ __global__ __launch_bounds__(kT) void k_scan_emit_mw(const T* __restrict__ w, in
 template <typename T>
 __global__ __launch_bounds__(kT) void k_scan_r(const T* __restrict__ w, int64_t n, uint32_t nb,
                                                const ScanHeader* __restrict__ hdr,
-                                               const BlockRec* __restrict__ recs,
-                                               const u128* __restrict__ C,
+                                               const BlockRec* __restrict__ recs, Carries C,
                                                double* __restrict__ r_out) {
   if (hdr->status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) return;
   const uint32_t b = blockIdx.x * kWavesPerWG +
@@ -1013,7 +1154,8 @@ __global__ __launch_bounds__(kT) void k_scan_r(const T* __restrict__ w, int64_t 
   if (b >= nb) return;
   const int64_t P0 = (int64_t)b * kBlock;
   BlockR R;
-  block_r_wave(w, n, P0, recs[b], C[b], C[b + 1], hdr->gscale, hdr->Q, R);
+  C.gscale = hdr->gscale;
+  block_r_wave(w, n, P0, recs[b], C[b], C[b + 1], C.gscale, hdr->Q, R);
   const int64_t i0 = P0 + (int64_t)lane_id() * kWPer;
 #pragma unroll
   for (int v = 0; v < kWPer; ++v)
@@ -1131,9 +1273,9 @@ __global__ __launch_bounds__(kT) void k_scan_batched(const T* __restrict__ w, in
   if constexpr (SCHEME == SCHEME_MULTINOMIAL) {
     __shared__ MultiWaveLds L[kWavesPerWG];
     for (uint32_t b = wave; b < nb; b += kWavesPerWG)
-      emit_multi_wave<T>(ws, n, (int64_t)b * kBlock, B.recs[b], B.C[b], B.C[b + 1], t.gscale,
-                         t.Q, key, filt, offset, (const u128*)B.CE, nbe, (const uint64_t*)nullptr,
-                         as, &L[wave]);
+      emit_multi_wave<T, false>(ws, n, (int64_t)b * kBlock, B.recs[b], B.C[b], B.C[b + 1],
+                                t.gscale, t.Q, key, filt, offset, (const u128*)B.CE, nbe,
+                                (const uint64_t*)nullptr, as, &L[wave]);
   } else {
     __shared__ StrataWaveLds<SCHEME == SCHEME_SYSTEMATIC> L[kWavesPerWG];
     for (uint32_t b = wave; b < nb; b += kWavesPerWG)
@@ -1278,40 +1420,6 @@ __global__ __launch_bounds__(kT) void k_seg_carries(uint32_t n_filters,
   }
 }
 
-template <typename T, int SCHEME>
-__global__ __launch_bounds__(kT) void k_seg_emit(
-    const T* __restrict__ w, const int64_t* __restrict__ offsets, uint32_t n_filters, Key key,
-    uint32_t offset, uint32_t filter_base, const uint32_t* __restrict__ bstart,
-    const uint32_t* __restrict__ estart, const BlockRec* __restrict__ recs,
-    const u128* __restrict__ C, const u128* __restrict__ CE, const SegHdr* __restrict__ hdr,
-    int32_t* __restrict__ a, uint32_t* __restrict__ flags, const uint64_t* __restrict__ evals) {
-  __shared__ EmitLds L;
-  __shared__ WgScratch s;
-  offset = counter_offset(key, offset);
-  const uint32_t g = blockIdx.x;
-  if (g >= bstart[n_filters]) return;
-  const uint32_t f = seg_of_block(bstart, n_filters, g);
-  const int64_t base = offsets[f];
-  const int64_t n = offsets[f + 1] - base;
-  const uint32_t b = g - bstart[f];
-  int32_t* __restrict__ as = a + base;
-  const uint32_t status = hdr[f].status;
-  if (flags && b == 0 && threadIdx.x == 0 && status) atomicOr(flags, status);
-  if (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
-    const int64_t P0 = (int64_t)b * kBlock;
-    for (int64_t i = P0 + threadIdx.x; i < min(P0 + kBlock, n); i += kT) as[i] = (int32_t)i;
-    return;
-  }
-  const u128* Cs = C + bstart[f] + f;
-  const uint32_t nbe = SCHEME == SCHEME_MULTINOMIAL ? estart[f + 1] - estart[f] : 0u;
-  const u128* CEs = SCHEME == SCHEME_MULTINOMIAL ? CE + estart[f] + f : CE;
-  const RMap rm = make_rmap(hdr[f].Q, n);
-  const uint64_t* evs =
-      SCHEME == SCHEME_MULTINOMIAL ? evals + (size_t)estart[f] * kBlock : nullptr;
-  emit_block<T, SCHEME>(w + base, n, b, recs[g], Cs[b], Cs[b + 1], hdr[f].gscale, rm, key,
-                        filter_base + f, offset, CEs, nbe, as, &L, &s, nullptr, nullptr, evs);
-}
-
 // Emission of the segmented batch, one block per wave (strata schemes).
 template <typename T, int SCHEME>
 __global__ __launch_bounds__(kT) void k_seg_emit_w(
@@ -1370,9 +1478,37 @@ __global__ __launch_bounds__(kT) void k_seg_emit_mw(
   }
   const u128* Cs = C + bstart[f] + f;
   const uint32_t nbe = estart[f + 1] - estart[f];
-  emit_multi_wave<T>(w + base, n, P0, recs[g], Cs[b], Cs[b + 1], hdr[f].gscale, hdr[f].Q, key,
-                     filter_base + f, offset, CE + estart[f] + f, nbe,
-                     evals + (size_t)estart[f] * kBlock, as, &L[wave]);
+  emit_multi_wave<T, true>(w + base, n, P0, recs[g], Cs[b], Cs[b + 1], hdr[f].gscale, hdr[f].Q,
+                           key, filter_base + f, offset, CE + estart[f] + f, nbe,
+                           evals + (size_t)estart[f] * kBlock, as, &L[wave]);
+}
+
+// The two-level carries of a single vector in its workspace.
+struct CarrySet {
+  Carries C;
+  ECarries CE;
+  CarryGroup* groups;
+  CarryGroup* egroups;
+};
+
+CarrySet carry_set(const ScanLayout& L, char* base, uint32_t nb, uint32_t nbe) {
+  CarrySet c;
+  const uint32_t G = carry_groups(nb), Ge = carry_groups(nbe);
+  c.groups = (CarryGroup*)(base + L.groups);
+  c.egroups = (CarryGroup*)(base + L.egroups);
+  c.C = Carries{(const u128*)(base + L.carries), (const u128*)(c.groups + G), c.groups, nb, G, 0};
+  c.CE = ECarries{(const u128*)(base + L.ecarries), (const u128*)(c.egroups + Ge), nbe, Ge};
+  return c;
+}
+
+template <bool MULTI>
+hipError_t launch_carries(const CarrySet& c, ScanHeader* hdr, const BlockRec* recs,
+                          const uint64_t* esums, hipStream_t stream) {
+  const uint32_t G = c.C.G, Ge = MULTI ? c.CE.Ge : 0u;
+  hipLaunchKernelGGL((k_carry_groups<MULTI>), dim3(G + Ge), dim3(kT), 0, stream, c.C.nb,
+                     c.CE.nbe, G, recs, esums, (u128*)c.C.P, (u128*)c.CE.PE, c.groups,
+                     c.egroups, Ge, (u128*)c.C.Tx, (u128*)c.CE.TEx, hdr);
+  return hipGetLastError();
 }
 
 template <typename T, int SCHEME>
@@ -1385,34 +1521,31 @@ hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, ui
   char* base = (char*)ws;
   ScanHeader* hdr = (ScanHeader*)base;
   BlockRec* recs = (BlockRec*)(base + L.recs);
-  u128* C = (u128*)(base + L.carries);
   uint64_t* esums = (uint64_t*)(base + L.erecs);
-  u128* CE = (u128*)(base + L.ecarries);
   uint64_t* evals = multi ? (uint64_t*)(base + L.evals) : nullptr;
   const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
   const uint32_t nbe = multi ? (uint32_t)((n + 1 + kBlock - 1) / kBlock) : 0u;
   const uint32_t wgs_b = (nb + kWavesPerWG - 1) / kWavesPerWG;
+  const CarrySet cs = carry_set(L, base, nb, nbe);
   hipLaunchKernelGGL((k_scan_records_w<T, multi>), dim3(wgs_b + nbe), dim3(kT), 0, stream, w, n,
-                     nb, wgs_b, key, offset, filter, recs, esums, evals);
+                     nb, wgs_b, key, offset, filter, recs, esums, evals, hdr);
   hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   if constexpr (!multi) {
     if (nb <= (uint32_t)tuning().direct_max_blocks && nb <= kDirectMax) {
       hipLaunchKernelGGL((k_scan_emit_w<T, SCHEME, true>), dim3(wgs_b), dim3(kT), 0, stream, w,
-                         n, nb, key, offset, filter, hdr, recs, C, a, flags, d_out, e_out);
+                         n, nb, key, offset, filter, hdr, recs, cs.C, a, flags, d_out, e_out);
       return hipGetLastError();
     }
   }
-  hipLaunchKernelGGL((k_scan_carries<multi>), dim3(1), dim3(kT), 0, stream, nb, nbe, hdr, recs,
-                     esums, C, CE);
-  e = hipGetLastError();
+  e = launch_carries<multi>(cs, hdr, recs, esums, stream);
   if (e != hipSuccess) return e;
   if constexpr (multi) {
     hipLaunchKernelGGL((k_scan_emit_mw<T>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb, nbe, key,
-                       offset, filter, hdr, recs, C, CE, (const uint64_t*)evals, a, flags);
+                       offset, filter, hdr, recs, cs.C, cs.CE, (const uint64_t*)evals, a, flags);
   } else {
     hipLaunchKernelGGL((k_scan_emit_w<T, SCHEME, false>), dim3(wgs_b), dim3(kT), 0, stream, w,
-                       n, nb, key, offset, filter, hdr, recs, C, a, flags, d_out, e_out);
+                       n, nb, key, offset, filter, hdr, recs, cs.C, a, flags, d_out, e_out);
   }
   return hipGetLastError();
 }
@@ -1557,7 +1690,10 @@ ScanLayout scan_layout(int64_t n, bool multinomial) {
   L.carries = L.recs + align256(nb * sizeof(BlockRec));
   L.erecs = L.carries + align256((nb + 1) * sizeof(u128));
   L.ecarries = L.erecs + align256(nbe * sizeof(uint64_t));
-  L.evals = L.ecarries + align256((nbe + 1) * sizeof(u128));
+  L.groups = L.ecarries + align256((nbe + 1) * sizeof(u128));
+  const size_t G = carry_groups((uint32_t)nb), Ge = carry_groups((uint32_t)nbe);
+  L.egroups = L.groups + align256(G * sizeof(CarryGroup) + (G + 1) * sizeof(u128));
+  L.evals = L.egroups + align256(Ge * sizeof(CarryGroup) + (Ge + 1) * sizeof(u128));
   L.total = L.evals + align256(nbe * kBlock * sizeof(uint64_t));
   return L;
 }
@@ -1583,15 +1719,15 @@ hipError_t launch_multinomial_iid_t(const T* w, int64_t n, Key key, uint32_t off
   char* base = (char*)ws;
   ScanHeader* hdr = (ScanHeader*)base;
   BlockRec* recs = (BlockRec*)(base + L.recs);
-  u128* C = (u128*)(base + L.carries);
   double* r = (double*)(base + L.total);
   const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
   const uint32_t wgs_b = (nb + kWavesPerWG - 1) / kWavesPerWG;
+  const CarrySet cs = carry_set(L, base, nb, 0u);
   hipLaunchKernelGGL((k_scan_records_w<T, false>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb,
-                     wgs_b, key, offset, filter, recs, (uint64_t*)nullptr, (uint64_t*)nullptr);
-  hipLaunchKernelGGL((k_scan_carries<false>), dim3(1), dim3(kT), 0, stream, nb, 0u, hdr, recs,
-                     (const uint64_t*)nullptr, C, (u128*)nullptr);
-  hipLaunchKernelGGL((k_scan_r<T>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb, hdr, recs, C, r);
+                     wgs_b, key, offset, filter, recs, (uint64_t*)nullptr, (uint64_t*)nullptr, hdr);
+  launch_carries<false>(cs, hdr, recs, nullptr, stream);
+  hipLaunchKernelGGL((k_scan_r<T>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb, hdr, recs, cs.C,
+                     r);
   // splitter stride: the smallest power of two leaving at most kSplit splitters
   int sl = 0;
   while (((n - 1) >> sl) > kSplit) ++sl;
@@ -1609,15 +1745,15 @@ hipError_t launch_scan_r_t(const T* w, int64_t n, double* r, void* ws, uint32_t*
   char* base = (char*)ws;
   ScanHeader* hdr = (ScanHeader*)base;
   BlockRec* recs = (BlockRec*)(base + L.recs);
-  u128* C = (u128*)(base + L.carries);
   const uint32_t nb = (uint32_t)((n + kBlock - 1) / kBlock);
   const uint32_t wgs_b = (nb + kWavesPerWG - 1) / kWavesPerWG;
+  const CarrySet cs = carry_set(L, base, nb, 0u);
   hipLaunchKernelGGL((k_scan_records_w<T, false>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb,
                      wgs_b, Key{0, 0, nullptr}, 0u, 0u, recs, (uint64_t*)nullptr,
-                     (uint64_t*)nullptr);
-  hipLaunchKernelGGL((k_scan_carries<false>), dim3(1), dim3(kT), 0, stream, nb, 0u, hdr, recs,
-                     (const uint64_t*)nullptr, C, (u128*)nullptr);
-  hipLaunchKernelGGL((k_scan_r<T>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb, hdr, recs, C, r);
+                     (uint64_t*)nullptr, hdr);
+  launch_carries<false>(cs, hdr, recs, nullptr, stream);
+  hipLaunchKernelGGL((k_scan_r<T>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb, hdr, recs, cs.C,
+                     r);
   if (flags) hipLaunchKernelGGL(k_scan_status, dim3(1), dim3(1), 0, stream, hdr, flags);
   return hipGetLastError();
 }

@@ -2,7 +2,8 @@
 
 The 4096-vector ragged batch and the 1024 x 2^14 filter step run whole on the
 GPU, in the launch configuration the benchmark uses; the oracle recomputes a
-sample of segments (the shortest, the longest and a spread of others).  The
+sample of segments (256 of the batch's: the shortest, the longest and a seeded
+spread of others).  The
 collective schemes are also checked on one 2^22 vector.
 """
 import math
@@ -73,7 +74,11 @@ def test_ragged_batch_full_size_sampled(batch):
     fl = torch.zeros(1, dtype=torch.int32, device="cuda")
     ar = host(pfr().resample_rejection(wd, 1.0, seed=1, offsets=od, max_len=ml, flags=fl))
     assert int(host(fl)[0]) == 0
-    sample = sorted({0, 1, 2, 777, 2047, 3000, F - 1, int(sizes.argmin()), int(sizes.argmax())})
+    # the extremes and 247 more spread over the batch (seeded): 256 segments
+    fixed = {0, 1, 2, 777, 2047, 3000, F - 1, int(sizes.argmin()), int(sizes.argmax())}
+    rest = [int(f) for f in np.random.default_rng(11).permutation(F) if int(f) not in fixed]
+    sample = sorted(fixed | set(rest[:256 - len(fixed)]))
+    assert len(sample) == 256
     for f in sample:
         seg = w[off[f]:off[f + 1]].astype(np.float64)
         sl = slice(off[f], off[f + 1])
@@ -91,6 +96,21 @@ def test_collective_long_vectors(scheme, n):
     w = inputs.weights(n, 3.0, seed=0)
     a = host(getattr(pfr(), "resample_" + scheme)(torch.from_numpy(w).cuda(), seed=5))
     check_collective(scheme, w.astype(np.float64), a, seed=5, filt=0)
+
+
+@pytest.mark.parametrize("scheme", ["systematic", "stratified", "multinomial"])
+def test_collective_carry_groups_of_different_scales(scheme):
+    """Four carry groups (1024 weight blocks each) of very different
+    magnitudes, one of them all zero, and a ragged last group: each group's
+    own fixed-point scale is converted to the global one."""
+    n = 3 * (1 << 20) + 5
+    w = inputs.weights(n, 2.0, seed=7, dtype=np.float64)
+    g = 1 << 20
+    w[:g] *= 2.0**-60
+    w[g:2 * g] = 0.0
+    w[3 * g:] *= 2.0**40
+    a = host(getattr(pfr(), "resample_" + scheme)(torch.from_numpy(w).cuda(), seed=2))
+    check_collective(scheme, w, a, seed=2, filt=0)
 
 
 def test_filter_step_full_size_sampled():

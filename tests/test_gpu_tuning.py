@@ -10,11 +10,17 @@ pytestmark = pytest.mark.gpu
 
 SETTINGS = [
     {"single_wg_max": 0, "direct_max_blocks": 0, "metropolis_table_min_B": 0,
-     "rejection_table": 0, "rejection_per_wave": 64, "metropolis_chunk": 256},
+     "rejection_table": 0, "rejection_per_wave": 64, "metropolis_chunk": 256,
+     "batch_scan_wg_max_len": 0, "batch_stage_max_kb": 16, "batch_metropolis_chunk": 1024,
+     "batch_rejection_per_wave": 64, "batch_permute_lds_max": 4096},
     {"single_wg_max": 65536, "direct_max_blocks": 2048, "metropolis_table_min_B": 1,
-     "rejection_table": 1, "rejection_per_wave": 4096, "metropolis_chunk": 8192},
+     "rejection_table": 1, "rejection_per_wave": 4096, "metropolis_chunk": 8192,
+     "batch_scan_wg_max_len": 65536, "batch_stage_max_kb": 128, "batch_metropolis_chunk": 65536,
+     "batch_rejection_per_wave": 4096, "batch_permute_lds_max": 16384},
     {"single_wg_max": 1000, "direct_max_blocks": 7, "metropolis_table_min_B": 20,
-     "rejection_table": 1, "rejection_per_wave": 192, "metropolis_chunk": 768},
+     "rejection_table": 1, "rejection_per_wave": 192, "metropolis_chunk": 768,
+     "batch_scan_wg_max_len": 4096, "batch_stage_max_kb": 64, "batch_metropolis_chunk": 3072,
+     "batch_rejection_per_wave": 192, "batch_permute_lds_max": 8192},
 ]
 
 
@@ -30,6 +36,9 @@ def run_all(w, off=None, max_len=None):
         outs.append(getattr(m, "resample_" + s)(w, seed=5, offsets=off, max_len=max_len))
     outs.append(m.resample_metropolis(w, 37, seed=5, offsets=off, max_len=max_len))
     outs.append(m.resample_rejection(w, 1.0, seed=5, offsets=off, max_len=max_len))
+    # the permutation of an unsorted (Metropolis) and a sorted (systematic) vector
+    outs.append(m.permute_ancestors(outs[3], offsets=off, max_len=max_len))
+    outs.append(m.permute_ancestors(outs[1], sorted_hint=True, offsets=off, max_len=max_len))
     torch.cuda.synchronize()
     return [o.cpu().numpy() for o in outs]
 
@@ -53,7 +62,7 @@ def test_results_do_not_depend_on_tuning(n):
 def test_batched_results_do_not_depend_on_tuning():
     m = pfr()
     saved = m.get_tuning()
-    lens = [300, 5000, 17000, 1, 0, 40000]
+    lens = [300, 5000, 17000, 1, 0, 40000, 4096, 8193, 1024]
     off = torch.tensor(np.concatenate([[0], np.cumsum(lens)]), dtype=torch.int64).cuda()
     w = torch.from_numpy(np.concatenate([inputs.weights(k, 2.5, seed=k + 1) for k in lens])).cuda()
     try:

@@ -220,14 +220,20 @@ def test_tuning_set_get_load_roundtrip(tmp_path):
             assert pfr.get_tuning() == t
         # JSON file: top-level integers, unknown keys ignored, absent keys kept
         f = tmp_path / "tuning.json"
-        f.write_text('{"version": 1, "rejection_per_wave": 128, "device": "x", '
+        f.write_text('{"version": 2, "rejection_per_wave": 128, "device": "x", '
                      '"measured_ms": {"metropolis_chunk": 7}}')
         lib = _lib.load()
         assert lib.pfr_load_tuning(str(f).encode()) == _lib.PFR_OK
         t2 = pfr.get_tuning()
         assert t2["rejection_per_wave"] == 128 and t2["metropolis_chunk"] == 1024
-        f.write_text('{"version": 2, "rejection_per_wave": 128}')
+        f.write_text('{"version": 1, "rejection_per_wave": 128}')
         assert lib.pfr_load_tuning(str(f).encode()) == _lib.PFR_EINVAL
+        f.write_text('{"version": 2, "batch_stage_max_kb": 32}')
+        assert lib.pfr_load_tuning(str(f).encode()) == _lib.PFR_EINVAL
+        f.write_text('{"version": 2, "batch_permute_lds_max": 8192, "batch_metropolis_chunk": 2048}')
+        assert lib.pfr_load_tuning(str(f).encode()) == _lib.PFR_OK
+        t3 = pfr.get_tuning()
+        assert (t3["batch_permute_lds_max"], t3["batch_metropolis_chunk"]) == (8192, 2048)
         assert lib.pfr_load_tuning(str(tmp_path / "missing.json").encode()) == _lib.PFR_EINVAL
     finally:
         pfr.set_tuning(**saved)
