@@ -306,7 +306,11 @@ PFR_API int offspring_to_ancestors(const int32_t* offspring, const pfr_segments*
  * collective resamplers) and the claim needs no atomics; otherwise any
  * ancestry is accepted.  An ancestor outside [0, n) is treated as its own
  * index and raises PFR_FLAG_BAD_ANCESTOR.  The workspace holds the claim
- * vector. */
+ * vector and the marked ancestry (8 bytes per particle at least); with the
+ * size pfr_workspace_bytes(PFR_OP_PERMUTE, ...) reports, a single unsorted
+ * vector is claimed by buckets of slots in LDS instead of global atomics
+ * (8 more bytes per particle and the bucket counts).  Either claim gives the
+ * same result. */
 PFR_API int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t sorted_hint,
                       int32_t* permuted, void* ws, size_t ws_bytes, uint32_t* dev_flags,
                       void* stream);
@@ -314,8 +318,9 @@ PFR_API int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg,
 /* permute_ancestors without a workspace argument, for callers that cannot
  * allocate device memory (code under HIP graph capture, tight serving loops,
  * harnesses that forbid hipMalloc).  Same arguments, result and flags as
- * permute_ancestors with the workspace removed; the claim vector and the
- * marked ancestry live in a static device array of
+ * permute_ancestors with the workspace removed; the claim vector, the
+ * marked ancestry and (when they fit) the bucket counts and pairs live in a
+ * static device array of
  * PFR_NOALLOC_SCRATCH_BYTES inside the library (one per GPU, held until the
  * process ends), so n_total is limited to PFR_NOALLOC_MAX_N: a longer input
  * returns PFR_ETOOBIG and enqueues nothing.  Every call on one GPU uses that

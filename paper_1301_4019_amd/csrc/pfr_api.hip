@@ -150,7 +150,7 @@ size_t pfr_workspace_bytes(pfr_op op, const pfr_segments* seg, pfr_dtype dtype) 
     case PFR_OP_OFFSPRING_TO_ANCESTORS:
       return o2a_workspace_bytes(s.n_total);
     case PFR_OP_PERMUTE:
-      return permute_workspace_bytes(s.n_total);
+      return permute_workspace_bytes(s.n_total, s.n_filters);
     case PFR_OP_ANCESTORS_TO_OFFSPRING:
       return 0;
     case PFR_OP_ESS:
@@ -325,13 +325,16 @@ int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t
   if (!ancestors || !permuted) return PFR_EINVAL;
   if (overlaps(ancestors, (size_t)s.n_total * 4, permuted, (size_t)s.n_total * 4))
     return PFR_EINVAL;
-  const size_t need = permute_workspace_bytes(s.n_total);
+  // the size pfr_workspace_bytes reports; a smaller one of at least the claim
+  // vector and marks (8 bytes per particle) runs the atomic claim instead
+  const size_t full = permute_workspace_bytes(s.n_total, s.n_filters);
+  const size_t need = ws_bytes >= full ? full : permute_workspace_min_bytes(s.n_total);
   if (!ws || ws_bytes < need || !aligned256(ws)) return PFR_EWORKSPACE;
   if (overlaps(ws, need, permuted, (size_t)s.n_total * 4) ||
       overlaps(ws, need, ancestors, (size_t)s.n_total * 4))
     return PFR_EINVAL;
   return launch_result(launch_permute(ancestors, s.n_total, s.offsets, s.n_filters, s.max_len,
-                                      sorted_hint != 0, permuted, ws, dev_flags,
+                                      sorted_hint != 0, permuted, ws, need, dev_flags,
                                       (hipStream_t)stream));
 }
 
@@ -341,7 +344,8 @@ namespace {
 
 // Scratch of permute_ancestors_noalloc: the claim vector and the marked
 // ancestry (4 + 4 bytes per particle, each part 256-byte aligned) of up to
-// PFR_NOALLOC_MAX_N particles.  One copy per GPU, at that GPU's own address,
+// PFR_NOALLOC_MAX_N particles, and the bucketed claim's counts and pairs when
+// they fit beside them.  One copy per GPU, at that GPU's own address,
 // held until the process ends.  Host code never uses the name `scratch` as an
 // address: the device address comes from hipGetSymbolAddress, once per device.
 static __device__ __align__(256) uint8_t scratch[PFR_NOALLOC_SCRATCH_BYTES];
@@ -351,8 +355,8 @@ std::mutex g_scratch_mu;
 void* g_scratch_dev[kMaxDevices];  // device address of `scratch` on each device (or null)
 
 // The current device's scratch address, looked up on the first call on that
-// device.  The permutation writes every claim and mark before reading it, so
-// the scratch needs no clearing.
+// device.  The permutation writes every claim, mark, count and pair before
+// reading it, so the scratch needs no clearing.
 int noalloc_scratch(void** out) {
   int dev = -1;
   if (hipGetDevice(&dev) != hipSuccess || dev < 0 || dev >= kMaxDevices) return PFR_ELAUNCH;
@@ -383,13 +387,13 @@ int permute_ancestors_noalloc(const int32_t* ancestors, const pfr_segments* seg,
     return PFR_EINVAL;
   static_assert(PFR_NOALLOC_SCRATCH_BYTES >= 2 * (size_t)PFR_NOALLOC_MAX_N * sizeof(int32_t),
                 "the scratch holds the claim vector and the marks of PFR_NOALLOC_MAX_N particles");
-  if (permute_workspace_bytes(s.n_total) > PFR_NOALLOC_SCRATCH_BYTES) return PFR_ETOOBIG;
+  if (permute_workspace_min_bytes(s.n_total) > PFR_NOALLOC_SCRATCH_BYTES) return PFR_ETOOBIG;
   void* ws = nullptr;
   rc = noalloc_scratch(&ws);
   if (rc) return rc;
   return launch_result(launch_permute(ancestors, s.n_total, s.offsets, s.n_filters, s.max_len,
-                                      sorted_hint != 0, permuted, ws, dev_flags,
-                                      (hipStream_t)stream));
+                                      sorted_hint != 0, permuted, ws, PFR_NOALLOC_SCRATCH_BYTES,
+                                      dev_flags, (hipStream_t)stream));
 }
 
 int ancestors_to_offspring(const int32_t* ancestors, const pfr_segments* seg, int32_t sorted_hint,
@@ -455,7 +459,7 @@ size_t pfr_resample_permuted_workspace_bytes(pfr_op scheme, const pfr_segments* 
   SegInfo s;
   if (check_segments(seg, &s)) return 0;
   if (scheme < PFR_OP_MULTINOMIAL || scheme > PFR_OP_REJECTION) return 0;
-  const size_t perm = permute_workspace_bytes(s.n_total);
+  const size_t perm = permute_workspace_bytes(s.n_total, s.n_filters);
   return perm + pfr_workspace_bytes(scheme, seg, dtype);
 }
 
@@ -474,7 +478,7 @@ int resample_permuted(pfr_op scheme, const void* w, pfr_dtype dtype, const pfr_s
   if (overlaps(ancestors, abytes, permuted, abytes) ||
       overlaps(w, (size_t)s.n_total * dtype_size(dtype), permuted, abytes))
     return PFR_EINVAL;
-  const size_t perm = permute_workspace_bytes(s.n_total);
+  const size_t perm = permute_workspace_bytes(s.n_total, s.n_filters);
   const size_t need = perm + pfr_workspace_bytes(scheme, seg, dtype);
   if (!ws || ws_bytes < need || !aligned256(ws)) return PFR_EWORKSPACE;
   if (overlaps(ws, need, ancestors, abytes) || overlaps(ws, need, permuted, abytes))
@@ -523,7 +527,7 @@ int resample_permuted(pfr_op scheme, const void* w, pfr_dtype dtype, const pfr_s
 size_t lgssm_workspace_bytes(int32_t n_filters, int32_t n) {
   if (n_filters < 1 || n < 1 || (int64_t)n_filters * n >= kMaxN) return 0;
   const int64_t total = (int64_t)n_filters * n;
-  const size_t perm = permute_workspace_bytes(total);
+  const size_t perm = permute_workspace_bytes(total, (uint32_t)n_filters);
   const size_t seg = seg_layout(total, (uint32_t)n_filters, true).total;
   return lgssm_offsets_bytes(n_filters) + (perm > seg ? perm : seg);
 }
@@ -590,7 +594,7 @@ int lgssm_step(const pfr_lgssm* model, pfr_op scheme, pfr_precision precision, i
   }
   if (e != hipSuccess) return PFR_ELAUNCH;
   e = launch_permute(ancestors, total, offsets, nf, n, collective_scheme, permuted, perm_ws,
-                     dev_flags, st);
+                     permute_workspace_bytes(total, nf), dev_flags, st);
   if (e != hipSuccess) return PFR_ELAUNCH;
   Key nkey = make_key(rng);
   nkey.offset_dev = nullptr;

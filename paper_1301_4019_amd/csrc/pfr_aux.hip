@@ -622,6 +622,257 @@ __global__ __launch_bounds__(kPermThreads) void k_permute_staged(
   }
 }
 
+// ---------------------------------------------------------------- bucketed claim
+// The claim vector of one unsorted vector without global atomics.  The slots
+// fall into B buckets of S consecutive slots and the positions into W chunks
+// of C; (1) every chunk counts its claims per bucket, (2) one workgroup per
+// bucket scans its chunks' counts (the bucket totals give the buckets' bases),
+// (3) every chunk writes its (position, slot) pairs to those places (the
+// order inside a bucket does not matter), and (4) one workgroup per bucket
+// takes the minimum claimer of each of its slots in LDS, writes that part of
+// d (unclaimed: n) and the mark e_i = a_i of every winner; (3) has marked
+// every position as a loser (-1 - a_i) before.  Claims that lose inside their
+// own chunk get no pair.  k_resolve then walks e.  The minimum does not depend
+// on the order, so d and e are those of the atomic claim.  Traffic: a read
+// four times (8 + 8 bytes, half from the L2), 4 + 8 + 8 bytes of marks and
+// pairs, 4 of d, and one scattered 4-byte write per claimed slot.
+struct BucketGeom {
+  int64_t n;
+  uint32_t S, C, B, W;  // slots per bucket, positions per chunk, buckets, chunks
+  int log2S;
+  size_t cnt_off, tot_off, pairs_off, bytes;  // workspace parts after d and e
+};
+
+constexpr int kBucketMax = 4096;  // buckets (LDS counters of the chunk kernels)
+constexpr int kBucketSlotsMax = 32768;
+constexpr int kBucketThreads = 1024;
+constexpr int kClaimThreads = 1024;
+
+__host__ __device__ inline uint32_t pow2_at_least(int64_t x) {
+  uint32_t p = 1;
+  while ((int64_t)p < x && p < (1u << 30)) p <<= 1;
+  return p;
+}
+
+BucketGeom bucket_geom(int64_t n) {
+  BucketGeom g;
+  g.n = n;
+  // about 256 buckets and 1024 chunks: S and C powers of two, S from 4096 to
+  // kBucketSlotsMax (the claim kernel's LDS table), C from 4096
+  const uint32_t t = pow2_at_least((n + 255) / 256), tc = pow2_at_least((n + 1023) / 1024);
+  g.S = t < 4096 ? 4096 : (t > (uint32_t)kBucketSlotsMax ? (uint32_t)kBucketSlotsMax : t);
+  g.C = tc < 4096 ? 4096 : tc;
+  g.log2S = 0;
+  while ((1u << g.log2S) < g.S) ++g.log2S;
+  g.B = (uint32_t)((n + g.S - 1) / g.S);
+  g.W = (uint32_t)((n + g.C - 1) / g.C);
+  const size_t base = 2 * align256((size_t)n * sizeof(int32_t));  // d, e
+  const size_t pairs = (size_t)g.B * g.W;
+  g.cnt_off = base;
+  g.tot_off = g.cnt_off + align256(pairs * sizeof(uint32_t));
+  g.pairs_off = g.tot_off + align256((size_t)g.B * sizeof(uint32_t));
+  g.bytes = g.pairs_off + align256((size_t)n * sizeof(uint64_t));
+  return g;
+}
+
+// the bucketed claim applies to single vectors of up to 2^31 - 1 particles
+// whose bucket count fits the chunk kernels' LDS counters
+bool bucket_claim_fits(int64_t n) {
+  return n > 0 && n < ((int64_t)1 << 31) && bucket_geom(n).B <= (uint32_t)kBucketMax;
+}
+
+// slot claimed by position i (out-of-range ancestors claim their own index)
+__device__ __forceinline__ uint32_t claim_slot(int32_t v, uint32_t i, uint32_t n, bool& bad) {
+  if (v < 0 || (uint32_t)v >= n) {
+    bad = true;
+    return i;
+  }
+  return (uint32_t)v;
+}
+
+// Positions of chunk w, four per thread and round, their loads issued together
+// (clamped to the chunk; f(i, slot) is called for the positions inside it).
+template <typename F>
+__device__ __forceinline__ void chunk_claims(const int32_t* __restrict__ a, uint32_t n,
+                                             uint32_t p0, uint32_t p1, bool& bad, F f) {
+  for (uint32_t i0 = p0; i0 < p1; i0 += 4 * kBucketThreads) {
+    int32_t v[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      v[k] = a[min(i0 + (uint32_t)(k * kBucketThreads) + threadIdx.x, p1 - 1)];
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      const uint32_t i = i0 + (uint32_t)(k * kBucketThreads) + threadIdx.x;
+      if (i < p1) f(i, claim_slot(v[k], i, n, bad));
+    }
+  }
+}
+
+// Equal claims inside a chunk are merged first: an LDS table keyed by the
+// slot's low bits keeps the smallest (slot, position) per entry, and a
+// position whose entry holds its slot with a smaller position has lost (it is
+// not the minimum claimer), so it needs no pair.  Distinct slots sharing an
+// entry all keep their pairs.  An ancestry with one parent then gives one
+// pair per chunk instead of one per particle.
+constexpr int kDedup = 4096;
+__device__ __forceinline__ void dedup_fill(const int32_t* __restrict__ a, uint32_t n, uint32_t p0,
+                                           uint32_t p1, unsigned long long* tab, bool& bad) {
+  for (uint32_t k = threadIdx.x; k < kDedup; k += kBucketThreads) tab[k] = ~0ull;
+  __syncthreads();
+  chunk_claims(a, n, p0, p1, bad, [&](uint32_t i, uint32_t slot) {
+    atomicMin(&tab[slot & (kDedup - 1)], ((unsigned long long)slot << 32) | i);
+  });
+  __syncthreads();
+}
+__device__ __forceinline__ bool dedup_lost(const unsigned long long* tab, uint32_t slot,
+                                           uint32_t i) {
+  const unsigned long long best = tab[slot & (kDedup - 1)];
+  return (uint32_t)(best >> 32) == slot && (uint32_t)best < i;
+}
+
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_count(
+    const int32_t* __restrict__ a, uint32_t n, int log2S, uint32_t C, uint32_t B, uint32_t W,
+    uint32_t* __restrict__ cnt, uint32_t* __restrict__ flags) {
+  __shared__ uint32_t hist[kBucketMax];
+  __shared__ unsigned long long tab[kDedup];
+  const uint32_t w = blockIdx.x;
+  for (uint32_t b = threadIdx.x; b < B; b += kBucketThreads) hist[b] = 0;
+  bool bad = false;
+  const uint32_t p0 = w * C, p1 = min(n, p0 + C);
+  dedup_fill(a, n, p0, p1, tab, bad);
+  chunk_claims(a, n, p0, p1, bad, [&](uint32_t i, uint32_t slot) {
+    if (!dedup_lost(tab, slot, i)) atomicAdd(&hist[slot >> log2S], 1u);
+  });
+  __syncthreads();
+  for (uint32_t b = threadIdx.x; b < B; b += kBucketThreads) cnt[(size_t)b * W + w] = hist[b];
+  if (flags) {
+    const uint32_t f = (uint32_t)wave_reduce((uint32_t)bad, OpOr());
+    if (f && lane_id() == 0) atomicOr(flags, FLAG_BAD_ANCESTOR);
+  }
+}
+
+// Exclusive scan in place of each bucket's W chunk counts (row b of the
+// bucket-major count matrix), one workgroup per bucket; the row total goes to
+// tot[b].  The bucket's first pair, the sum of the totals of the buckets
+// before it, is formed by its readers (bucket_bases).
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_rows(uint32_t* __restrict__ cnt,
+                                                                uint32_t W,
+                                                                uint32_t* __restrict__ tot) {
+  __shared__ uint32_t s_w[kBucketThreads / kWave];
+  const int tid = (int)threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  uint32_t* row = cnt + (size_t)blockIdx.x * W;
+  uint32_t carry = 0;
+  for (uint32_t c0 = 0; c0 < W; c0 += kBucketThreads) {
+    const uint32_t j = c0 + (uint32_t)tid;
+    const uint32_t x = j < W ? row[j] : 0u;
+    const uint32_t inc = wave_incl_add_u32(x);
+    if (lane == kWave - 1) s_w[wave] = inc;
+    __syncthreads();
+    uint32_t before = carry + inc - x, t = 0;
+    for (int w2 = 0; w2 < kBucketThreads / kWave; ++w2) {
+      before += w2 < wave ? s_w[w2] : 0u;
+      t += s_w[w2];
+    }
+    if (j < W) row[j] = before;
+    carry += t;
+    __syncthreads();
+  }
+  if (tid == 0) tot[blockIdx.x] = carry;
+}
+
+// base[b] = sum of tot[b'] for b' < b, for b <= B, by the calling workgroup
+// (kBucketThreads threads, B <= kBucketMax; s_w holds kBucketThreads / 64).
+__device__ void bucket_bases(const uint32_t* __restrict__ tot, uint32_t B, uint32_t* base,
+                             uint32_t* s_w) {
+  const int tid = (int)threadIdx.x, wave = tid / kWave, lane = tid % kWave;
+  constexpr int kPerT = kBucketMax / kBucketThreads;  // 4 consecutive buckets per thread
+  uint32_t x[kPerT], run = 0;
+#pragma unroll
+  for (int k = 0; k < kPerT; ++k) {
+    const uint32_t b = (uint32_t)tid * kPerT + k;
+    const uint32_t v = b < B ? tot[b] : 0u;
+    x[k] = run;
+    run += v;
+  }
+  const uint32_t inc = wave_incl_add_u32(run);
+  if (lane == kWave - 1) s_w[wave] = inc;
+  __syncthreads();
+  uint32_t before = inc - run;
+  for (int w2 = 0; w2 < wave; ++w2) before += s_w[w2];
+#pragma unroll
+  for (int k = 0; k < kPerT; ++k) {
+    const uint32_t b = (uint32_t)tid * kPerT + k;
+    if (b <= B) base[b] = before + x[k];
+  }
+  __syncthreads();
+}
+
+__global__ __launch_bounds__(kBucketThreads) void k_bucket_scatter(
+    const int32_t* __restrict__ a, uint32_t n, int log2S, uint32_t C, uint32_t B, uint32_t W,
+    const uint32_t* __restrict__ off, const uint32_t* __restrict__ tot,
+    uint64_t* __restrict__ pairs, int32_t* __restrict__ e) {
+  __shared__ uint32_t cur[kBucketMax + 1];
+  __shared__ uint32_t s_w[kBucketThreads / kWave];
+  __shared__ unsigned long long tab[kDedup];
+  const uint32_t w = blockIdx.x;
+  bucket_bases(tot, B, cur, s_w);
+  for (uint32_t b = threadIdx.x; b < B; b += kBucketThreads) cur[b] += off[(size_t)b * W + w];
+  bool bad = false;
+  const uint32_t p0 = w * C, p1 = min(n, p0 + C);
+  dedup_fill(a, n, p0, p1, tab, bad);
+  // every position is marked as a loser here (in order, coalesced); the
+  // claim kernel then marks the winners, one per claimed slot
+  chunk_claims(a, n, p0, p1, bad, [&](uint32_t i, uint32_t slot) {
+    e[i] = -1 - (int32_t)slot;
+    if (!dedup_lost(tab, slot, i)) {  // (a loser here: a smaller position of the chunk claims it)
+      const uint32_t r = atomicAdd(&cur[slot >> log2S], 1u);
+      pairs[r] = ((uint64_t)i << 32) | slot;
+    }
+  });
+}
+
+// The pairs [q0, q1) of a bucket, four per thread and round, loads together.
+template <typename F>
+__device__ __forceinline__ void bucket_pairs(const uint64_t* __restrict__ pairs, uint32_t q0,
+                                             uint32_t q1, F f) {
+  for (uint32_t b0 = q0; b0 < q1; b0 += 4 * kClaimThreads) {
+    uint64_t p[4];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      p[k] = pairs[min(b0 + (uint32_t)(k * kClaimThreads) + threadIdx.x, q1 - 1)];
+#pragma unroll
+    for (int k = 0; k < 4; ++k)
+      if (b0 + (uint32_t)(k * kClaimThreads) + threadIdx.x < q1)
+        f((uint32_t)(p[k] >> 32), (uint32_t)p[k]);
+  }
+}
+
+__global__ __launch_bounds__(kClaimThreads) void k_bucket_claim(
+    uint32_t n, uint32_t S, const uint32_t* __restrict__ tot,
+    const uint64_t* __restrict__ pairs, int32_t* __restrict__ d, int32_t* __restrict__ e) {
+  __shared__ uint32_t tab[kBucketSlotsMax];
+  __shared__ uint32_t s_q[kClaimThreads / kWave];
+  const uint32_t b = blockIdx.x;
+  const uint32_t s0 = b * S, ns = min(S, n - s0);
+  for (uint32_t k = threadIdx.x; k < ns; k += kClaimThreads) tab[k] = n;
+  // the bucket's first pair: the pairs of the buckets before it
+  uint32_t q = 0;
+  for (uint32_t k = threadIdx.x; k < b; k += kClaimThreads) q += tot[k];
+  q = wave_reduce(q, OpAdd());
+  if (lane_id() == 0) s_q[threadIdx.x / kWave] = q;
+  __syncthreads();
+  uint32_t q0 = 0;
+  for (int w2 = 0; w2 < kClaimThreads / kWave; ++w2) q0 += s_q[w2];
+  const uint32_t q1 = q0 + tot[b];
+  bucket_pairs(pairs, q0, q1, [&](uint32_t i, uint32_t slot) { atomicMin(&tab[slot - s0], i); });
+  __syncthreads();
+  for (uint32_t k = threadIdx.x; k < ns; k += kClaimThreads) {
+    const uint32_t i = tab[k];
+    d[s0 + k] = (int32_t)i;
+    if (i < n) e[i] = (int32_t)(s0 + k);  // the winner of slot s0 + k
+  }
+}
+
 int grid_for(int64_t n) {
   int64_t b = (n + 255) / 256;
   if (b > 65536) b = 65536;
@@ -652,9 +903,17 @@ hipError_t launch_offspring_to_ancestors(const int32_t* o, int64_t n_total, cons
   return hipGetLastError();
 }
 
-// Workspace: the claim vector d and the marked ancestry e, n int32 each.
-size_t permute_workspace_bytes(int64_t n_total) {
+// Workspace: the claim vector d and the marked ancestry e, n int32 each; a
+// single unsorted vector beyond the LDS path also gets the bucketed claim's
+// counts and pairs (8 more bytes per particle), without which it takes the
+// atomic claim.
+size_t permute_workspace_min_bytes(int64_t n_total) {
   return 2 * align256((size_t)n_total * sizeof(int32_t));
+}
+size_t permute_workspace_bytes(int64_t n_total, uint32_t n_filters) {
+  if (n_filters <= 1 && n_total > kPermSingleMax && bucket_claim_fits(n_total))
+    return bucket_geom(n_total).bytes;
+  return permute_workspace_min_bytes(n_total);
 }
 
 // Batches whose segments fit in LDS, and short single vectors, are permuted
@@ -662,7 +921,7 @@ size_t permute_workspace_bytes(int64_t n_total) {
 // through the global kernels.  max_len: longest segment (0 = unknown).
 hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offsets,
                           uint32_t n_filters, int64_t max_len, bool sorted, int32_t* c, void* ws,
-                          uint32_t* flags, hipStream_t stream) {
+                          size_t ws_bytes, uint32_t* flags, hipStream_t stream) {
   int32_t* d = (int32_t*)ws;
   int32_t* e = (int32_t*)((char*)ws + align256((size_t)n_total * sizeof(int32_t)));
   const int grid = grid_for(n_total);
@@ -693,6 +952,27 @@ hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offs
   if (sorted) {
     hipLaunchKernelGGL(k_claim_sorted, dim3(grid), dim3(256), 0, stream, a, n_total, offsets,
                        n_filters, min_len, d, e, flags);
+    hipLaunchKernelGGL(k_resolve, dim3(grid), dim3(256), 0, stream, n_total, offsets, n_filters,
+                       min_len, d, e, c, flags);
+    return hipGetLastError();
+  }
+  if (!(offsets && n_filters > 1) && bucket_claim_fits(n_total) &&
+      ws_bytes >= bucket_geom(n_total).bytes) {
+    // one vector: the bucketed claim writes d and e, then the walk on e
+    const BucketGeom g = bucket_geom(n_total);
+    char* base = (char*)ws;
+    uint32_t* cnt = (uint32_t*)(base + g.cnt_off);
+    uint32_t* tot = (uint32_t*)(base + g.tot_off);
+    uint64_t* pairs = (uint64_t*)(base + g.pairs_off);
+    const uint32_t n = (uint32_t)n_total;
+    hipLaunchKernelGGL(k_bucket_count, dim3(g.W), dim3(kBucketThreads), 0, stream, a, n, g.log2S,
+                       g.C, g.B, g.W, cnt, flags);
+    hipLaunchKernelGGL(k_bucket_rows, dim3(g.B), dim3(kBucketThreads), 0, stream, cnt, g.W, tot);
+    hipLaunchKernelGGL(k_bucket_scatter, dim3(g.W), dim3(kBucketThreads), 0, stream, a, n,
+                       g.log2S, g.C, g.B, g.W, (const uint32_t*)cnt, (const uint32_t*)tot, pairs,
+                       e);
+    hipLaunchKernelGGL(k_bucket_claim, dim3(g.B), dim3(kClaimThreads), 0, stream, n, g.S,
+                       (const uint32_t*)tot, (const uint64_t*)pairs, d, e);
     hipLaunchKernelGGL(k_resolve, dim3(grid), dim3(256), 0, stream, n_total, offsets, n_filters,
                        min_len, d, e, c, flags);
     return hipGetLastError();

@@ -108,7 +108,10 @@ __device__ __forceinline__ uint4 draw_uniform(Key key, uint32_t index, uint32_t 
 
 
 // u in (0, 1] on the 2^-32 lattice (accept tests).
-__device__ __forceinline__ double u_accept(uint32_t x) { return ((double)x + 1.0) * 0x1p-32; }
+// ((double)x + 1) 2^-32 as one fused multiply-add (every step exact).
+__device__ __forceinline__ double u_accept(uint32_t x) {
+  return __fma_rn((double)x, 0x1p-32, 0x1p-32);
+}
 // u in [0, 1) on the 2^-32 lattice (stratum offsets).
 __device__ __forceinline__ double u_offset(uint32_t x) { return (double)x * 0x1p-32; }
 // j uniform on [0, n): high 64 bits of the 64x64-bit product.
@@ -315,6 +318,15 @@ __device__ __forceinline__ uint64_t wave_incl_add_u64(uint64_t x) {
   return x;
 }
 // Inclusive max-scan of values >= -1.
+__device__ __forceinline__ uint32_t wave_incl_add_u32(uint32_t x) {
+  x += dpp_u32<kDppShr1>(0u, x);
+  x += dpp_u32<kDppShr2>(0u, x);
+  x += dpp_u32<kDppShr4>(0u, x);
+  x += dpp_u32<kDppShr8>(0u, x);
+  x += dpp_u32<kDppBcast15, 0xA>(0u, x);
+  x += dpp_u32<kDppBcast31, 0xC>(0u, x);
+  return x;
+}
 __device__ __forceinline__ int32_t wave_incl_max_i32(int32_t x) {
   const uint32_t m1 = 0xFFFFFFFFu;
   x = max(x, (int32_t)dpp_u32<kDppShr1>(m1, (uint32_t)x));

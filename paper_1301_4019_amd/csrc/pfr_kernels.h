@@ -125,7 +125,8 @@ size_t o2a_workspace_bytes(int64_t n_total);
 hipError_t launch_offspring_to_ancestors(const int32_t* o, int64_t n_total, const int64_t* offsets,
                                          uint32_t n_filters, int32_t* a, void* ws,
                                          uint32_t* flags, hipStream_t stream);
-size_t permute_workspace_bytes(int64_t n_total);
+size_t permute_workspace_bytes(int64_t n_total, uint32_t n_filters);
+size_t permute_workspace_min_bytes(int64_t n_total);
 // The rest of Code 10 after an emission that wrote the claim vector and the
 // marked ancestry itself (launch_scan_claimed): the resolve pass over a
 // single vector.  permute_claims / permute_marks locate d and e in a
@@ -139,7 +140,7 @@ hipError_t launch_scan_claimed(int scheme, bool f64, const void* w, int64_t n, K
                                uint32_t* flags, int32_t* d, int32_t* e, hipStream_t stream);
 hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offsets,
                           uint32_t n_filters, int64_t max_len, bool sorted, int32_t* c, void* ws,
-                          uint32_t* flags, hipStream_t stream);
+                          size_t ws_bytes, uint32_t* flags, hipStream_t stream);
 
 // Code 12; max_len as for launch_permute.
 hipError_t launch_ancestors_to_offspring(const int32_t* a, int64_t n_total, const int64_t* offsets,

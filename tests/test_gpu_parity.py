@@ -527,6 +527,28 @@ def test_permute_degenerate_ancestries():
         assert np.array_equal(c[off[f]:off[f + 1]], ref), f
 
 
+@pytest.mark.parametrize("n", [4097, 5000, (1 << 22) + 3, 5 * (1 << 20) + 7])
+def test_permute_unsorted_bucketed_and_atomic_claims(n):
+    """One unsorted vector beyond the LDS path: the claim by buckets of slots
+    (full workspace) and the atomic claim (a workspace of only the claim
+    vector and marks) give Code 10's permutation; out-of-range ancestors are
+    flagged and count as their own index on both."""
+    m = pfr()
+    g = np.random.default_rng(n)
+    p = g.random(n) ** 8
+    a = g.choice(n, size=n, p=p / p.sum()).astype(np.int32)
+    a[g.integers(0, n, 5)] = np.array([-1, n, n + 7, -100, 2**31 - 1], dtype=np.int32)
+    ref, rfl = oracle.permute(a)
+    full = m.workspace_bytes(m._lib.OP_PERMUTE, n)
+    small = 2 * ((4 * n + 255) // 256 * 256)
+    assert full > small
+    for nbytes in (full, small):
+        fl = new_flags()
+        c = host(m.permute_ancestors(dev(a), flags=fl, workspace=m.new_workspace(nbytes)))
+        assert np.array_equal(c, ref), nbytes
+        assert int(host(fl)[0]) == rfl == m.FLAG_BAD_ANCESTOR
+
+
 def test_permute_long_chain():
     # a = [0, 0, 1, 2, ..., n-2]: one chain runs through every slot
     n = 3000
