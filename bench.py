@@ -159,16 +159,18 @@ def implied_bias(torch, pfr, w, precision, e=None, workspace=None):
 
 def batch_implied_bias(torch, pfr, w32, off_np):
     """Deterministic bias (as implied_bias) over the vectors of a ragged batch,
-    for the batched compensated-binary32 form (float32 weights) and the plain
-    per-filter binary64 form (float64 weights): the sum over the vectors and
-    the largest single-vector value."""
+    for the batched exact and compensated-binary32 forms (float32 weights; a
+    batched call forms each vector's prefix bit for bit as a call on it alone)
+    and the plain per-filter binary64 form (float64 weights): the sum over the
+    vectors and the largest single-vector value."""
     out = {}
     w64 = w32.double()
     # one workspace of the largest vector's size serves every call
     from paper_1301_4019_amd import _lib
     max_len = int(np.diff(off_np).max())
     ws = pfr.new_workspace(pfr.workspace_bytes(_lib.OP_SCALED_PREFIX, max_len), w32.device)
-    for name, ww, prec in (("comp_f32_batched", w32, pfr.SCAN_COMP_F32),
+    for name, ww, prec in (("exact_batched", w32, pfr.SCAN_EXACT),
+                           ("comp_f32_batched", w32, pfr.SCAN_COMP_F32),
                            ("f64_per_filter", w64, pfr.SCAN_F64)):
         tot, worst, dmax = 0.0, 0.0, 0.0
         for f in range(off_np.size - 1):
@@ -905,6 +907,66 @@ def scaling_workload(args):
                       "rows": rows}), flush=True)
 
 
+def permute_workload(args):
+    """The ancestor permutation (Code 10) on one vector, n = 2^20 .. 2^24: the
+    Metropolis ancestry (B = 60) of the bench weights for y = 0 and 4, with the
+    bucketed claim (the workspace pfr_workspace_bytes reports) and with the
+    atomic claim (a workspace of 8 bytes per particle), and the systematic
+    ancestry through the sorted claim.  Device time per call (HIP events, median
+    of 9, the Infinity Cache flushed before each) and the HBM fraction of the 8
+    algorithmic bytes per particle (read a, write c)."""
+    import torch
+    import paper_1301_4019_amd as pfr
+    from paper_1301_4019_amd import inputs, _lib
+
+    dev = torch.device("cuda:0")
+    torch.cuda.set_device(dev)
+    stream = torch.cuda.current_stream()
+    flush = torch.empty(512 << 20, dtype=torch.uint8, device=dev)
+    rows = []
+
+    def timed(fn):
+        fn()
+        ts = []
+        for r in range(9):
+            flush.fill_(r)
+            e0 = torch.cuda.Event(enable_timing=True)
+            e1 = torch.cuda.Event(enable_timing=True)
+            e0.record(stream)
+            fn()
+            e1.record(stream)
+            e1.synchronize()
+            ts.append(e0.elapsed_time(e1) * 1e-3)
+        return sorted(ts)[4]
+
+    for lg in args.permute_log2n:
+        n = 1 << lg
+        out = torch.empty(n, dtype=torch.int32, device=dev)
+        full = pfr.workspace_bytes(_lib.OP_PERMUTE, n)
+        small = 2 * ((4 * n + 255) // 256 * 256)
+        ws_full, ws_small = pfr.new_workspace(full, dev), pfr.new_workspace(small, dev)
+        for y in (0.0, 4.0):
+            w = torch.from_numpy(inputs.weights(n, y, seed=100 + int(y))).to(dev)
+            a = pfr.resample_metropolis(w, 60, seed=1)
+            s = pfr.resample_systematic(w, seed=1)
+            cases = {"unsorted_bucketed": lambda: pfr.permute_ancestors(a, out=out, workspace=ws_full),
+                     "unsorted_atomic": lambda: pfr.permute_ancestors(a, out=out, workspace=ws_small),
+                     "sorted": lambda: pfr.permute_ancestors(s, sorted_hint=True, out=out,
+                                                             workspace=ws_full)}
+            for name, fn in cases.items():
+                t = timed(fn)
+                rows.append({"log2n": lg, "y": y, "case": name, "us": t * 1e6,
+                             "hbm_frac_8B_per_particle": 8.0 * n / t / (HBM_PEAK_GBS * 1e9)})
+                log(f"  n=2^{lg} y={y:.0f} {name:18s} {t * 1e6:9.1f} us  "
+                    f"{100 * 8.0 * n / t / (HBM_PEAK_GBS * 1e9):.1f} % HBM")
+    print(json.dumps({"metric": "ancestor permutation on one vector", "unit": "us",
+                      "higher_is_better": False, "n_gpus": 1, "data": "synthetic",
+                      "config": {"workload": "Metropolis (B = 60) and systematic ancestries of "
+                                             "the bench weights, n = 2^" +
+                                             ",".join(map(str, args.permute_log2n))},
+                      "rows": rows}), flush=True)
+
+
 def filter_workload(args):
     """Bootstrap filter on x_t = 0.9 x_{t-1} + N(0,1), y_t = x_t + N(0, 0.5^2):
     1024 filters of 2^14 particles, T = 200 synthetic observations (seed 0); one
@@ -983,14 +1045,15 @@ def main():
     ap.add_argument("--no-cold", action="store_true",
                     help="skip the cold-cache variant of the step")
     ap.add_argument("--workload", choices=("step", "precision", "batch", "filter", "decision",
-                                              "aux", "philox", "scaling"),
+                                              "aux", "philox", "scaling", "permute"),
                     default="step",
                     help="step: the timed resampling step (default); precision: the bias "
                          "sweep over prefix-sum precision modes; batch: ragged batch of "
                          "4096 filters; filter: full bootstrap filter, 1024 x 2^14 x 200; "
                          "decision: fastest scheme per (N, y) and the Metropolis B*/C "
                          "trade-off; aux: the auxiliary exports; philox: 10 vs 7 Philox "
-                         "rounds; scaling: collective schemes at n = 2^20..2^26")
+                         "rounds; scaling: collective schemes at n = 2^20..2^26; permute: "
+                         "the ancestor permutation at n = 2^20..2^24")
     ap.add_argument("--filters", type=int, default=4096)
     ap.add_argument("--filters-ssm", type=int, default=1024)
     ap.add_argument("--filter-reps", type=int, default=3)
@@ -1001,6 +1064,7 @@ def main():
     ap.add_argument("--tradeoff-log2n", type=int, nargs="+", default=[12, 16, 20])
     ap.add_argument("--forms-log2n", type=int, nargs="+", default=[10, 14, 18, 20, 22, 24])
     ap.add_argument("--scaling-log2n", type=int, nargs="+", default=[20, 22, 24, 26])
+    ap.add_argument("--permute-log2n", type=int, nargs="+", default=[20, 22, 24])
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the resampling step here runs on a single MI355X "
@@ -1026,6 +1090,9 @@ def main():
         return
     if args.workload == "scaling":
         scaling_workload(args)
+        return
+    if args.workload == "permute":
+        permute_workload(args)
         return
 
     import torch

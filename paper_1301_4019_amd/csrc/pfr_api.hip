@@ -16,7 +16,8 @@ namespace {
 // Set by pfr_set_tuning, read by the launchers of any host thread: every
 // access holds the lock, and readers get a copy.
 std::mutex g_tuning_mu;
-Tuning g_tuning = {4096, 2048, 32, 1, 256, 256, 0, 128, 4096, 256, 16384};
+// the values the autotuner chose on MI355X (gfx950), also in tuning.json
+Tuning g_tuning = {4096, 512, 60, 1, 256, 2048, 0, 128, 2048, 512, 16384};
 }  // namespace
 
 Tuning tuning() {
@@ -608,15 +609,15 @@ void pfr_tuning_defaults(pfr_tuning* t) {
   if (!t) return;
   t->version = PFR_TUNING_VERSION;
   t->single_wg_max = 4096;
-  t->direct_max_blocks = 2048;
-  t->metropolis_table_min_B = 32;
+  t->direct_max_blocks = 512;
+  t->metropolis_table_min_B = 60;
   t->rejection_table = 1;
   t->rejection_per_wave = 256;
-  t->metropolis_chunk = 256;
+  t->metropolis_chunk = 2048;
   t->batch_scan_wg_max_len = 0;
   t->batch_stage_max_kb = 128;
-  t->batch_metropolis_chunk = 4096;
-  t->batch_rejection_per_wave = 256;
+  t->batch_metropolis_chunk = 2048;
+  t->batch_rejection_per_wave = 512;
   t->batch_permute_lds_max = 16384;
 }
 

@@ -108,10 +108,7 @@ __device__ __forceinline__ uint4 draw_uniform(Key key, uint32_t index, uint32_t 
 
 
 // u in (0, 1] on the 2^-32 lattice (accept tests).
-// ((double)x + 1) 2^-32 as one fused multiply-add (every step exact).
-__device__ __forceinline__ double u_accept(uint32_t x) {
-  return __fma_rn((double)x, 0x1p-32, 0x1p-32);
-}
+__device__ __forceinline__ double u_accept(uint32_t x) { return ((double)x + 1.0) * 0x1p-32; }
 // u in [0, 1) on the 2^-32 lattice (stratum offsets).
 __device__ __forceinline__ double u_offset(uint32_t x) { return (double)x * 0x1p-32; }
 // j uniform on [0, n): high 64 bits of the 64x64-bit product.
