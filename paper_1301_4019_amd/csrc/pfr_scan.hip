@@ -348,6 +348,8 @@ __global__ __launch_bounds__(kT) void k_carry_groups(uint32_t nb, uint32_t nbe, 
 #pragma unroll
   for (int k = 0; k < kGPer; ++k)
     if (j0 + k < m) out[j0 + k] = before + x[k];
+  // a single group is its own last group: no count, no fences
+  const bool single = G + (MULTI ? Ge : 0u) == 1u;
   if (tid == 0) {
     CarryGroup c;
     c.T = total;
@@ -356,14 +358,18 @@ __global__ __launch_bounds__(kT) void k_carry_groups(uint32_t nb, uint32_t nbe, 
     c.bad = bad;
     c.pad = 0;
     (weights ? groups : egroups)[g] = c;
-    // the last group to finish (the records pass zeroed the count) runs the
-    // top level: release this group's record, count it, acquire the others
-    __threadfence();
-    s_last = atomicAdd(&hdr->groups_done, 1u) == G + (MULTI ? Ge : 0u) - 1u ? 1u : 0u;
+    if (!single) {
+      // the last group to finish (the records pass zeroed the count) runs the
+      // top level: release this group's record, count it, acquire the others
+      __threadfence();
+      s_last = atomicAdd(&hdr->groups_done, 1u) == G + (MULTI ? Ge : 0u) - 1u ? 1u : 0u;
+    }
   }
   __syncthreads();
-  if (!s_last) return;
-  __threadfence();
+  if (!single) {
+    if (!s_last) return;
+    __threadfence();
+  }
   carry_top<MULTI>(nb, G, Ge, groups, egroups, Tx, TEx, hdr, s_u, s_w);
 }
 
