@@ -90,6 +90,8 @@ typedef enum {
 #define PFR_FLAG_BAD_WEIGHTS 8u  /* a weight is negative, NaN or infinite: output is the identity */
 #define PFR_FLAG_BAD_ANCESTOR 16u /* permute: an ancestor outside [0, n) is replaced by its own index */
 #define PFR_FLAG_BAD_STEP 32u    /* lgssm_step: step index t outside [1, T]; the state is left unchanged */
+#define PFR_FLAG_WMAX_BELOW 64u  /* checks on (pfr_set_checks): a weight exceeds rejection's w_max */
+#define PFR_FLAG_NOT_SORTED 128u /* checks on: sorted_hint given with a decreasing ancestry */
 
 /* Longest segment a batched collective call (n_filters > 1) accepts. */
 #define PFR_MAX_BATCH_SEGMENT (256 * 1024 - 1)
@@ -464,6 +466,28 @@ PFR_API int pfr_load_tuning(const char* path);
 PFR_API const char* pfr_status_string(int status);
 /* Library version, e.g. "0.1.0". */
 PFR_API const char* pfr_version(void);
+
+/* Precondition checks, for debugging (off by default).  The hot path does not
+ * test what the operations assume: finite, non-negative weights for
+ * resample_metropolis, resample_rejection and resample_partial_rejection (the
+ * collective schemes test them anyway), a w_max (or w_max_dev entry) at least
+ * every weight of its segment for resample_rejection (section 2.2: a smaller
+ * bound biases the output), and a non-decreasing ancestry inside every
+ * segment where sorted_hint != 0 (permute_ancestors,
+ * permute_ancestors_noalloc, ancestors_to_offspring).  With the checks on,
+ * these calls first enqueue one pass over their input that ORs each
+ * violation (PFR_FLAG_BAD_WEIGHTS, PFR_FLAG_WMAX_BELOW, PFR_FLAG_NOT_SORTED)
+ * into *dev_flags where the call has it and into a word the library keeps per
+ * GPU, and a sorted_hint is not relied on: the call takes the path for any
+ * ancestry, which gives the same result for sorted input and the defined
+ * result for any other.  Outputs of valid inputs are unchanged; the extra
+ * pass makes the calls slower.  The setting is process-wide. */
+PFR_API int pfr_set_checks(int32_t on);
+PFR_API int32_t pfr_get_checks(void);
+/* Waits for the stream, stores in *flags the violations recorded on the
+ * current GPU since the previous call (or since start-up) and clears them.
+ * It synchronises, so it is not for use under graph capture. */
+PFR_API int pfr_take_check_flags(void* stream, uint32_t* flags);
 
 /* Rounds of the Philox4x32 generator this library was built with: 10 (the
  * generator named above) unless a study build chose another count. */

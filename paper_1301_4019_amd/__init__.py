@@ -19,7 +19,7 @@ import os
 
 from . import _lib
 from ._lib import (FLAG_BAD_ANCESTOR, FLAG_BAD_COUNTS, FLAG_BAD_STEP, FLAG_BAD_WEIGHTS,
-                   FLAG_TRIAL_CAP,
+                   FLAG_NOT_SORTED, FLAG_TRIAL_CAP, FLAG_WMAX_BELOW,
                    FLAG_ZERO_TOTAL, MAX_BATCH_SEGMENT, SCAN_COMP_F32, SCAN_EXACT, SCAN_F64,
                    SCAN_NAIVE_F32, PfrError)
 
@@ -30,7 +30,8 @@ __all__ = [
     "LGSSMFilter", "get_tuning", "set_tuning", "default_tuning",
     "SCAN_EXACT", "SCAN_F64", "SCAN_COMP_F32", "SCAN_NAIVE_F32",
     "FLAG_ZERO_TOTAL", "FLAG_TRIAL_CAP", "FLAG_BAD_COUNTS", "FLAG_BAD_WEIGHTS",
-    "FLAG_BAD_ANCESTOR", "FLAG_BAD_STEP", "MAX_BATCH_SEGMENT",
+    "FLAG_BAD_ANCESTOR", "FLAG_BAD_STEP", "FLAG_WMAX_BELOW", "FLAG_NOT_SORTED",
+    "MAX_BATCH_SEGMENT", "set_checks", "get_checks", "take_check_flags",
 ]
 
 
@@ -41,6 +42,24 @@ def _torch():
 
 def version() -> str:
     return _lib.load().pfr_version().decode()
+
+
+def set_checks(on: bool) -> None:
+    """Turn the library's precondition checks on or off (process-wide)."""
+    _lib.check(_lib.load().pfr_set_checks(1 if on else 0), "set_checks")
+
+
+def get_checks() -> bool:
+    return bool(_lib.load().pfr_get_checks())
+
+
+def take_check_flags() -> int:
+    """Wait for the current stream; return and clear the FLAG_* bits that the
+    checks recorded on the current GPU."""
+    out = ctypes.c_uint32(0)
+    _lib.check(_lib.load().pfr_take_check_flags(_stream(), ctypes.byref(out)),
+               "take_check_flags")
+    return int(out.value)
 
 
 def get_tuning() -> dict:

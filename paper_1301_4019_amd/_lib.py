@@ -26,6 +26,8 @@ FLAG_BAD_COUNTS = 4
 FLAG_BAD_WEIGHTS = 8
 FLAG_BAD_ANCESTOR = 16
 FLAG_BAD_STEP = 32
+FLAG_WMAX_BELOW = 64
+FLAG_NOT_SORTED = 128
 MAX_BATCH_SEGMENT = 256 * 1024 - 1
 NOALLOC_MAX_N = 1 << 22
 
@@ -39,6 +41,7 @@ EXPORTS = (
     "lgssm_workspace_bytes", "lgssm_init", "lgssm_step",
     "pfr_tuning_defaults", "pfr_get_tuning", "pfr_set_tuning", "pfr_load_tuning",
     "pfr_status_string", "pfr_version", "pfr_philox_rounds",
+    "pfr_set_checks", "pfr_get_checks", "pfr_take_check_flags",
 )
 
 TUNING_VERSION = 2
@@ -127,6 +130,9 @@ def open_library(path: str) -> ctypes.CDLL:
         "pfr_status_string": (ctypes.c_char_p, [I]),
         "pfr_version": (ctypes.c_char_p, []),
         "pfr_philox_rounds": (I, []),
+        "pfr_set_checks": (I, [I32]),
+        "pfr_get_checks": (I32, []),
+        "pfr_take_check_flags": (I, [P, ctypes.POINTER(ctypes.c_uint32)]),
     }
     for name, (res, args) in sigs.items():
         fn = getattr(lib, name)

@@ -18,7 +18,7 @@ LIB = os.path.join(HERE, "libpfresample.so")
 BUILD_DIR = os.path.join(HERE, "_build")
 
 SOURCES = ["pfr_api.hip", "pfr_alt.hip", "pfr_scan.hip", "pfr_fscan.hip", "pfr_aux.hip", "pfr_filter.hip",
-           "pfr_util.hip"]
+           "pfr_util.hip", "pfr_check.hip"]
 
 ARCH = os.environ.get("PFR_OFFLOAD_ARCH", "gfx950")
 

@@ -5,6 +5,7 @@
 #include <stdlib.h>
 #include <string.h>
 
+#include <atomic>
 #include <mutex>
 
 #include "pfresample.h"
@@ -73,6 +74,21 @@ bool overlaps(const void* a, size_t abytes, const void* b, size_t bbytes) {
 }
 
 int launch_result(hipError_t e) { return e == hipSuccess ? PFR_OK : PFR_ELAUNCH; }
+
+// pfr_set_checks: the precondition checks run before the calls they cover.
+std::atomic<int> g_checks{0};
+bool checks_on() { return g_checks.load(std::memory_order_relaxed) != 0; }
+
+// With the checks on, a sorted_hint is tested and then not relied on: the
+// call takes the path for any ancestry, whose result is the same for sorted
+// input and the defined one for any other.
+int check_hint(const int32_t* a, const SegInfo& s, int32_t* sorted_hint, uint32_t* dev_flags,
+               void* stream) {
+  if (!checks_on() || !*sorted_hint) return PFR_OK;
+  *sorted_hint = 0;
+  return launch_result(
+      launch_check_sorted(a, s.n_total, s.offsets, s.n_filters, dev_flags, (hipStream_t)stream));
+}
 
 size_t lgssm_offsets_bytes(int32_t n_filters) {
   return (((size_t)n_filters + 1) * sizeof(int64_t) + 255) & ~(size_t)255;
@@ -249,16 +265,27 @@ int resample_metropolis(const void* w, pfr_dtype dtype, const pfr_segments* seg,
   if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), ancestors, (size_t)s.n_total * 4))
     return PFR_EINVAL;
   if (ws && !aligned256(ws)) return PFR_EWORKSPACE;
+  if (checks_on()) {
+    rc = launch_result(launch_check_weights(dtype == PFR_F64, w, s.n_total, s.offsets,
+                                            s.n_filters, false, 0.0, nullptr, nullptr,
+                                            (hipStream_t)stream));
+    if (rc) return rc;
+  }
   return launch_result(launch_metropolis(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters,
                                          s.max_len, B, B_dev, make_key(rng), rng.offset,
                                          rng.filter_base, ancestors, ws, ws ? ws_bytes : 0,
                                          (hipStream_t)stream));
 }
 
-int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, double w_max,
-                       const double* w_max_dev, uint32_t max_trials, pfr_rng rng,
-                       int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
-                       void* stream) {
+}  // extern "C"
+
+namespace {
+
+// resample_rejection, with the bound check of the precondition checks unless
+// the bound need not hold (partial rejection control)
+int rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, double w_max,
+              const double* w_max_dev, uint32_t max_trials, pfr_rng rng, int32_t* ancestors,
+              void* ws, size_t ws_bytes, uint32_t* dev_flags, void* stream, bool bounded) {
   SegInfo s;
   int rc = check_segments(seg, &s);
   if (rc) return rc;
@@ -270,11 +297,29 @@ int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, 
   if (overlaps(w, (size_t)s.n_total * dtype_size(dtype), ancestors, (size_t)s.n_total * 4))
     return PFR_EINVAL;
   if (ws && !aligned256(ws)) return PFR_EWORKSPACE;
+  if (checks_on()) {
+    rc = launch_result(launch_check_weights(dtype == PFR_F64, w, s.n_total, s.offsets,
+                                            s.n_filters, bounded, w_max, w_max_dev, dev_flags,
+                                            (hipStream_t)stream));
+    if (rc) return rc;
+  }
   return launch_result(launch_rejection(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters,
                                         s.max_len, w_max, w_max_dev, max_trials, make_key(rng),
                                         rng.offset, rng.filter_base, ancestors, dev_flags, ws,
                                         ws ? ws_bytes : 0,
                                         (hipStream_t)stream));
+}
+
+}  // namespace
+
+extern "C" {
+
+int resample_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg, double w_max,
+                       const double* w_max_dev, uint32_t max_trials, pfr_rng rng,
+                       int32_t* ancestors, void* ws, size_t ws_bytes, uint32_t* dev_flags,
+                       void* stream) {
+  return rejection(w, dtype, seg, w_max, w_max_dev, max_trials, rng, ancestors, ws, ws_bytes,
+                   dev_flags, stream, true);
 }
 
 int resample_partial_rejection(const void* w, pfr_dtype dtype, const pfr_segments* seg,
@@ -292,8 +337,8 @@ int resample_partial_rejection(const void* w, pfr_dtype dtype, const pfr_segment
         (w && overlaps(weights_out, wb, w, wb)))
       return PFR_EINVAL;
   }
-  rc = resample_rejection(w, dtype, seg, v_max, v_max_dev, max_trials, rng, ancestors, ws,
-                          ws_bytes, dev_flags, stream);
+  rc = rejection(w, dtype, seg, v_max, v_max_dev, max_trials, rng, ancestors, ws, ws_bytes,
+                 dev_flags, stream, false);
   if (rc || s.n_total == 0) return rc;
   return launch_result(launch_prc_weights(dtype == PFR_F64, w, s.n_total, s.offsets, s.n_filters,
                                           v_max, v_max_dev, ancestors, weights_out,
@@ -334,6 +379,8 @@ int permute_ancestors(const int32_t* ancestors, const pfr_segments* seg, int32_t
   if (overlaps(ws, need, permuted, (size_t)s.n_total * 4) ||
       overlaps(ws, need, ancestors, (size_t)s.n_total * 4))
     return PFR_EINVAL;
+  rc = check_hint(ancestors, s, &sorted_hint, dev_flags, stream);
+  if (rc) return rc;
   return launch_result(launch_permute(ancestors, s.n_total, s.offsets, s.n_filters, s.max_len,
                                       sorted_hint != 0, permuted, ws, need, dev_flags,
                                       (hipStream_t)stream));
@@ -392,6 +439,8 @@ int permute_ancestors_noalloc(const int32_t* ancestors, const pfr_segments* seg,
   void* ws = nullptr;
   rc = noalloc_scratch(&ws);
   if (rc) return rc;
+  rc = check_hint(ancestors, s, &sorted_hint, dev_flags, stream);
+  if (rc) return rc;
   return launch_result(launch_permute(ancestors, s.n_total, s.offsets, s.n_filters, s.max_len,
                                       sorted_hint != 0, permuted, ws, PFR_NOALLOC_SCRATCH_BYTES,
                                       dev_flags, (hipStream_t)stream));
@@ -406,6 +455,8 @@ int ancestors_to_offspring(const int32_t* ancestors, const pfr_segments* seg, in
   if (!ancestors || !offspring) return PFR_EINVAL;
   if (overlaps(ancestors, (size_t)s.n_total * 4, offspring, (size_t)s.n_total * 4))
     return PFR_EINVAL;
+  rc = check_hint(ancestors, s, &sorted_hint, dev_flags, stream);
+  if (rc) return rc;
   return launch_result(launch_ancestors_to_offspring(ancestors, s.n_total, s.offsets,
                                                      s.n_filters, s.max_len, sorted_hint != 0,
                                                      offspring, dev_flags,
@@ -752,6 +803,18 @@ const char* pfr_status_string(int status) {
 }
 
 const char* pfr_version(void) { return "0.1.0"; }
+
+int pfr_set_checks(int32_t on) {
+  g_checks.store(on ? 1 : 0, std::memory_order_relaxed);
+  return PFR_OK;
+}
+
+int32_t pfr_get_checks(void) { return checks_on() ? 1 : 0; }
+
+int pfr_take_check_flags(void* stream, uint32_t* flags) {
+  if (!flags) return PFR_EINVAL;
+  return launch_result(take_check_word((hipStream_t)stream, flags));
+}
 
 int pfr_philox_rounds(void) { return kPhiloxRounds; }
 

@@ -28,6 +28,8 @@ constexpr uint32_t FLAG_BAD_COUNTS = 4u;
 constexpr uint32_t FLAG_BAD_WEIGHTS = 8u;
 constexpr uint32_t FLAG_BAD_ANCESTOR = 16u;
 constexpr uint32_t FLAG_BAD_STEP = 32u;
+constexpr uint32_t FLAG_WMAX_BELOW = 64u;   // precondition checks only
+constexpr uint32_t FLAG_NOT_SORTED = 128u;  // precondition checks only
 
 // Philox key, and optionally the device word that holds the counter offset
 // (read when the kernel runs, so that a captured graph can advance it).

@@ -138,6 +138,16 @@ hipError_t launch_resolve(int64_t n_total, int32_t* c, void* ws, uint32_t* flags
 hipError_t launch_scan_claimed(int scheme, bool f64, const void* w, int64_t n, Key key,
                                uint32_t offset, uint32_t filter, int32_t* a, void* ws,
                                uint32_t* flags, int32_t* d, int32_t* e, hipStream_t stream);
+// Precondition checks (pfr_check.hip): OR violations into flags (may be null)
+// and into the library's per-GPU check word; take_check_word waits for the
+// stream, returns the word and clears it.
+hipError_t launch_check_weights(bool f64, const void* w, int64_t n_total, const int64_t* offsets,
+                                uint32_t n_filters, bool use_bound, double bound,
+                                const double* bound_dev, uint32_t* flags, hipStream_t stream);
+hipError_t launch_check_sorted(const int32_t* a, int64_t n_total, const int64_t* offsets,
+                               uint32_t n_filters, uint32_t* flags, hipStream_t stream);
+hipError_t take_check_word(hipStream_t stream, uint32_t* out);
+
 hipError_t launch_permute(const int32_t* a, int64_t n_total, const int64_t* offsets,
                           uint32_t n_filters, int64_t max_len, bool sorted, int32_t* c, void* ws,
                           size_t ws_bytes, uint32_t* flags, hipStream_t stream);
