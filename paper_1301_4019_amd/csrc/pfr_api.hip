@@ -1,6 +1,6 @@
 // pfr_api.hip -- the C ABI of libpfresample (declared in include/pfresample.h):
 // argument checks, workspace sizing and kernel launches.  Nothing here
-// allocates, frees or synchronises.
+// allocates or frees, and only pfr_take_check_flags synchronises.
 #include <stdio.h>
 #include <stdlib.h>
 #include <string.h>

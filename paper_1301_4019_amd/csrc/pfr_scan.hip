@@ -299,24 +299,14 @@ __device__ void carry_top(uint32_t nb, uint32_t G, uint32_t Ge,
   }
 }
 
-template <bool MULTI>
-__global__ __launch_bounds__(kT) void k_carry_groups(uint32_t nb, uint32_t nbe, uint32_t G,
-                                                     const BlockRec* __restrict__ recs,
-                                                     const uint64_t* __restrict__ esums,
-                                                     u128* __restrict__ P, u128* __restrict__ PE,
-                                                     CarryGroup* __restrict__ groups,
-                                                     CarryGroup* __restrict__ egroups,
-                                                     uint32_t Ge, u128* __restrict__ Tx,
-                                                     u128* __restrict__ TEx,
-                                                     ScanHeader* __restrict__ hdr) {
-  __shared__ u128 s_w[kNW];
-  __shared__ uint32_t s_u[2 * kNW];
-  __shared__ uint32_t s_last;
+// The group step: group g of the weight blocks (weights) or of the
+// exponential blocks; its scale, every block's prefix inside it and its
+// record.  All kT threads call it.
+__device__ void carry_group(bool weights, uint32_t g, uint32_t m,
+                            const BlockRec* __restrict__ recs,
+                            const uint64_t* __restrict__ esums, u128* __restrict__ out,
+                            CarryGroup* __restrict__ rec_out, u128* s_w, uint32_t* s_u) {
   const int tid = (int)threadIdx.x;
-  const bool weights = blockIdx.x < G;
-  if (!MULTI && !weights) return;  // (never: the grid has G workgroups then)
-  const uint32_t g = weights ? blockIdx.x : blockIdx.x - G;
-  const uint32_t m = weights ? nb : nbe;
   const uint32_t j0 = g * kGrp + (uint32_t)tid * kGPer;
   u128 x[kGPer];
   uint32_t key = 0xFFFFFFFFu, bad = 0;
@@ -344,12 +334,9 @@ __global__ __launch_bounds__(kT) void k_carry_groups(uint32_t nb, uint32_t nbe, 
   }
   u128 total;
   const u128 before = group_scan(x, s_w, &total);
-  u128* out = weights ? P : PE;
 #pragma unroll
   for (int k = 0; k < kGPer; ++k)
     if (j0 + k < m) out[j0 + k] = before + x[k];
-  // a single group is its own last group: no count, no fences
-  const bool single = G + (MULTI ? Ge : 0u) == 1u;
   if (tid == 0) {
     CarryGroup c;
     c.T = total;
@@ -357,22 +344,60 @@ __global__ __launch_bounds__(kT) void k_carry_groups(uint32_t nb, uint32_t nbe, 
     c.key = key;
     c.bad = bad;
     c.pad = 0;
-    (weights ? groups : egroups)[g] = c;
-    if (!single) {
-      // the last group to finish (the records pass zeroed the count) runs the
-      // top level: release this group's record, count it, acquire the others
-      __threadfence();
-      s_last = atomicAdd(&hdr->groups_done, 1u) == G + (MULTI ? Ge : 0u) - 1u ? 1u : 0u;
-    }
+    rec_out[g] = c;
   }
-  __syncthreads();
-  if (!single) {
-    if (!s_last) return;
-    __threadfence();
-  }
-  carry_top<MULTI>(nb, G, Ge, groups, egroups, Tx, TEx, hdr, s_u, s_w);
 }
 
+// With a single group in all (strata schemes up to 2^20 particles) its
+// workgroup goes on to the top level: no count and no fences.  Otherwise one
+// workgroup per group, and the last to finish runs the top level (measured:
+// one workgroup taking the three groups of a 2^20 multinomial call in turn,
+// 9.7 us, is slower than three in parallel with the count, 8.8 us).
+constexpr uint32_t kFewGroups = 1;
+
+template <bool MULTI>
+__global__ __launch_bounds__(kT) void k_carry_groups(uint32_t nb, uint32_t nbe, uint32_t G,
+                                                     const BlockRec* __restrict__ recs,
+                                                     const uint64_t* __restrict__ esums,
+                                                     u128* __restrict__ P, u128* __restrict__ PE,
+                                                     CarryGroup* __restrict__ groups,
+                                                     CarryGroup* __restrict__ egroups,
+                                                     uint32_t Ge, u128* __restrict__ Tx,
+                                                     u128* __restrict__ TEx,
+                                                     ScanHeader* __restrict__ hdr) {
+  __shared__ u128 s_w[kNW];
+  __shared__ uint32_t s_u[2 * kNW];
+  __shared__ uint32_t s_last;
+  if (G + (MULTI ? Ge : 0u) <= kFewGroups) {
+    for (uint32_t g = 0; g < G; ++g) {
+      carry_group(true, g, nb, recs, esums, P, groups, s_w, s_u);
+      __syncthreads();  // the scratch is reused; the group records are read by all
+    }
+    if (MULTI) {
+      for (uint32_t g = 0; g < Ge; ++g) {
+        carry_group(false, g, nbe, recs, esums, PE, egroups, s_w, s_u);
+        __syncthreads();
+      }
+    }
+    carry_top<MULTI>(nb, G, Ge, groups, egroups, Tx, TEx, hdr, s_u, s_w);
+    return;
+  }
+  const bool weights = blockIdx.x < G;
+  if (!MULTI && !weights) return;  // (never: the grid has G workgroups then)
+  const uint32_t g = weights ? blockIdx.x : blockIdx.x - G;
+  carry_group(weights, g, weights ? nb : nbe, recs, esums, weights ? P : PE,
+              weights ? groups : egroups, s_w, s_u);
+  if (threadIdx.x == 0) {
+    // the last group to finish (the records pass zeroed the count) runs the
+    // top level: release this group's record, count it, acquire the others
+    __threadfence();
+    s_last = atomicAdd(&hdr->groups_done, 1u) == G + (MULTI ? Ge : 0u) - 1u ? 1u : 0u;
+  }
+  __syncthreads();
+  if (!s_last) return;
+  __threadfence();
+  carry_top<MULTI>(nb, G, Ge, groups, egroups, Tx, TEx, hdr, s_u, s_w);
+}
 
 // The exact carry C_b of block b (0 <= b <= nb) from the two levels.
 struct Carries {
@@ -1511,7 +1536,9 @@ template <bool MULTI>
 hipError_t launch_carries(const CarrySet& c, ScanHeader* hdr, const BlockRec* recs,
                           const uint64_t* esums, hipStream_t stream) {
   const uint32_t G = c.C.G, Ge = MULTI ? c.CE.Ge : 0u;
-  hipLaunchKernelGGL((k_carry_groups<MULTI>), dim3(G + Ge), dim3(kT), 0, stream, c.C.nb,
+  // one workgroup for all groups when there are few
+  const uint32_t grid = G + Ge <= kFewGroups ? 1u : G + Ge;
+  hipLaunchKernelGGL((k_carry_groups<MULTI>), dim3(grid), dim3(kT), 0, stream, c.C.nb,
                      c.CE.nbe, G, recs, esums, (u128*)c.C.P, (u128*)c.CE.PE, c.groups,
                      c.egroups, Ge, (u128*)c.C.Tx, (u128*)c.CE.TEx, hdr);
   return hipGetLastError();
