@@ -98,6 +98,16 @@ def test_collective_long_vectors(scheme, n):
     check_collective(scheme, w.astype(np.float64), a, seed=5, filt=0)
 
 
+def test_collective_long_vector_float64():
+    """binary64 weights over 8193 blocks (nine carry groups, the last with a
+    single block): the quantisation of binary64 weights at the block scale and
+    their group conversion on a long vector."""
+    n = (1 << 23) + 999
+    w = inputs.weights(n, 1.0, seed=4, dtype=np.float64)
+    a = host(pfr().resample_systematic(torch.from_numpy(w).cuda(), seed=6))
+    check_collective("systematic", w, a, seed=6, filt=0)
+
+
 @pytest.mark.parametrize("scheme", ["systematic", "stratified", "multinomial"])
 def test_collective_carry_groups_of_different_scales(scheme):
     """Four carry groups (1024 weight blocks each) of very different
