@@ -201,7 +201,9 @@ def batch_tune(torch, pfr, inputs, timer, chosen, meas, with_tuning, same, log):
     """Launch shapes of the ragged-batch kernels, each checked bit for bit
     against the first candidate.  The collective threshold is measured per
     bucket of the longest segment (batches of 4096 vectors with lengths
-    log-uniform up to 2^10 .. 2^16), the others on the full config-4 batch."""
+    log-uniform up to 2^10 .. 2^16), the others on the full 4096-vector batch;
+    the Metropolis chunk also on the filter step's shape (1024 vectors of 2^14
+    particles, short chains), since one value serves both."""
     from . import _lib
 
     def batch(hi_log2, seed=0):
@@ -274,8 +276,43 @@ def batch_tune(torch, pfr, inputs, timer, chosen, meas, with_tuning, same, log):
         metro()
         rej()
 
+    # the filter step's shape: 1024 vectors of 2^14 particles with the short
+    # chains of moderate weight sets (y_f ~ U[0, 1.5), B of eq. (B))
+    g = np.random.default_rng(1)
+    fy = g.uniform(0.0, 1.5, 1024)
+    fw = torch.from_numpy(np.concatenate(
+        [inputs.weights(1 << 14, float(y), seed=f + 1) for f, y in enumerate(fy)])).cuda()
+    foff = torch.arange(0, 1025, dtype=torch.int64, device="cuda") * (1 << 14)
+    fB = torch.tensor([_b_star(float(y)) for y in fy], dtype=torch.int32, device="cuda")
+    both_f = torch.empty(fw.numel() + w.numel(), dtype=torch.int32, device="cuda")
+
+    def metro_filter():
+        pfr.resample_metropolis(fw, 0, seed=1, B_per_filter=fB, offsets=foff, max_len=1 << 14,
+                                out=both_f[:fw.numel()])
+
+    def pick_shared(name, cands, fns, result):
+        """One value for several workloads: the smallest sum over the
+        workloads of the time relative to that workload's best candidate."""
+        rows, ref = {}, None
+        for c in cands:
+            ts = [with_tuning({name: c}, lambda: timer(fn)) for fn in fns]
+            if ref is None:
+                ref = result.clone()
+            same(result, ref, name)
+            rows[c] = ts
+            log(f"{name} {c}: " + ", ".join(f"{t:.4f} ms" for t in ts))
+        best = [min(r[i] for r in rows.values()) for i in range(len(fns))]
+        score = {c: sum(t / b for t, b in zip(ts, best)) for c, ts in rows.items()}
+        chosen[name] = min(score, key=score.get)
+        meas[name] = {c: {"ms": ts, "score": score[c]} for c, ts in rows.items()}
+
+    def metro_ragged():
+        pfr.resample_metropolis(w, 0, seed=1, B_per_filter=B, offsets=off, max_len=max_len,
+                                out=both_f[fw.numel():])
+
     pick("batch_stage_max_kb", (128, 64, 16), alt_both, both)
-    pick("batch_metropolis_chunk", (1024, 2048, 4096, 8192, 16384), metro, out_m)
+    pick_shared("batch_metropolis_chunk", (1024, 2048, 4096, 8192, 16384),
+                (metro_ragged, metro_filter), both_f)
     pick("batch_rejection_per_wave", (64, 128, 256, 512, 1024), rej, out)
 
     a_unsorted = torch.empty_like(out)
