@@ -31,8 +31,10 @@ Tuning tuning();  // a copy of the current settings (thread-safe)
 // Collective schemes handled by the scan kernels.
 enum Scheme : int { SCHEME_MULTINOMIAL = 0, SCHEME_STRATIFIED = 1, SCHEME_SYSTEMATIC = 2 };
 
-// Canonical quantisation block of the exact prefix sums: 1024 weights, held
-// by one workgroup of kWGThreads = 256 threads, 4 consecutive weights each.
+// Canonical quantisation block of the exact prefix sums: 1024 weights.  The
+// single-vector kernels give a block to one wave (16 consecutive weights per
+// lane); the one-workgroup-per-segment and floating-point kernels to one
+// workgroup of kWGThreads = 256 threads, 4 consecutive weights each.
 constexpr int kBlock = 1024;
 constexpr int kBlocksPerWG = 4;
 constexpr int kWGThreads = kWave * kBlocksPerWG;
