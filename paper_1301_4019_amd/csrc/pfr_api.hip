@@ -18,7 +18,7 @@ namespace {
 // access holds the lock, and readers get a copy.
 std::mutex g_tuning_mu;
 // the values the autotuner chose on MI355X (gfx950), also in tuning.json
-Tuning g_tuning = {4096, 0, 60, 1, 256, 2048, 0, 128, 8192, 512, 16384};
+Tuning g_tuning = {4096, 256, 60, 1, 256, 2048, 0, 128, 8192, 512, 16384};
 }  // namespace
 
 Tuning tuning() {
@@ -660,7 +660,7 @@ void pfr_tuning_defaults(pfr_tuning* t) {
   if (!t) return;
   t->version = PFR_TUNING_VERSION;
   t->single_wg_max = 4096;
-  t->direct_max_blocks = 0;
+  t->direct_max_blocks = 256;
   t->metropolis_table_min_B = 60;
   t->rejection_table = 1;
   t->rejection_per_wave = 256;

@@ -1033,52 +1033,43 @@ __global__ __launch_bounds__(kT) void k_scan_records_w(const T* __restrict__ w, 
   }
 }
 
-// Direct carries for the four blocks b0 .. b0 + 3 of a workgroup: every
-// workgroup reduces all records itself (at most kDirectMax), which saves the
-// carries launch for short vectors.
-struct Direct4 {
-  u128 C[kWavesPerWG + 1], Q;
+// Direct carries of block b by its own wave: the global scale, the block's
+// exact carry and the total from all nb records, read by the wave in two
+// lane-strided passes and summed by DPP scans, with no workgroup barrier and
+// no LDS.  Every record is converted straight to the global scale (the
+// carries pass converts a group's sums to the group's scale first, which
+// gives the same values when there is one group of 1024 blocks).
+struct DirectW {
+  u128 Cb, Cb1, Q;
   int32_t gscale;
   uint32_t status;
 };
 
-__device__ Direct4 direct_carries4(uint32_t nb, uint32_t b0, const BlockRec* __restrict__ recs,
-                                   WgScratch* s) {
-  const int tid = (int)threadIdx.x;
-  BlockRec r[8];
-  uint32_t bad = 0, smin_key = 0xFFFFFFFFu;
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint32_t j = (uint32_t)tid + (uint32_t)k * kT;
-    if (j < nb) r[k] = recs[j];
-    else r[k].sum = 0, r[k].scale = 0, r[k].bad = 0;
+__device__ DirectW wave_direct_carries(uint32_t nb, uint32_t b,
+                                       const BlockRec* __restrict__ recs) {
+  const uint32_t lane = lane_id();
+  uint32_t bad = 0, key = 0xFFFFFFFFu;
+  for (uint32_t j = lane; j < nb; j += kWave) {
+    const BlockRec r = recs[j];
+    bad |= r.bad;
+    if (r.sum) key = min(key, (uint32_t)r.scale ^ 0x80000000u);
   }
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    bad |= r[k].bad;
-    if (r[k].sum) smin_key = min(smin_key, (uint32_t)r[k].scale ^ 0x80000000u);
-  }
-  bad = wg_reduce(bad, OpOr(), (uint32_t*)s->i);
-  smin_key = wg_reduce(smin_key, OpMin(), (uint32_t*)s->i);
-  Direct4 d;
-  d.gscale = (smin_key == 0xFFFFFFFFu)
+  bad = wave_reduce(bad, OpOr());
+  key = wave_reduce(key, OpMin());
+  DirectW d;
+  d.gscale = key == 0xFFFFFFFFu
                  ? 0
-                 : (int32_t)(smin_key ^ 0x80000000u) + (kCarryBits - 63) - ceil_log2(nb);
-  u128 before = 0, all = 0, own[kWavesPerWG] = {0, 0, 0, 0};
-#pragma unroll
-  for (int k = 0; k < 8; ++k) {
-    const uint32_t j = (uint32_t)tid + (uint32_t)k * kT;
-    const u128 v = (j < nb) ? conv_rec(r[k], d.gscale) : (u128)0;
+                 : (int32_t)(key ^ 0x80000000u) + (kCarryBits - 63) - ceil_log2(nb);
+  u128 before = 0, all = 0, own = 0;
+  for (uint32_t j = lane; j < nb; j += kWave) {
+    const u128 v = conv_rec(recs[j], d.gscale);
     all += v;
-    if (j < b0) before += v;
-#pragma unroll
-    for (int q = 0; q < kWavesPerWG; ++q)
-      if (j == b0 + (uint32_t)q) own[q] = v;
+    before += j < b ? v : (u128)0;
+    own += j == b ? v : (u128)0;
   }
-  d.C[0] = wg_reduce(before, OpAdd(), s->v);
-  d.Q = wg_reduce(all, OpAdd(), s->v);
-#pragma unroll
-  for (int q = 0; q < kWavesPerWG; ++q) d.C[q + 1] = d.C[q] + wg_reduce(own[q], OpAdd(), s->v);
+  d.Q = readlane(wave_incl_add_u128(all), kWave - 1);
+  d.Cb = readlane(wave_incl_add_u128(before), kWave - 1);
+  d.Cb1 = d.Cb + readlane(wave_incl_add_u128(own), kWave - 1);
   d.status = bad;
   if (!bad && d.Q == 0) d.status |= FLAG_ZERO_TOTAL;
   return d;
@@ -1103,11 +1094,11 @@ __global__ __launch_bounds__(kT) void k_scan_emit_w(const T* __restrict__ w, int
   u128 Cb, Cb1, Q;
   int32_t gscale;
   if (DIRECT) {
-    __shared__ WgScratch s;
-    const Direct4 d = direct_carries4(nb, blockIdx.x * kWavesPerWG, recs, &s);
+    if (b >= nb) return;
+    const DirectW d = wave_direct_carries(nb, b, recs);
     status = d.status;
-    Cb = d.C[wave];
-    Cb1 = d.C[wave + 1];
+    Cb = d.Cb;
+    Cb1 = d.Cb1;
     Q = d.Q;
     gscale = d.gscale;
   } else {
