@@ -56,11 +56,11 @@ GATHER_CEILING_PER_S = 2.65e11
 # HBM bytes per launch of the dominant kernel (FETCH_SIZE x 2.0 + WRITE_SIZE x 1.0 from
 # two rocprofv3 --pmc passes, scaled by a 256 MiB copy; profiles/metropolis_table_n2p20_pmc.md).
 # Set to None when the kernel changes until the counters are taken again.
-DOMINANT_TRAFFIC_BYTES = (43.4 + 4.0) * (1 << 20)
+DOMINANT_TRAFFIC_BYTES = (42.5 + 4.0) * (1 << 20)
 # VALU instructions per lane and Metropolis step of the dominant kernel (SQ_INSTS_VALU x 64 /
 # steps, same profile; None when the kernel changes), against the lane-instruction rate of
 # 256 CUs x 4 SIMDs x 16 lanes at 2.4 GHz.
-DOMINANT_VALU_PER_STEP = 45.6
+DOMINANT_VALU_PER_STEP = 44.5
 LANE_INSTR_PER_S = 256 * 4 * 16 * 2.4e9
 
 

@@ -257,24 +257,28 @@ struct BoundTable {
   }
 };
 
-// Workgroup prologue: the largest code from the per-workgroup maxima and the
-// 4-bit table in LDS.
-__device__ BoundTable load_bound_table(const uint8_t* __restrict__ codes,
-                                       const uint32_t* __restrict__ wg_max, uint32_t n_wg,
-                                       uint32_t nb, int shift, uint8_t* nib, uint32_t* slot) {
+// The 4-bit table, packed once per call: every workgroup takes the largest
+// code from the per-workgroup maxima of k_bound_codes, each thread packs 8
+// codes into one word (the code array is padded to a multiple of 8; the
+// padding is never looked up), and workgroup 0 stores the largest code.
+constexpr int kPackThreads = 256;
+
+__global__ __launch_bounds__(kPackThreads) void k_pack_table(const uint8_t* __restrict__ codes,
+                                                             const uint32_t* __restrict__ wg_max,
+                                                             uint32_t n_wg, uint32_t nb,
+                                                             uint32_t* __restrict__ nib,
+                                                             uint32_t* __restrict__ cm_out) {
+  __shared__ uint32_t slot[kPackThreads / kWave];
   uint32_t m = 0;
-  for (uint32_t k = threadIdx.x; k < n_wg; k += blockDim.x) m = wg_max[k] > m ? wg_max[k] : m;
+  for (uint32_t k = threadIdx.x; k < n_wg; k += kPackThreads) m = wg_max[k] > m ? wg_max[k] : m;
   m = wave_reduce(m, OpMax());
   if (lane_id() == 0) slot[threadIdx.x / kWave] = m;
   __syncthreads();
   uint32_t cM = slot[0];
-  for (uint32_t k = 1; k < blockDim.x / kWave; ++k) cM = slot[k] > cM ? slot[k] : cM;
-  // 8 codes per thread and pass (the code array is padded to a multiple of 8;
-  // the padding is never looked up)
-  const uint2* __restrict__ c8 = reinterpret_cast<const uint2*>(codes);
-  uint32_t* nib32 = reinterpret_cast<uint32_t*>(nib);
-  for (uint32_t p = threadIdx.x; 8 * p < nb; p += blockDim.x) {
-    const uint2 v = c8[p];
+  for (int k = 1; k < kPackThreads / kWave; ++k) cM = slot[k] > cM ? slot[k] : cM;
+  const uint32_t p = blockIdx.x * kPackThreads + threadIdx.x;
+  if (8 * p < nb) {
+    const uint2 v = reinterpret_cast<const uint2*>(codes)[p];
     uint32_t packed = 0;
 #pragma unroll
     for (int q = 0; q < 8; ++q) {
@@ -282,8 +286,21 @@ __device__ BoundTable load_bound_table(const uint8_t* __restrict__ codes,
       const uint32_t d = c > cM ? 15u : (cM - c > 15u ? 15u : cM - c);
       packed |= d << (4 * q);
     }
-    nib32[p] = packed;
+    nib[p] = packed;
   }
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cm_out = cM;
+}
+
+// Workgroup prologue: the packed table copied into LDS with 16-byte loads (the
+// packed array is padded to a multiple of 16 bytes).
+__device__ BoundTable load_bound_table(const uint32_t* __restrict__ nib_g,
+                                       const uint32_t* __restrict__ cm, uint32_t nb, int shift,
+                                       uint8_t* nib) {
+  const uint32_t n4 = (nb + 31) / 32;  // 16-byte pieces (32 nibbles each)
+  const uint4* __restrict__ src = reinterpret_cast<const uint4*>(nib_g);
+  uint4* dst = reinterpret_cast<uint4*>(nib);
+  for (uint32_t p = threadIdx.x; p < n4; p += blockDim.x) dst[p] = src[p];
+  const uint32_t cM = *cm;
   __syncthreads();
   BoundTable t;
   t.nib = nib;
@@ -302,12 +319,11 @@ __device__ BoundTable load_bound_table(const uint8_t* __restrict__ codes,
 template <typename T, int K>
 __global__ __launch_bounds__(kTableThreads) void k_metropolis_table(
     const T* __restrict__ w, int64_t n, int32_t B, Key key, uint32_t offset, uint32_t filter,
-    int32_t* __restrict__ a, int64_t chunk, const uint8_t* __restrict__ codes,
-    const uint32_t* __restrict__ wg_max, uint32_t n_wg, uint32_t nb, int shift) {
-  __shared__ uint8_t nib[kTableBuckets / 2];
-  __shared__ uint32_t slot[kTableThreads / kWave];
+    int32_t* __restrict__ a, int64_t chunk, const uint32_t* __restrict__ nib_g,
+    const uint32_t* __restrict__ cm, uint32_t nb, int shift) {
+  __shared__ __align__(16) uint8_t nib[kTableBuckets / 2];
   offset = counter_offset(key, offset);
-  const BoundTable tab = load_bound_table(codes, wg_max, n_wg, nb, shift, nib, slot);
+  const BoundTable tab = load_bound_table(nib_g, cm, nb, shift, nib);
   // n * sizeof(T) < 2^31 (checked by the launcher)
   const __amdgpu_buffer_rsrc_t wv = buffer_view(w, (uint32_t)(n * (int64_t)sizeof(T)));
   const int64_t p0 = (int64_t)blockIdx.x * chunk;
@@ -648,12 +664,11 @@ template <typename T>
 __global__ __launch_bounds__(kTableThreads) void k_rejection_table(
     const T* __restrict__ w, int64_t n, double w_max, uint32_t max_trials, Key key,
     uint32_t offset, uint32_t filter, int32_t* __restrict__ a, uint32_t* __restrict__ flags,
-    int64_t chunk, const uint8_t* __restrict__ codes, const uint32_t* __restrict__ wg_max,
-    uint32_t n_wg, uint32_t nb, int shift) {
-  __shared__ uint8_t nib[kTableBuckets / 2];
-  __shared__ uint32_t slot[kTableThreads / kWave];
+    int64_t chunk, const uint32_t* __restrict__ nib_g, const uint32_t* __restrict__ cm,
+    uint32_t nb, int shift) {
+  __shared__ __align__(16) uint8_t nib[kTableBuckets / 2];
   offset = counter_offset(key, offset);
-  const BoundTable tab = load_bound_table(codes, wg_max, n_wg, nb, shift, nib, slot);
+  const BoundTable tab = load_bound_table(nib_g, cm, nb, shift, nib);
   constexpr int kWaves = kTableThreads / kWave;
   const int wave = (int)threadIdx.x / kWave;
   const int64_t p0 = (int64_t)blockIdx.x * chunk;
@@ -763,7 +778,7 @@ hipError_t launch_metropolis_t(const void* wv, int64_t n_total, const int64_t* o
 struct TableGeom {
   int shift;
   uint32_t nb, n_wg;
-  size_t wg_off, codes_off, bytes;
+  size_t wg_off, codes_off, nib_off, cm_off, bytes;
 };
 
 TableGeom table_geom(int64_t n) {
@@ -774,7 +789,10 @@ TableGeom table_geom(int64_t n) {
   g.n_wg = (g.nb + kCodeThreads - 1) / kCodeThreads;
   g.wg_off = 0;
   g.codes_off = ((size_t)g.n_wg * 4 + 255) & ~(size_t)255;
-  g.bytes = g.codes_off + (((size_t)g.nb + 7) / 8 * 8 + 255) / 256 * 256;
+  g.nib_off = g.codes_off + (((size_t)g.nb + 7) / 8 * 8 + 255) / 256 * 256;
+  // packed nibbles, padded to 16-byte pieces; then the largest code
+  g.cm_off = g.nib_off + (((size_t)g.nb + 31) / 32 * 16 + 255) / 256 * 256;
+  g.bytes = g.cm_off + 256;
   return g;
 }
 
@@ -801,6 +819,11 @@ hipError_t launch_bound_codes(const T* w, int64_t n, const TableGeom& g, void* w
   char* base = (char*)ws;
   hipLaunchKernelGGL(k_bound_codes<T>, dim3(g.n_wg), dim3(kCodeThreads), 0, stream, w, n, g.shift,
                      (uint8_t*)(base + g.codes_off), (uint32_t*)(base + g.wg_off));
+  const uint32_t words = (g.nb + 7) / 8;
+  hipLaunchKernelGGL(k_pack_table, dim3((words + kPackThreads - 1) / kPackThreads),
+                     dim3(kPackThreads), 0, stream, (const uint8_t*)(base + g.codes_off),
+                     (const uint32_t*)(base + g.wg_off), g.n_wg, g.nb,
+                     (uint32_t*)(base + g.nib_off), (uint32_t*)(base + g.cm_off));
   return hipGetLastError();
 }
 
@@ -816,19 +839,19 @@ hipError_t launch_metropolis_table(const T* w, int64_t n, int32_t B, Key key, ui
   const int64_t chunk = (n + kTableGrid - 1) / kTableGrid;
   char* base = (char*)ws;
   const dim3 grid((unsigned)((n + chunk - 1) / chunk));
-  const uint8_t* codes = (const uint8_t*)(base + g.codes_off);
-  const uint32_t* wg_max = (const uint32_t*)(base + g.wg_off);
+  const uint32_t* nib = (const uint32_t*)(base + g.nib_off);
+  const uint32_t* cm = (const uint32_t*)(base + g.cm_off);
   // chains per lane: as many as the chunk fills (four from 2^20 particles up);
   // more than that would run copies of dead chains on every lane
   if (chunk <= kTableThreads)
     hipLaunchKernelGGL((k_metropolis_table<T, 1>), grid, dim3(kTableThreads), 0, stream, w, n, B,
-                       key, offset, filter, a, chunk, codes, wg_max, g.n_wg, g.nb, g.shift);
+                       key, offset, filter, a, chunk, nib, cm, g.nb, g.shift);
   else if (chunk <= 2 * kTableThreads)
     hipLaunchKernelGGL((k_metropolis_table<T, 2>), grid, dim3(kTableThreads), 0, stream, w, n, B,
-                       key, offset, filter, a, chunk, codes, wg_max, g.n_wg, g.nb, g.shift);
+                       key, offset, filter, a, chunk, nib, cm, g.nb, g.shift);
   else
     hipLaunchKernelGGL((k_metropolis_table<T, 4>), grid, dim3(kTableThreads), 0, stream, w, n, B,
-                       key, offset, filter, a, chunk, codes, wg_max, g.n_wg, g.nb, g.shift);
+                       key, offset, filter, a, chunk, nib, cm, g.nb, g.shift);
   return hipGetLastError();
 }
 
@@ -917,8 +940,8 @@ hipError_t launch_rejection_table(const T* w, int64_t n, double w_max, uint32_t 
   char* base = (char*)ws;
   hipLaunchKernelGGL(k_rejection_table<T>, dim3((unsigned)((n + chunk - 1) / chunk)),
                      dim3(kTableThreads), 0, stream, w, n, w_max, max_trials, key, offset, filter,
-                     a, flags, chunk, (const uint8_t*)(base + g.codes_off),
-                     (const uint32_t*)(base + g.wg_off), g.n_wg, g.nb, g.shift);
+                     a, flags, chunk, (const uint32_t*)(base + g.nib_off),
+                     (const uint32_t*)(base + g.cm_off), g.nb, g.shift);
   return hipGetLastError();
 }
 
