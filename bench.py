@@ -5,8 +5,8 @@ x_i ~ N(0,1), for each y in {0, 1, 2, 3, 4}; each weight set is resampled by
 all five resamplers -- multinomial, stratified, systematic (exact prefix sums),
 Metropolis with B from the bias bound (eps = 1/100, beta = E[w]/w_max, giving
 B = 4, 6, 16, 60, 354), rejection with w_max = 1 -- and every ancestry is then
-permuted for in-place propagation (for stratified and systematic the claim
-pass of the permutation is fused into the emission: resample_permuted).
+permuted for in-place propagation (for the three collective schemes the
+claim pass of the permutation is fused into the emission: resample_permuted).
 That is 25 resamples of 2^20 particles per step; inputs are resident in HBM
 before the timed region.
 
@@ -41,7 +41,7 @@ YS = (0.0, 1.0, 2.0, 3.0, 4.0)
 SCHEMES = ("multinomial", "stratified", "systematic", "metropolis", "rejection")
 # schemes whose claim pass of the permutation is fused into the resampler
 # (resample_permuted); the others run resample_<scheme> then permute_ancestors
-FUSED = ("stratified", "systematic")
+FUSED = ("multinomial", "stratified", "systematic")
 HBM_PEAK_GBS = 8000.0
 # Philox4x32-10 per call: 20 32x32->64-bit products (one v_mad_u64_u32 each)
 # and 20 three-input xors (one v_bitop3_b32 each) = 40 VALU instructions per

@@ -279,7 +279,7 @@ PFR_API size_t pfr_resample_permuted_workspace_bytes(pfr_op scheme, const pfr_se
  * Code 10 permutation to `permuted`, bit for bit what resample_<scheme>
  * followed by permute_ancestors (sorted_hint set for the collective schemes)
  * would write, with the same flags.  For a long single vector of the exact
- * stratified or systematic scheme the emission writes the claim vector and
+ * multinomial, stratified or systematic scheme the emission writes the claim vector and
  * the marked ancestry itself, so only the resolve pass follows; the other
  * cases run the two steps one after the other (claiming inside Metropolis and
  * rejection, with atomics beside their random weight loads, measured slower

@@ -540,11 +540,13 @@ int resample_permuted(pfr_op scheme, const void* w, pfr_dtype dtype, const pfr_s
   const bool sorted_out = scheme <= PFR_OP_SYSTEMATIC;  // collective schemes
   const hipStream_t st = (hipStream_t)stream;
   // the claim fused into the emission: long single vectors of the exact
-  // stratified and systematic schemes (shorter ones are permuted in LDS)
-  if (s.n_filters == 1 && (scheme == PFR_OP_STRATIFIED || scheme == PFR_OP_SYSTEMATIC) &&
-      params->precision == PFR_SCAN_EXACT && uses_scan_workspace(s) && s.n_total > 1024) {
-    rc = launch_result(launch_scan_claimed(scheme == PFR_OP_STRATIFIED ? SCHEME_STRATIFIED
-                                                                       : SCHEME_SYSTEMATIC,
+  // collective schemes, whose ancestries are sorted (shorter ones are
+  // permuted in LDS)
+  if (s.n_filters == 1 && sorted_out && params->precision == PFR_SCAN_EXACT &&
+      uses_scan_workspace(s) && s.n_total > 1024) {
+    rc = launch_result(launch_scan_claimed(scheme == PFR_OP_MULTINOMIAL   ? SCHEME_MULTINOMIAL
+                                           : scheme == PFR_OP_STRATIFIED ? SCHEME_STRATIFIED
+                                                                         : SCHEME_SYSTEMATIC,
                                            dtype == PFR_F64, w, s.n_total, make_key(rng),
                                            rng.offset, rng.filter_base, ancestors, rws, dev_flags,
                                            permute_claims(ws), permute_marks(ws, s.n_total), st));

@@ -908,11 +908,14 @@ __device__ __forceinline__ void emit_multi_wave(const T* __restrict__ w, int64_t
                                                 int32_t gscale, u128 Q, Key key, uint32_t filter,
                                                 uint32_t offset, CEPtr CE, uint32_t nbe,
                                                 const uint64_t* __restrict__ evals,
-                                                int32_t* __restrict__ a_out, MultiWaveLds* L) {
+                                                int32_t* __restrict__ a_out, MultiWaveLds* L,
+                                                int32_t* __restrict__ d_out = nullptr,
+                                                int32_t* __restrict__ e_out = nullptr) {
   const int lane = (int)lane_id();
+  const int cnt = (int)min((int64_t)kBlock, n - P0);
   BlockR R;
   block_r_wave(w, n, P0, rec, Cb, Cb1, gscale, Q, R, L->M);
-  if (!(R.hi > R.lo)) return;  // an empty range has no outputs
+  if (!(R.hi > R.lo) && !d_out) return;  // an empty range has no outputs
   const RMap em = make_rmap(CE[nbe], n);
   const double ce = em.Nd * em.invQ;
   const uint32_t e_first = (uint32_t)__builtin_amdgcn_readfirstlane(exp_block_of(R.lo, n, CE, nbe, em));
@@ -1001,7 +1004,14 @@ __device__ __forceinline__ void emit_multi_wave(const T* __restrict__ w, int64_t
   Op[0] = wave_shift_up_u32(O[kWPer - 1], O_lo);
 #pragma unroll
   for (int v = 1; v < kWPer; ++v) Op[v] = O[v - 1];
-  expand_wave(O, Op, O_lo, O_hi, P0, n, a_out, L->M, nullptr);
+  if (d_out) {  // the ancestry is sorted: the sorted claim, as the strata schemes form it
+#pragma unroll
+    for (int v = 0; v < kWPer; ++v) {
+      const int i = lane * kWPer + v;
+      if (i < cnt) d_out[P0 + i] = O[v] > Op[v] ? (int32_t)Op[v] : (int32_t)n;
+    }
+  }
+  expand_wave(O, Op, O_lo, O_hi, P0, n, a_out, L->M, e_out);
 }
 
 // Weight records, one block per wave (blockIdx.x < wgs_b), and for the
@@ -1128,7 +1138,9 @@ __global__ __launch_bounds__(kT) void k_scan_emit_w(const T* __restrict__ w, int
                                                    filter, offset, a, &L[wave], d_out, e_out);
 }
 
-// Multinomial emission, one weight block per wave (after the carries).
+// Multinomial emission, one weight block per wave (after the carries); with
+// d_out and e_out also the claim vector and the marked ancestry of Code 10's
+// Prepermute (the multinomial ancestry is sorted, as the strata schemes' is).
 template <typename T>
 __global__ __launch_bounds__(kT) void k_scan_emit_mw(const T* __restrict__ w, int64_t n,
                                                      uint32_t nb, uint32_t nbe, Key key,
@@ -1138,7 +1150,9 @@ __global__ __launch_bounds__(kT) void k_scan_emit_mw(const T* __restrict__ w, in
                                                      Carries C, ECarries CE,
                                                      const uint64_t* __restrict__ evals,
                                                      int32_t* __restrict__ a,
-                                                     uint32_t* __restrict__ flags) {
+                                                     uint32_t* __restrict__ flags,
+                                                     int32_t* __restrict__ d_out,
+                                                     int32_t* __restrict__ e_out) {
   offset = counter_offset(key, offset);
   __shared__ MultiWaveLds L[kWavesPerWG];
   const uint32_t wave = (uint32_t)__builtin_amdgcn_readfirstlane(threadIdx.x / kWave);
@@ -1148,12 +1162,18 @@ __global__ __launch_bounds__(kT) void k_scan_emit_mw(const T* __restrict__ w, in
   if (flags && b == 0 && threadIdx.x == 0 && status) atomicOr(flags, status);
   const int64_t P0 = (int64_t)b * kBlock;
   if (status & (FLAG_BAD_WEIGHTS | FLAG_ZERO_TOTAL)) {
-    for (int64_t i = P0 + lane_id(); i < min(P0 + kBlock, n); i += kWave) a[i] = (int32_t)i;
+    for (int64_t i = P0 + lane_id(); i < min(P0 + kBlock, n); i += kWave) {
+      a[i] = (int32_t)i;
+      if (d_out) {
+        d_out[i] = (int32_t)i;
+        e_out[i] = (int32_t)i;
+      }
+    }
     return;
   }
   C.gscale = hdr->gscale;
   emit_multi_wave<T, true>(w, n, P0, recs[b], C[b], C[b + 1], C.gscale, hdr->Q, key, filter,
-                           offset, CE, nbe, evals, a, &L[wave]);
+                           offset, CE, nbe, evals, a, &L[wave], d_out, e_out);
 }
 
 // ---------------------------------------------------------------- Code 5
@@ -1566,7 +1586,8 @@ hipError_t launch_scan_t(const void* wv, int64_t n, Key key, uint32_t offset, ui
   if (e != hipSuccess) return e;
   if constexpr (multi) {
     hipLaunchKernelGGL((k_scan_emit_mw<T>), dim3(wgs_b), dim3(kT), 0, stream, w, n, nb, nbe, key,
-                       offset, filter, hdr, recs, cs.C, cs.CE, (const uint64_t*)evals, a, flags);
+                       offset, filter, hdr, recs, cs.C, cs.CE, (const uint64_t*)evals, a, flags,
+                       d_out, e_out);
   } else {
     hipLaunchKernelGGL((k_scan_emit_w<T, SCHEME, false>), dim3(wgs_b), dim3(kT), 0, stream, w,
                        n, nb, key, offset, filter, hdr, recs, cs.C, a, flags, d_out, e_out);
@@ -1800,6 +1821,11 @@ hipError_t launch_multinomial_iid(bool f64, const void* w, int64_t n, Key key, u
 hipError_t launch_scan_claimed(int scheme, bool f64, const void* w, int64_t n, Key key,
                                uint32_t offset, uint32_t filter, int32_t* a, void* ws,
                                uint32_t* flags, int32_t* d, int32_t* e, hipStream_t stream) {
+  if (scheme == SCHEME_MULTINOMIAL)
+    return f64 ? launch_scan_t<double, SCHEME_MULTINOMIAL>(w, n, key, offset, filter, a, ws,
+                                                           flags, stream, d, e)
+               : launch_scan_t<float, SCHEME_MULTINOMIAL>(w, n, key, offset, filter, a, ws, flags,
+                                                          stream, d, e);
   if (scheme == SCHEME_STRATIFIED)
     return f64 ? launch_scan_t<double, SCHEME_STRATIFIED>(w, n, key, offset, filter, a, ws, flags,
                                                           stream, d, e)

@@ -4,7 +4,7 @@ One step of the timed workload -- n = 2^20 float32 weights for y = 0..4 (data
 seed 100 + y), all five resamplers with Philox seed 1 (Metropolis with
 B = 4, 6, 16, 60, 354 from eq. (B), rejection with w_max = 1), and the
 permutation of every ancestry (the fused claim of resample_permuted for
-stratified and systematic) -- is run through the benchmark's own StepWorkload
+the three collective schemes) -- is run through the benchmark's own StepWorkload
 and every output is compared with the oracle: bit for bit for Metropolis
 (Code 2), rejection (Code 3) and the permutation (Code 10), by the tie rule
 for the collective schemes (Codes 5, 7, 8).  The oracle's Metropolis and

@@ -1,5 +1,5 @@
 """resample_permuted against the two separate calls and the oracle: the
-claim pass fused into the stratified / systematic emission (the claim vector
+claim pass fused into the multinomial / stratified / systematic emission (the claim vector
 and the marked ancestry written there) must give the ancestors and the
 permutation bit for bit, on one and several emission workgroups; the other
 schemes, short vectors and batches run the two steps in turn."""
@@ -53,7 +53,7 @@ def test_fused_equals_separate(scheme, n, y):
         assert np.array_equal(c, oracle.permute(a)[0])
 
 
-@pytest.mark.parametrize("scheme", ["stratified", "systematic"])
+@pytest.mark.parametrize("scheme", ["multinomial", "stratified", "systematic"])
 def test_fused_long_vector_pipelined_emission(scheme):
     n = (1 << 23) + 5
     w = torch.from_numpy(inputs.weights(n, 1.0, seed=3)).cuda()
@@ -67,7 +67,7 @@ def test_fused_long_vector_pipelined_emission(scheme):
 def test_fused_float64_and_table_path(dtype):
     n = 1 << 18
     w = torch.from_numpy(inputs.weights(n, 4.0, seed=1).astype(dtype)).cuda()
-    for scheme in ("metropolis", "rejection", "systematic"):
+    for scheme in ("metropolis", "rejection", "systematic", "multinomial"):
         a, c = pfr().resample_permuted(scheme, w, seed=2, B=354)
         a_ref, c_ref = separate(scheme, w, 2, B=354)
         assert np.array_equal(host(a), a_ref), scheme
@@ -77,7 +77,7 @@ def test_fused_float64_and_table_path(dtype):
 def test_zero_weights_give_identity_and_flag():
     n = 50000
     w = torch.zeros(n, device="cuda")
-    for scheme in ("stratified", "systematic"):
+    for scheme in ("multinomial", "stratified", "systematic"):
         fl = torch.zeros(1, dtype=torch.int32, device="cuda")
         a, c = pfr().resample_permuted(scheme, w, seed=1, flags=fl)
         assert int(host(fl)[0]) == pfr().FLAG_ZERO_TOTAL
