@@ -6,6 +6,7 @@
 // the Philox counter, never on which lane or wave did the work, so every
 // launch shape gives the same bits.
 #include "pfr_kernels.h"
+#include <cstring>
 
 namespace pfr {
 
@@ -289,6 +290,39 @@ __global__ __launch_bounds__(kPackThreads) void k_pack_table(const uint8_t* __re
     nib[p] = packed;
   }
   if (blockIdx.x == 0 && threadIdx.x == 0) *cm_out = cM;
+}
+
+// The rejection table in one pass, without the vector's largest code: the
+// distances are taken from c_ref, the code of the caller's w_max, which
+// bounds every valid weight.  A bucket whose code reaches c_ref (or whose
+// weights are invalid, code 255) gets distance 0, i.e. the bound
+// 2^(c_ref - 127) >= w_max, which no trial's u * w_max exceeds: it is never
+// skipped, and the exact test decides as without the table.  One thread per
+// bucket; eight lanes OR their nibbles into one word, stored by the first.
+template <typename T>
+__global__ __launch_bounds__(kCodeThreads) void k_bound_nibbles(const T* __restrict__ w,
+                                                                int64_t n, int shift, uint32_t nb,
+                                                                uint32_t c_ref,
+                                                                uint32_t* __restrict__ nib,
+                                                                uint32_t* __restrict__ cm_out) {
+  const int64_t b = (int64_t)blockIdx.x * kCodeThreads + threadIdx.x;
+  uint32_t d = 0;
+  if (b < (int64_t)nb) {
+    const int64_t e = ((b + 1) << shift) < n ? ((b + 1) << shift) : n;
+    uint32_t c = 0;
+    for (int64_t k = b << shift; k < e; ++k) {
+      const T v = w[k];
+      const uint32_t ck = weight_ok(v) ? bound_code(v) : 255u;
+      c = ck > c ? ck : c;
+    }
+    d = c >= c_ref ? 0u : (c_ref - c > 15u ? 15u : c_ref - c);
+  }
+  uint32_t word = d << (4 * (threadIdx.x & 7u));
+  word |= __shfl_xor(word, 1);
+  word |= __shfl_xor(word, 2);
+  word |= __shfl_xor(word, 4);
+  if ((threadIdx.x & 7u) == 0 && b < (int64_t)nb) nib[b >> 3] = word;
+  if (blockIdx.x == 0 && threadIdx.x == 0) *cm_out = c_ref;
 }
 
 // Workgroup prologue: the packed table copied into LDS with 16-byte loads (the
@@ -827,6 +861,16 @@ hipError_t launch_bound_codes(const T* w, int64_t n, const TableGeom& g, void* w
   return hipGetLastError();
 }
 
+// bound_code of a finite positive binary64 on the host: 2^(c - 127) >= v
+uint32_t ref_code(double v) {
+  uint64_t bits;
+  memcpy(&bits, &v, sizeof bits);
+  const int e = (int)((bits >> 52) & 0x7FF);
+  if (e == 0) return 0u;  // below 2^-1022: every code reaches it
+  const int c = e - 1023 + 127 + ((bits & 0xFFFFFFFFFFFFFull) != 0ull ? 1 : 0);
+  return c < 0 ? 0u : (c > 255 ? 255u : (uint32_t)c);
+}
+
 // Workgroups of the table kernels: one per CU, each with a chunk of particles.
 constexpr int64_t kTableGrid = 256;
 
@@ -933,11 +977,14 @@ hipError_t launch_rejection_table(const T* w, int64_t n, double w_max, uint32_t 
                                   Key key, uint32_t offset, uint32_t filter, int32_t* a,
                                   uint32_t* flags, void* ws, hipStream_t stream) {
   const TableGeom g = table_geom(n);
-  hipError_t e = launch_bound_codes(w, n, g, ws, stream);
+  char* base = (char*)ws;
+  hipLaunchKernelGGL(k_bound_nibbles<T>, dim3((g.nb + kCodeThreads - 1) / kCodeThreads),
+                     dim3(kCodeThreads), 0, stream, w, n, g.shift, g.nb, ref_code(w_max),
+                     (uint32_t*)(base + g.nib_off), (uint32_t*)(base + g.cm_off));
+  hipError_t e = hipGetLastError();
   if (e != hipSuccess) return e;
   // chunks of 16 waves x rejection_per_wave particles, several per CU
   const int64_t chunk = (int64_t)tuning().rejection_per_wave * (kTableThreads / kWave);
-  char* base = (char*)ws;
   hipLaunchKernelGGL(k_rejection_table<T>, dim3((unsigned)((n + chunk - 1) / chunk)),
                      dim3(kTableThreads), 0, stream, w, n, w_max, max_trials, key, offset, filter,
                      a, flags, chunk, (const uint32_t*)(base + g.nib_off),

@@ -74,3 +74,41 @@ def test_batched_results_do_not_depend_on_tuning():
                 assert np.array_equal(a, b), st
     finally:
         m.set_tuning(**saved)
+
+
+@pytest.mark.parametrize("case", ["invalid_weights", "loose_bound", "tight_bound", "float64"])
+def test_rejection_table_equals_plain_kernel(case):
+    """The rejection bound table (distances from the code of w_max) against the
+    plain kernel, the table switched off: the same bits, with invalid weights
+    (their buckets are never skipped), a bound 16 times the largest weight
+    (distances saturate four octaves earlier), one equal to the largest weight
+    and binary64 weights near 2^-100."""
+    m = pfr()
+    saved = m.get_tuning()
+    n = 1 << 20
+    x = inputs.weights(n, 2.0, seed=11)
+    w_max = 1.0
+    if case == "invalid_weights":
+        x[[7, n // 3]] = np.nan
+        x[n // 2] = -0.5
+        x[n - 5] = np.inf
+    elif case == "loose_bound":
+        w_max = 16.0
+    elif case == "tight_bound":
+        w_max = float(x.max())
+    elif case == "float64":
+        x = x.astype(np.float64) * 2.0**-100
+        w_max = 2.0**-100
+    w = torch.from_numpy(x).cuda()
+    kw = dict(seed=5)
+    try:
+        m.set_tuning(**{**saved, "rejection_table": 1})
+        fa = torch.zeros(1, dtype=torch.int32, device="cuda")
+        a = m.resample_rejection(w, w_max, flags=fa, **kw).cpu().numpy()
+        m.set_tuning(**{**saved, "rejection_table": 0})
+        fb = torch.zeros(1, dtype=torch.int32, device="cuda")
+        b = m.resample_rejection(w, w_max, flags=fb, **kw).cpu().numpy()
+    finally:
+        m.set_tuning(**saved)
+    assert np.array_equal(a, b)
+    assert int(fa.cpu()[0]) == int(fb.cpu()[0])
