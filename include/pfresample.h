@@ -278,9 +278,10 @@ PFR_API size_t pfr_resample_permuted_workspace_bytes(pfr_op scheme, const pfr_se
  * PFR_OP_REJECTION.  Writes the scheme's ancestry to `ancestors` and its
  * Code 10 permutation to `permuted`, bit for bit what resample_<scheme>
  * followed by permute_ancestors (sorted_hint set for the collective schemes)
- * would write, with the same flags.  For a long single vector of the exact
- * multinomial, stratified or systematic scheme the emission writes the claim vector and
- * the marked ancestry itself, so only the resolve pass follows; the other
+ * would write, with the same flags.  For a long single vector of an exact
+ * collective scheme (multinomial, stratified, systematic: sorted ancestries)
+ * the emission writes the claim vector and the marked ancestry itself, so
+ * only the resolve pass follows; the other
  * cases run the two steps one after the other (claiming inside Metropolis and
  * rejection, with atomics beside their random weight loads, measured slower
  * than the separate claim pass on MI355X). */

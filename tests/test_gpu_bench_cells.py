@@ -108,7 +108,7 @@ def test_bench_collective_tie_rule(step_outputs, scheme, yi):
     assert np.all(np.diff(a) >= 0) and a[0] >= 0 and a[-1] < w.size
     assert np.all(w[a] > 0)
     check_ties(a, a_or, r, pts, delta, max_ties=5 + int(20 * delta * w.size))
-    # the permutation (fused claim for stratified / systematic) of the GPU's ancestry
+    # the permutation (fused claim for the collective schemes) of the GPU's ancestry
     assert np.array_equal(perms[(y, scheme)], oracle.permute(a)[0])
 
 
