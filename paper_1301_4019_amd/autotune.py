@@ -313,7 +313,17 @@ def batch_tune(torch, pfr, inputs, timer, chosen, meas, with_tuning, same, log):
     pick("batch_stage_max_kb", (128, 64, 16), alt_both, both)
     pick_shared("batch_metropolis_chunk", (1024, 2048, 4096, 8192, 16384),
                 (metro_ragged, metro_filter), both_f)
-    pick("batch_rejection_per_wave", (64, 128, 256, 512, 1024), rej, out)
+    def rej_ragged():
+        pfr.resample_rejection(w, 1.0, seed=1, offsets=off, max_len=max_len,
+                               out=both_f[fw.numel():])
+
+    def rej_filter():
+        pfr.resample_rejection(fw, 1.0, seed=1, offsets=foff, max_len=1 << 14,
+                               out=both_f[:fw.numel()])
+
+    # like the Metropolis chunk, the rejection schedule serves both batch shapes
+    pick_shared("batch_rejection_per_wave", (64, 128, 256, 512, 1024), (rej_ragged, rej_filter),
+                both_f)
 
     a_unsorted = torch.empty_like(out)
     pfr.resample_metropolis(w, 0, seed=1, B_per_filter=B, offsets=off, max_len=max_len,

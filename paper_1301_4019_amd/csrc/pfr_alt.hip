@@ -463,7 +463,12 @@ __device__ __forceinline__ int nth_set_bit(uint64_t mask, int q) {
 }
 
 // One wave works through the particles [r0, r1) (global indices) of one
-// segment (weights ws, length n, filter id filt).
+// segment (weights ws, length n, filter id filt).  With a queue (an LDS
+// counter shared by the workgroup's waves, starting at 0) the waves hand out
+// the particles of [r0, r1) among themselves, so that none runs out of work
+// while another still holds a long range: a wave takes as many particles as
+// it has free lanes.  (Pieces of about four passes' worth, to wait on the
+// counter less often, were slower: the waves then ran out unevenly.)
 // With TABLE, a trial whose u * w_max exceeds the bucket bound of j is
 // rejected without loading w_j.
 constexpr int kRejBatch = 4;  // trials per lane and pass (past the first pass)
@@ -471,7 +476,8 @@ template <bool TABLE, typename T>
 __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint32_t filt,
                                      double wmax, int64_t r0, int64_t r1, uint32_t max_trials,
                                      Key key, uint32_t offset, int32_t* __restrict__ a,
-                                     uint32_t& my_flags, const BoundTable& tab) {
+                                     uint32_t& my_flags, const BoundTable& tab,
+                                     uint32_t* queue = nullptr) {
   const uint32_t lane = lane_id();
   // table kernels: ws is a global vector of n * sizeof(T) < 2^31 bytes
   const __amdgpu_buffer_rsrc_t wv = buffer_view(ws, TABLE ? n * (uint32_t)sizeof(T) : 0u);
@@ -490,15 +496,21 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
   while (true) {
     const uint64_t freem = ballot(cur < 0);
     if (freem != 0 && next < r1) {
-      const int64_t avail = r1 - next;
       const int64_t nfree = __popcll(freem);
+      if (queue) {  // the next nfree particles of the workgroup's range
+        uint32_t old = 0;
+        if (lane == 0) old = atomicAdd(queue, (uint32_t)nfree);
+        next = r0 + (int64_t)shfl(old, 0);
+      }
+      const int64_t avail = r1 - next > 0 ? r1 - next : 0;
       const int64_t take = nfree < avail ? nfree : avail;
       const int64_t rank = __popcll(freem & lanemask_lt());
       if (cur < 0 && rank < take) {
         cur = next + rank;
         t = 0;
       }
-      next += take;
+      // past the range: the queue is used up for every wave
+      next += queue ? nfree : take;
     }
     if (next >= r1) break;
     const int nq = accepted * 2u < tried ? kRejBatch : 1;  // (results do not depend on nq)
@@ -648,8 +660,9 @@ __device__ void rejection_wave_range(const T* ws, int64_t base, uint32_t n, uint
 }
 
 // A workgroup takes the particles [p0, p1) and walks the segments that overlap
-// them; each segment part is split evenly among the workgroup's waves.  A
-// segment of at most CAP weights is first copied into LDS.
+// them; the waves hand out each segment part among themselves (an LDS
+// counter reset between the part's barriers).  A segment of at most CAP
+// weights is first copied into LDS.
 template <typename T, int CAP, int THREADS>
 __global__ __launch_bounds__(THREADS) void k_rejection(
     const T* __restrict__ w, int64_t n_total, const int64_t* __restrict__ offsets,
@@ -657,9 +670,8 @@ __global__ __launch_bounds__(THREADS) void k_rejection(
     Key key, uint32_t offset, uint32_t filter_base, int32_t* __restrict__ a,
     uint32_t* __restrict__ flags, int64_t chunk) {
   __shared__ T sw[CAP > 0 ? CAP : 1];
+  __shared__ uint32_t queue;  // particles of the segment part handed out so far
   offset = counter_offset(key, offset);
-  constexpr int kWaves = THREADS / kWave;
-  const int wave = (int)threadIdx.x / kWave;
   const int64_t p0 = (int64_t)blockIdx.x * chunk;
   const int64_t p1 = p0 + chunk < n_total ? p0 + chunk : n_total;
   uint32_t my_flags = 0;
@@ -671,19 +683,17 @@ __global__ __launch_bounds__(THREADS) void k_rejection(
     if (q1 <= g0) continue;  // empty segment
     const uint32_t n = (uint32_t)(end - base);
     const double wmax = w_max_dev ? w_max_dev[f] : w_max;
-    const int64_t len = q1 - g0;
-    const int64_t r0 = g0 + len * wave / kWaves;
-    const int64_t r1 = g0 + len * (wave + 1) / kWaves;
-    if (CAP > 0 && n <= (uint32_t)CAP) {
-      __syncthreads();  // the previous segment's trials are done with sw
-      stage_weights(w + base, n, sw);
-      __syncthreads();
-      rejection_wave_range<false>(sw, base, n, filter_base + f, wmax, r0, r1, max_trials, key,
-                                  offset, a, my_flags, BoundTable{});
-    } else {
-      rejection_wave_range<false>(w + base, base, n, filter_base + f, wmax, r0, r1, max_trials,
-                                  key, offset, a, my_flags, BoundTable{});
-    }
+    const bool staged = CAP > 0 && n <= (uint32_t)CAP;
+    __syncthreads();  // the previous part's trials are done with sw and the queue
+    if (threadIdx.x == 0) queue = 0;
+    if (staged) stage_weights(w + base, n, sw);
+    __syncthreads();
+    if (staged)
+      rejection_wave_range<false>(sw, base, n, filter_base + f, wmax, g0, q1, max_trials, key,
+                                  offset, a, my_flags, BoundTable{}, &queue);
+    else
+      rejection_wave_range<false>(w + base, base, n, filter_base + f, wmax, g0, q1, max_trials,
+                                  key, offset, a, my_flags, BoundTable{}, &queue);
     g0 = q1;
   }
   if (flags) {
@@ -692,8 +702,8 @@ __global__ __launch_bounds__(THREADS) void k_rejection(
   }
 }
 
-// One vector with the LDS bound table; the workgroup's chunk is split among
-// its waves.
+// One vector with the LDS bound table; the workgroup's waves hand out its
+// chunk among themselves.
 template <typename T>
 __global__ __launch_bounds__(kTableThreads) void k_rejection_table(
     const T* __restrict__ w, int64_t n, double w_max, uint32_t max_trials, Key key,
@@ -701,19 +711,16 @@ __global__ __launch_bounds__(kTableThreads) void k_rejection_table(
     int64_t chunk, const uint32_t* __restrict__ nib_g, const uint32_t* __restrict__ cm,
     uint32_t nb, int shift) {
   __shared__ __align__(16) uint8_t nib[kTableBuckets / 2];
+  __shared__ uint32_t queue;  // particles of the chunk handed out so far
   offset = counter_offset(key, offset);
+  if (threadIdx.x == 0) queue = 0;  // before the barrier of the table's load
   const BoundTable tab = load_bound_table(nib_g, cm, nb, shift, nib);
-  constexpr int kWaves = kTableThreads / kWave;
-  const int wave = (int)threadIdx.x / kWave;
   const int64_t p0 = (int64_t)blockIdx.x * chunk;
   const int64_t p1 = p0 + chunk < n ? p0 + chunk : n;
   uint32_t my_flags = 0;
-  if (p0 < p1) {
-    const int64_t len = p1 - p0;
-    rejection_wave_range<true>(w, 0, (uint32_t)n, filter, w_max, p0 + len * wave / kWaves,
-                               p0 + len * (wave + 1) / kWaves, max_trials, key, offset, a,
-                               my_flags, tab);
-  }
+  if (p0 < p1)
+    rejection_wave_range<true>(w, 0, (uint32_t)n, filter, w_max, p0, p1, max_trials, key,
+                               offset, a, my_flags, tab, &queue);
   if (flags) {
     const uint32_t wf = wave_reduce(my_flags, OpOr());
     if (lane_id() == 0 && wf) atomicOr(flags, wf);

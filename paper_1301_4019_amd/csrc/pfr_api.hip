@@ -18,7 +18,7 @@ namespace {
 // access holds the lock, and readers get a copy.
 std::mutex g_tuning_mu;
 // the values the autotuner chose on MI355X (gfx950), also in tuning.json
-Tuning g_tuning = {4096, 256, 60, 1, 256, 2048, 0, 128, 8192, 256, 16384};
+Tuning g_tuning = {4096, 256, 60, 1, 256, 2048, 0, 128, 8192, 1024, 16384};
 }  // namespace
 
 Tuning tuning() {
@@ -670,7 +670,7 @@ void pfr_tuning_defaults(pfr_tuning* t) {
   t->batch_scan_wg_max_len = 0;
   t->batch_stage_max_kb = 128;
   t->batch_metropolis_chunk = 8192;
-  t->batch_rejection_per_wave = 256;
+  t->batch_rejection_per_wave = 1024;
   t->batch_permute_lds_max = 16384;
 }
 
